@@ -1,0 +1,277 @@
+"""Seeded synthetic inputs for the coupled-macromodel solve of a lattice of
+fictitious boxes (Patel, Triverio, Hum, "A Fast Macromodeling Approach to
+Efficiently Simulate Inhomogeneous Electromagnetic Surfaces").
+
+This module only *draws and lays out inputs*: the patch geometry of one box,
+random per-cell-type macromodels, the cell-type map of the lattice, incidence
+angles, the sampled plane-wave excitation, random dense coupling blocks and
+random vectors.  None of the method's arithmetic lives here: no coupling
+operator, no FFT, no macromodel apply, no Krylov solve.  Both the CPU oracle
+and the GPU library consume what this module produces; neither is imported.
+
+Conventions (one wavelength = 1, so k = 2*pi; e^{+j w t} time convention,
+free-space impedance eta = 1 so that M is scaled by 1/eta):
+
+* Box of one lattice element: 0.45 x 0.45 x 0.10, centred on its lattice
+  point; lattice pitch 0.5 so facing faces of neighbours leave a 0.05 gap.
+* Patches: the +z and -z faces carry an n_t x n_t grid; each of the four side
+  faces an s_a (along its 0.45 edge) x s_h (along z) grid.  Face order
+  [+z, -z, +x, -x, +y, -y]; row-major inside a face with the index along the
+  first tangent fastest.  Tangents: +-z faces (x, y); +-x faces (y, z);
+  +-y faces (x, z).  Normals point out of the box.
+* Local unknown order on one box (J block first, then M, Sec. II-A):
+  u = tau*(2*n_patch) + 2*p + alpha, tau = 0 for J, 1 for M, alpha the
+  tangent index.  Element m = iy*nx + ix; vectors are [rhs][iy][ix][u]
+  (the element-major stacking of Sec. III-A).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+SEED_ROOT = 191104576          # arXiv id 1911.04576
+WAVELENGTH = 1.0
+K0 = 2.0 * math.pi / WAVELENGTH
+PITCH = 0.5
+BOX_A = 0.45                    # box edge along x and y
+BOX_H = 0.10                    # box height along z
+
+# (n_t, s_a, s_h) patch grids -> 24, 48, 72 patches per box
+PATCH_GRIDS = {24: (2, 2, 2), 48: (4, 4, 1), 72: (4, 5, 2)}
+
+# stream order of SeedSequence.spawn for every config
+_STREAMS = ("s_types", "type_map", "rhs_angles", "arrivals", "serving", "test_blocks")
+
+
+@dataclasses.dataclass(frozen=True)
+class BoxGeometry:
+    """Patch layout of one fictitious box (identical for every element)."""
+    rho: np.ndarray      # [n_patch, 3] patch centres relative to the box centre
+    area: np.ndarray     # [n_patch]
+    tan: np.ndarray      # [n_patch, 2, 3] unit tangents
+    normal: np.ndarray   # [n_patch, 3] outward unit normal
+    grid: tuple
+
+    @property
+    def n_patch(self) -> int:
+        return int(self.rho.shape[0])
+
+    @property
+    def n_eq(self) -> int:
+        return 4 * self.n_patch
+
+
+def box_geometry(n_patch: int) -> BoxGeometry:
+    n_t, s_a, s_h = PATCH_GRIDS[n_patch]
+    a, h = BOX_A, BOX_H
+    ex, ey, ez = np.eye(3)
+    rho, area, tan, nrm = [], [], [], []
+
+    def face(origin, t1, t2, n1, n2, len1, len2, normal):
+        d1, d2 = len1 / n1, len2 / n2
+        for i2 in range(n2):
+            for i1 in range(n1):
+                c = origin + t1 * (-len1 / 2 + (i1 + 0.5) * d1) + t2 * (-len2 / 2 + (i2 + 0.5) * d2)
+                rho.append(c)
+                area.append(d1 * d2)
+                tan.append(np.stack([t1, t2]))
+                nrm.append(normal)
+
+    face(+ez * h / 2, ex, ey, n_t, n_t, a, a, +ez)
+    face(-ez * h / 2, ex, ey, n_t, n_t, a, a, -ez)
+    face(+ex * a / 2, ey, ez, s_a, s_h, a, h, +ex)
+    face(-ex * a / 2, ey, ez, s_a, s_h, a, h, -ex)
+    face(+ey * a / 2, ex, ez, s_a, s_h, a, h, +ey)
+    face(-ey * a / 2, ex, ez, s_a, s_h, a, h, -ey)
+    g = BoxGeometry(np.array(rho, dtype=np.float64), np.array(area, dtype=np.float64),
+                    np.array(tan, dtype=np.float64), np.array(nrm, dtype=np.float64),
+                    (n_t, s_a, s_h))
+    assert g.n_patch == n_patch
+    return g
+
+
+@dataclasses.dataclass(frozen=True)
+class Config:
+    cfg: int
+    nx: int
+    ny: int
+    n_patch: int
+    n_types: int
+    angles: tuple          # ((theta_rad, pol), ...) pol in {"TE", "TM"}
+    tol: float
+
+    @property
+    def n_eq(self) -> int:
+        return 4 * self.n_patch
+
+    @property
+    def M(self) -> int:
+        return self.nx * self.ny
+
+    @property
+    def nrhs(self) -> int:
+        return len(self.angles)
+
+    @property
+    def n_unknowns(self) -> int:
+        return self.M * self.n_eq
+
+
+def streams(cfg: int):
+    ss = np.random.SeedSequence([SEED_ROOT, cfg])
+    kids = ss.spawn(len(_STREAMS))
+    return {name: np.random.Generator(np.random.PCG64(k)) for name, k in zip(_STREAMS, kids)}
+
+
+def config(cfg: int) -> Config:
+    """The four fixed lattice workloads (the fifth, serving, is drawn per request)."""
+    d = math.radians
+    if cfg == 1:
+        return Config(1, 4, 4, 24, 4, ((0.0, "TE"),), 1e-10)
+    if cfg == 2:
+        return Config(2, 32, 32, 48, 16, ((d(30.0), "TE"),), 1e-8)
+    if cfg == 3:
+        th = np.sort(streams(3)["rhs_angles"].uniform(0.0, d(60.0), size=8))
+        ang = tuple((float(t), p) for t in th for p in ("TE", "TM"))
+        return Config(3, 64, 64, 72, 32, ang, 1e-6)
+    if cfg == 4:
+        ang = tuple((d(t), p) for t in (0.0, 30.0) for p in ("TE", "TM"))
+        return Config(4, 128, 128, 48, 16, ang, 1e-6)
+    raise ValueError(f"no fixed config {cfg}")
+
+
+def small_config(nx: int, ny: int, n_patch: int = 24, n_types: int = 4, nrhs: int = 1, seed: int = 0) -> Config:
+    """Reduced lattices for tests (same recipe, seeded by `seed` instead of a config id)."""
+    angles = tuple((math.radians(10.0 * i), "TE" if i % 2 == 0 else "TM") for i in range(nrhs))
+    return Config(1000 + seed, nx, ny, n_patch, n_types, angles, 1e-10)
+
+
+def s_types(cfg: Config, rng=None) -> np.ndarray:
+    """Per-cell-type macromodels: iid complex Gaussian, scaled to spectral norm 0.5.
+
+    Returns complex128 [n_types][n_eq][n_eq]; the apply is y_u = sum_v S[u][v] x_v.
+    """
+    rng = rng if rng is not None else streams(cfg.cfg)["s_types"]
+    n = cfg.n_eq
+    out = np.empty((cfg.n_types, n, n), dtype=np.complex128)
+    for t in range(cfg.n_types):
+        z = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / math.sqrt(2.0)
+        smax = np.linalg.svd(z, compute_uv=False)[0]
+        out[t] = 0.5 * z / smax
+    return out
+
+
+def type_map(cfg: Config, rng=None) -> np.ndarray:
+    """Cell type of every element, int32 [ny][nx], uniform over the types."""
+    rng = rng if rng is not None else streams(cfg.cfg)["type_map"]
+    return rng.integers(0, cfg.n_types, size=(cfg.ny, cfg.nx)).astype(np.int32)
+
+
+def element_positions(nx: int, ny: int, pitch: float = PITCH) -> np.ndarray:
+    """Lattice point of every element, [ny][nx][3]; element (0, 0) at the origin."""
+    iy, ix = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    pos = np.zeros((ny, nx, 3))
+    pos[..., 0] = ix * pitch
+    pos[..., 1] = iy * pitch
+    return pos
+
+
+def incident_fields(theta: float, pol: str, pts: np.ndarray, k: float = K0):
+    """Plane wave travelling along k_hat = (sin t, 0, -cos t) (phi = 0).
+
+    TE: E along y; TM: E along y x k_hat.  eta = 1, so H = k_hat x E.
+    Returns (E, H), each complex [..., 3] at the points `pts` [..., 3].
+    """
+    khat = np.array([math.sin(theta), 0.0, -math.cos(theta)])
+    yhat = np.array([0.0, 1.0, 0.0])
+    ehat = yhat if pol == "TE" else np.cross(yhat, khat)
+    phase = np.exp(-1j * k * (pts @ khat))
+    E = phase[..., None] * ehat
+    H = phase[..., None] * np.cross(khat, ehat)
+    return E, H
+
+
+def plane_wave_rhs(cfg: Config, geom: BoxGeometry | None = None, pitch: float = PITCH, k: float = K0) -> np.ndarray:
+    """Excitation b sampled at the patch centres: the equivalent incident currents
+    J = n x H_inc and M = -n x E_inc (Love's equivalence, Sec. II-A), projected on
+    each patch tangent.  complex128 [nrhs][ny][nx][n_eq]."""
+    geom = geom if geom is not None else box_geometry(cfg.n_patch)
+    pos = element_positions(cfg.nx, cfg.ny, pitch)                    # [ny][nx][3]
+    pts = pos[:, :, None, :] + geom.rho[None, None, :, :]            # [ny][nx][p][3]
+    npch = geom.n_patch
+    b = np.zeros((cfg.nrhs, cfg.ny, cfg.nx, 4 * npch), dtype=np.complex128)
+    for r, (theta, pol) in enumerate(cfg.angles):
+        E, H = incident_fields(theta, pol, pts, k)
+        nxH = np.cross(geom.normal[None, None], H)
+        nxE = np.cross(geom.normal[None, None], E)
+        for a in range(2):
+            t = geom.tan[:, a, :][None, None]
+            b[r, :, :, 2 * np.arange(npch) + a] = np.moveaxis(np.sum(t * nxH, axis=-1), -1, 0)
+            b[r, :, :, 2 * npch + 2 * np.arange(npch) + a] = np.moveaxis(np.sum(t * (-nxE), axis=-1), -1, 0)
+    return b
+
+
+def random_blocks(nx: int, ny: int, n_eq: int, seed: int, zero_self: bool = True) -> np.ndarray:
+    """Dense, non-symmetric random coupling blocks T(d), complex128
+    [2ny-1][2nx-1][n_eq][n_eq] indexed [dy+ny-1][dx+nx-1].  T(0) = 0 unless
+    `zero_self` is False.  Scaled so the summed operator has modest norm."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 77, seed])))
+    shape = (2 * ny - 1, 2 * nx - 1, n_eq, n_eq)
+    scale = 0.5 / math.sqrt(n_eq * max(1, nx * ny))
+    t = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) * scale
+    if zero_self:
+        t[ny - 1, nx - 1] = 0.0
+    return t
+
+
+def random_vectors(nrhs: int, nx: int, ny: int, n_eq: int, seed: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 78, seed])))
+    shape = (nrhs, ny, nx, n_eq)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def random_types(n_types: int, n_eq: int, seed: int, norm: float = 0.5) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 79, seed])))
+    out = np.empty((n_types, n_eq, n_eq), dtype=np.complex128)
+    for t in range(n_types):
+        z = (rng.standard_normal((n_eq, n_eq)) + 1j * rng.standard_normal((n_eq, n_eq))) / math.sqrt(2.0)
+        out[t] = norm * z / np.linalg.svd(z, compute_uv=False)[0]
+    return out
+
+
+def random_type_map(nx: int, ny: int, n_types: int, seed: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 80, seed])))
+    return rng.integers(0, n_types, size=(ny, nx)).astype(np.int32)
+
+
+# ----------------------------------------------------------------------------- serving
+@dataclasses.dataclass(frozen=True)
+class Request:
+    rid: int
+    arrival_s: float
+    n: int            # lattice is n x n
+    n_patch: int
+    nrhs: int
+    angles: tuple
+    type_seed: int
+
+
+def serving_stream(n_requests: int, rate_hz: float, n_min: int = 8, n_max: int = 96,
+                   patches=(24, 48, 72), max_rhs: int = 32, cfg: int = 5):
+    """Poisson arrivals of solve requests: n ~ U{n_min..n_max}, n_eq ~ U{96,192,288},
+    nrhs ~ U{1..max_rhs}, per-request seeded angles/polarisations and cell types."""
+    st = streams(cfg)
+    arr = np.cumsum(st["arrivals"].exponential(1.0 / rate_hz, size=n_requests))
+    par = st["serving"]
+    out = []
+    for i in range(n_requests):
+        n = int(par.integers(n_min, n_max + 1))
+        npch = int(par.choice(patches))
+        nrhs = int(par.integers(1, max_rhs + 1))
+        th = par.uniform(0.0, math.radians(60.0), size=nrhs)
+        pol = par.integers(0, 2, size=nrhs)
+        ang = tuple((float(t), "TE" if q == 0 else "TM") for t, q in zip(th, pol))
+        out.append(Request(i, float(arr[i]), n, npch, nrhs, ang, int(par.integers(0, 2**31 - 1))))
+    return out
