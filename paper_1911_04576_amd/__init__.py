@@ -1,0 +1,272 @@
+"""Python binding of the emsurf C ABI (include/emsurf.h): argument marshalling
+only.  Every step of the coupled-macromodel path runs in the HIP kernels of
+libemsurf.so; there is no Python or CPU fallback, and importing the binding
+fails loudly when the library has not been built.
+
+Device buffers are passed as torch tensors (their data_ptr()) or raw integer
+addresses; host arrays as numpy arrays.  Streams are torch.cuda.Stream objects,
+raw hipStream_t integers, or None for the null stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libemsurf.so")
+
+EMSURF_OK = 0
+EMSURF_ERR_ARG = 1
+EMSURF_ERR_OOM = 2
+EMSURF_ERR_DEVICE = 3
+EMSURF_ERR_NOT_CONVERGED = 4
+EMSURF_ERR_BUSY = 5
+EMSURF_ERR_UNSUPPORTED = 6
+
+EMSURF_FP64 = 0
+EMSURF_FP32 = 1
+EMSURF_FP32_IR = 2
+
+EMSURF_STORE_FP64 = 1
+EMSURF_STORE_FP32 = 2
+
+PHASES = ("fft_x_fwd", "fft_y_fwd", "block_product", "fft_y_inv", "fft_x_inv")
+
+
+class EmsurfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"emsurf status {status}: {msg}")
+        self.status = status
+
+
+class emsurf_plan_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("n_eq", ctypes.c_int32),
+                ("n_types", ctypes.c_int32), ("max_rhs", ctypes.c_int32), ("store", ctypes.c_uint32)]
+
+
+class emsurf_geom(ctypes.Structure):
+    _fields_ = [("n_patch", ctypes.c_int32), ("rho", ctypes.c_void_p), ("area", ctypes.c_void_p),
+                ("tan", ctypes.c_void_p), ("pitch", ctypes.c_double), ("k", ctypes.c_double)]
+
+
+class emsurf_solve_opts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("tol", ctypes.c_double), ("restart", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("use_x0", ctypes.c_int32), ("inner_tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int32)]
+
+
+class emsurf_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("rel_res_true", ctypes.c_double), ("ms", ctypes.c_double)]
+
+
+class emsurf_plan_stats(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("n_freq", ctypes.c_int64),
+                ("bytes_that64", ctypes.c_size_t), ("bytes_that32", ctypes.c_size_t),
+                ("bytes_total", ctypes.c_size_t)]
+
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "emsurf_plan_bytes": (ctypes.c_size_t, [ctypes.POINTER(emsurf_plan_desc)]),
+    "emsurf_plan_create": (ctypes.c_int, [ctypes.POINTER(emsurf_plan_desc), _P, ctypes.c_int32, _P, _P, _P,
+                                          ctypes.POINTER(_P)]),
+    "emsurf_plan_create_green": (ctypes.c_int, [ctypes.POINTER(emsurf_plan_desc), ctypes.POINTER(emsurf_geom), _P,
+                                                _P, _P, ctypes.POINTER(_P)]),
+    "emsurf_fill_T_point_green": (ctypes.c_int, [ctypes.POINTER(emsurf_geom), ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "emsurf_apply_T": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
+    "emsurf_apply_S": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
+    "emsurf_apply_A": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
+    "emsurf_solve": (ctypes.c_int, [_P, ctypes.POINTER(emsurf_solve_opts), ctypes.c_int32, _P, _P,
+                                    ctypes.POINTER(emsurf_solve_info), _P]),
+    "emsurf_plan_query": (ctypes.c_int, [_P, ctypes.POINTER(emsurf_plan_stats)]),
+    "emsurf_kernel_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "emsurf_kernel_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "emsurf_plan_destroy": (None, [_P]),
+    "emsurf_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "emsurf_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libemsurf.so (raises if it has not been built: no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(python -m paper_1911_04576_amd._build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != EMSURF_OK:
+        msg = lib().emsurf_last_error().decode()
+        raise EmsurfError(st, msg)
+
+
+def _dptr(t) -> int:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return int(t.data_ptr())
+
+
+def _stream(s) -> int:
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return int(s.cuda_stream)
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Geometry:
+    """Host-side emsurf_geom that keeps its arrays alive."""
+
+    def __init__(self, rho, area, tan, pitch: float, k: float):
+        self._rho, prho = _host(rho, np.float64)
+        self._area, parea = _host(area, np.float64)
+        self._tan, ptan = _host(tan, np.float64)
+        assert self._rho.shape[1:] == (3,) and self._tan.shape[1:] == (2, 3)
+        self.c = emsurf_geom(self._rho.shape[0], prho, parea, ptan, float(pitch), float(k))
+
+    @property
+    def n_patch(self):
+        return self._rho.shape[0]
+
+
+class Plan:
+    """An emsurf_plan handle (destroyed with the object or by .destroy())."""
+
+    def __init__(self, handle: int, desc: emsurf_plan_desc):
+        self.h = handle
+        self.desc = desc
+
+    def destroy(self):
+        if self.h:
+            lib().emsurf_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def stats(self) -> emsurf_plan_stats:
+        return emsurf_plan_query(self)
+
+
+def _desc(nx, ny, n_eq, n_types, max_rhs, store):
+    return emsurf_plan_desc(int(nx), int(ny), int(n_eq), int(n_types), int(max_rhs), int(store))
+
+
+def emsurf_plan_bytes(nx, ny, n_eq, n_types, max_rhs, store=EMSURF_STORE_FP64 | EMSURF_STORE_FP32) -> int:
+    d = _desc(nx, ny, n_eq, n_types, max_rhs, store)
+    return int(lib().emsurf_plan_bytes(ctypes.byref(d)))
+
+
+def emsurf_plan_create(nx, ny, n_eq, n_types, max_rhs, T_blocks, S_types, elem_type,
+                       store=EMSURF_STORE_FP64 | EMSURF_STORE_FP32, stream=None) -> Plan:
+    """T_blocks: numpy complex128 [2ny-1][2nx-1][n][n] (host) or a device tensor."""
+    d = _desc(nx, ny, n_eq, n_types, max_rhs, store)
+    if isinstance(T_blocks, np.ndarray):
+        tb, ptb = _host(T_blocks, np.complex128)
+        is_dev = 0
+    else:
+        tb, ptb, is_dev = T_blocks, _dptr(T_blocks), 1
+    S, pS = _host(S_types, np.complex128)
+    et, pet = _host(elem_type, np.int32)
+    out = ctypes.c_void_p()
+    _check(lib().emsurf_plan_create(ctypes.byref(d), ptb, is_dev, pS, pet, _stream(stream), ctypes.byref(out)))
+    return Plan(out.value, d)
+
+
+def emsurf_plan_create_green(nx, ny, n_types, max_rhs, geom: Geometry, S_types, elem_type,
+                             store=EMSURF_STORE_FP64 | EMSURF_STORE_FP32, stream=None) -> Plan:
+    d = _desc(nx, ny, 4 * geom.n_patch, n_types, max_rhs, store)
+    S, pS = _host(S_types, np.complex128)
+    et, pet = _host(elem_type, np.int32)
+    out = ctypes.c_void_p()
+    _check(lib().emsurf_plan_create_green(ctypes.byref(d), ctypes.byref(geom.c), pS, pet, _stream(stream),
+                                          ctypes.byref(out)))
+    return Plan(out.value, d)
+
+
+def emsurf_fill_T_point_green(geom: Geometry, nx, ny, T_blocks_dev, stream=None):
+    _check(lib().emsurf_fill_T_point_green(ctypes.byref(geom.c), int(nx), int(ny), _dptr(T_blocks_dev),
+                                           _stream(stream)))
+
+
+def emsurf_apply_T(plan: Plan, prec, nrhs, x_dev, y_dev, stream=None):
+    _check(lib().emsurf_apply_T(plan.h, int(prec), int(nrhs), _dptr(x_dev), _dptr(y_dev), _stream(stream)))
+
+
+def emsurf_apply_S(plan: Plan, prec, nrhs, x_dev, y_dev, stream=None):
+    _check(lib().emsurf_apply_S(plan.h, int(prec), int(nrhs), _dptr(x_dev), _dptr(y_dev), _stream(stream)))
+
+
+def emsurf_apply_A(plan: Plan, prec, nrhs, x_dev, y_dev, stream=None):
+    _check(lib().emsurf_apply_A(plan.h, int(prec), int(nrhs), _dptr(x_dev), _dptr(y_dev), _stream(stream)))
+
+
+def solve_opts(prec=EMSURF_FP64, tol=1e-10, restart=30, max_iter=500, use_x0=0, inner_tol=1e-5, max_outer=10):
+    return emsurf_solve_opts(int(prec), float(tol), int(restart), int(max_iter), int(use_x0), float(inner_tol),
+                             int(max_outer))
+
+
+def emsurf_solve(plan: Plan, opts: emsurf_solve_opts, nrhs, b_dev, x_dev, stream=None, raise_not_converged=False):
+    """Returns (status, [info per RHS as dicts])."""
+    infos = (emsurf_solve_info * int(nrhs))()
+    st = lib().emsurf_solve(plan.h, ctypes.byref(opts), int(nrhs), _dptr(b_dev), _dptr(x_dev), infos,
+                            _stream(stream))
+    if st != EMSURF_OK and (st != EMSURF_ERR_NOT_CONVERGED or raise_not_converged):
+        _check(st)
+    out = [dict(iters=i.iters, outer_iters=i.outer_iters, converged=bool(i.converged),
+                rel_res_true=i.rel_res_true, ms=i.ms) for i in infos]
+    return st, out
+
+
+def emsurf_plan_query(plan: Plan) -> emsurf_plan_stats:
+    s = emsurf_plan_stats()
+    _check(lib().emsurf_plan_query(plan.h, ctypes.byref(s)))
+    return s
+
+
+def emsurf_kernel_timing(plan: Plan, enable: bool):
+    _check(lib().emsurf_kernel_timing(plan.h, 1 if enable else 0))
+
+
+def emsurf_kernel_times(plan: Plan):
+    """Summed ms and launch counts per apply_T phase since the last call."""
+    ms = (ctypes.c_double * 5)()
+    cnt = (ctypes.c_int64 * 5)()
+    _check(lib().emsurf_kernel_times(plan.h, ms, cnt))
+    return {p: (ms[i], cnt[i]) for i, p in enumerate(PHASES)}
+
+
+def emsurf_status_str(st: int) -> str:
+    return lib().emsurf_status_str(int(st)).decode()
+
+
+def emsurf_last_error() -> str:
+    return lib().emsurf_last_error().decode()
+
+
+def emsurf_plan_destroy(plan: Plan):
+    plan.destroy()

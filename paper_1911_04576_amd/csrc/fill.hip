@@ -1,0 +1,190 @@
+// Plan-time kernels: circulant embedding of the coupling blocks (Sec. IV-B,
+// eq. (LJV3): block T(d) goes to padded slot d mod L on each lattice axis, all
+// other slots stay zero), the synthetic point-sampled coupling fill, and the
+// scatter of transformed kernel columns into the resident Fourier-domain
+// store (FP64 and/or FP32 rounded to nearest).
+//
+// The padded kernel chunk holds columns c in [c0, c0 + nc) of the n*n batch,
+// c = v*n + u (source v, test u), as a dense [Ly][Lx][nc] array, so that after
+// the 2-D transform every frequency's block is stored column-major.
+#include "internal.h"
+
+namespace emsurf {
+namespace {
+
+__device__ __forceinline__ int slot_to_offset(int s, int L, int N, bool* ok) {
+  if (s <= N - 1) { *ok = true; return s; }
+  if (s >= L - (N - 1)) { *ok = true; return s - L; }
+  *ok = false;
+  return 0;
+}
+
+__global__ void pad_blocks_kernel(const double2* __restrict__ Tb, int nx, int ny, int n, int Lx, int Ly,
+                                  long long c0, long long nc, double2* __restrict__ K) {
+  const long long total = (long long)Ly * Lx * nc;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long j = i % nc;
+    const long long sxy = i / nc;
+    const int sx = (int)(sxy % Lx), sy = (int)(sxy / Lx);
+    bool okx, oky;
+    const int dx = slot_to_offset(sx, Lx, nx, &okx);
+    const int dy = slot_to_offset(sy, Ly, ny, &oky);
+    double2 val{0.0, 0.0};
+    if (okx && oky) {
+      const long long c = c0 + j;
+      const int v = (int)(c / n), u = (int)(c - (long long)v * n);
+      const long long blk = (long long)(dy + ny - 1) * (2 * nx - 1) + (dx + nx - 1);
+      val = Tb[blk * n * n + (long long)u * n + v];
+    }
+    K[i] = val;
+  }
+}
+
+// T(d)[(tau,p,a),(tau',q,b)] = delta(tau,tau') (t_pa . t_qb) A_q exp(-jkR)/(4 pi R),
+// R = |rho_p - rho_q + pitch (dx, dy, 0)|, T(0) = 0.
+__device__ __forceinline__ double2 green_entry(const double* __restrict__ rho, const double* __restrict__ area,
+                                               const double* __restrict__ tan, int P, double pitch, double k,
+                                               int dx, int dy, int u, int v) {
+  if (dx == 0 && dy == 0) return double2{0.0, 0.0};
+  const int hu = u / (2 * P), hv = v / (2 * P);
+  if (hu != hv) return double2{0.0, 0.0};
+  const int lu = u - hu * 2 * P, lv = v - hv * 2 * P;
+  const int p = lu >> 1, a = lu & 1, q = lv >> 1, b = lv & 1;
+  const double* tp = tan + (p * 2 + a) * 3;
+  const double* tq = tan + (q * 2 + b) * 3;
+  const double dot = tp[0] * tq[0] + tp[1] * tq[1] + tp[2] * tq[2];
+  if (dot == 0.0) return double2{0.0, 0.0};
+  const double ex = rho[3 * p + 0] - rho[3 * q + 0] + pitch * dx;
+  const double ey = rho[3 * p + 1] - rho[3 * q + 1] + pitch * dy;
+  const double ez = rho[3 * p + 2] - rho[3 * q + 2];
+  const double R = sqrt(ex * ex + ey * ey + ez * ez);
+  double sn, cs;
+  sincos(k * R, &sn, &cs);
+  const double w = dot * area[q] / (4.0 * 3.14159265358979323846 * R);
+  return double2{w * cs, -w * sn};
+}
+
+__global__ void green_padded_kernel(const double* __restrict__ rho, const double* __restrict__ area,
+                                    const double* __restrict__ tan, int P, double pitch, double k, int nx, int ny,
+                                    int Lx, int Ly, long long c0, long long nc, double2* __restrict__ K) {
+  const int n = 4 * P;
+  const long long total = (long long)Ly * Lx * nc;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long j = i % nc;
+    const long long sxy = i / nc;
+    const int sx = (int)(sxy % Lx), sy = (int)(sxy / Lx);
+    bool okx, oky;
+    const int dx = slot_to_offset(sx, Lx, nx, &okx);
+    const int dy = slot_to_offset(sy, Ly, ny, &oky);
+    double2 val{0.0, 0.0};
+    if (okx && oky) {
+      const long long c = c0 + j;
+      const int v = (int)(c / n), u = (int)(c - (long long)v * n);
+      val = green_entry(rho, area, tan, P, pitch, k, dx, dy, u, v);
+    }
+    K[i] = val;
+  }
+}
+
+__global__ void green_blocks_kernel(const double* __restrict__ rho, const double* __restrict__ area,
+                                    const double* __restrict__ tan, int P, double pitch, double k, int nx, int ny,
+                                    double2* __restrict__ Tb) {
+  const int n = 4 * P;
+  const long long total = (long long)(2 * ny - 1) * (2 * nx - 1) * n * n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long nn = (long long)n * n;
+    const long long blk = i / nn;
+    const int rem = (int)(i - blk * nn);
+    const int u = rem / n, v = rem - u * n;
+    const int dx = (int)(blk % (2 * nx - 1)) - (nx - 1);
+    const int dy = (int)(blk / (2 * nx - 1)) - (ny - 1);
+    Tb[i] = green_entry(rho, area, tan, P, pitch, k, dx, dy, u, v);
+  }
+}
+
+__global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, long long nn, long long c0,
+                                   long long nc, double2* __restrict__ t64, float2* __restrict__ t32) {
+  const long long total = P * nc;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long kf = i / nc, j = i - kf * nc;
+    const double2 v = Kc[i];
+    const long long dst = kf * nn + c0 + j;
+    if (t64) t64[dst] = v;
+    if (t32) t32[dst] = float2{(float)v.x, (float)v.y};
+  }
+}
+
+template <typename VI, typename VO>
+__global__ void convert_kernel(const VI* __restrict__ in, VO* __restrict__ out, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const VI a = in[i];
+    out[i] = VO{static_cast<decltype(out[0].x)>(a.x), static_cast<decltype(out[0].x)>(a.y)};
+  }
+}
+
+unsigned grid_for(long long total, int threads) {
+  long long g = (total + threads - 1) / threads;
+  if (g > 65536LL * 8) g = 65536LL * 8;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+void launch_pad_blocks(const void* T_blocks_dev, int nx, int ny, int n, int Lx, int Ly, int64_t c0, int64_t nc,
+                       void* K, hipStream_t s) {
+  const long long total = (long long)Ly * Lx * nc;
+  hipLaunchKernelGGL(pad_blocks_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s,
+                     static_cast<const double2*>(T_blocks_dev), nx, ny, n, Lx, Ly, (long long)c0, (long long)nc,
+                     static_cast<double2*>(K));
+  EMS_LAUNCH_CHECK();
+}
+
+void launch_green_padded(const GreenGeomDev& g, int nx, int ny, int Lx, int Ly, int64_t c0, int64_t nc, void* K,
+                         hipStream_t s) {
+  const long long total = (long long)Ly * Lx * nc;
+  hipLaunchKernelGGL(green_padded_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, g.rho.as<const double>(),
+                     g.area.as<const double>(), g.tan.as<const double>(), g.n_patch, g.pitch, g.k, nx, ny, Lx, Ly,
+                     (long long)c0, (long long)nc, static_cast<double2*>(K));
+  EMS_LAUNCH_CHECK();
+}
+
+void launch_green_blocks(const GreenGeomDev& g, int nx, int ny, void* T_blocks, hipStream_t s) {
+  const long long n = 4LL * g.n_patch;
+  const long long total = (long long)(2 * ny - 1) * (2 * nx - 1) * n * n;
+  hipLaunchKernelGGL(green_blocks_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, g.rho.as<const double>(),
+                     g.area.as<const double>(), g.tan.as<const double>(), g.n_patch, g.pitch, g.k, nx, ny,
+                     static_cast<double2*>(T_blocks));
+  EMS_LAUNCH_CHECK();
+}
+
+void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, void* that64, void* that32,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(store_chunk_kernel, dim3(grid_for((long long)P * nc, 256)), dim3(256), 0, s,
+                     static_cast<const double2*>(Kc), (long long)P, (long long)nn, (long long)c0, (long long)nc,
+                     static_cast<double2*>(that64), static_cast<float2*>(that32));
+  EMS_LAUNCH_CHECK();
+}
+
+void launch_convert(Cx tin, Cx tout, const void* in, void* out, int64_t n, hipStream_t s) {
+  const unsigned g = grid_for(n, 256);
+  if (tin == Cx::C128 && tout == Cx::C64)
+    hipLaunchKernelGGL((convert_kernel<double2, float2>), dim3(g), dim3(256), 0, s,
+                       static_cast<const double2*>(in), static_cast<float2*>(out), (long long)n);
+  else if (tin == Cx::C64 && tout == Cx::C128)
+    hipLaunchKernelGGL((convert_kernel<float2, double2>), dim3(g), dim3(256), 0, s,
+                       static_cast<const float2*>(in), static_cast<double2*>(out), (long long)n);
+  else if (tin == Cx::C128)
+    hipLaunchKernelGGL((convert_kernel<double2, double2>), dim3(g), dim3(256), 0, s,
+                       static_cast<const double2*>(in), static_cast<double2*>(out), (long long)n);
+  else
+    hipLaunchKernelGGL((convert_kernel<float2, float2>), dim3(g), dim3(256), 0, s,
+                       static_cast<const float2*>(in), static_cast<float2*>(out), (long long)n);
+  EMS_LAUNCH_CHECK();
+}
+
+}  // namespace emsurf

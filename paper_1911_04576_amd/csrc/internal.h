@@ -1,0 +1,192 @@
+// Internal declarations of the emsurf library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/emsurf.h"
+
+namespace emsurf {
+
+// ----------------------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+const char* last_error();
+
+struct Err {
+  emsurf_status st;
+};
+
+#define EMS_HIP(call)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) {                                                                \
+      ::emsurf::set_error(std::string(#call) + ": " + hipGetErrorString(e_));              \
+      throw ::emsurf::Err{e_ == hipErrorOutOfMemory ? EMSURF_ERR_OOM : EMSURF_ERR_DEVICE}; \
+    }                                                                                      \
+  } while (0)
+
+#define EMS_CHECK_ARG(cond, msg)                 \
+  do {                                           \
+    if (!(cond)) {                               \
+      ::emsurf::set_error(msg);                  \
+      throw ::emsurf::Err{EMSURF_ERR_ARG};       \
+    }                                            \
+  } while (0)
+
+#define EMS_LAUNCH_CHECK() EMS_HIP(hipGetLastError())
+
+// ----------------------------------------------------------------------------- device buffer
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t n) { alloc(n); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) return;
+    EMS_HIP(hipMalloc(&p, n));
+    bytes = n;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  PinnedBuf() = default;
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  ~PinnedBuf() { if (p) (void)hipHostFree(p); }
+  void alloc(size_t n) {
+    if (p) (void)hipHostFree(p);
+    p = nullptr; bytes = 0;
+    if (n == 0) return;
+    EMS_HIP(hipHostMalloc(&p, n, hipHostMallocDefault));
+    bytes = n;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ----------------------------------------------------------------------------- FFT
+// One pass of a batched 1-D FFT along one lattice axis.  A "line" is one 1-D
+// transform over L points for a contiguous set of batch columns; line l is
+// split as (l1, l0) = (l / nl0, l % nl0) to form its base offsets.
+struct FftPass {
+  int L = 0;           // transform length (power of two, 2..1024)
+  int n_in = 0;        // points read; points >= n_in are zero
+  int n_out = 0;       // points written (crop)
+  int batch = 0;       // batch columns per line (contiguous, stride 1)
+  int n_lines = 0;
+  int nl0 = 1;
+  int64_t in_s0 = 0, in_s1 = 0, out_s0 = 0, out_s1 = 0;   // line strides (elements)
+  int64_t in_pt = 0, out_pt = 0;                          // point strides (elements)
+  int sign = -1;       // -1 forward, +1 inverse
+  double scale = 1.0;  // applied to outputs
+};
+
+enum class Cx { C64, C128 };
+
+// Launch a pass. tin/tcomp/tout select element types of input, arithmetic and output.
+void launch_fft_pass(const FftPass& p, Cx tin, Cx tcomp, Cx tout, const void* in, void* out,
+                     const void* twiddles, hipStream_t s);
+// Twiddle table exp(-2 pi i j / L), j < L, in FP64 (computed on the host with
+// long-double arithmetic) and FP32 (rounded from it).  Device memory, cached.
+const void* twiddle_table(int L, Cx t);
+
+// ----------------------------------------------------------------------------- block products
+// yh[k][r][u] = sum_v That[k](u, v) xh[k][r][v]; yh and xh must not overlap.
+// That layout: [k][v][u] (column-major n x n blocks).
+void launch_block_product(Cx t, const void* That, const void* xh, void* yh, int n, int nrhs, int64_t P,
+                          hipStream_t s);
+
+// ----------------------------------------------------------------------------- S apply
+struct TypeTiles {
+  DevBuf elem_sorted;   // int32 [M] elements sorted by type
+  DevBuf tiles;         // int32 [n_tiles][3] = (type, start in elem_sorted, count)
+  int n_tiles = 0;
+};
+// y[r][m] = (axpy ? x_axpy[r][m] - : ) S_{type(m)} t[r][m]
+// types: S store type; t type; x_axpy and y types (FP64 or FP32 per ty/tx).
+void launch_apply_S(Cx ts, Cx tt, Cx txy, const void* S, const TypeTiles& tiles, int n, int M, int nrhs,
+                    const void* t, const void* x_axpy, void* y, hipStream_t s);
+
+// ----------------------------------------------------------------------------- fill
+// Write padded kernel K[sy][sx][v][u] (columns cols [c0, c0+nc) of the n*n batch
+// only, as a dense [Ly][Lx][nc] array) from blocks or from the Green fill.
+struct GreenGeomDev {
+  DevBuf rho, area, tan;   // double [P][3], [P], [P][2][3]
+  int n_patch = 0;
+  double pitch = 0, k = 0;
+};
+void launch_pad_blocks(const void* T_blocks_dev, int nx, int ny, int n, int Lx, int Ly, int64_t c0, int64_t nc,
+                       void* K, hipStream_t s);
+void launch_green_padded(const GreenGeomDev& g, int nx, int ny, int Lx, int Ly, int64_t c0, int64_t nc, void* K,
+                         hipStream_t s);
+void launch_green_blocks(const GreenGeomDev& g, int nx, int ny, void* T_blocks, hipStream_t s);
+// Scatter a [P][nc] chunk into the [P][n*n] store at column offset c0 (FP64 and/or FP32 rounded).
+void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, void* that64, void* that32,
+                        hipStream_t s);
+
+// ----------------------------------------------------------------------------- vector ops (GMRES)
+void launch_convert(Cx tin, Cx tout, const void* in, void* out, int64_t n, hipStream_t s);
+
+// ----------------------------------------------------------------------------- plan
+struct Workspace {
+  DevBuf W;     // half-transformed [Ny][Lx][B]
+  DevBuf X;     // spectral input [Ly][Lx][B]
+  DevBuf Y;     // spectral output [Ly][Lx][B]
+  DevBuf t;     // T x result for A-apply [nrhs][M][n] (widest type)
+};
+
+struct KernelTimer {
+  bool enabled = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[5];
+  size_t used[5] = {0, 0, 0, 0, 0};
+  double ms_acc[5] = {0, 0, 0, 0, 0};
+  int64_t cnt[5] = {0, 0, 0, 0, 0};
+};
+
+}  // namespace emsurf
+
+struct emsurf_plan_s {
+  emsurf_plan_desc d{};
+  int Lx = 0, Ly = 0;
+  int64_t P = 0;
+  int M = 0;
+  emsurf::DevBuf that64, that32;  // [P][v][u]
+  emsurf::DevBuf S64, S32;        // [n_types][n][n] row-major
+  emsurf::TypeTiles tiles;
+  std::mutex mu;
+  std::map<hipStream_t, emsurf::Workspace*> ws;
+  emsurf::KernelTimer timer;
+  hipStream_t timer_stream = nullptr;
+  ~emsurf_plan_s();
+};
+
+namespace emsurf {
+Workspace& workspace(emsurf_plan p, hipStream_t s);
+// apply_T with explicit element types: input tin, compute/that type tc, output tout.
+void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* x, void* y, hipStream_t s);
+// apply_A with explicit types: x (tx) -> y (ty) = x - S T x, arithmetic in tc.
+void apply_A_typed(emsurf_plan p, Cx tx, Cx tc, Cx ty, int nrhs, const void* x, void* y, hipStream_t s);
+inline size_t cx_bytes(Cx t) { return t == Cx::C128 ? 16 : 8; }
+}  // namespace emsurf

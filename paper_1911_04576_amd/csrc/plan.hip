@@ -1,0 +1,515 @@
+// Plans and operator applies of the C ABI: circulant embedding and kernel FFT
+// at plan time, then y = T x (Sec. IV-B), y = S x (Sec. III-A) and
+// y = x - S T x per apply.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+
+#include "internal.h"
+
+namespace emsurf {
+
+namespace {
+thread_local std::string g_last_error;
+
+int pow2_at_least(int v) {
+  int L = 2;
+  while (L < v) L <<= 1;
+  return L;
+}
+
+void validate_desc(const emsurf_plan_desc* d) {
+  EMS_CHECK_ARG(d != nullptr, "plan descriptor is NULL");
+  EMS_CHECK_ARG(d->nx >= 1 && d->ny >= 1, "lattice sizes nx, ny must be >= 1");
+  EMS_CHECK_ARG(d->nx <= 512 && d->ny <= 512, "lattice sizes above 512 are not supported");
+  EMS_CHECK_ARG(d->n_eq >= 1 && d->n_eq <= 512, "n_eq must be in [1, 512]");
+  EMS_CHECK_ARG(d->n_types >= 1, "n_types must be >= 1");
+  EMS_CHECK_ARG(d->max_rhs >= 1 && d->max_rhs <= 64, "max_rhs must be in [1, 64]");
+  EMS_CHECK_ARG((d->store & (EMSURF_STORE_FP64 | EMSURF_STORE_FP32)) != 0 &&
+                    (d->store & ~(EMSURF_STORE_FP64 | EMSURF_STORE_FP32)) == 0,
+                "store must be a non-empty mask of EMSURF_STORE_FP64 | EMSURF_STORE_FP32");
+}
+
+struct Sizes {
+  int Lx, Ly;
+  int64_t P, M, n, nn;
+  size_t that64, that32, S, tiles, ws;
+};
+
+Sizes sizes_of(const emsurf_plan_desc* d) {
+  Sizes z{};
+  z.Lx = pow2_at_least(2 * d->nx - 1);
+  z.Ly = pow2_at_least(2 * d->ny - 1);
+  z.P = (int64_t)z.Lx * z.Ly;
+  z.M = (int64_t)d->nx * d->ny;
+  z.n = d->n_eq;
+  z.nn = z.n * z.n;
+  z.that64 = (d->store & EMSURF_STORE_FP64) ? (size_t)(z.P * z.nn) * 16 : 0;
+  z.that32 = (d->store & EMSURF_STORE_FP32) ? (size_t)(z.P * z.nn) * 8 : 0;
+  z.S = (size_t)d->n_types * z.nn * (16 + 8);
+  z.tiles = (size_t)z.M * 4 + (size_t)(z.M + d->n_types) * 12;
+  const int64_t B = (int64_t)d->max_rhs * z.n;
+  z.ws = (size_t)(d->ny * (int64_t)z.Lx * B) * 16 + 2 * (size_t)(z.P * B) * 16 + (size_t)(B * z.M) * 16;
+  return z;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error() { return g_last_error.c_str(); }
+
+// Workspaces: one per stream, sized for max_rhs at FP64 width.
+Workspace& workspace(emsurf_plan p, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(p->mu);
+  auto it = p->ws.find(s);
+  if (it != p->ws.end()) return *it->second;
+  const int64_t B = (int64_t)p->d.max_rhs * p->d.n_eq;
+  auto w = std::make_unique<Workspace>();
+  w->W.alloc((size_t)(p->d.ny * (int64_t)p->Lx * B) * 16);
+  w->X.alloc((size_t)(p->P * B) * 16);
+  w->Y.alloc((size_t)(p->P * B) * 16);
+  w->t.alloc((size_t)(B * p->M) * 16);
+  Workspace* raw = w.release();
+  p->ws[s] = raw;
+  return *raw;
+}
+
+namespace {
+
+void timer_begin(emsurf_plan p, int phase, hipStream_t s, hipEvent_t* end_out) {
+  *end_out = nullptr;
+  if (!p->timer.enabled) return;
+  auto& T = p->timer;
+  if (T.used[phase] == T.ev[phase].size()) {
+    hipEvent_t a, b;
+    EMS_HIP(hipEventCreate(&a));
+    EMS_HIP(hipEventCreate(&b));
+    T.ev[phase].push_back({a, b});
+  }
+  auto& pr = T.ev[phase][T.used[phase]++];
+  EMS_HIP(hipEventRecord(pr.first, s));
+  *end_out = pr.second;
+}
+
+void timer_end(hipEvent_t e, hipStream_t s) {
+  if (e) EMS_HIP(hipEventRecord(e, s));
+}
+
+}  // namespace
+
+void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* x, void* y, hipStream_t s) {
+  const void* That = (tc == Cx::C128) ? p->that64.p : p->that32.p;
+  if (!That) {
+    set_error(tc == Cx::C128 ? "plan has no FP64 Fourier-domain store" : "plan has no FP32 Fourier-domain store");
+    throw Err{EMSURF_ERR_UNSUPPORTED};
+  }
+  Workspace& w = workspace(p, s);
+  const int n = p->d.n_eq, Nx = p->d.nx, Ny = p->d.ny, Lx = p->Lx, Ly = p->Ly;
+  const int64_t M = p->M;
+  const int64_t B = (int64_t)nrhs * n;
+  const void* twx = twiddle_table(Lx, tc);
+  const void* twy = twiddle_table(Ly, tc);
+  hipEvent_t e;
+
+  // forward along x: lines (r, iy); x[r][iy][ix][u] -> W[iy][kx][r][u]
+  FftPass fx;
+  fx.L = Lx; fx.n_in = Nx; fx.n_out = Lx; fx.batch = n;
+  fx.n_lines = nrhs * Ny; fx.nl0 = Ny;
+  fx.in_s1 = M * n; fx.in_s0 = (int64_t)Nx * n; fx.in_pt = n;
+  fx.out_s1 = n; fx.out_s0 = (int64_t)Lx * B; fx.out_pt = B;
+  fx.sign = -1;
+  timer_begin(p, 0, s, &e);
+  launch_fft_pass(fx, tin, tc, tc, x, w.W.p, twx, s);
+  timer_end(e, s);
+
+  // forward along y: lines kx; W[iy][kx][b] -> X[ky][kx][b]
+  FftPass fy;
+  fy.L = Ly; fy.n_in = Ny; fy.n_out = Ly; fy.batch = (int)B;
+  fy.n_lines = Lx; fy.nl0 = Lx;
+  fy.in_s0 = B; fy.in_pt = (int64_t)Lx * B;
+  fy.out_s0 = B; fy.out_pt = (int64_t)Lx * B;
+  fy.sign = -1;
+  timer_begin(p, 1, s, &e);
+  launch_fft_pass(fy, tc, tc, tc, w.W.p, w.X.p, twy, s);
+  timer_end(e, s);
+
+  // Fourier-domain block products
+  timer_begin(p, 2, s, &e);
+  launch_block_product(tc, That, w.X.p, w.Y.p, n, nrhs, p->P, s);
+  timer_end(e, s);
+
+  // inverse along y, keep rows iy < Ny
+  FftPass iy = fy;
+  iy.n_in = Ly; iy.n_out = Ny; iy.sign = +1;
+  timer_begin(p, 3, s, &e);
+  launch_fft_pass(iy, tc, tc, tc, w.Y.p, w.W.p, twy, s);
+  timer_end(e, s);
+
+  // inverse along x, keep ix < Nx, scale 1/(Lx Ly)
+  FftPass ix;
+  ix.L = Lx; ix.n_in = Lx; ix.n_out = Nx; ix.batch = n;
+  ix.n_lines = nrhs * Ny; ix.nl0 = Ny;
+  ix.in_s1 = n; ix.in_s0 = (int64_t)Lx * B; ix.in_pt = B;
+  ix.out_s1 = M * n; ix.out_s0 = (int64_t)Nx * n; ix.out_pt = n;
+  ix.sign = +1;
+  ix.scale = 1.0 / ((double)Lx * (double)Ly);
+  timer_begin(p, 4, s, &e);
+  launch_fft_pass(ix, tc, tc, tout, w.W.p, y, twx, s);
+  timer_end(e, s);
+}
+
+void apply_A_typed(emsurf_plan p, Cx tx, Cx tc, Cx ty, int nrhs, const void* x, void* y, hipStream_t s) {
+  Workspace& w = workspace(p, s);
+  apply_T_typed(p, tx, tc, tc, nrhs, x, w.t.p, s);
+  const void* S = (tc == Cx::C128) ? p->S64.p : p->S32.p;
+  launch_apply_S(tc, tc, ty, S, p->tiles, p->d.n_eq, p->M, nrhs, w.t.p, x, y, s);
+}
+
+}  // namespace emsurf
+
+emsurf_plan_s::~emsurf_plan_s() {
+  for (auto& kv : ws) delete kv.second;
+  for (int ph = 0; ph < 5; ++ph)
+    for (auto& pr : timer.ev[ph]) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+}
+
+using namespace emsurf;
+
+namespace {
+
+template <typename F>
+emsurf_status guarded(F&& f) {
+  try {
+    f();
+    return EMSURF_OK;
+  } catch (const Err& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return EMSURF_ERR_OOM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return EMSURF_ERR_DEVICE;
+  } catch (...) {
+    set_error("unknown error");
+    return EMSURF_ERR_DEVICE;
+  }
+}
+
+void build_tiles(emsurf_plan p, const int32_t* elem_type, hipStream_t s) {
+  const int M = p->M;
+  const int nt = p->d.n_types;
+  std::vector<int> order(M);
+  for (int m = 0; m < M; ++m) {
+    EMS_CHECK_ARG(elem_type[m] >= 0 && elem_type[m] < nt, "elem_type entry out of [0, n_types)");
+    order[m] = m;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return elem_type[a] < elem_type[b]; });
+  const int TC = 32;
+  std::vector<int> tiles;
+  int i = 0;
+  while (i < M) {
+    const int t = elem_type[order[i]];
+    int j = i;
+    while (j < M && elem_type[order[j]] == t) ++j;
+    for (int a = i; a < j; a += TC) {
+      tiles.push_back(t);
+      tiles.push_back(a);
+      tiles.push_back(std::min(TC, j - a));
+    }
+    i = j;
+  }
+  p->tiles.n_tiles = (int)(tiles.size() / 3);
+  p->tiles.elem_sorted.alloc(order.size() * sizeof(int));
+  p->tiles.tiles.alloc(tiles.size() * sizeof(int));
+  EMS_HIP(hipMemcpyAsync(p->tiles.elem_sorted.p, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  EMS_HIP(hipMemcpyAsync(p->tiles.tiles.p, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  EMS_HIP(hipStreamSynchronize(s));
+}
+
+void upload_S(emsurf_plan p, const void* S_types, hipStream_t s) {
+  const size_t cnt = (size_t)p->d.n_types * p->d.n_eq * p->d.n_eq;
+  const double* h = static_cast<const double*>(S_types);
+  for (size_t i = 0; i < 2 * cnt; ++i) EMS_CHECK_ARG(std::isfinite(h[i]), "S_types has a non-finite entry");
+  p->S64.alloc(cnt * 16);
+  p->S32.alloc(cnt * 8);
+  EMS_HIP(hipMemcpyAsync(p->S64.p, S_types, cnt * 16, hipMemcpyHostToDevice, s));
+  launch_convert(Cx::C128, Cx::C64, p->S64.p, p->S32.p, (int64_t)cnt, s);
+  EMS_HIP(hipStreamSynchronize(s));
+}
+
+// Kernel FFT of the padded blocks, in column chunks, into the resident stores.
+template <typename FillChunk>
+void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill) {
+  const int64_t nn = (int64_t)p->d.n_eq * p->d.n_eq;
+  const int64_t P = p->P;
+  if (p->d.store & EMSURF_STORE_FP64) p->that64.alloc((size_t)(P * nn) * 16);
+  if (p->d.store & EMSURF_STORE_FP32) p->that32.alloc((size_t)(P * nn) * 8);
+  // two chunk buffers of at most ~512 MB each
+  int64_t nc = (int64_t)((512ull << 20) / ((size_t)P * 16));
+  nc = std::max<int64_t>(1, std::min<int64_t>(nc, nn));
+  nc = std::min<int64_t>(nc, 0x7fffffff);
+  DevBuf K((size_t)(P * nc) * 16), tmp((size_t)(P * nc) * 16);
+  const void* twx = twiddle_table(p->Lx, Cx::C128);
+  const void* twy = twiddle_table(p->Ly, Cx::C128);
+  for (int64_t c0 = 0; c0 < nn; c0 += nc) {
+    const int64_t cnt = std::min(nc, nn - c0);
+    fill(c0, cnt, K.p);
+    FftPass fx;
+    fx.L = p->Lx; fx.n_in = p->Lx; fx.n_out = p->Lx; fx.batch = (int)cnt;
+    fx.n_lines = p->Ly; fx.nl0 = p->Ly;
+    fx.in_s0 = (int64_t)p->Lx * cnt; fx.in_pt = cnt;
+    fx.out_s0 = (int64_t)p->Lx * cnt; fx.out_pt = cnt;
+    fx.sign = -1;
+    launch_fft_pass(fx, Cx::C128, Cx::C128, Cx::C128, K.p, tmp.p, twx, s);
+    FftPass fy;
+    fy.L = p->Ly; fy.n_in = p->Ly; fy.n_out = p->Ly; fy.batch = (int)cnt;
+    fy.n_lines = p->Lx; fy.nl0 = p->Lx;
+    fy.in_s0 = cnt; fy.in_pt = (int64_t)p->Lx * cnt;
+    fy.out_s0 = cnt; fy.out_pt = (int64_t)p->Lx * cnt;
+    fy.sign = -1;
+    launch_fft_pass(fy, Cx::C128, Cx::C128, Cx::C128, tmp.p, K.p, twy, s);
+    launch_store_chunk(K.p, P, nn, c0, cnt, p->that64.p, p->that32.p, s);
+  }
+  EMS_HIP(hipStreamSynchronize(s));
+}
+
+void upload_geom(const emsurf_geom* g, GreenGeomDev& d) {
+  EMS_CHECK_ARG(g != nullptr && g->rho && g->area && g->tan, "geometry pointers must be non-NULL");
+  EMS_CHECK_ARG(g->n_patch >= 1, "n_patch must be >= 1");
+  EMS_CHECK_ARG(std::isfinite(g->pitch) && g->pitch > 0 && std::isfinite(g->k), "pitch must be > 0, k finite");
+  const int P = g->n_patch;
+  for (int i = 0; i < P; ++i) EMS_CHECK_ARG(g->area[i] > 0 && std::isfinite(g->area[i]), "patch areas must be > 0");
+  d.n_patch = P;
+  d.pitch = g->pitch;
+  d.k = g->k;
+  d.rho.alloc((size_t)P * 3 * 8);
+  d.area.alloc((size_t)P * 8);
+  d.tan.alloc((size_t)P * 6 * 8);
+  EMS_HIP(hipMemcpy(d.rho.p, g->rho, (size_t)P * 3 * 8, hipMemcpyHostToDevice));
+  EMS_HIP(hipMemcpy(d.area.p, g->area, (size_t)P * 8, hipMemcpyHostToDevice));
+  EMS_HIP(hipMemcpy(d.tan.p, g->tan, (size_t)P * 6 * 8, hipMemcpyHostToDevice));
+}
+
+emsurf_plan new_plan(const emsurf_plan_desc* desc) {
+  validate_desc(desc);
+  auto z = sizes_of(desc);
+  emsurf_plan p = new emsurf_plan_s();
+  p->d = *desc;
+  p->Lx = z.Lx;
+  p->Ly = z.Ly;
+  p->P = z.P;
+  p->M = (int)z.M;
+  return p;
+}
+
+Cx prec_type(emsurf_prec prec) {
+  if (prec == EMSURF_FP64) return Cx::C128;
+  if (prec == EMSURF_FP32) return Cx::C64;
+  set_error("apply precision must be EMSURF_FP64 or EMSURF_FP32");
+  throw Err{EMSURF_ERR_ARG};
+}
+
+void check_apply(emsurf_plan plan, int32_t nrhs, const void* x, const void* y) {
+  EMS_CHECK_ARG(plan != nullptr, "plan is NULL");
+  EMS_CHECK_ARG(x != nullptr && y != nullptr, "x and y must be non-NULL device pointers");
+  EMS_CHECK_ARG(nrhs >= 1 && nrhs <= plan->d.max_rhs, "nrhs must be in [1, max_rhs]");
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t emsurf_plan_bytes(const emsurf_plan_desc* desc) {
+  size_t out = 0;
+  if (guarded([&] {
+        validate_desc(desc);
+        auto z = sizes_of(desc);
+        out = z.that64 + z.that32 + z.S + z.tiles + z.ws;
+      }) != EMSURF_OK)
+    return 0;
+  return out;
+}
+
+emsurf_status emsurf_plan_create(const emsurf_plan_desc* desc, const void* T_blocks, int32_t T_is_device,
+                                 const void* S_types, const int32_t* elem_type, void* stream, emsurf_plan* out) {
+  emsurf_plan p = nullptr;
+  emsurf_status st = guarded([&] {
+    EMS_CHECK_ARG(out != nullptr, "out is NULL");
+    EMS_CHECK_ARG(T_blocks && S_types && elem_type, "T_blocks, S_types and elem_type must be non-NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    p = new_plan(desc);
+    const int nx = desc->nx, ny = desc->ny, n = desc->n_eq;
+    const size_t tb_bytes = (size_t)(2 * ny - 1) * (2 * nx - 1) * n * n * 16;
+    DevBuf Tdev;
+    const void* Tb = T_blocks;
+    if (!T_is_device) {
+      Tdev.alloc(tb_bytes);
+      EMS_HIP(hipMemcpyAsync(Tdev.p, T_blocks, tb_bytes, hipMemcpyHostToDevice, s));
+      Tb = Tdev.p;
+    }
+    build_that(p, s, [&](int64_t c0, int64_t cnt, void* K) {
+      launch_pad_blocks(Tb, nx, ny, n, p->Lx, p->Ly, c0, cnt, K, s);
+    });
+    upload_S(p, S_types, s);
+    build_tiles(p, elem_type, s);
+    (void)workspace(p, s);
+    EMS_HIP(hipStreamSynchronize(s));
+  });
+  if (st != EMSURF_OK) {
+    delete p;
+    return st;
+  }
+  *out = p;
+  return EMSURF_OK;
+}
+
+emsurf_status emsurf_plan_create_green(const emsurf_plan_desc* desc, const emsurf_geom* geom, const void* S_types,
+                                       const int32_t* elem_type, void* stream, emsurf_plan* out) {
+  emsurf_plan p = nullptr;
+  emsurf_status st = guarded([&] {
+    EMS_CHECK_ARG(out != nullptr, "out is NULL");
+    EMS_CHECK_ARG(S_types && elem_type, "S_types and elem_type must be non-NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    validate_desc(desc);
+    EMS_CHECK_ARG(geom != nullptr && desc->n_eq == 4 * geom->n_patch, "n_eq must equal 4 * geom->n_patch");
+    GreenGeomDev g;
+    upload_geom(geom, g);
+    p = new_plan(desc);
+    build_that(p, s, [&](int64_t c0, int64_t cnt, void* K) {
+      launch_green_padded(g, desc->nx, desc->ny, p->Lx, p->Ly, c0, cnt, K, s);
+    });
+    upload_S(p, S_types, s);
+    build_tiles(p, elem_type, s);
+    (void)workspace(p, s);
+    EMS_HIP(hipStreamSynchronize(s));
+  });
+  if (st != EMSURF_OK) {
+    delete p;
+    return st;
+  }
+  *out = p;
+  return EMSURF_OK;
+}
+
+emsurf_status emsurf_fill_T_point_green(const emsurf_geom* geom, int32_t nx, int32_t ny, void* T_blocks_dev,
+                                        void* stream) {
+  return guarded([&] {
+    EMS_CHECK_ARG(T_blocks_dev != nullptr, "T_blocks_dev is NULL");
+    EMS_CHECK_ARG(nx >= 1 && ny >= 1 && nx <= 512 && ny <= 512, "lattice sizes must be in [1, 512]");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GreenGeomDev g;
+    upload_geom(geom, g);
+    launch_green_blocks(g, nx, ny, T_blocks_dev, s);
+    // the geometry buffers are freed on return: finish using them first
+    EMS_HIP(hipStreamSynchronize(s));
+  });
+}
+
+emsurf_status emsurf_apply_T(emsurf_plan plan, emsurf_prec prec, int32_t nrhs, const void* x_dev, void* y_dev,
+                             void* stream) {
+  return guarded([&] {
+    check_apply(plan, nrhs, x_dev, y_dev);
+    EMS_CHECK_ARG(x_dev != y_dev, "apply_T needs distinct x and y buffers");
+    const Cx t = prec_type(prec);
+    apply_T_typed(plan, t, t, t, nrhs, x_dev, y_dev, static_cast<hipStream_t>(stream));
+  });
+}
+
+emsurf_status emsurf_apply_S(emsurf_plan plan, emsurf_prec prec, int32_t nrhs, const void* x_dev, void* y_dev,
+                             void* stream) {
+  return guarded([&] {
+    check_apply(plan, nrhs, x_dev, y_dev);
+    const Cx t = prec_type(prec);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const void* S = (t == Cx::C128) ? plan->S64.p : plan->S32.p;
+    const void* src = x_dev;
+    if (x_dev == y_dev) {
+      Workspace& w = workspace(plan, s);
+      const size_t bytes = (size_t)nrhs * plan->M * plan->d.n_eq * cx_bytes(t);
+      EMS_HIP(hipMemcpyAsync(w.t.p, x_dev, bytes, hipMemcpyDeviceToDevice, s));
+      src = w.t.p;
+    }
+    launch_apply_S(t, t, t, S, plan->tiles, plan->d.n_eq, plan->M, nrhs, src, nullptr, y_dev, s);
+  });
+}
+
+emsurf_status emsurf_apply_A(emsurf_plan plan, emsurf_prec prec, int32_t nrhs, const void* x_dev, void* y_dev,
+                             void* stream) {
+  return guarded([&] {
+    check_apply(plan, nrhs, x_dev, y_dev);
+    EMS_CHECK_ARG(x_dev != y_dev, "apply_A needs distinct x and y buffers");
+    const Cx t = prec_type(prec);
+    apply_A_typed(plan, t, t, t, nrhs, x_dev, y_dev, static_cast<hipStream_t>(stream));
+  });
+}
+
+emsurf_status emsurf_plan_query(emsurf_plan plan, emsurf_plan_stats* out) {
+  return guarded([&] {
+    EMS_CHECK_ARG(plan != nullptr && out != nullptr, "plan and out must be non-NULL");
+    out->Lx = plan->Lx;
+    out->Ly = plan->Ly;
+    out->n_freq = plan->P;
+    out->bytes_that64 = plan->that64.bytes;
+    out->bytes_that32 = plan->that32.bytes;
+    size_t tot = plan->that64.bytes + plan->that32.bytes + plan->S64.bytes + plan->S32.bytes +
+                 plan->tiles.elem_sorted.bytes + plan->tiles.tiles.bytes;
+    std::lock_guard<std::mutex> lk(plan->mu);
+    for (auto& kv : plan->ws) tot += kv.second->W.bytes + kv.second->X.bytes + kv.second->Y.bytes + kv.second->t.bytes;
+    out->bytes_total = tot;
+  });
+}
+
+emsurf_status emsurf_kernel_timing(emsurf_plan plan, int32_t enable) {
+  return guarded([&] {
+    EMS_CHECK_ARG(plan != nullptr, "plan is NULL");
+    plan->timer.enabled = enable != 0;
+  });
+}
+
+emsurf_status emsurf_kernel_times(emsurf_plan plan, double* ms, int64_t* count) {
+  return guarded([&] {
+    EMS_CHECK_ARG(plan != nullptr && ms != nullptr && count != nullptr, "plan, ms and count must be non-NULL");
+    auto& T = plan->timer;
+    for (int ph = 0; ph < 5; ++ph) {
+      double acc = 0;
+      for (size_t i = 0; i < T.used[ph]; ++i) {
+        EMS_HIP(hipEventSynchronize(T.ev[ph][i].second));
+        float f = 0;
+        EMS_HIP(hipEventElapsedTime(&f, T.ev[ph][i].first, T.ev[ph][i].second));
+        acc += f;
+      }
+      ms[ph] = acc;
+      count[ph] = (int64_t)T.used[ph];
+      T.used[ph] = 0;
+    }
+  });
+}
+
+void emsurf_plan_destroy(emsurf_plan plan) {
+  if (!plan) return;
+  (void)hipDeviceSynchronize();
+  delete plan;
+}
+
+const char* emsurf_status_str(emsurf_status s) {
+  switch (s) {
+    case EMSURF_OK: return "ok";
+    case EMSURF_ERR_ARG: return "invalid argument";
+    case EMSURF_ERR_OOM: return "out of memory";
+    case EMSURF_ERR_DEVICE: return "device error";
+    case EMSURF_ERR_NOT_CONVERGED: return "not converged";
+    case EMSURF_ERR_BUSY: return "busy";
+    case EMSURF_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* emsurf_last_error(void) { return emsurf::last_error(); }
+
+}  // extern "C"
