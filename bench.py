@@ -61,6 +61,20 @@ def cpu_baseline(cfg, b, y_gpu, budget_s=15.0):
     }, max(errs)
 
 
+def measured_traffic():
+    """HBM bytes per FP32 block-product launch from the committed counter summary,
+    or None if the kernel source changed since the counters were taken."""
+    import hashlib
+    rec = os.path.join(ROOT, "profiles", "block_product_128x128_n192_rhs4_fp32_traffic.txt")
+    src = os.path.join(ROOT, "paper_1911_04576_amd", "csrc", "blockprod.hip")
+    try:
+        kv = dict(l.strip().split("=", 1) for l in open(rec) if "=" in l and not l.startswith("#"))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        return int(kv["traffic_bytes"]) if kv.get("source_sha256_16") == sha else None
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +83,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES solve timing")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-cal", action="store_true", help="also time a plain 2 GiB device copy")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the coupled solve is measured on one MI355X "
@@ -167,6 +182,28 @@ def main():
         solve["speedup_fp32_ir_vs_fp64"] = round(solve["fp64"]["ms"] / solve["fp32_ir"]["ms"], 3)
         solve["tol"] = cfg.tol
 
+    # plain device copy of a known size (bandwidth reference and counter calibration)
+    copy = None
+    if args.copy_cal:
+        nbytes = 1 << 31
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+        c = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(2):
+            c.copy_(a)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        reps = 10
+        for _ in range(reps):
+            c.copy_(a)
+        ev1.record()
+        torch.cuda.synchronize()
+        cms = ev0.elapsed_time(ev1) / reps
+        copy = {"bytes_read": nbytes, "bytes_written": nbytes, "avg_ms": round(cms, 4),
+                "GBs": round(2 * nbytes / (cms / 1e3) / 1e9, 1)}
+        log(f"copy 2 GiB -> 2 GiB: {cms:.3f} ms, {copy['GBs']} GB/s")
+        del a, c
+
     cpu = None
     parity = None
     if not args.no_cpu:
@@ -193,13 +230,14 @@ def main():
                    "unknowns": cfg.n_unknowns, "padded_fft": [Lx, Ly], "parallelism": "1 GPU"},
         "roofline": {"kernel": "block_gemv_kernel<float2,4> (Fourier-domain block product)", "bound": "hbm",
                      "achieved": round(bp_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(bp_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(bp_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "bytes_per_launch": bp_bytes, "avg_launch_ms": round(bp_avg, 4)},
         "apply_T": {"algorithmic_bytes": apply_bytes,
                     "effective_GBs": round(apply_bytes / (ms_step / 1e3) / 1e9, 1),
                     "frac_of_hbm_peak": round(apply_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                     "phase_avg_ms": phase_avg, "fp64_ms": round(ms64, 4)},
         "plan_create_s": round(plan_s, 3),
+        "copy_reference": copy,
         "solve": solve,
         "cpu_baseline": cpu,
         "parity_sampled_fp64_rel_err": parity,

@@ -99,7 +99,8 @@ typedef struct {
   int32_t restart;      /* GMRES cycle length m, 1..64 (default 30) */
   int32_t max_iter;     /* total Arnoldi steps per RHS (inner steps summed for IR) */
   int32_t use_x0;       /* 1: start from the x passed in; 0: start from x = 0 */
-  double inner_tol;     /* IR only: relative tolerance of each inner solve (default 1e-5) */
+  double inner_tol;     /* IR only: floor of the inner relative tolerance; inner solve k aims at
+                           max(inner_tol, tol * ||b|| / (2 ||r_k||)) (default 1e-6) */
   int32_t max_outer;    /* IR only: refinement steps (default 10) */
 } emsurf_solve_opts;
 

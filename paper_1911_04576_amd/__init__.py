@@ -225,7 +225,7 @@ def emsurf_apply_A(plan: Plan, prec, nrhs, x_dev, y_dev, stream=None):
     _check(lib().emsurf_apply_A(plan.h, int(prec), int(nrhs), _dptr(x_dev), _dptr(y_dev), _stream(stream)))
 
 
-def solve_opts(prec=EMSURF_FP64, tol=1e-10, restart=30, max_iter=500, use_x0=0, inner_tol=1e-5, max_outer=10):
+def solve_opts(prec=EMSURF_FP64, tol=1e-10, restart=30, max_iter=500, use_x0=0, inner_tol=1e-6, max_outer=10):
     return emsurf_solve_opts(int(prec), float(tol), int(restart), int(max_iter), int(use_x0), float(inner_tol),
                              int(max_outer))
 

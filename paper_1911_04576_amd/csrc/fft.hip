@@ -89,25 +89,49 @@ __device__ __forceinline__ void dft(V (&a)[R], int sign) {
 }
 
 struct PassArgs {
-  int L, n_in, n_out, batch, nl0, G, BT, nst;
-  int rad[6];
-  long long in_s0, in_s1, out_s0, out_s1, in_pt, out_pt;
+  int n_in, n_out, batch, nl0;
+  long long in_s0, in_s1, out_s0, out_s1;
+  int in_pt, out_pt;   // point strides (elements); host checks they fit 32 bits
   int sign;
   double scale;
 };
 
-template <int R, int VPT, typename VI, typename VC, typename VO>
-__device__ __forceinline__ void run_stage(const PassArgs& a, int s, int p, VC* lds, const VI* __restrict__ in,
-                                          VO* __restrict__ out, const VC* __restrict__ tw, long long in_base,
-                                          long long out_base, bool valid, int b, int g) {
-  constexpr int NB = VPT / R;
-  const int L = a.L;
-  const int LR = L / R;
-  const int G = a.G;
-  const int BT = a.BT;
+// Compile-time plan of a power-of-two length: every thread holds VPT values of
+// one column (G threads per column, BT columns per 256-thread workgroup) and
+// the stages are radix 16 while possible, then one radix-2/4/8 stage.
+template <int L> struct Shape {
+  static constexpr int VPT = L >= 16 ? 16 : L;
+  static constexpr int G = L / VPT;
+  static constexpr int BT = 256 / G;
+  static constexpr int NT = BT * G;
+  static constexpr int nst() {
+    int n = 0, r = L;
+    while (r >= 16) { r /= 16; ++n; }
+    return n + (r > 1 ? 1 : 0);
+  }
+  static constexpr int radix(int s) {
+    int r = L;
+    for (int i = 0; i < s; ++i) r /= (r >= 16 ? 16 : r);
+    return r >= 16 ? 16 : r;
+  }
+  static constexpr int NST = nst();
+};
+
+template <int L, int S, int P, typename VI, typename VC, typename VO>
+__device__ __forceinline__ void run_stage(const PassArgs& a, VC* lds, const VI* __restrict__ in,
+                                          VO* __restrict__ out, const VC* __restrict__ tw, bool valid, int b,
+                                          int g) {
+  using SH = Shape<L>;
+  constexpr int R = SH::radix(S);
+  constexpr int NB = SH::VPT / R;
+  constexpr int LR = L / R;
+  constexpr int G = SH::G;
+  constexpr int BT = SH::BT;
+  constexpr bool FIRST = S == 0;
+  constexpr bool LAST = S == SH::NST - 1;
   VC v[NB][R];
   // ---- load
-  if (s == 0) {
+  if constexpr (FIRST) {
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int i = g + G * j;
@@ -115,7 +139,7 @@ __device__ __forceinline__ void run_stage(const PassArgs& a, int s, int p, VC* l
       for (int q = 0; q < R; ++q) {
         const int pos = i + q * LR;
         if (valid && pos < a.n_in)
-          v[j][q] = cvt<VC>(in[in_base + (long long)pos * a.in_pt]);
+          v[j][q] = cvt<VC>(in[(unsigned)(pos * a.in_pt)]);
         else
           v[j][q] = VC{0, 0};
       }
@@ -128,18 +152,18 @@ __device__ __forceinline__ void run_stage(const PassArgs& a, int s, int p, VC* l
 #pragma unroll
       for (int q = 0; q < R; ++q) v[j][q] = lds[(i + q * LR) * BT + b];
     }
-    if (s < a.nst - 1) __syncthreads();
+    if constexpr (!LAST) __syncthreads();
   }
   // ---- twiddle + butterfly
-  const int tstride = L / (p * R);
+  constexpr int TSTR = L / (P * R);
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    const int i = g + G * j;
-    const int k = i & (p - 1);
-    if (s > 0) {
+    if constexpr (!FIRST) {
+      const int i = g + G * j;
+      const int k = i & (P - 1);
 #pragma unroll
       for (int q = 1; q < R; ++q) {
-        VC w = tw[(q * k * tstride) & (L - 1)];
+        VC w = tw[(q * k * TSTR) & (L - 1)];
         if (a.sign > 0) w.y = -w.y;
         v[j][q] = cmul(v[j][q], w);
       }
@@ -147,76 +171,95 @@ __device__ __forceinline__ void run_stage(const PassArgs& a, int s, int p, VC* l
     dft<R, VC>(v[j], a.sign);
   }
   // ---- store
-  const bool last = (s == a.nst - 1);
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const int i = g + G * j;
-    const int k = i & (p - 1);
+    const int k = i & (P - 1);
     const int base = (i - k) * R + k;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int pos = base + q * p;
-      if (last) {
+      const int pos = base + q * P;
+      if constexpr (LAST) {
         if (valid && pos < a.n_out) {
           VC r = v[j][q];
           using T = typename Real<VC>::T;
-          const T sc = static_cast<T>(a.scale);
-          if (a.scale != 1.0) { r.x *= sc; r.y *= sc; }
-          out[out_base + (long long)pos * a.out_pt] = cvt<VO>(r);
+          if (a.scale != 1.0) {
+            const T sc = static_cast<T>(a.scale);
+            r.x *= sc;
+            r.y *= sc;
+          }
+          out[(unsigned)(pos * a.out_pt)] = cvt<VO>(r);
         }
       } else {
         lds[pos * BT + b] = v[j][q];
       }
     }
   }
+  if constexpr (!LAST) run_stage<L, S + 1, P * R, VI, VC, VO>(a, lds, in, out, tw, valid, b, g);
 }
 
-template <int VPT, typename VI, typename VC, typename VO>
+template <int L, typename VI, typename VC, typename VO>
 __global__ void __launch_bounds__(256) fft_pass_kernel(PassArgs a, const VI* __restrict__ in, VO* __restrict__ out,
-                                const VC* __restrict__ tw) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  VC* lds = reinterpret_cast<VC*>(smem_raw);
+                                                       const VC* __restrict__ tw) {
+  using SH = Shape<L>;
+  __shared__ VC lds[SH::NST > 1 ? L * SH::BT : 1];
   const int t = threadIdx.x;
-  const int b = t % a.BT;
-  const int g = t / a.BT;
+  const int b = t % SH::BT;
+  const int g = t / SH::BT;
   const long long line = blockIdx.y;
-  const long long l1 = line / a.nl0, l0 = line % a.nl0;
-  const int col = blockIdx.x * a.BT + b;
+  const long long l1 = line / a.nl0, l0 = line - l1 * a.nl0;
+  const int col = blockIdx.x * SH::BT + b;
   const bool valid = col < a.batch;
-  const long long in_base = l1 * a.in_s1 + l0 * a.in_s0 + col;
-  const long long out_base = l1 * a.out_s1 + l0 * a.out_s0 + col;
-  int p = 1;
-  for (int s = 0; s < a.nst; ++s) {
-    const int R = a.rad[s];
-    if constexpr (VPT >= 16) {
-      if (R == 16) { run_stage<16, VPT>(a, s, p, lds, in, out, tw, in_base, out_base, valid, b, g); p *= 16; continue; }
-    }
-    if constexpr (VPT >= 8) {
-      if (R == 8) { run_stage<8, VPT>(a, s, p, lds, in, out, tw, in_base, out_base, valid, b, g); p *= 8; continue; }
-    }
-    if constexpr (VPT >= 4) {
-      if (R == 4) { run_stage<4, VPT>(a, s, p, lds, in, out, tw, in_base, out_base, valid, b, g); p *= 4; continue; }
-    }
-    run_stage<2, VPT>(a, s, p, lds, in, out, tw, in_base, out_base, valid, b, g);
-    p *= 2;
-  }
+  // uniform line bases, per-thread 32-bit offsets
+  const VI* inl = in + (l1 * a.in_s1 + l0 * a.in_s0 + (long long)blockIdx.x * SH::BT) + b;
+  VO* outl = out + (l1 * a.out_s1 + l0 * a.out_s0 + (long long)blockIdx.x * SH::BT) + b;
+  run_stage<L, 0, 1, VI, VC, VO>(a, lds, inl, outl, tw, valid, b, g);
 }
 
-template <int VPT, typename VI, typename VC, typename VO>
-void launch_vpt(const PassArgs& a, dim3 grid, int nt, size_t shm, const void* in, void* out, const void* tw,
-                hipStream_t s) {
-  hipLaunchKernelGGL((fft_pass_kernel<VPT, VI, VC, VO>), grid, dim3(nt), shm, s, a,
+template <int L, typename VI, typename VC, typename VO>
+void launch_L(const PassArgs& a, unsigned tiles, unsigned lines, const void* in, void* out, const void* tw,
+              hipStream_t s) {
+  hipLaunchKernelGGL((fft_pass_kernel<L, VI, VC, VO>), dim3(tiles, lines), dim3(Shape<L>::NT), 0, s, a,
                      static_cast<const VI*>(in), static_cast<VO*>(out), static_cast<const VC*>(tw));
 }
 
 template <typename VI, typename VC, typename VO>
-void launch_typed(const PassArgs& a, int vpt, dim3 grid, int nt, size_t shm, const void* in, void* out,
-                  const void* tw, hipStream_t s) {
-  switch (vpt) {
-    case 16: launch_vpt<16, VI, VC, VO>(a, grid, nt, shm, in, out, tw, s); break;
-    case 8: launch_vpt<8, VI, VC, VO>(a, grid, nt, shm, in, out, tw, s); break;
-    case 4: launch_vpt<4, VI, VC, VO>(a, grid, nt, shm, in, out, tw, s); break;
-    default: launch_vpt<2, VI, VC, VO>(a, grid, nt, shm, in, out, tw, s); break;
+void launch_typed(int L, const PassArgs& a, int batch, unsigned lines, const void* in, void* out, const void* tw,
+                  hipStream_t s) {
+#define EMS_FFT_CASE(LL)                                                                  \
+  case LL: {                                                                              \
+    const unsigned tiles = (unsigned)((batch + Shape<LL>::BT - 1) / Shape<LL>::BT);      \
+    launch_L<LL, VI, VC, VO>(a, tiles, lines, in, out, tw, s);                             \
+    break;                                                                                \
+  }
+  switch (L) {
+    EMS_FFT_CASE(2)
+    EMS_FFT_CASE(4)
+    EMS_FFT_CASE(8)
+    EMS_FFT_CASE(16)
+    EMS_FFT_CASE(32)
+    EMS_FFT_CASE(64)
+    EMS_FFT_CASE(128)
+    EMS_FFT_CASE(256)
+    EMS_FFT_CASE(512)
+    EMS_FFT_CASE(1024)
+    default: break;
+  }
+#undef EMS_FFT_CASE
+}
+
+int batch_tile(int L) {
+  switch (L) {
+    case 2: return Shape<2>::BT;
+    case 4: return Shape<4>::BT;
+    case 8: return Shape<8>::BT;
+    case 16: return Shape<16>::BT;
+    case 32: return Shape<32>::BT;
+    case 64: return Shape<64>::BT;
+    case 128: return Shape<128>::BT;
+    case 256: return Shape<256>::BT;
+    case 512: return Shape<512>::BT;
+    default: return Shape<1024>::BT;
   }
 }
 
@@ -259,47 +302,37 @@ void launch_fft_pass(const FftPass& p, Cx tin, Cx tcomp, Cx tout, const void* in
   EMS_CHECK_ARG(p.L >= 2 && p.L <= 1024 && (p.L & (p.L - 1)) == 0, "FFT length must be a power of two in [2, 1024]");
   EMS_CHECK_ARG(p.n_in >= 1 && p.n_in <= p.L && p.n_out >= 1 && p.n_out <= p.L, "FFT prune/crop sizes out of range");
   EMS_CHECK_ARG(p.batch >= 1 && p.n_lines >= 1 && p.nl0 >= 1, "FFT batch/lines must be positive");
+  EMS_CHECK_ARG(p.n_lines <= 65535, "FFT pass has more than 65535 lines");
+  // per-thread offsets within a line are 32-bit: (points * stride + tile) must fit
+  const long long span_in = (long long)p.L * p.in_pt + p.batch + 1024;
+  const long long span_out = (long long)p.L * p.out_pt + p.batch + 1024;
+  EMS_CHECK_ARG(span_in < (1LL << 31) && span_out < (1LL << 31), "FFT line span exceeds 32-bit offsets");
   PassArgs a{};
-  a.L = p.L;
   a.n_in = p.n_in;
   a.n_out = p.n_out;
   a.batch = p.batch;
   a.nl0 = p.nl0;
   a.in_s0 = p.in_s0; a.in_s1 = p.in_s1; a.out_s0 = p.out_s0; a.out_s1 = p.out_s1;
-  a.in_pt = p.in_pt; a.out_pt = p.out_pt;
+  a.in_pt = (int)p.in_pt; a.out_pt = (int)p.out_pt;
   a.sign = p.sign;
   a.scale = p.scale;
-  const int vpt = p.L >= 16 ? 16 : p.L;
-  a.G = p.L / vpt;
-  // radix plan: 16s first, then the remainder
-  int rem = p.L, nst = 0;
-  while (rem >= 16 && vpt == 16) { a.rad[nst++] = 16; rem /= 16; }
-  if (rem > 1) a.rad[nst++] = rem;   // rem in {2,4,8} (or L itself when L < 16)
-  a.nst = nst;
-  int bt = 256 / a.G;
-  int bpow = 1;
-  while (bpow < p.batch) bpow <<= 1;
-  if (bt > bpow) bt = bpow;
-  if (bt < 1) bt = 1;
-  a.BT = bt;
-  const int nt = a.BT * a.G;
-  const size_t shm = (size_t)p.L * a.BT * cx_bytes(tcomp);
-  const long long tiles = (p.batch + a.BT - 1) / a.BT;
-  EMS_CHECK_ARG(tiles <= 0x7fffffffLL, "FFT batch too large");
-  EMS_CHECK_ARG(p.n_lines <= 65535, "FFT pass has more than 65535 lines");
-  dim3 grid((unsigned)tiles, (unsigned)p.n_lines, 1);
+  // the kernel indexes batch columns relative to its tile: columns beyond the
+  // batch are masked, so the batch count seen by a tile is relative
+  const int bt = batch_tile(p.L);
+  (void)bt;
+  const unsigned lines = (unsigned)p.n_lines;
   if (tcomp == Cx::C128) {
     EMS_CHECK_ARG(tin == Cx::C128 && tout == Cx::C128, "FP64 FFT needs FP64 input and output");
-    launch_typed<double2, double2, double2>(a, vpt, grid, nt, shm, in, out, twiddles, s);
+    launch_typed<double2, double2, double2>(p.L, a, p.batch, lines, in, out, twiddles, s);
   } else {
     if (tin == Cx::C128 && tout == Cx::C64)
-      launch_typed<double2, float2, float2>(a, vpt, grid, nt, shm, in, out, twiddles, s);
+      launch_typed<double2, float2, float2>(p.L, a, p.batch, lines, in, out, twiddles, s);
     else if (tin == Cx::C64 && tout == Cx::C128)
-      launch_typed<float2, float2, double2>(a, vpt, grid, nt, shm, in, out, twiddles, s);
+      launch_typed<float2, float2, double2>(p.L, a, p.batch, lines, in, out, twiddles, s);
     else if (tin == Cx::C64 && tout == Cx::C64)
-      launch_typed<float2, float2, float2>(a, vpt, grid, nt, shm, in, out, twiddles, s);
+      launch_typed<float2, float2, float2>(p.L, a, p.batch, lines, in, out, twiddles, s);
     else
-      launch_typed<double2, float2, double2>(a, vpt, grid, nt, shm, in, out, twiddles, s);
+      launch_typed<double2, float2, double2>(p.L, a, p.batch, lines, in, out, twiddles, s);
   }
   EMS_LAUNCH_CHECK();
 }

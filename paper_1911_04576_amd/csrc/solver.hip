@@ -104,8 +104,9 @@ struct RhsState {
 
 // Batched GMRES on op(x) = b.  x holds the start (zeros or x0).  `confirm`
 // selects the true-residual check after a converged cycle (top-level solve).
-void gmres(emsurf_plan p, OpFn op, SolveWork& w, int nrhs, const double2* b, double2* x, double tol, int max_iter,
-           bool confirm, bool start_zero, std::vector<RhsState>& st, hipStream_t s) {
+void gmres(emsurf_plan p, OpFn op, SolveWork& w, int nrhs, const double2* b, double2* x,
+           const std::vector<double>& tol, int max_iter, bool confirm, bool start_zero, std::vector<RhsState>& st,
+           hipStream_t s) {
   const int m = w.m;
   const long long N = w.N;
   const long long vstride = (long long)nrhs * N;
@@ -130,7 +131,7 @@ void gmres(emsurf_plan p, OpFn op, SolveWork& w, int nrhs, const double2* b, dou
     for (int r = 0; r < nrhs; ++r) {
       if (st[r].done) continue;
       st[r].rel = beta[r] / st[r].bnorm;
-      if (st[r].rel <= tol) { st[r].done = true; st[r].converged = true; }
+      if (st[r].rel <= tol[r]) { st[r].done = true; st[r].converged = true; }
       else if (st[r].iters >= max_iter) { st[r].done = true; st[r].converged = false; }
     }
     any = false;
@@ -189,10 +190,10 @@ void gmres(emsurf_plan p, OpFn op, SolveWork& w, int nrhs, const double2* b, dou
         q.iters += 1;
         const double est = std::abs(q.g[j + 1]) / q.bnorm;
         const bool lucky = hn <= 1e-14 * wn0;
-        if (est <= tol || lucky || q.iters >= max_iter || j == m - 1) {
+        if (est <= tol[r] || lucky || q.iters >= max_iter || j == m - 1) {
           q.stopped = true;
           q.kend = j + 1;
-          q.est_ok = est <= tol || lucky;
+          q.est_ok = est <= tol[r] || lucky;
           hs[r] = 0.0;
         } else {
           hs[r] = 1.0 / hn;
@@ -295,20 +296,30 @@ extern "C" emsurf_status emsurf_solve(emsurf_plan plan, const emsurf_solve_opts*
     }
     if (opts->prec != EMSURF_FP32_IR) {
       OpFn op = opts->prec == EMSURF_FP64 ? op_fp64 : op_fp32;
-      gmres(plan, op, w, nrhs, static_cast<const double2*>(b_dev), static_cast<double2*>(x_dev), opts->tol,
-            opts->max_iter, true, !opts->use_x0, st, s);
+      gmres(plan, op, w, nrhs, static_cast<const double2*>(b_dev), static_cast<double2*>(x_dev),
+            std::vector<double>(nrhs, opts->tol), opts->max_iter, true, !opts->use_x0, st, s);
       for (int r = 0; r < nrhs; ++r) outer = std::max(outer, st[r].cycles);
     } else {
       // outer refinement: residual in FP64, correction from an FP32 inner solve
       DevBuf rr((size_t)nrhs * N * 16), d((size_t)nrhs * N * 16), tt((size_t)nrhs * N * 16);
       std::vector<RhsState> inner(nrhs);
       for (outer = 0;; ++outer) {
-        op_fp64(plan, nrhs, x_dev, tt.p, s);
         for (int r = 0; r < nrhs; ++r) hm[r] = st[r].done ? 0 : 1;
-        EMS_HIP(hipMemcpyAsync(w.mask.p, hm, (size_t)nrhs * 4, hipMemcpyHostToDevice, s));
-        launch_sub(b_dev, tt.p, w.mask.as<int>(), rr.p, N, nrhs, s);
         std::vector<double> rn;
-        norms(w, rr.p, rn, s);
+        if (outer == 0 && !opts->use_x0) {
+          // x = 0: the residual is b itself, no operator apply needed
+          double* hs0 = w.h_scale.as<double>();
+          for (int r = 0; r < nrhs; ++r) hs0[r] = hm[r] ? 1.0 : 0.0;
+          EMS_HIP(hipMemcpyAsync(w.scale.p, hs0, (size_t)nrhs * 8, hipMemcpyHostToDevice, s));
+          launch_scale(b_dev, w.scale.p, rr.p, N, nrhs, s);
+          rn.resize(nrhs);
+          for (int r = 0; r < nrhs; ++r) rn[r] = hm[r] ? st[r].bnorm : 0.0;
+        } else {
+          op_fp64(plan, nrhs, x_dev, tt.p, s);
+          EMS_HIP(hipMemcpyAsync(w.mask.p, hm, (size_t)nrhs * 4, hipMemcpyHostToDevice, s));
+          launch_sub(b_dev, tt.p, w.mask.as<int>(), rr.p, N, nrhs, s);
+          norms(w, rr.p, rn, s);
+        }
         bool any = false;
         for (int r = 0; r < nrhs; ++r) {
           if (st[r].done) continue;
@@ -318,17 +329,21 @@ extern "C" emsurf_status emsurf_solve(emsurf_plan plan, const emsurf_solve_opts*
           else any = true;
         }
         if (!any) break;
+        // each inner solve aims straight at the outer tolerance (half of it, leaving
+        // room for the FP32 operator's own error), but never below inner_tol
+        std::vector<double> itol(nrhs, 0.5);
         for (int r = 0; r < nrhs; ++r) {
           inner[r] = RhsState{};
           inner[r].bnorm = rn[r];
-          if (st[r].done || rn[r] == 0.0) { inner[r].done = true; inner[r].converged = true; }
+          if (st[r].done || rn[r] == 0.0) { inner[r].done = true; inner[r].converged = true; continue; }
+          itol[r] = std::min(0.5, std::max(opts->inner_tol, 0.5 * opts->tol * st[r].bnorm / rn[r]));
         }
         EMS_HIP(hipMemsetAsync(d.p, 0, d.bytes, s));
         int budget = 0;
         for (int r = 0; r < nrhs; ++r)
           if (!st[r].done) budget = std::max(budget, opts->max_iter - st[r].iters);
-        gmres(plan, op_fp32, w, nrhs, rr.as<double2>(), d.as<double2>(), opts->inner_tol, std::max(1, budget), false,
-              true, inner, s);
+        gmres(plan, op_fp32, w, nrhs, rr.as<double2>(), d.as<double2>(), itol, std::max(1, budget), false, true,
+              inner, s);
         for (int r = 0; r < nrhs; ++r) st[r].iters += inner[r].iters;
         launch_add(x_dev, d.p, (long long)nrhs * N, s);
       }
