@@ -75,6 +75,70 @@ def measured_traffic():
         return None
 
 
+MFMA_FP32_PEAK_TFS = 157.3
+
+
+def multi_rhs_section(E, W, torch, np, with_oracle):
+    """64 x 64 lattice, n_eq 288, 16 RHS: Fourier-domain products as MFMA GEMMs.
+    Autotunes the FP32 block-product variants, times the chosen one inside a
+    full T-apply, and reports the FP32 error against the FP64 path (itself
+    checked against the oracle at a sampled element)."""
+    cfg = W.config(3)
+    g = W.box_geometry(cfg.n_patch)
+    S, tm = W.s_types(cfg), W.type_map(cfg)
+    b = W.plane_wave_rhs(cfg, g)
+    nrhs, n = cfg.nrhs, cfg.n_eq
+    geom = E.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)
+    plan = E.emsurf_plan_create_green(cfg.nx, cfg.ny, cfg.n_types, nrhs, geom, S, tm)
+    st = plan.stats()
+    P = st.n_freq
+    best, ms = E.emsurf_plan_autotune(plan, nrhs)
+    flops = 8 * P * n * n * nrhs
+    bytes_bp = P * n * n * 8 + 2 * P * nrhs * n * 8
+    variants = {k: (None if v is None else {"ms": round(v, 4), "TFs": round(flops / (v / 1e3) / 1e12, 2),
+                                             "GBs": round(bytes_bp / (v / 1e3) / 1e9, 1)})
+                for k, v in ms.items()}
+    bms = ms[E.BP_NAMES[best]]
+    log(f"64x64 n=288 16 RHS block product: {variants} -> {E.BP_NAMES[best]}")
+    b64 = torch.from_numpy(b).to("cuda")
+    x32 = b64.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    for _ in range(2):
+        E.emsurf_apply_T(plan, E.EMSURF_FP32, nrhs, x32, y32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 10
+    for _ in range(reps):
+        E.emsurf_apply_T(plan, E.EMSURF_FP32, nrhs, x32, y32)
+    torch.cuda.synchronize()
+    apply_ms = 1e3 * (time.perf_counter() - t0) / reps
+    y64 = torch.empty_like(b64)
+    E.emsurf_apply_T(plan, E.EMSURF_FP64, nrhs, b64, y64)
+    torch.cuda.synchronize()
+    ref = y64.cpu().numpy()
+    out = y32.cpu().numpy().astype(np.complex128)
+    err32 = float(np.max(np.linalg.norm((out - ref).reshape(nrhs, -1), axis=1) /
+                         np.linalg.norm(ref.reshape(nrhs, -1), axis=1)))
+    sec = {"workload": "64x64 lattice, n_eq 288 (72 patches/box), 16 RHS (8 seeded theta x TE/TM), 32 types, "
+                       "128x128 padded FFT, FP32 blocks",
+           "block_product_variants": variants, "chosen": E.BP_NAMES[best],
+           "block_product_ms": round(bms, 4), "block_product_TFs": round(flops / (bms / 1e3) / 1e12, 2),
+           "frac_fp32_mfma_peak": round(flops / (bms / 1e3) / 1e12 / MFMA_FP32_PEAK_TFS, 4),
+           "block_product_GBs": round(bytes_bp / (bms / 1e3) / 1e9, 1),
+           "apply_T_ms": round(apply_ms, 4),
+           "unknowns_rhs_per_s": cfg.n_unknowns * nrhs / (apply_ms / 1e3),
+           "fp32_rel_err_vs_fp64": err32}
+    if with_oracle:
+        from oracle import coupling as C
+        e = (cfg.ny // 3, cfg.nx // 2)
+        ys = C.apply_T_elements(g.rho, g.area, g.tan, W.PITCH, W.K0, b, [e], chunk_rows=4)[0]
+        sec["fp64_sampled_rel_err_vs_oracle"] = float(np.linalg.norm(ref[:, e[0], e[1]] - ys) / np.linalg.norm(ys))
+        sec["fp32_sampled_rel_err_vs_oracle"] = float(np.linalg.norm(out[:, e[0], e[1]] - ys) / np.linalg.norm(ys))
+    log(f"64x64 multi-RHS: {sec}")
+    plan.destroy()
+    return sec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +148,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES solve timing")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-cal", action="store_true", help="also time a plain 2 GiB device copy")
+    ap.add_argument("--no-multi", action="store_true", help="skip the 64x64, 16-RHS MFMA section")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the coupled solve is measured on one MI355X "
@@ -204,6 +269,10 @@ def main():
         log(f"copy 2 GiB -> 2 GiB: {cms:.3f} ms, {copy['GBs']} GB/s")
         del a, c
 
+    multi = None
+    if not args.no_multi:
+        multi = multi_rhs_section(E, W, torch, np, not args.no_cpu)
+
     cpu = None
     parity = None
     if not args.no_cpu:
@@ -238,6 +307,7 @@ def main():
                     "phase_avg_ms": phase_avg, "fp64_ms": round(ms64, 4)},
         "plan_create_s": round(plan_s, 3),
         "copy_reference": copy,
+        "multi_rhs_64x64": multi,
         "solve": solve,
         "cpu_baseline": cpu,
         "parity_sampled_fp64_rel_err": parity,

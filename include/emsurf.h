@@ -187,6 +187,139 @@ emsurf_status emsurf_plan_query(emsurf_plan plan, emsurf_plan_stats* out);
 emsurf_status emsurf_kernel_timing(emsurf_plan plan, int32_t enable);
 emsurf_status emsurf_kernel_times(emsurf_plan plan, double* ms, int64_t* count);
 
+/* ---- Fourier-domain block-product variants and autotuning (FP32 applies) ----
+ * EMSURF_BP_GEMV streams each frequency's block with one lane per row (best for
+ * few right-hand sides); EMSURF_BP_MFMA_T1..T4 run the per-frequency complex
+ * product as a real MFMA GEMM with 1..4 row tiles of 32 per wavefront and 16
+ * right-hand sides per pass (n_eq a multiple of 32, at most 480, and at most
+ * 4 wavefronts: ceil(n_eq / 32 / k) <= 4; best for many right-hand sides),
+ * keeping 4 pairs of block columns in flight per wavefront; the _DEEP forms
+ * keep 8 (more registers, longer latency cover).  FP64 applies always use the
+ * GEMV form. */
+#define EMSURF_BP_AUTO (-1)
+#define EMSURF_BP_GEMV 0
+#define EMSURF_BP_MFMA_T1 1
+#define EMSURF_BP_MFMA_T2 2
+#define EMSURF_BP_MFMA_T3 3
+#define EMSURF_BP_MFMA_T4 4
+#define EMSURF_BP_MFMA_T1_DEEP 5
+#define EMSURF_BP_MFMA_T2_DEEP 6
+#define EMSURF_BP_MFMA_T3_DEEP 7
+#define EMSURF_BP_MFMA_T4_DEEP 8
+#define EMSURF_BP_NVARIANTS 9
+
+/* Time every FP32 block-product variant for `nrhs` right-hand sides on this
+ * plan's blocks (HIP events, 3 launches each after a warm-up; the workspace
+ * spectra of `stream` are used as scratch), keep the fastest as the plan's
+ * choice for that nrhs and, if the environment variable EMSURF_TUNE_CACHE names
+ * a file, record it there ("n_eq nrhs variant" lines) for later processes.
+ * ms_out (may be NULL): EMSURF_BP_NVARIANTS entries, -1 for unsupported
+ * variants.  best_out (may be NULL) receives the chosen variant.  Blocks. */
+emsurf_status emsurf_plan_autotune(emsurf_plan plan, int32_t nrhs, double* ms_out, int32_t* best_out,
+                                   void* stream);
+
+/* Force the FP32 block-product variant used for `nrhs` right-hand sides
+ * (EMSURF_BP_AUTO restores: tuned cache entry, else for nrhs >= 8 the deep
+ * MFMA variant with the fewest row tiles that fits, else GEMV).
+ * EMSURF_ERR_UNSUPPORTED for an MFMA variant this n_eq cannot run. */
+emsurf_status emsurf_plan_set_variant(emsurf_plan plan, int32_t nrhs, int32_t variant);
+
+/* ---- HIP-graph capture of an apply ----
+ * Records the kernels of one apply (op EMSURF_OP_T: y = T x, EMSURF_OP_S:
+ * y = S x, EMSURF_OP_A: y = x - S T x) with fixed buffers into a HIP graph on
+ * `stream` (must not be the null stream) and instantiates it.  Launching the
+ * graph on any stream then recomputes y from the current content of x.  The
+ * graph uses the workspace belonging to `stream`: do not overlap a graph
+ * launch with other applies issued on that stream. */
+typedef struct emsurf_graph_s* emsurf_graph;
+#define EMSURF_OP_T 0
+#define EMSURF_OP_S 1
+#define EMSURF_OP_A 2
+emsurf_status emsurf_graph_create(emsurf_plan plan, int32_t op, emsurf_prec prec, int32_t nrhs, const void* x_dev,
+                                  void* y_dev, void* stream, emsurf_graph* out);
+emsurf_status emsurf_graph_launch(emsurf_graph graph, void* stream);
+void emsurf_graph_destroy(emsurf_graph graph);
+
+/* ---- Continuous-batching sessions (serving) ----
+ * A session holds max_slots right-hand-side slots on one plan and its own
+ * stream.  emsurf_session_submit places one right-hand side (c128
+ * [ny][nx][n_eq], device, copied) into a free slot; emsurf_session_step runs
+ * one batched GMRES iteration for every busy slot: slots join and leave at
+ * iteration granularity and run at their own Arnoldi index (same algorithm and
+ * stopping rule as emsurf_solve; opts.prec EMSURF_FP32_IR runs each cycle's
+ * Arnoldi steps with the FP32 operator and every cycle's starting residual
+ * with the FP64 operator, aiming each cycle at max(inner_tol * ||r||,
+ * tol * ||b|| / 2)).  A slot's numbers never depend on the other slots, so a
+ * result is bitwise the same alone and in a mix.  Finished slots keep their
+ * solution until emsurf_session_collect copies it out and frees the slot.
+ * Calls on one session must not overlap; different sessions may run
+ * concurrently (each on its own stream). */
+typedef struct emsurf_session_s* emsurf_session;
+/* device bytes a session with these parameters allocates (slot vectors,
+ * Krylov bases, reduction buffers, its stream's apply workspace) */
+size_t emsurf_session_bytes(emsurf_plan plan, int32_t max_slots, const emsurf_solve_opts* opts);
+/* stream NULL: the session creates (and later destroys) its own non-blocking stream. */
+emsurf_status emsurf_session_create(emsurf_plan plan, int32_t max_slots, const emsurf_solve_opts* opts, void* stream,
+                                    emsurf_session* out);
+/* EMSURF_ERR_BUSY if no slot is free.  *slot receives the slot index. */
+emsurf_status emsurf_session_submit(emsurf_session session, const void* b_dev, int64_t tag, int32_t* slot);
+/* one batched iteration; blocks until its reductions are on the host */
+emsurf_status emsurf_session_step(emsurf_session session, int32_t* n_finished);
+/* finished, not yet collected slots (up to cap) and their tags; *count = total */
+emsurf_status emsurf_session_finished(emsurf_session session, int32_t* slots, int64_t* tags, int32_t cap,
+                                      int32_t* count);
+emsurf_status emsurf_session_active(emsurf_session session, int32_t* busy_slots);
+/* copy the slot's x (c128, may be NULL) and info out, free the slot; EMSURF_ERR_ARG
+ * if its right-hand side was not finite.  info->ms = submit-to-finish host time. */
+emsurf_status emsurf_session_collect(emsurf_session session, int32_t slot, void* x_dev, emsurf_solve_info* info);
+void emsurf_session_destroy(emsurf_session session);
+
+/* ---- Serving loop over many surfaces ----
+ * A server accepts solve requests for any number of surfaces.  A surface is
+ * identified by a caller key; requests with the same key must describe the
+ * same surface (lattice, geometry, macromodels, type map).  Each resident
+ * surface has a plan (synthetic point-sampled coupling, FP64 and/or FP32
+ * stores per desc.store) and a session with max_slots slots on its own stream.
+ * emsurf_server_step admits queued requests whose plan fits budget_bytes
+ * (evicting idle plans least-recently-used first) and whose session has
+ * nrhs free slots, then runs one batched iteration on every busy session
+ * (launching all sessions before waiting for any, so they overlap on the
+ * device), and moves finished requests to the completion queue.  All host
+ * inputs are copied at submit. */
+typedef struct emsurf_server_s* emsurf_server;
+typedef struct {
+  size_t budget_bytes;        /* device bytes plans + sessions may hold */
+  int32_t max_slots;          /* slots per session = largest nrhs of a request, 1..64 */
+  uint32_t store;             /* EMSURF_STORE_* of every plan */
+  emsurf_solve_opts opts;     /* solve options of every request */
+} emsurf_server_desc;
+typedef struct {
+  int32_t queued, active, resident_plans;
+  size_t bytes_used;
+  int64_t plans_built, evictions;
+} emsurf_server_stats;
+emsurf_status emsurf_server_create(const emsurf_server_desc* desc, emsurf_server* out);
+/* desc: nx, ny, n_eq (= 4 geom->n_patch), n_types (max_rhs, store ignored);
+ * S_types, elem_type as for emsurf_plan_create (host); b_host c128
+ * [nrhs][ny][nx][n_eq] (host).  *req_id receives the request id. */
+emsurf_status emsurf_server_submit(emsurf_server server, uint64_t key, const emsurf_plan_desc* desc,
+                                   const emsurf_geom* geom, const void* S_types, const int32_t* elem_type,
+                                   int32_t nrhs, const void* b_host, int64_t* req_id);
+emsurf_status emsurf_server_step(emsurf_server server, int32_t* n_completed);
+/* pop the oldest completed request (*req_id = -1 if none); nrhs and unknowns per RHS */
+emsurf_status emsurf_server_next_completed(emsurf_server server, int64_t* req_id, int32_t* nrhs,
+                                           int64_t* n_unknowns);
+/* copy a completed request's solution (c128 [nrhs][N], host, may be NULL), per-RHS
+ * info and times_ms[2] = {submit->admit, submit->done} (may be NULL), then forget it.
+ * EMSURF_ERR_ARG if the request could not be solved. */
+emsurf_status emsurf_server_fetch(emsurf_server server, int64_t req_id, void* x_host, emsurf_solve_info* info,
+                                  double* times_ms);
+emsurf_status emsurf_server_query(emsurf_server server, emsurf_server_stats* out);
+/* device bytes a resident surface with this desc (nx, ny, n_eq, n_types) takes on this
+ * server (plan + session + staging), as used for admission; 0 if invalid */
+size_t emsurf_server_entry_bytes(emsurf_server server, const emsurf_plan_desc* desc);
+void emsurf_server_destroy(emsurf_server server);
+
 void emsurf_plan_destroy(emsurf_plan plan);
 const char* emsurf_status_str(emsurf_status s);
 const char* emsurf_last_error(void);

@@ -32,6 +32,24 @@ EMSURF_FP32_IR = 2
 EMSURF_STORE_FP64 = 1
 EMSURF_STORE_FP32 = 2
 
+EMSURF_BP_AUTO = -1
+EMSURF_BP_GEMV = 0
+EMSURF_BP_MFMA_T1 = 1
+EMSURF_BP_MFMA_T2 = 2
+EMSURF_BP_MFMA_T3 = 3
+EMSURF_BP_MFMA_T4 = 4
+EMSURF_BP_MFMA_T1_DEEP = 5
+EMSURF_BP_MFMA_T2_DEEP = 6
+EMSURF_BP_MFMA_T3_DEEP = 7
+EMSURF_BP_MFMA_T4_DEEP = 8
+EMSURF_BP_NVARIANTS = 9
+BP_NAMES = ("gemv", "mfma_t1", "mfma_t2", "mfma_t3", "mfma_t4", "mfma_t1_deep", "mfma_t2_deep", "mfma_t3_deep",
+            "mfma_t4_deep")
+
+EMSURF_OP_T = 0
+EMSURF_OP_S = 1
+EMSURF_OP_A = 2
+
 PHASES = ("fft_x_fwd", "fft_y_fwd", "block_product", "fft_y_inv", "fft_x_inv")
 
 
@@ -62,6 +80,16 @@ class emsurf_solve_info(ctypes.Structure):
                 ("rel_res_true", ctypes.c_double), ("ms", ctypes.c_double)]
 
 
+class emsurf_server_desc(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("store", ctypes.c_uint32),
+                ("opts", emsurf_solve_opts)]
+
+
+class emsurf_server_stats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int32), ("active", ctypes.c_int32), ("resident_plans", ctypes.c_int32),
+                ("bytes_used", ctypes.c_size_t), ("plans_built", ctypes.c_int64), ("evictions", ctypes.c_int64)]
+
+
 class emsurf_plan_stats(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("n_freq", ctypes.c_int64),
                 ("bytes_that64", ctypes.c_size_t), ("bytes_that32", ctypes.c_size_t),
@@ -85,6 +113,35 @@ _SIGS = {
     "emsurf_kernel_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "emsurf_kernel_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "emsurf_plan_destroy": (None, [_P]),
+    "emsurf_plan_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_int32), _P]),
+    "emsurf_plan_set_variant": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "emsurf_graph_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int, ctypes.c_int32, _P, _P, _P,
+                                           ctypes.POINTER(_P)]),
+    "emsurf_graph_launch": (ctypes.c_int, [_P, _P]),
+    "emsurf_graph_destroy": (None, [_P]),
+    "emsurf_session_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.POINTER(emsurf_solve_opts)]),
+    "emsurf_session_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(emsurf_solve_opts), _P,
+                                             ctypes.POINTER(_P)]),
+    "emsurf_session_submit": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]),
+    "emsurf_session_step": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "emsurf_session_finished": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "emsurf_session_active": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "emsurf_session_collect": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.POINTER(emsurf_solve_info)]),
+    "emsurf_session_destroy": (None, [_P]),
+    "emsurf_server_create": (ctypes.c_int, [ctypes.POINTER(emsurf_server_desc), ctypes.POINTER(_P)]),
+    "emsurf_server_submit": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(emsurf_plan_desc),
+                                            ctypes.POINTER(emsurf_geom), _P, _P, ctypes.c_int32, _P,
+                                            ctypes.POINTER(ctypes.c_int64)]),
+    "emsurf_server_step": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "emsurf_server_next_completed": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64),
+                                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
+    "emsurf_server_fetch": (ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.POINTER(emsurf_solve_info),
+                                           ctypes.POINTER(ctypes.c_double)]),
+    "emsurf_server_query": (ctypes.c_int, [_P, ctypes.POINTER(emsurf_server_stats)]),
+    "emsurf_server_destroy": (None, [_P]),
+    "emsurf_server_entry_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(emsurf_plan_desc)]),
     "emsurf_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "emsurf_last_error": (ctypes.c_char_p, []),
 }
@@ -270,3 +327,190 @@ def emsurf_last_error() -> str:
 
 def emsurf_plan_destroy(plan: Plan):
     plan.destroy()
+
+
+def emsurf_plan_autotune(plan: Plan, nrhs, stream=None):
+    """Returns (best variant, {variant name: ms or None})."""
+    ms = (ctypes.c_double * EMSURF_BP_NVARIANTS)()
+    best = ctypes.c_int32()
+    _check(lib().emsurf_plan_autotune(plan.h, int(nrhs), ms, ctypes.byref(best), _stream(stream)))
+    return best.value, {BP_NAMES[i]: (ms[i] if ms[i] >= 0 else None) for i in range(EMSURF_BP_NVARIANTS)}
+
+
+def emsurf_plan_set_variant(plan: Plan, nrhs, variant):
+    _check(lib().emsurf_plan_set_variant(plan.h, int(nrhs), int(variant)))
+
+
+class Graph:
+    def __init__(self, handle):
+        self.h = handle
+
+    def launch(self, stream=None):
+        emsurf_graph_launch(self, stream)
+
+    def destroy(self):
+        if self.h:
+            lib().emsurf_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def emsurf_graph_create(plan: Plan, op, prec, nrhs, x_dev, y_dev, stream) -> Graph:
+    out = ctypes.c_void_p()
+    _check(lib().emsurf_graph_create(plan.h, int(op), int(prec), int(nrhs), _dptr(x_dev), _dptr(y_dev),
+                                     _stream(stream), ctypes.byref(out)))
+    return Graph(out.value)
+
+
+def emsurf_graph_launch(graph: Graph, stream=None):
+    _check(lib().emsurf_graph_launch(graph.h, _stream(stream)))
+
+
+def emsurf_graph_destroy(graph: Graph):
+    graph.destroy()
+
+
+def _info_dict(i):
+    return dict(iters=i.iters, outer_iters=i.outer_iters, converged=bool(i.converged),
+                rel_res_true=i.rel_res_true, ms=i.ms)
+
+
+class Session:
+    def __init__(self, handle):
+        self.h = handle
+
+    def destroy(self):
+        if self.h:
+            lib().emsurf_session_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def emsurf_session_bytes(plan: Plan, max_slots, opts) -> int:
+    return int(lib().emsurf_session_bytes(plan.h, int(max_slots), ctypes.byref(opts)))
+
+
+def emsurf_session_create(plan: Plan, max_slots, opts, stream=None) -> Session:
+    out = ctypes.c_void_p()
+    _check(lib().emsurf_session_create(plan.h, int(max_slots), ctypes.byref(opts), _stream(stream), ctypes.byref(out)))
+    return Session(out.value)
+
+
+def emsurf_session_submit(sess: Session, b_dev, tag=0) -> int:
+    slot = ctypes.c_int32()
+    _check(lib().emsurf_session_submit(sess.h, _dptr(b_dev), int(tag), ctypes.byref(slot)))
+    return slot.value
+
+
+def emsurf_session_step(sess: Session) -> int:
+    n = ctypes.c_int32()
+    _check(lib().emsurf_session_step(sess.h, ctypes.byref(n)))
+    return n.value
+
+
+def emsurf_session_finished(sess: Session, cap=64):
+    slots = (ctypes.c_int32 * cap)()
+    tags = (ctypes.c_int64 * cap)()
+    cnt = ctypes.c_int32()
+    _check(lib().emsurf_session_finished(sess.h, slots, tags, int(cap), ctypes.byref(cnt)))
+    return [(slots[i], tags[i]) for i in range(min(cnt.value, cap))]
+
+
+def emsurf_session_active(sess: Session) -> int:
+    n = ctypes.c_int32()
+    _check(lib().emsurf_session_active(sess.h, ctypes.byref(n)))
+    return n.value
+
+
+def emsurf_session_collect(sess: Session, slot, x_dev=None):
+    info = emsurf_solve_info()
+    _check(lib().emsurf_session_collect(sess.h, int(slot), _dptr(x_dev), ctypes.byref(info)))
+    return _info_dict(info)
+
+
+def emsurf_session_destroy(sess: Session):
+    sess.destroy()
+
+
+class Server:
+    def __init__(self, handle):
+        self.h = handle
+
+    def destroy(self):
+        if self.h:
+            lib().emsurf_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def emsurf_server_create(budget_bytes, max_slots, opts, store=EMSURF_STORE_FP64 | EMSURF_STORE_FP32) -> Server:
+    d = emsurf_server_desc(int(budget_bytes), int(max_slots), int(store), opts)
+    out = ctypes.c_void_p()
+    _check(lib().emsurf_server_create(ctypes.byref(d), ctypes.byref(out)))
+    return Server(out.value)
+
+
+def emsurf_server_submit(srv: Server, key, nx, ny, n_types, geom: Geometry, S_types, elem_type, b) -> int:
+    """b: numpy complex128 [nrhs][ny][nx][n_eq] (host)."""
+    d = _desc(nx, ny, 4 * geom.n_patch, n_types, 1, EMSURF_STORE_FP64)
+    S, pS = _host(S_types, np.complex128)
+    et, pet = _host(elem_type, np.int32)
+    bb, pb = _host(b, np.complex128)
+    rid = ctypes.c_int64()
+    _check(lib().emsurf_server_submit(srv.h, int(key), ctypes.byref(d), ctypes.byref(geom.c), pS, pet,
+                                      int(bb.shape[0]), pb, ctypes.byref(rid)))
+    return rid.value
+
+
+def emsurf_server_step(srv: Server) -> int:
+    n = ctypes.c_int32()
+    _check(lib().emsurf_server_step(srv.h, ctypes.byref(n)))
+    return n.value
+
+
+def emsurf_server_next_completed(srv: Server):
+    rid = ctypes.c_int64()
+    nrhs = ctypes.c_int32()
+    nu = ctypes.c_int64()
+    _check(lib().emsurf_server_next_completed(srv.h, ctypes.byref(rid), ctypes.byref(nrhs), ctypes.byref(nu)))
+    return (rid.value, nrhs.value, nu.value) if rid.value >= 0 else None
+
+
+def emsurf_server_fetch(srv: Server, req_id, nrhs, n_unknowns, want_x=True):
+    x = np.empty((nrhs, n_unknowns), dtype=np.complex128) if want_x else None
+    infos = (emsurf_solve_info * int(nrhs))()
+    times = (ctypes.c_double * 2)()
+    _check(lib().emsurf_server_fetch(srv.h, int(req_id), x.ctypes.data_as(ctypes.c_void_p) if want_x else None,
+                                     infos, times))
+    return x, [_info_dict(i) for i in infos], (times[0], times[1])
+
+
+def emsurf_server_query(srv: Server):
+    s = emsurf_server_stats()
+    _check(lib().emsurf_server_query(srv.h, ctypes.byref(s)))
+    return dict(queued=s.queued, active=s.active, resident_plans=s.resident_plans, bytes_used=s.bytes_used,
+                plans_built=s.plans_built, evictions=s.evictions)
+
+
+def emsurf_server_destroy(srv: Server):
+    srv.destroy()
+
+
+def emsurf_server_entry_bytes(srv: Server, nx, ny, n_eq, n_types) -> int:
+    d = _desc(nx, ny, n_eq, n_types, 1, EMSURF_STORE_FP64)
+    return int(lib().emsurf_server_entry_bytes(srv.h, ctypes.byref(d)))

@@ -117,18 +117,176 @@ void launch_t(const void* That, const void* xh, void* yh, int n, int nrhs, int64
   }
 }
 
+// ----------------------------------------------------------------------------- MFMA path
+// Many right-hand sides make each frequency a small dense GEMM.  The complex
+// product y = A x is the real product of the interleaved block (n x 2n real,
+// column index 2v + re/im) with the 2n x 2nrhs real embedding of x:
+//   [Re y_r] = sum_v Ar Br - Ai Bi,   [Im y_r] = sum_v Ar Bi + Ai Br,
+// run on v_mfma_f32_32x32x2f32.  A lane supplies A[row][k] for one row of a
+// 32-row tile and one of two block columns per instruction; with the
+// column-major store ([v][u]) the wave's load of two columns x 32 rows is two
+// contiguous 256-byte runs, fed straight from HBM into operand registers
+// (double-buffered, non-temporal).  Each wave owns TPW row tiles (one group;
+// at most 4 waves) and 16 right-hand sides; the spectral columns sit in LDS
+// (rows padded to spread banks) and the outputs are staged through the same
+// LDS for coalesced stores once every wave is done reading it.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <int TPW, int U>
+__global__ void __launch_bounds__(256) block_mfma_kernel(const float2* __restrict__ That,
+                                                         const float2* __restrict__ xh, float2* __restrict__ yh,
+                                                         int n, int nrhs, int r0, int nr) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float2* xs = reinterpret_cast<float2*>(smem_raw);     // [16][n + 1]
+  constexpr int NR = 16;
+  const int ld = n + 1;
+  const long long k = blockIdx.x;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5;
+  const int jl = lane & 31;
+  const int ntile = n >> 5;
+  const int rsel = jl >> 1;
+  const bool dimag = (jl & 1) != 0;
+  int tile[TPW];
+  bool tv[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    tile[i] = wave * TPW + i;
+    tv[i] = tile[i] < ntile;
+  }
+  floatx16 acc[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[i][e] = 0.f;
+  const float2* Ak = That + k * (long long)n * n;
+  // per-lane base: column h, row tile*32 + jl (a tile past the end re-reads
+  // tile 0 and its results are dropped)
+  const float2* abase[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) abase[i] = Ak + (long long)h * n + (tv[i] ? tile[i] * 32 : 0) + jl;
+  // first block columns are requested before the spectral columns are staged,
+  // so the two latencies overlap
+  float2 acur[U][TPW], anxt[U][TPW];
+#pragma unroll
+  for (int st = 0; st < U; ++st)
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) acur[st][i] = ld_nt(abase[i] + (long long)(2 * st) * n);
+  const float2* xk = xh + k * (long long)nrhs * n + (long long)r0 * n;
+  for (int i = threadIdx.x; i < NR * n; i += blockDim.x) {
+    const int r = i / n, v = i - r * n;
+    xs[r * ld + v] = (r < nr) ? xk[(long long)r * n + v] : float2{0.f, 0.f};
+  }
+  __syncthreads();
+  for (int v0 = 0; v0 < n; v0 += 2 * U) {
+    const bool more = v0 + 2 * U < n;
+    if (more) {
+#pragma unroll
+      for (int st = 0; st < U; ++st)
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) anxt[st][i] = ld_nt(abase[i] + (long long)(v0 + 2 * U + 2 * st) * n);
+    }
+#pragma unroll
+    for (int st = 0; st < U; ++st) {
+      const int v = v0 + 2 * st + h;
+      const float2 xv = xs[rsel * ld + v];
+      const float bre = dimag ? xv.y : xv.x;
+      const float bim = dimag ? xv.x : -xv.y;
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(acur[st][i].x, bre, acc[i], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(acur[st][i].y, bim, acc[i], 0, 0, 0);
+    }
+    if (more) {
+#pragma unroll
+      for (int st = 0; st < U; ++st)
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) acur[st][i] = anxt[st][i];
+    }
+  }
+  // stage outputs in LDS as [r][u] complex, then store the frequency's panel
+  __syncthreads();
+  float* ysf = reinterpret_cast<float*>(xs);
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    if (!tv[i]) continue;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int u = tile[i] * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+      ysf[2 * (rsel * ld + u) + (dimag ? 1 : 0)] = acc[i][e];
+    }
+  }
+  __syncthreads();
+  float2* yk = yh + k * (long long)nrhs * n + (long long)r0 * n;
+  for (int i = threadIdx.x; i < nr * n; i += blockDim.x) {
+    const int r = i / n, u = i - r * n;
+    yk[(long long)r * n + u] = xs[r * ld + u];
+  }
+}
+
+// row-tile groups (= wavefronts) for TPW tiles per wave
+inline int mfma_waves(int n, int tpw) { return (n / 32 + tpw - 1) / tpw; }
+
+template <int TPW, int U>
+void launch_mfma(const void* That, const void* xh, void* yh, int n, int nrhs, int r0, int nr, int64_t P,
+                 hipStream_t s) {
+  const int waves = mfma_waves(n, TPW);
+  EMS_CHECK_ARG(waves >= 1 && waves <= 4, "MFMA variant needs at most 4 wavefronts per frequency");
+  EMS_CHECK_ARG((n / 2) % U == 0, "MFMA variant needs n_eq / 2 divisible by its prefetch depth");
+  const size_t shm = (size_t)16 * (n + 1) * sizeof(float2);
+  EMS_CHECK_ARG(shm <= 65536, "MFMA variant needs n_eq <= 480");
+  hipLaunchKernelGGL((block_mfma_kernel<TPW, U>), dim3((unsigned)P), dim3(64 * waves), shm, s,
+                     static_cast<const float2*>(That), static_cast<const float2*>(xh), static_cast<float2*>(yh), n,
+                     nrhs, r0, nr);
+}
+
 }  // namespace
 
-void launch_block_product(Cx t, const void* That, const void* xh, void* yh, int n, int nrhs, int64_t P,
-                          hipStream_t s) {
+bool block_mfma_supported(int n, int nrhs) { return n % 32 == 0 && n >= 32 && n <= 480 && nrhs >= 1; }
+
+// variant 1..4: k = variant row tiles per wave, 4 K steps prefetched;
+// variant 5..8: k = variant - 4 row tiles per wave, 8 K steps prefetched
+static int variant_tiles(int variant) { return variant <= BP_MFMA_T4 ? variant : variant - BP_MFMA_T4; }
+
+bool block_variant_supported(int variant, int n, int nrhs) {
+  if (variant == BP_GEMV) return true;
+  if (variant < BP_MFMA_T1 || variant >= BP_NVARIANTS || !block_mfma_supported(n, nrhs)) return false;
+  return mfma_waves(n, variant_tiles(variant)) <= 4;
+}
+
+void launch_block_product_variant(Cx t, int variant, const void* That, const void* xh, void* yh, int n, int nrhs,
+                                  int64_t P, hipStream_t s) {
   EMS_CHECK_ARG(n >= 1 && n <= 512, "block product supports 1 <= n_eq <= 512");
   EMS_CHECK_ARG(nrhs >= 1 && nrhs <= 64, "block product supports 1 <= nrhs <= 64");
   EMS_CHECK_ARG(P >= 1 && P <= 0x7fffffffLL, "frequency count out of range");
-  if (t == Cx::C128)
-    launch_t<double2>(That, xh, yh, n, nrhs, P, s);
-  else
-    launch_t<float2>(That, xh, yh, n, nrhs, P, s);
+  if (t == Cx::C128 || !block_variant_supported(variant, n, nrhs) || variant == BP_GEMV) {
+    if (t == Cx::C128)
+      launch_t<double2>(That, xh, yh, n, nrhs, P, s);
+    else
+      launch_t<float2>(That, xh, yh, n, nrhs, P, s);
+  } else {
+    // 16 right-hand sides per pass
+    for (int r0 = 0; r0 < nrhs; r0 += 16) {
+      const int nr = nrhs - r0 < 16 ? nrhs - r0 : 16;
+      switch (variant) {
+        case BP_MFMA_T1: launch_mfma<1, 4>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
+        case BP_MFMA_T2: launch_mfma<2, 4>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
+        case BP_MFMA_T3: launch_mfma<3, 4>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
+        case BP_MFMA_T4: launch_mfma<4, 4>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
+        case BP_MFMA_T1D: launch_mfma<1, 8>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
+        case BP_MFMA_T2D: launch_mfma<2, 8>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
+        case BP_MFMA_T3D: launch_mfma<3, 8>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
+        default: launch_mfma<4, 8>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
+      }
+    }
+  }
   EMS_LAUNCH_CHECK();
+}
+
+void launch_block_product(Cx t, const void* That, const void* xh, void* yh, int n, int nrhs, int64_t P,
+                          hipStream_t s) {
+  launch_block_product_variant(t, BP_GEMV, That, xh, yh, n, nrhs, P, s);
 }
 
 }  // namespace emsurf

@@ -117,6 +117,19 @@ const void* twiddle_table(int L, Cx t);
 // That layout: [k][v][u] (column-major n x n blocks).
 void launch_block_product(Cx t, const void* That, const void* xh, void* yh, int n, int nrhs, int64_t P,
                           hipStream_t s);
+// Kernel variants of the FP32 product (FP64 always uses the lane-per-row GEMV):
+// BP_GEMV = lane-per-row streaming GEMV; BP_MFMA_Tk = MFMA GEMM with k row
+// tiles of 32 per wavefront (n_eq a multiple of 32, ceil(n_eq/32/k) <= 4),
+// 4 K steps of block columns in flight; BP_MFMA_TkD the same with 8.
+enum BpVariant {
+  BP_GEMV = 0, BP_MFMA_T1 = 1, BP_MFMA_T2 = 2, BP_MFMA_T3 = 3, BP_MFMA_T4 = 4,
+  BP_MFMA_T1D = 5, BP_MFMA_T2D = 6, BP_MFMA_T3D = 7, BP_MFMA_T4D = 8, BP_NVARIANTS = 9
+};
+bool block_mfma_supported(int n, int nrhs);
+// variant runnable for this n_eq (MFMA: n_eq % 32 == 0, <= 480, at most 4 wavefronts)
+bool block_variant_supported(int variant, int n, int nrhs);
+void launch_block_product_variant(Cx t, int variant, const void* That, const void* xh, void* yh, int n, int nrhs,
+                                  int64_t P, hipStream_t s);
 
 // ----------------------------------------------------------------------------- S apply
 struct TypeTiles {
@@ -179,14 +192,22 @@ struct emsurf_plan_s {
   std::map<hipStream_t, emsurf::Workspace*> ws;
   emsurf::KernelTimer timer;
   hipStream_t timer_stream = nullptr;
+  int bp_variant[65];             // FP32 block-product variant per nrhs, -1 = automatic
+  emsurf_plan_s() { for (int& v : bp_variant) v = -1; }
   ~emsurf_plan_s();
 };
 
 namespace emsurf {
 Workspace& workspace(emsurf_plan p, hipStream_t s);
+// FP32 block-product variant for this plan and nrhs: explicit choice, else the
+// persisted autotuning cache, else a heuristic.
+int choose_variant(emsurf_plan p, int nrhs);
 // apply_T with explicit element types: input tin, compute/that type tc, output tout.
-void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* x, void* y, hipStream_t s);
+// variant: FP32 block-product variant, -1 = the plan's choice for nrhs.
+void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* x, void* y, hipStream_t s,
+                   int variant = -1);
 // apply_A with explicit types: x (tx) -> y (ty) = x - S T x, arithmetic in tc.
-void apply_A_typed(emsurf_plan p, Cx tx, Cx tc, Cx ty, int nrhs, const void* x, void* y, hipStream_t s);
+void apply_A_typed(emsurf_plan p, Cx tx, Cx tc, Cx ty, int nrhs, const void* x, void* y, hipStream_t s,
+                   int variant = -1);
 inline size_t cx_bytes(Cx t) { return t == Cx::C128 ? 16 : 8; }
 }  // namespace emsurf

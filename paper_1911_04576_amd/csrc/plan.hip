@@ -99,7 +99,8 @@ void timer_end(hipEvent_t e, hipStream_t s) {
 
 }  // namespace
 
-void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* x, void* y, hipStream_t s) {
+void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* x, void* y, hipStream_t s,
+                   int variant) {
   const void* That = (tc == Cx::C128) ? p->that64.p : p->that32.p;
   if (!That) {
     set_error(tc == Cx::C128 ? "plan has no FP64 Fourier-domain store" : "plan has no FP32 Fourier-domain store");
@@ -137,7 +138,8 @@ void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* 
 
   // Fourier-domain block products
   timer_begin(p, 2, s, &e);
-  launch_block_product(tc, That, w.X.p, w.Y.p, n, nrhs, p->P, s);
+  const int v = tc == Cx::C64 ? (variant >= 0 ? variant : choose_variant(p, nrhs)) : BP_GEMV;
+  launch_block_product_variant(tc, v, That, w.X.p, w.Y.p, n, nrhs, p->P, s);
   timer_end(e, s);
 
   // inverse along y, keep rows iy < Ny
@@ -160,9 +162,10 @@ void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* 
   timer_end(e, s);
 }
 
-void apply_A_typed(emsurf_plan p, Cx tx, Cx tc, Cx ty, int nrhs, const void* x, void* y, hipStream_t s) {
+void apply_A_typed(emsurf_plan p, Cx tx, Cx tc, Cx ty, int nrhs, const void* x, void* y, hipStream_t s,
+                   int variant) {
   Workspace& w = workspace(p, s);
-  apply_T_typed(p, tx, tc, tc, nrhs, x, w.t.p, s);
+  apply_T_typed(p, tx, tc, tc, nrhs, x, w.t.p, s, variant);
   const void* S = (tc == Cx::C128) ? p->S64.p : p->S32.p;
   launch_apply_S(tc, tc, ty, S, p->tiles, p->d.n_eq, p->M, nrhs, w.t.p, x, y, s);
 }
@@ -296,6 +299,17 @@ void upload_geom(const emsurf_geom* g, GreenGeomDev& d) {
   EMS_HIP(hipMemcpy(d.tan.p, g->tan, (size_t)P * 6 * 8, hipMemcpyHostToDevice));
 }
 
+// Workspace of the creating stream and every twiddle table the applies need are
+// made now, so no apply (or graph capture) allocates or copies on first use.
+void finish_plan(emsurf_plan p, hipStream_t s) {
+  (void)workspace(p, s);
+  for (Cx t : {Cx::C128, Cx::C64}) {
+    (void)twiddle_table(p->Lx, t);
+    (void)twiddle_table(p->Ly, t);
+  }
+  EMS_HIP(hipStreamSynchronize(s));
+}
+
 emsurf_plan new_plan(const emsurf_plan_desc* desc) {
   validate_desc(desc);
   auto z = sizes_of(desc);
@@ -358,8 +372,7 @@ emsurf_status emsurf_plan_create(const emsurf_plan_desc* desc, const void* T_blo
     });
     upload_S(p, S_types, s);
     build_tiles(p, elem_type, s);
-    (void)workspace(p, s);
-    EMS_HIP(hipStreamSynchronize(s));
+    finish_plan(p, s);
   });
   if (st != EMSURF_OK) {
     delete p;
@@ -386,8 +399,7 @@ emsurf_status emsurf_plan_create_green(const emsurf_plan_desc* desc, const emsur
     });
     upload_S(p, S_types, s);
     build_tiles(p, elem_type, s);
-    (void)workspace(p, s);
-    EMS_HIP(hipStreamSynchronize(s));
+    finish_plan(p, s);
   });
   if (st != EMSURF_OK) {
     delete p;

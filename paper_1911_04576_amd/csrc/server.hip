@@ -1,0 +1,360 @@
+// Serving loop: requests for different surfaces (lattice, n_eq, macromodels)
+// arrive at any time; each surface's plan (its Fourier-domain blocks) stays
+// resident in HBM and is shared by every request on that surface; requests
+// are admitted when their plan fits the HBM budget (idle plans are evicted
+// least-recently-used first) and their session has free slots; every step
+// runs one batched GMRES iteration on every busy session, each session on its
+// own stream so that work on different plans overlaps on the device.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "internal.h"
+#include "session.h"
+
+namespace emsurf {
+namespace {
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+  int64_t id = 0;
+  uint64_t key = 0;
+  emsurf_plan_desc desc{};
+  std::vector<double> rho, area, tan;
+  double pitch = 0, k = 0;
+  std::vector<double> S;        // interleaved complex
+  std::vector<int32_t> types;
+  int nrhs = 0;
+  std::vector<double> b;        // interleaved complex [nrhs][N]
+  enum { QUEUED, ACTIVE, DONE } state = QUEUED;
+  std::vector<int> slots;
+  std::vector<double> x;        // result [nrhs][N]
+  std::vector<emsurf_solve_info> info;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  bool bad = false;
+};
+
+struct PlanEntry {
+  emsurf_plan plan = nullptr;
+  emsurf_session session = nullptr;
+  hipStream_t stream = nullptr;
+  size_t bytes = 0;
+  double last_used = 0;
+  int active = 0;
+  DevBuf staging;   // one right-hand side, for host -> slot copies
+};
+
+}  // namespace
+}  // namespace emsurf
+
+struct emsurf_server_s {
+  emsurf_server_desc d{};
+  std::map<uint64_t, std::unique_ptr<emsurf::PlanEntry>> plans;
+  std::deque<std::unique_ptr<emsurf::Request>> queue;
+  std::map<int64_t, std::unique_ptr<emsurf::Request>> active, done;
+  std::deque<int64_t> completed;
+  int64_t next_id = 1;
+  size_t used = 0;
+  int64_t evictions = 0, plans_built = 0;
+  ~emsurf_server_s() {
+    for (auto& kv : plans) {
+      if (kv.second->session) emsurf_session_destroy(kv.second->session);
+      if (kv.second->plan) emsurf_plan_destroy(kv.second->plan);
+      if (kv.second->stream) (void)hipStreamDestroy(kv.second->stream);
+    }
+  }
+};
+
+using namespace emsurf;
+
+namespace {
+
+void destroy_entry(emsurf_server sv, std::map<uint64_t, std::unique_ptr<PlanEntry>>::iterator it) {
+  PlanEntry& e = *it->second;
+  if (e.session) emsurf_session_destroy(e.session);
+  if (e.plan) emsurf_plan_destroy(e.plan);
+  if (e.stream) (void)hipStreamDestroy(e.stream);
+  sv->used -= e.bytes;
+  sv->plans.erase(it);
+}
+
+// Device bytes a resident surface takes: plan, session, staging vector.
+size_t entry_bytes(emsurf_server sv, emsurf_plan_desc pd) {
+  pd.max_rhs = sv->d.max_slots;
+  pd.store = sv->d.store;
+  const size_t pb = emsurf_plan_bytes(&pd);
+  if (pb == 0) return 0;
+  return pb + session_bytes(pd, sv->d.max_slots, sv->d.opts.restart) + (size_t)pd.nx * pd.ny * pd.n_eq * 16;
+}
+
+// Make the plan of request rq resident (building it if needed).  Returns null
+// when it does not fit the budget even after evicting every idle plan.
+PlanEntry* resident(emsurf_server sv, Request& rq) {
+  auto it = sv->plans.find(rq.key);
+  if (it != sv->plans.end()) return it->second.get();
+  emsurf_plan_desc pd = rq.desc;
+  pd.max_rhs = sv->d.max_slots;
+  pd.store = sv->d.store;
+  const size_t pb = emsurf_plan_bytes(&pd);
+  if (pb == 0) {
+    rq.bad = true;
+    return nullptr;
+  }
+  const size_t need = entry_bytes(sv, pd);
+  if (need > sv->d.budget_bytes) {   // can never be admitted
+    rq.bad = true;
+    return nullptr;
+  }
+  while (sv->used + need > sv->d.budget_bytes) {
+    // least recently used idle plan
+    auto victim = sv->plans.end();
+    for (auto p = sv->plans.begin(); p != sv->plans.end(); ++p)
+      if (p->second->active == 0 && (victim == sv->plans.end() || p->second->last_used < victim->second->last_used))
+        victim = p;
+    if (victim == sv->plans.end()) return nullptr;
+    destroy_entry(sv, victim);
+    ++sv->evictions;
+  }
+  auto e = std::make_unique<PlanEntry>();
+  EMS_HIP(hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking));
+  emsurf_geom g{(int32_t)rq.area.size(), rq.rho.data(), rq.area.data(), rq.tan.data(), rq.pitch, rq.k};
+  emsurf_status st = emsurf_plan_create_green(&pd, &g, rq.S.data(), rq.types.data(), e->stream, &e->plan);
+  if (st != EMSURF_OK) {
+    (void)hipStreamDestroy(e->stream);
+    throw Err{st};
+  }
+  st = emsurf_session_create(e->plan, sv->d.max_slots, &sv->d.opts, e->stream, &e->session);
+  if (st != EMSURF_OK) {
+    emsurf_plan_destroy(e->plan);
+    (void)hipStreamDestroy(e->stream);
+    throw Err{st};
+  }
+  e->staging.alloc((size_t)pd.nx * pd.ny * pd.n_eq * 16);
+  e->bytes = need;
+  sv->used += need;
+  ++sv->plans_built;
+  PlanEntry* raw = e.get();
+  sv->plans[rq.key] = std::move(e);
+  return raw;
+}
+
+int free_slots(emsurf_session ss) {
+  int c = 0;
+  for (auto& q : ss->slot) c += q.ph == SessionSlot::FREE;
+  return c;
+}
+
+void admit(emsurf_server sv) {
+  for (auto it = sv->queue.begin(); it != sv->queue.end();) {
+    Request& rq = **it;
+    PlanEntry* e = resident(sv, rq);
+    if (rq.bad) {
+      rq.state = Request::DONE;
+      rq.t_done = now_ms();
+      sv->completed.push_back(rq.id);
+      sv->done[rq.id] = std::move(*it);
+      it = sv->queue.erase(it);
+      continue;
+    }
+    if (!e || free_slots(e->session) < rq.nrhs) {
+      ++it;
+      continue;
+    }
+    const size_t N = (size_t)rq.desc.nx * rq.desc.ny * rq.desc.n_eq;
+    rq.slots.resize(rq.nrhs);
+    for (int r = 0; r < rq.nrhs; ++r) {
+      EMS_HIP(hipMemcpyAsync(e->staging.p, rq.b.data() + 2 * N * r, N * 16, hipMemcpyHostToDevice, e->stream));
+      int32_t slot = -1;
+      emsurf_status st = emsurf_session_submit(e->session, e->staging.p, rq.id, &slot);
+      if (st != EMSURF_OK) throw Err{st};
+      rq.slots[r] = slot;
+    }
+    EMS_HIP(hipStreamSynchronize(e->stream));
+    e->active += 1;
+    e->last_used = now_ms();
+    rq.state = Request::ACTIVE;
+    rq.t_admit = now_ms();
+    rq.b.clear();
+    rq.b.shrink_to_fit();
+    const int64_t id = rq.id;
+    sv->active[id] = std::move(*it);
+    it = sv->queue.erase(it);
+  }
+}
+
+void harvest(emsurf_server sv) {
+  std::vector<int64_t> finished;
+  for (auto& kv : sv->active) {
+    Request& rq = *kv.second;
+    PlanEntry& e = *sv->plans.at(rq.key);
+    bool all = true;
+    for (int s : rq.slots) all = all && e.session->slot[s].ph == SessionSlot::DONE;
+    if (!all) continue;
+    const size_t N = (size_t)rq.desc.nx * rq.desc.ny * rq.desc.n_eq;
+    rq.x.assign(2 * N * rq.nrhs, 0.0);
+    rq.info.resize(rq.nrhs);
+    for (int r = 0; r < rq.nrhs; ++r) {
+      emsurf_status st = emsurf_session_collect(e.session, rq.slots[r], e.staging.p, &rq.info[r]);
+      if (st == EMSURF_ERR_ARG) rq.bad = true;
+      else if (st != EMSURF_OK) throw Err{st};
+      EMS_HIP(hipMemcpy(rq.x.data() + 2 * N * r, e.staging.p, N * 16, hipMemcpyDeviceToHost));
+    }
+    e.active -= 1;
+    e.last_used = now_ms();
+    rq.state = Request::DONE;
+    rq.t_done = now_ms();
+    finished.push_back(kv.first);
+  }
+  for (int64_t id : finished) {
+    sv->done[id] = std::move(sv->active[id]);
+    sv->active.erase(id);
+    sv->completed.push_back(id);
+  }
+}
+
+template <typename F>
+emsurf_status vguard(F&& f) {
+  try {
+    f();
+    return EMSURF_OK;
+  } catch (const Err& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return EMSURF_ERR_OOM;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+emsurf_status emsurf_server_create(const emsurf_server_desc* desc, emsurf_server* out) {
+  return vguard([&] {
+    EMS_CHECK_ARG(desc != nullptr && out != nullptr, "desc and out must be non-NULL");
+    EMS_CHECK_ARG(desc->budget_bytes > 0, "budget must be > 0");
+    EMS_CHECK_ARG(desc->max_slots >= 1 && desc->max_slots <= 64, "max_slots must be in [1, 64]");
+    EMS_CHECK_ARG(desc->opts.restart >= 1 && desc->opts.restart <= 64 && desc->opts.tol > 0, "bad solve options");
+    EMS_CHECK_ARG(desc->store != 0, "store must be non-zero");
+    auto* sv = new emsurf_server_s();
+    sv->d = *desc;
+    *out = sv;
+  });
+}
+
+emsurf_status emsurf_server_submit(emsurf_server sv, uint64_t key, const emsurf_plan_desc* desc,
+                                   const emsurf_geom* geom, const void* S_types, const int32_t* elem_type,
+                                   int32_t nrhs, const void* b_host, int64_t* req_id) {
+  return vguard([&] {
+    EMS_CHECK_ARG(sv && desc && geom && S_types && elem_type && b_host, "arguments must be non-NULL");
+    EMS_CHECK_ARG(nrhs >= 1 && nrhs <= sv->d.max_slots, "nrhs must be in [1, max_slots]");
+    EMS_CHECK_ARG(desc->nx >= 1 && desc->ny >= 1 && desc->nx <= 512 && desc->ny <= 512, "bad lattice");
+    EMS_CHECK_ARG(desc->n_eq == 4 * geom->n_patch && desc->n_types >= 1, "n_eq must equal 4 * n_patch");
+    auto rq = std::make_unique<Request>();
+    rq->id = sv->next_id++;
+    rq->key = key;
+    rq->desc = *desc;
+    const int P = geom->n_patch;
+    rq->rho.assign(geom->rho, geom->rho + 3 * P);
+    rq->area.assign(geom->area, geom->area + P);
+    rq->tan.assign(geom->tan, geom->tan + 6 * P);
+    rq->pitch = geom->pitch;
+    rq->k = geom->k;
+    const size_t nS = (size_t)desc->n_types * desc->n_eq * desc->n_eq * 2;
+    rq->S.assign(static_cast<const double*>(S_types), static_cast<const double*>(S_types) + nS);
+    rq->types.assign(elem_type, elem_type + (size_t)desc->nx * desc->ny);
+    for (int32_t t : rq->types) EMS_CHECK_ARG(t >= 0 && t < desc->n_types, "elem_type entry out of range");
+    const size_t N = (size_t)desc->nx * desc->ny * desc->n_eq;
+    rq->nrhs = nrhs;
+    rq->b.assign(static_cast<const double*>(b_host), static_cast<const double*>(b_host) + 2 * N * nrhs);
+    rq->t_submit = now_ms();
+    if (req_id) *req_id = rq->id;
+    sv->queue.push_back(std::move(rq));
+  });
+}
+
+emsurf_status emsurf_server_step(emsurf_server sv, int32_t* n_completed) {
+  return vguard([&] {
+    EMS_CHECK_ARG(sv != nullptr, "server is NULL");
+    const size_t before = sv->completed.size();
+    admit(sv);
+    std::vector<emsurf_session> busy;
+    for (auto& kv : sv->plans)
+      if (kv.second->active > 0) busy.push_back(kv.second->session);
+    // launch every session's step first (each on its own stream), then wait
+    for (auto* ss : busy) session_launch(ss);
+    for (auto* ss : busy) session_finish(ss);
+    harvest(sv);
+    if (n_completed) *n_completed = (int32_t)(sv->completed.size() - before);
+  });
+}
+
+emsurf_status emsurf_server_next_completed(emsurf_server sv, int64_t* req_id, int32_t* nrhs, int64_t* n_unknowns) {
+  return vguard([&] {
+    EMS_CHECK_ARG(sv && req_id, "server and req_id must be non-NULL");
+    *req_id = -1;
+    if (sv->completed.empty()) return;
+    const int64_t id = sv->completed.front();
+    sv->completed.pop_front();
+    Request& rq = *sv->done.at(id);
+    *req_id = id;
+    if (nrhs) *nrhs = rq.nrhs;
+    if (n_unknowns) *n_unknowns = (int64_t)rq.desc.nx * rq.desc.ny * rq.desc.n_eq;
+  });
+}
+
+emsurf_status emsurf_server_fetch(emsurf_server sv, int64_t req_id, void* x_host, emsurf_solve_info* info,
+                                  double* times_ms) {
+  return vguard([&] {
+    EMS_CHECK_ARG(sv != nullptr, "server is NULL");
+    auto it = sv->done.find(req_id);
+    EMS_CHECK_ARG(it != sv->done.end(), "unknown or not finished request id");
+    Request& rq = *it->second;
+    if (x_host && !rq.x.empty()) std::memcpy(x_host, rq.x.data(), rq.x.size() * sizeof(double));
+    if (info)
+      for (int r = 0; r < (int)rq.info.size(); ++r) info[r] = rq.info[r];
+    if (times_ms) {
+      times_ms[0] = rq.t_admit - rq.t_submit;
+      times_ms[1] = rq.t_done - rq.t_submit;
+    }
+    const bool bad = rq.bad;
+    sv->done.erase(it);
+    if (bad) {
+      set_error("request could not be solved (invalid plan or non-finite right-hand side)");
+      throw Err{EMSURF_ERR_ARG};
+    }
+  });
+}
+
+emsurf_status emsurf_server_query(emsurf_server sv, emsurf_server_stats* out) {
+  return vguard([&] {
+    EMS_CHECK_ARG(sv && out, "server and out must be non-NULL");
+    out->queued = (int32_t)sv->queue.size();
+    out->active = (int32_t)sv->active.size();
+    out->resident_plans = (int32_t)sv->plans.size();
+    out->bytes_used = sv->used;
+    out->plans_built = sv->plans_built;
+    out->evictions = sv->evictions;
+  });
+}
+
+size_t emsurf_server_entry_bytes(emsurf_server sv, const emsurf_plan_desc* desc) {
+  if (!sv || !desc) return 0;
+  try {
+    return entry_bytes(sv, *desc);
+  } catch (...) {
+    return 0;
+  }
+}
+
+void emsurf_server_destroy(emsurf_server sv) { delete sv; }
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Autotuning of the FP32 Fourier-domain block product: every kernel variant
+// (lane-per-row GEMV, MFMA GEMM with 1, 2 or 3 row tiles per wavefront) is
+// timed with HIP events on the plan's own blocks and workspace, the fastest
+// is kept in the plan for that right-hand-side count, and, when the
+// environment variable EMSURF_TUNE_CACHE names a file, recorded there as
+// "n_eq nrhs variant" lines so later processes reuse it.
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+
+#include "internal.h"
+
+namespace emsurf {
+namespace {
+
+std::mutex g_cache_mu;
+bool g_cache_loaded = false;
+std::map<std::pair<int, int>, int> g_cache;   // (n_eq, nrhs) -> variant
+
+const char* cache_path() {
+  const char* p = std::getenv("EMSURF_TUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+void load_cache_locked() {
+  if (g_cache_loaded) return;
+  g_cache_loaded = true;
+  const char* path = cache_path();
+  if (!path) return;
+  std::ifstream f(path);
+  int n, r, v;
+  while (f >> n >> r >> v)
+    if (v >= 0 && v < BP_NVARIANTS) g_cache[{n, r}] = v;
+}
+
+void save_cache_locked() {
+  const char* path = cache_path();
+  if (!path) return;
+  std::ofstream f(path, std::ios::trunc);
+  for (auto& kv : g_cache) f << kv.first.first << " " << kv.first.second << " " << kv.second << "\n";
+}
+
+int heuristic(int n, int nrhs) {
+  if (!block_mfma_supported(n, nrhs) || nrhs < 8) return BP_GEMV;
+  // deep prefetch, fewest row tiles per wave that fits in 4 wavefronts
+  for (int v = BP_MFMA_T1D; v <= BP_MFMA_T4D; ++v)
+    if (block_variant_supported(v, n, nrhs)) return v;
+  return BP_GEMV;
+}
+
+}  // namespace
+
+int choose_variant(emsurf_plan p, int nrhs) {
+  const int n = p->d.n_eq;
+  if (nrhs >= 1 && nrhs <= 64 && p->bp_variant[nrhs] >= 0) return p->bp_variant[nrhs];
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    load_cache_locked();
+    auto it = g_cache.find({n, nrhs});
+    if (it != g_cache.end()) return it->second;
+  }
+  return heuristic(n, nrhs);
+}
+
+}  // namespace emsurf
+
+using namespace emsurf;
+
+extern "C" emsurf_status emsurf_plan_set_variant(emsurf_plan plan, int32_t nrhs, int32_t variant) {
+  try {
+    EMS_CHECK_ARG(plan != nullptr, "plan is NULL");
+    EMS_CHECK_ARG(nrhs >= 1 && nrhs <= plan->d.max_rhs, "nrhs must be in [1, max_rhs]");
+    EMS_CHECK_ARG(variant >= -1 && variant < BP_NVARIANTS, "unknown block-product variant");
+    if (variant > BP_GEMV && !block_variant_supported(variant, plan->d.n_eq, nrhs)) {
+      set_error("this MFMA block-product variant needs n_eq a multiple of 32 (<= 480) and at most 4 "
+                "wavefronts of row tiles");
+      throw Err{EMSURF_ERR_UNSUPPORTED};
+    }
+    plan->bp_variant[nrhs] = variant;
+    return EMSURF_OK;
+  } catch (const Err& e) {
+    return e.st;
+  }
+}
+
+extern "C" emsurf_status emsurf_plan_autotune(emsurf_plan plan, int32_t nrhs, double* ms_out, int32_t* best_out,
+                                              void* stream) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  try {
+    EMS_CHECK_ARG(plan != nullptr, "plan is NULL");
+    EMS_CHECK_ARG(nrhs >= 1 && nrhs <= plan->d.max_rhs, "nrhs must be in [1, max_rhs]");
+    if (!plan->that32.p) {
+      set_error("plan has no FP32 Fourier-domain store");
+      throw Err{EMSURF_ERR_UNSUPPORTED};
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace& w = workspace(plan, s);
+    const int n = plan->d.n_eq;
+    EMS_HIP(hipEventCreate(&e0));
+    EMS_HIP(hipEventCreate(&e1));
+    int best = BP_GEMV;
+    double best_ms = 1e300;
+    for (int v = 0; v < BP_NVARIANTS; ++v) {
+      double ms = -1.0;
+      if (block_variant_supported(v, n, nrhs)) {
+        launch_block_product_variant(Cx::C64, v, plan->that32.p, w.X.p, w.Y.p, n, nrhs, plan->P, s);  // warm-up
+        const int reps = 3;
+        EMS_HIP(hipEventRecord(e0, s));
+        for (int i = 0; i < reps; ++i)
+          launch_block_product_variant(Cx::C64, v, plan->that32.p, w.X.p, w.Y.p, n, nrhs, plan->P, s);
+        EMS_HIP(hipEventRecord(e1, s));
+        EMS_HIP(hipEventSynchronize(e1));
+        float f = 0;
+        EMS_HIP(hipEventElapsedTime(&f, e0, e1));
+        ms = f / reps;
+        if (ms < best_ms) { best_ms = ms; best = v; }
+      }
+      if (ms_out) ms_out[v] = ms;
+    }
+    plan->bp_variant[nrhs] = best;
+    if (best_out) *best_out = best;
+    {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      load_cache_locked();
+      g_cache[{n, nrhs}] = best;
+      save_cache_locked();
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return EMSURF_OK;
+  } catch (const Err& e) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return e.st;
+  }
+}

@@ -3,6 +3,26 @@
 #include <hip/hip_runtime.h>
 
 namespace emsurf {
+// One item of a pointer-list launch (device memory).  Meaning per kernel:
+//   copy:   dst = scale * (b ? b - a : a)
+//   dot:    a = basis (nv vectors of length N, contiguous), dst = w
+//   update: a = basis, dst = w (w -= basis * coefficients from the reduction buffer)
+//   axpy:   a = basis, b = coefficients (nv complex), dst = x (x += basis * y)
+struct VecItem {
+  const void* a;
+  const void* b;
+  void* dst;
+  double scale;
+  int nv;
+  int pad;
+};
+void launch_copy_list(const VecItem* items_dev, int nq, long long N, hipStream_t s);
+// red[q][off + l] = basis_l^H w (l < nv_q), red[q][off + nv_q].x = ||w||^2; ns >= max nv_q + 1
+void launch_dot_list(const VecItem* items_dev, int nq, int ns, long long N, void* partial, int nblk, void* red,
+                     int rstride, int off, hipStream_t s);
+void launch_update_list(const VecItem* items_dev, int nq, long long N, const void* red, int rstride, int off,
+                        hipStream_t s);
+void launch_axpy_list(const VecItem* items_dev, int nq, long long N, hipStream_t s);
 int dot_blocks(long long N);
 // red[r][off + l] = V_l^H w (l < nv), red[r][off + nv].x = ||w||^2 ; partial: [nrhs][nblk][nv+1] scratch
 void launch_dot(const void* V, long long vstride, int nv, const void* w, long long N, int nrhs, void* partial,

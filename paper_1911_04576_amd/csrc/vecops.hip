@@ -238,3 +238,143 @@ void launch_finite(const void* b, long long N, int nrhs, int* flag, hipStream_t 
 }
 
 }  // namespace emsurf
+
+// ----------------------------------------------------------------------------- pointer-list forms
+// Continuous batching runs one kernel over a list of independent vectors that
+// live at arbitrary places (each slot's own Krylov basis); item q of a list
+// carries its own pointers and sizes.  Same arithmetic per item as above, so a
+// slot's numbers do not depend on which other slots share the launch.
+namespace emsurf {
+namespace {
+
+__global__ void copy_list_kernel(const VecItem* __restrict__ items, long long N) {
+  const VecItem it = items[blockIdx.y];
+  const double2* a = reinterpret_cast<const double2*>(it.a);
+  const double2* b = reinterpret_cast<const double2*>(it.b);
+  double2* d = reinterpret_cast<double2*>(it.dst);
+  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < N; i += (long long)gridDim.x * NT) {
+    double2 v = a[i];
+    if (b) { v.x = b[i].x - v.x; v.y = b[i].y - v.y; }   // dst = b - a
+    if (it.scale != 1.0) { v.x *= it.scale; v.y *= it.scale; }
+    d[i] = v;
+  }
+}
+
+// partial[q][blk][l] = sum conj(basis_l) w (l < nv_q), slot nv_q: sum |w|^2; layout stride ns
+__global__ void __launch_bounds__(NT) dot_list_kernel(const VecItem* __restrict__ items, long long N, int ns,
+                                                      double2* __restrict__ partial, int nblk) {
+  __shared__ double2 sh[NT / 64];
+  const VecItem it = items[blockIdx.y];
+  const int blk = blockIdx.x;
+  const double2* V = reinterpret_cast<const double2*>(it.a);
+  const double2* w = reinterpret_cast<const double2*>(it.dst);
+  double2* out = partial + ((long long)blockIdx.y * nblk + blk) * ns;
+  for (int l = 0; l <= it.nv; ++l) {
+    double2 acc{0, 0};
+    for (long long base = (long long)blk * CHUNK; base < N; base += (long long)nblk * CHUNK) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const long long i = base + e * NT + threadIdx.x;
+        if (i < N) {
+          const double2 b = w[i];
+          if (l < it.nv) {
+            const double2 a = V[(long long)l * N + i];
+            acc.x += a.x * b.x + a.y * b.y;
+            acc.y += a.x * b.y - a.y * b.x;
+          } else {
+            acc.x += b.x * b.x + b.y * b.y;
+          }
+        }
+      }
+    }
+    const double2 s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[l] = s;
+  }
+}
+
+// red[q][off + l] = sum_blk partial[q][blk][l], l < ns; grid (ns, nq)
+__global__ void __launch_bounds__(NT) reduce_list_kernel(const double2* __restrict__ partial, int nblk, int ns,
+                                                         double2* __restrict__ red, int rstride, int off) {
+  __shared__ double2 sh[NT / 64];
+  const int l = blockIdx.x, q = blockIdx.y;
+  double2 acc{0, 0};
+  for (int b = threadIdx.x; b < nblk; b += NT) {
+    const double2 v = partial[((long long)q * nblk + b) * ns + l];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  const double2 t = block_sum(acc, sh);
+  if (threadIdx.x == 0) red[(long long)q * rstride + off + l] = t;
+}
+
+// w -= sum_{l < nv} basis_l red[q][off + l]
+__global__ void __launch_bounds__(NT) update_list_kernel(const VecItem* __restrict__ items, long long N,
+                                                         const double2* __restrict__ red, int rstride, int off) {
+  const VecItem it = items[blockIdx.y];
+  const double2* V = reinterpret_cast<const double2*>(it.a);
+  double2* w = reinterpret_cast<double2*>(it.dst);
+  const double2* c = red + (long long)blockIdx.y * rstride + off;
+  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < N; i += (long long)gridDim.x * NT) {
+    double2 acc = w[i];
+    for (int l = 0; l < it.nv; ++l) {
+      const double2 a = V[(long long)l * N + i];
+      const double2 h = c[l];
+      acc.x -= a.x * h.x - a.y * h.y;
+      acc.y -= a.x * h.y + a.y * h.x;
+    }
+    w[i] = acc;
+  }
+}
+
+// x += sum_{l < nv} basis_l y_l, y = items[q].coef[0..nv)
+__global__ void axpy_list_kernel(const VecItem* __restrict__ items, long long N) {
+  const VecItem it = items[blockIdx.y];
+  const double2* V = reinterpret_cast<const double2*>(it.a);
+  const double2* y = reinterpret_cast<const double2*>(it.b);
+  double2* x = reinterpret_cast<double2*>(it.dst);
+  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < N; i += (long long)gridDim.x * NT) {
+    double2 acc = x[i];
+    for (int l = 0; l < it.nv; ++l) {
+      const double2 a = V[(long long)l * N + i];
+      const double2 h = y[l];
+      acc.x += a.x * h.x - a.y * h.y;
+      acc.y += a.x * h.y + a.y * h.x;
+    }
+    x[i] = acc;
+  }
+}
+
+}  // namespace
+
+void launch_copy_list(const VecItem* items_dev, int nq, long long N, hipStream_t s) {
+  if (nq <= 0) return;
+  hipLaunchKernelGGL(copy_list_kernel, dim3(stream_blocks(N), nq), dim3(NT), 0, s, items_dev, N);
+  EMS_LAUNCH_CHECK();
+}
+
+void launch_dot_list(const VecItem* items_dev, int nq, int ns, long long N, void* partial, int nblk, void* red,
+                     int rstride, int off, hipStream_t s) {
+  if (nq <= 0) return;
+  hipLaunchKernelGGL(dot_list_kernel, dim3(nblk, nq), dim3(NT), 0, s, items_dev, N, ns,
+                     static_cast<double2*>(partial), nblk);
+  EMS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(reduce_list_kernel, dim3(ns, nq), dim3(NT), 0, s, static_cast<const double2*>(partial), nblk,
+                     ns, static_cast<double2*>(red), rstride, off);
+  EMS_LAUNCH_CHECK();
+}
+
+void launch_update_list(const VecItem* items_dev, int nq, long long N, const void* red, int rstride, int off,
+                        hipStream_t s) {
+  if (nq <= 0) return;
+  hipLaunchKernelGGL(update_list_kernel, dim3(stream_blocks(N), nq), dim3(NT), 0, s, items_dev, N,
+                     static_cast<const double2*>(red), rstride, off);
+  EMS_LAUNCH_CHECK();
+}
+
+void launch_axpy_list(const VecItem* items_dev, int nq, long long N, hipStream_t s) {
+  if (nq <= 0) return;
+  hipLaunchKernelGGL(axpy_list_kernel, dim3(stream_blocks(N), nq), dim3(NT), 0, s, items_dev, N);
+  EMS_LAUNCH_CHECK();
+}
+
+}  // namespace emsurf
