@@ -10,8 +10,8 @@
 // in place, and the last stage writes global memory directly, dropping the
 // points >= n_out (the crop of the inverse transform).
 //
-// Every thread holds VPT = L / G values of one column (G threads per column);
-// radices 2, 4, 8 and 16 run as register butterflies.  The arithmetic type may
+// Every thread holds VPT values of one column (G threads per column); radices
+// 2, 3, 4, 8 and 16 run as register butterflies.  The arithmetic type may
 // differ from the input and output types (FP64 <-> FP32 converting loads and
 // stores for the mixed-precision solve).
 #include "internal.h"
@@ -52,12 +52,22 @@ __device__ constexpr double kS16[16] = {
     0.0, -0.38268343236508978178, -0.70710678118654757274, -0.92387953251128673848,
     -1.0, -0.92387953251128673848, -0.70710678118654757274, -0.38268343236508978178};
 
-// In-register DFT of length R (power of two <= 16): a[k] <- sum_n a[n] e^{sign 2 pi i n k / R}
+// In-register DFT of length R (3, or a power of two <= 16): a[k] <- sum_n a[n] e^{sign 2 pi i n k / R}
 template <int R, typename V>
 __device__ __forceinline__ void dft(V (&a)[R], int sign) {
   using T = typename Real<V>::T;
   if constexpr (R == 1) {
     return;
+  } else if constexpr (R == 3) {
+    // X1,2 = a0 - (a1 + a2)/2 +- i sign sqrt(3)/2 (a1 - a2)
+    const T s3 = static_cast<T>(sign < 0 ? -0.86602540378443864676 : 0.86602540378443864676);
+    const V t1 = cadd(a[1], a[2]);
+    const V t2 = V{a[0].x - static_cast<T>(0.5) * t1.x, a[0].y - static_cast<T>(0.5) * t1.y};
+    const V d = csub(a[1], a[2]);
+    const V u = V{-s3 * d.y, s3 * d.x};
+    a[0] = cadd(a[0], t1);
+    a[1] = cadd(t2, u);
+    a[2] = csub(t2, u);
   } else if constexpr (R == 2) {
     V t = a[0];
     a[0] = cadd(t, a[1]);
@@ -96,20 +106,37 @@ struct PassArgs {
   double scale;
 };
 
-// Compile-time plan of a power-of-two length: every thread holds VPT values of
-// one column (G threads per column, BT columns per 256-thread workgroup) and
-// the stages are radix 16 while possible, then one radix-2/4/8 stage.
+// Compile-time plan of a transform length L = 2^a (2..1024) or 3 * 2^a
+// (24..768): every thread holds VPT values of one column (G = L / VPT threads
+// per column, BT columns per workgroup of NT threads).  Power-of-two lengths
+// run radix-16 stages while possible, then one radix-2/4/8 stage; lengths with
+// a factor 3 run radix-8 stages, one radix-2/4 stage if needed, then radix 3.
 template <int L> struct Shape {
-  static constexpr int VPT = L >= 16 ? 16 : L;
+  static constexpr bool R3 = L % 3 == 0;
+  static constexpr int VPT = R3 ? 24 : (L >= 16 ? 16 : L);
+  static constexpr int NT = R3 ? 128 : 256;
   static constexpr int G = L / VPT;
-  static constexpr int BT = 256 / G;
-  static constexpr int NT = BT * G;
+  static constexpr int BT = NT / G;
   static constexpr int nst() {
-    int n = 0, r = L;
+    int n = 0;
+    if (R3) {
+      int r = L / 3;
+      while (r >= 8) { r /= 8; ++n; }
+      return n + (r > 1 ? 1 : 0) + 1;
+    }
+    int r = L;
     while (r >= 16) { r /= 16; ++n; }
     return n + (r > 1 ? 1 : 0);
   }
   static constexpr int radix(int s) {
+    if (R3) {
+      int r = L / 3;
+      for (int i = 0; i < s; ++i) {
+        if (r == 1) return 3;
+        r /= (r >= 8 ? 8 : r);
+      }
+      return r == 1 ? 3 : (r >= 8 ? 8 : r);
+    }
     int r = L;
     for (int i = 0; i < s; ++i) r /= (r >= 16 ? 16 : r);
     return r >= 16 ? 16 : r;
@@ -160,10 +187,10 @@ __device__ __forceinline__ void run_stage(const PassArgs& a, VC* lds, const VI* 
   for (int j = 0; j < NB; ++j) {
     if constexpr (!FIRST) {
       const int i = g + G * j;
-      const int k = i & (P - 1);
+      const int k = i % P;
 #pragma unroll
       for (int q = 1; q < R; ++q) {
-        VC w = tw[(q * k * TSTR) & (L - 1)];
+        VC w = tw[q * k * TSTR];   // q k L / (P R) < L
         if (a.sign > 0) w.y = -w.y;
         v[j][q] = cmul(v[j][q], w);
       }
@@ -174,7 +201,7 @@ __device__ __forceinline__ void run_stage(const PassArgs& a, VC* lds, const VI* 
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const int i = g + G * j;
-    const int k = i & (P - 1);
+    const int k = i % P;
     const int base = (i - k) * R + k;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -199,7 +226,7 @@ __device__ __forceinline__ void run_stage(const PassArgs& a, VC* lds, const VI* 
 }
 
 template <int L, typename VI, typename VC, typename VO>
-__global__ void __launch_bounds__(256) fft_pass_kernel(PassArgs a, const VI* __restrict__ in, VO* __restrict__ out,
+__global__ void __launch_bounds__(Shape<L>::NT) fft_pass_kernel(PassArgs a, const VI* __restrict__ in, VO* __restrict__ out,
                                                        const VC* __restrict__ tw) {
   using SH = Shape<L>;
   __shared__ VC lds[SH::NST > 1 ? L * SH::BT : 1];
@@ -243,25 +270,17 @@ void launch_typed(int L, const PassArgs& a, int batch, unsigned lines, const voi
     EMS_FFT_CASE(256)
     EMS_FFT_CASE(512)
     EMS_FFT_CASE(1024)
+    EMS_FFT_CASE(24)
+    EMS_FFT_CASE(48)
+    EMS_FFT_CASE(96)
+    EMS_FFT_CASE(192)
+    EMS_FFT_CASE(384)
+    EMS_FFT_CASE(768)
     default: break;
   }
 #undef EMS_FFT_CASE
 }
 
-int batch_tile(int L) {
-  switch (L) {
-    case 2: return Shape<2>::BT;
-    case 4: return Shape<4>::BT;
-    case 8: return Shape<8>::BT;
-    case 16: return Shape<16>::BT;
-    case 32: return Shape<32>::BT;
-    case 64: return Shape<64>::BT;
-    case 128: return Shape<128>::BT;
-    case 256: return Shape<256>::BT;
-    case 512: return Shape<512>::BT;
-    default: return Shape<1024>::BT;
-  }
-}
 
 std::mutex g_tw_mu;
 std::map<std::pair<int, int>, DevBuf*> g_tw;
@@ -297,9 +316,24 @@ const void* twiddle_table(int L, Cx t) {
   return buf->p;
 }
 
+bool fft_length_supported(int L) {
+  if (L >= 2 && L <= 1024 && (L & (L - 1)) == 0) return true;
+  if (L % 3 != 0) return false;
+  const int q = L / 3;
+  return q >= 8 && q <= 256 && (q & (q - 1)) == 0;
+}
+
+int fft_length_at_least(int v) {
+  int best = 2;
+  while (best < v) best <<= 1;
+  for (int q = 8; 3 * q <= 768; q <<= 1)
+    if (3 * q >= v && 3 * q < best) best = 3 * q;
+  return best;
+}
+
 void launch_fft_pass(const FftPass& p, Cx tin, Cx tcomp, Cx tout, const void* in, void* out,
                      const void* twiddles, hipStream_t s) {
-  EMS_CHECK_ARG(p.L >= 2 && p.L <= 1024 && (p.L & (p.L - 1)) == 0, "FFT length must be a power of two in [2, 1024]");
+  EMS_CHECK_ARG(fft_length_supported(p.L), "FFT length must be 2^a in [2, 1024] or 3 * 2^a in [24, 768]");
   EMS_CHECK_ARG(p.n_in >= 1 && p.n_in <= p.L && p.n_out >= 1 && p.n_out <= p.L, "FFT prune/crop sizes out of range");
   EMS_CHECK_ARG(p.batch >= 1 && p.n_lines >= 1 && p.nl0 >= 1, "FFT batch/lines must be positive");
   EMS_CHECK_ARG(p.n_lines <= 65535, "FFT pass has more than 65535 lines");
@@ -316,10 +350,6 @@ void launch_fft_pass(const FftPass& p, Cx tin, Cx tcomp, Cx tout, const void* in
   a.in_pt = (int)p.in_pt; a.out_pt = (int)p.out_pt;
   a.sign = p.sign;
   a.scale = p.scale;
-  // the kernel indexes batch columns relative to its tile: columns beyond the
-  // batch are masked, so the batch count seen by a tile is relative
-  const int bt = batch_tile(p.L);
-  (void)bt;
   const unsigned lines = (unsigned)p.n_lines;
   if (tcomp == Cx::C128) {
     EMS_CHECK_ARG(tin == Cx::C128 && tout == Cx::C128, "FP64 FFT needs FP64 input and output");

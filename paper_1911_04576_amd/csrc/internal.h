@@ -91,7 +91,7 @@ struct PinnedBuf {
 // transform over L points for a contiguous set of batch columns; line l is
 // split as (l1, l0) = (l / nl0, l % nl0) to form its base offsets.
 struct FftPass {
-  int L = 0;           // transform length (power of two, 2..1024)
+  int L = 0;           // transform length: 2^a in [2, 1024] or 3 * 2^a in [24, 768]
   int n_in = 0;        // points read; points >= n_in are zero
   int n_out = 0;       // points written (crop)
   int batch = 0;       // batch columns per line (contiguous, stride 1)
@@ -104,6 +104,10 @@ struct FftPass {
 };
 
 enum class Cx { C64, C128 };
+
+bool fft_length_supported(int L);
+// smallest supported FFT length >= v (the circulant embedding needs >= 2N - 1)
+int fft_length_at_least(int v);
 
 // Launch a pass. tin/tcomp/tout select element types of input, arithmetic and output.
 void launch_fft_pass(const FftPass& p, Cx tin, Cx tcomp, Cx tout, const void* in, void* out,

@@ -14,12 +14,6 @@ namespace emsurf {
 namespace {
 thread_local std::string g_last_error;
 
-int pow2_at_least(int v) {
-  int L = 2;
-  while (L < v) L <<= 1;
-  return L;
-}
-
 void validate_desc(const emsurf_plan_desc* d) {
   EMS_CHECK_ARG(d != nullptr, "plan descriptor is NULL");
   EMS_CHECK_ARG(d->nx >= 1 && d->ny >= 1, "lattice sizes nx, ny must be >= 1");
@@ -40,8 +34,8 @@ struct Sizes {
 
 Sizes sizes_of(const emsurf_plan_desc* d) {
   Sizes z{};
-  z.Lx = pow2_at_least(2 * d->nx - 1);
-  z.Ly = pow2_at_least(2 * d->ny - 1);
+  z.Lx = fft_length_at_least(2 * d->nx - 1);
+  z.Ly = fft_length_at_least(2 * d->ny - 1);
   z.P = (int64_t)z.Lx * z.Ly;
   z.M = (int64_t)d->nx * d->ny;
   z.n = d->n_eq;

@@ -66,8 +66,8 @@ size_t session_bytes(const emsurf_plan_desc& d, int max_slots, int restart) {
   const size_t red = (size_t)max_slots * (2 * (restart + 2) + 8) * 16 * 2;
   const size_t partial = (size_t)max_slots * nblk * (restart + 2) * 16;
   // the session's own stream gets its own apply workspace in the plan
-  const int64_t Lx = [](int v) { int L = 2; while (L < v) L <<= 1; return L; }(2 * d.nx - 1);
-  const int64_t Ly = [](int v) { int L = 2; while (L < v) L <<= 1; return L; }(2 * d.ny - 1);
+  const int64_t Lx = fft_length_at_least(2 * d.nx - 1);
+  const int64_t Ly = fft_length_at_least(2 * d.ny - 1);
   const int64_t B = (int64_t)d.max_rhs * d.n_eq;
   const size_t ws = (size_t)(d.ny * Lx * B) * 16 + 2 * (size_t)(Lx * Ly * B) * 16 + (size_t)(B * d.nx * d.ny) * 16;
   return per_slot * max_slots + red + partial + ws + (size_t)16 * max_slots * 64 * sizeof(VecItem);

@@ -57,6 +57,8 @@ def random_plan(nx, ny, n, nrhs, seed, n_types=3, zero_self=True, store=3):
     (1, 1, 4, 1), (2, 1, 3, 1), (1, 3, 5, 2), (3, 2, 7, 1), (5, 3, 6, 3), (4, 4, 16, 2),
     (9, 7, 10, 1), (17, 5, 12, 2), (33, 2, 8, 1), (2, 65, 4, 1), (129, 1, 3, 1), (6, 6, 130, 1),
     (3, 4, 257, 1), (8, 8, 40, 9), (5, 5, 33, 17),
+    # padded lengths with a factor 3: 24, 48, 96, 192, 384, 768
+    (10, 3, 5, 1), (20, 12, 6, 2), (33, 1, 4, 1), (65, 2, 3, 1), (130, 2, 2, 1), (300, 1, 2, 1), (24, 24, 4, 3),
 ])
 def test_apply_T_fp64_random_blocks(nx, ny, n, nrhs):
     say(f"apply_T fp64 random {nx}x{ny} n={n} nrhs={nrhs}")
@@ -86,9 +88,9 @@ def test_apply_T_nonzero_self_block():
     assert rel_per_rhs(y.cpu().numpy(), yr).max() <= FP64_TOL
 
 
-def test_apply_T_fp32_error_reported():
+@pytest.mark.parametrize("nx,ny,n,nrhs", [(9, 6, 24, 3), (65, 17, 8, 2)])
+def test_apply_T_fp32_error_reported(nx, ny, n, nrhs):
     e = E()
-    nx, ny, n, nrhs = 9, 6, 24, 3
     plan, B, S, tm = random_plan(nx, ny, n, nrhs, seed=3)
     x = W.random_vectors(nrhs, nx, ny, n, seed=9)
     y = torch.empty(x.shape, dtype=torch.complex64, device="cuda")
