@@ -139,6 +139,106 @@ def multi_rhs_section(E, W, torch, np, with_oracle):
     return sec
 
 
+def serving_section(E, W, np, n_requests, budget_gb, n_surfaces=12, load=0.7):
+    """Poisson stream of solve requests over a catalogue of surfaces (lattices
+    8..96, n_eq 96/192/288, 1..32 RHS each), FP32 inner / FP64 refinement to
+    1e-6.  A closed-loop pass (every request queued at once) measures capacity;
+    the open-loop pass then offers `load` x that rate and reports latency."""
+    tol = 1e-6
+    opts = E.solve_opts(E.EMSURF_FP32_IR, tol=tol, restart=8, inner_tol=1e-6)
+    cat = W.serving_catalogue(n_surfaces)
+    inputs = []
+    for sf in cat:
+        g = W.box_geometry(sf.n_patch)
+        inputs.append((E.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0), sf.s_types(), sf.type_map(), g))
+
+    def run(rate_hz, closed):
+        import queue
+        import threading
+        reqs = W.serving_stream(n_requests, rate_hz, n_surfaces)
+        # right-hand sides are produced ahead of time by a host thread (bounded
+        # queue), so the client side never stalls the serving loop
+        ready = queue.Queue(maxsize=24)
+
+        def produce():
+            for r in reqs:
+                sf = cat[r.surface]
+                ready.put((r, W.plane_wave_rhs(sf.config(r.angles), inputs[r.surface][3])))
+
+        prod = threading.Thread(target=produce, daemon=True)
+        prod.start()
+        pending = []
+        while len(pending) < min(8, len(reqs)):
+            pending.append(ready.get())
+        srv = E.emsurf_server_create(int(budget_gb * 1e9), 32, opts)
+        t0 = time.perf_counter()
+        nxt, lat, done, unk, bad = 0, [], 0, 0, 0
+        arrive = {}
+        last_log = 0.0
+        while done < len(reqs):
+            now = time.perf_counter() - t0
+            if now - last_log > 5.0:
+                st = E.emsurf_server_query(srv)
+                log(f"  serving {'closed' if closed else 'open'} t={now:.1f}s submitted {nxt} done {done} {st}")
+                last_log = now
+            while nxt < len(reqs):
+                if not pending:
+                    try:
+                        pending.append(ready.get_nowait())
+                    except queue.Empty:
+                        break
+                r, b = pending[0]
+                if not (closed or r.arrival_s <= now):
+                    break
+                pending.pop(0)
+                sf = cat[r.surface]
+                geom, S, tm, g = inputs[r.surface]
+                rid = E.emsurf_server_submit(srv, sf.key, sf.n, sf.n, sf.n_types, geom, S, tm, b)
+                arrive[rid] = (0.0 if closed else r.arrival_s, r.nrhs * sf.n * sf.n * sf.n_eq)
+                nxt += 1
+            st = E.emsurf_server_query(srv)
+            if st["queued"] + st["active"] == 0:
+                time.sleep(0.0005)
+                continue
+            E.emsurf_server_step(srv)
+            while True:
+                c = E.emsurf_server_next_completed(srv)
+                if c is None:
+                    break
+                rid, nrhs, nu = c
+                _, infos, _ = E.emsurf_server_fetch(srv, rid, nrhs, nu, want_x=False)
+                t_done = time.perf_counter() - t0
+                a, u = arrive.pop(rid)
+                lat.append(1e3 * (t_done - a))
+                unk += u
+                bad += sum(1 for i in infos if not (i["converged"] and i["rel_res_true"] <= tol))
+                done += 1
+        wall = time.perf_counter() - t0
+        stats = E.emsurf_server_query(srv)
+        srv.destroy()
+        prod.join()
+        return np.array(lat), wall, unk, bad, stats
+
+    lat_c, wall_c, unk_c, bad_c, st_c = run(1.0, closed=True)
+    cap_rps = n_requests / wall_c
+    rate = load * cap_rps
+    log(f"serving closed loop: {n_requests} requests in {wall_c:.2f} s ({cap_rps:.1f} req/s, "
+        f"{unk_c / wall_c:.3e} unknowns*RHS/s), stats {st_c}")
+    lat, wall, unk, bad, st = run(rate, closed=False)
+    sec = {"workload": f"{n_surfaces} surfaces (n x n lattices, n in 8..96; n_eq 96/192/288; 16 types each), "
+                       f"{n_requests} requests of 1..32 RHS, Poisson arrivals at {rate:.2f} req/s "
+                       f"(= {load} x closed-loop capacity {cap_rps:.2f} req/s), FP32 inner + FP64 refinement "
+                       f"to {tol}, HBM budget {budget_gb} GB, 32 slots per surface",
+           "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+           "mean_ms": round(float(lat.mean()), 2),
+           "unknowns_rhs_per_s": unk / wall, "wall_s": round(wall, 3), "requests_failing_tol": bad,
+           "closed_loop": {"wall_s": round(wall_c, 3), "req_per_s": round(cap_rps, 3),
+                           "unknowns_rhs_per_s": unk_c / wall_c, "requests_failing_tol": bad_c},
+           "plans_built": st["plans_built"], "evictions": st["evictions"]}
+    log(f"serving open loop: {sec}")
+    return sec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +249,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-cal", action="store_true", help="also time a plain 2 GiB device copy")
     ap.add_argument("--no-multi", action="store_true", help="skip the 64x64, 16-RHS MFMA section")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--serving-budget-gb", type=float, default=230.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the coupled solve is measured on one MI355X "
@@ -273,6 +376,13 @@ def main():
     if not args.no_multi:
         multi = multi_rhs_section(E, W, torch, np, not args.no_cpu)
 
+    serving = None
+    if not args.no_serving:
+        plan.destroy()
+        plan = None
+        torch.cuda.empty_cache()
+        serving = serving_section(E, W, np, args.serving_requests, args.serving_budget_gb)
+
     cpu = None
     parity = None
     if not args.no_cpu:
@@ -308,12 +418,14 @@ def main():
         "plan_create_s": round(plan_s, 3),
         "copy_reference": copy,
         "multi_rhs_64x64": multi,
+        "serving": serving,
         "solve": solve,
         "cpu_baseline": cpu,
         "parity_sampled_fp64_rel_err": parity,
     }
     print(json.dumps(out), flush=True)
-    plan.destroy()
+    if plan is not None:
+        plan.destroy()
 
 
 if __name__ == "__main__":

@@ -297,6 +297,8 @@ typedef struct {
   int32_t queued, active, resident_plans;
   size_t bytes_used;
   int64_t plans_built, evictions;
+  double admit_ms;            /* host time spent admitting (building plans, evicting, uploading b) */
+  double step_ms;             /* host time spent in batched iterations (launch to reductions back) */
 } emsurf_server_stats;
 emsurf_status emsurf_server_create(const emsurf_server_desc* desc, emsurf_server* out);
 /* desc: nx, ny, n_eq (= 4 geom->n_patch), n_types (max_rhs, store ignored);

@@ -87,7 +87,8 @@ class emsurf_server_desc(ctypes.Structure):
 
 class emsurf_server_stats(ctypes.Structure):
     _fields_ = [("queued", ctypes.c_int32), ("active", ctypes.c_int32), ("resident_plans", ctypes.c_int32),
-                ("bytes_used", ctypes.c_size_t), ("plans_built", ctypes.c_int64), ("evictions", ctypes.c_int64)]
+                ("bytes_used", ctypes.c_size_t), ("plans_built", ctypes.c_int64), ("evictions", ctypes.c_int64),
+                ("admit_ms", ctypes.c_double), ("step_ms", ctypes.c_double)]
 
 
 class emsurf_plan_stats(ctypes.Structure):
@@ -504,7 +505,8 @@ def emsurf_server_query(srv: Server):
     s = emsurf_server_stats()
     _check(lib().emsurf_server_query(srv.h, ctypes.byref(s)))
     return dict(queued=s.queued, active=s.active, resident_plans=s.resident_plans, bytes_used=s.bytes_used,
-                plans_built=s.plans_built, evictions=s.evictions)
+                plans_built=s.plans_built, evictions=s.evictions, admit_ms=round(s.admit_ms, 1),
+                step_ms=round(s.step_ms, 1))
 
 
 def emsurf_server_destroy(srv: Server):

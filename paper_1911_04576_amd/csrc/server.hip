@@ -64,6 +64,7 @@ struct emsurf_server_s {
   int64_t next_id = 1;
   size_t used = 0;
   int64_t evictions = 0, plans_built = 0;
+  double admit_ms = 0, step_ms = 0;
   ~emsurf_server_s() {
     for (auto& kv : plans) {
       if (kv.second->session) emsurf_session_destroy(kv.second->session);
@@ -95,29 +96,30 @@ size_t entry_bytes(emsurf_server sv, emsurf_plan_desc pd) {
   return pb + session_bytes(pd, sv->d.max_slots, sv->d.opts.restart) + (size_t)pd.nx * pd.ny * pd.n_eq * 16;
 }
 
-// Make the plan of request rq resident (building it if needed).  Returns null
-// when it does not fit the budget even after evicting every idle plan.
-PlanEntry* resident(emsurf_server sv, Request& rq) {
+// Make the plan of request rq resident (building it if needed), evicting
+// least-recently-used plans that have neither active nor queued requests.
+// Returns null when it does not fit the budget even then.
+PlanEntry* resident(emsurf_server sv, Request& rq, const std::map<uint64_t, int>& queued_keys) {
   auto it = sv->plans.find(rq.key);
   if (it != sv->plans.end()) return it->second.get();
   emsurf_plan_desc pd = rq.desc;
   pd.max_rhs = sv->d.max_slots;
   pd.store = sv->d.store;
-  const size_t pb = emsurf_plan_bytes(&pd);
-  if (pb == 0) {
-    rq.bad = true;
-    return nullptr;
-  }
   const size_t need = entry_bytes(sv, pd);
-  if (need > sv->d.budget_bytes) {   // can never be admitted
+  if (need == 0 || need > sv->d.budget_bytes) {   // invalid, or can never be admitted
     rq.bad = true;
     return nullptr;
   }
+  auto idle = [&](const PlanEntry& e, uint64_t key) { return e.active == 0 && queued_keys.count(key) == 0; };
+  size_t freeable = 0;
+  for (auto& kv : sv->plans)
+    if (idle(*kv.second, kv.first)) freeable += kv.second->bytes;
+  if (sv->used - freeable + need > sv->d.budget_bytes) return nullptr;   // wait; evict nothing
   while (sv->used + need > sv->d.budget_bytes) {
-    // least recently used idle plan
     auto victim = sv->plans.end();
     for (auto p = sv->plans.begin(); p != sv->plans.end(); ++p)
-      if (p->second->active == 0 && (victim == sv->plans.end() || p->second->last_used < victim->second->last_used))
+      if (idle(*p->second, p->first) &&
+          (victim == sv->plans.end() || p->second->last_used < victim->second->last_used))
         victim = p;
     if (victim == sv->plans.end()) return nullptr;
     destroy_entry(sv, victim);
@@ -139,6 +141,7 @@ PlanEntry* resident(emsurf_server sv, Request& rq) {
   }
   e->staging.alloc((size_t)pd.nx * pd.ny * pd.n_eq * 16);
   e->bytes = need;
+  e->last_used = now_ms();
   sv->used += need;
   ++sv->plans_built;
   PlanEntry* raw = e.get();
@@ -152,41 +155,70 @@ int free_slots(emsurf_session ss) {
   return c;
 }
 
+void place(emsurf_server sv, Request& rq, PlanEntry* e) {
+  const size_t N = (size_t)rq.desc.nx * rq.desc.ny * rq.desc.n_eq;
+  rq.slots.resize(rq.nrhs);
+  for (int r = 0; r < rq.nrhs; ++r) {
+    EMS_HIP(hipMemcpyAsync(e->staging.p, rq.b.data() + 2 * N * r, N * 16, hipMemcpyHostToDevice, e->stream));
+    int32_t slot = -1;
+    emsurf_status st = emsurf_session_submit(e->session, e->staging.p, rq.id, &slot);
+    if (st != EMSURF_OK) throw Err{st};
+    rq.slots[r] = slot;
+  }
+  EMS_HIP(hipStreamSynchronize(e->stream));
+  e->active += 1;
+  e->last_used = now_ms();
+  rq.state = Request::ACTIVE;
+  rq.t_admit = now_ms();
+  rq.b.clear();
+  rq.b.shrink_to_fit();
+}
+
+// Admission: first every queued request whose plan is resident and has free
+// slots (in arrival order); then, for the oldest waiting requests whose plan is
+// not resident, build plans as long as they fit after evicting idle plans.
 void admit(emsurf_server sv) {
+  auto take = [&](std::deque<std::unique_ptr<Request>>::iterator it) {
+    const int64_t id = (*it)->id;
+    sv->active[id] = std::move(*it);
+    return sv->queue.erase(it);
+  };
   for (auto it = sv->queue.begin(); it != sv->queue.end();) {
     Request& rq = **it;
-    PlanEntry* e = resident(sv, rq);
+    auto pe = sv->plans.find(rq.key);
+    if (pe != sv->plans.end() && free_slots(pe->second->session) >= rq.nrhs) {
+      place(sv, rq, pe->second.get());
+      it = take(it);
+    } else {
+      ++it;
+    }
+  }
+  std::map<uint64_t, int> queued_keys;
+  for (auto& q : sv->queue) queued_keys[q->key] += 1;
+  for (auto it = sv->queue.begin(); it != sv->queue.end();) {
+    Request& rq = **it;
+    if (sv->plans.count(rq.key)) { ++it; continue; }
+    // the request's own key does not protect plans from eviction, other queued keys do
+    auto mine = queued_keys.find(rq.key);
+    std::map<uint64_t, int> others = queued_keys;
+    others.erase(rq.key);
+    (void)mine;
+    PlanEntry* e = resident(sv, rq, others);
     if (rq.bad) {
       rq.state = Request::DONE;
       rq.t_done = now_ms();
       sv->completed.push_back(rq.id);
-      sv->done[rq.id] = std::move(*it);
+      const int64_t id = rq.id;
+      sv->done[id] = std::move(*it);
       it = sv->queue.erase(it);
       continue;
     }
-    if (!e || free_slots(e->session) < rq.nrhs) {
-      ++it;
+    if (e && free_slots(e->session) >= rq.nrhs) {
+      place(sv, rq, e);
+      it = take(it);
       continue;
     }
-    const size_t N = (size_t)rq.desc.nx * rq.desc.ny * rq.desc.n_eq;
-    rq.slots.resize(rq.nrhs);
-    for (int r = 0; r < rq.nrhs; ++r) {
-      EMS_HIP(hipMemcpyAsync(e->staging.p, rq.b.data() + 2 * N * r, N * 16, hipMemcpyHostToDevice, e->stream));
-      int32_t slot = -1;
-      emsurf_status st = emsurf_session_submit(e->session, e->staging.p, rq.id, &slot);
-      if (st != EMSURF_OK) throw Err{st};
-      rq.slots[r] = slot;
-    }
-    EMS_HIP(hipStreamSynchronize(e->stream));
-    e->active += 1;
-    e->last_used = now_ms();
-    rq.state = Request::ACTIVE;
-    rq.t_admit = now_ms();
-    rq.b.clear();
-    rq.b.shrink_to_fit();
-    const int64_t id = rq.id;
-    sv->active[id] = std::move(*it);
-    it = sv->queue.erase(it);
+    ++it;
   }
 }
 
@@ -285,7 +317,9 @@ emsurf_status emsurf_server_step(emsurf_server sv, int32_t* n_completed) {
   return vguard([&] {
     EMS_CHECK_ARG(sv != nullptr, "server is NULL");
     const size_t before = sv->completed.size();
+    const double t0 = now_ms();
     admit(sv);
+    const double t1 = now_ms();
     std::vector<emsurf_session> busy;
     for (auto& kv : sv->plans)
       if (kv.second->active > 0) busy.push_back(kv.second->session);
@@ -293,6 +327,8 @@ emsurf_status emsurf_server_step(emsurf_server sv, int32_t* n_completed) {
     for (auto* ss : busy) session_launch(ss);
     for (auto* ss : busy) session_finish(ss);
     harvest(sv);
+    sv->admit_ms += t1 - t0;
+    sv->step_ms += now_ms() - t1;
     if (n_completed) *n_completed = (int32_t)(sv->completed.size() - before);
   });
 }
@@ -343,6 +379,8 @@ emsurf_status emsurf_server_query(emsurf_server sv, emsurf_server_stats* out) {
     out->bytes_used = sv->used;
     out->plans_built = sv->plans_built;
     out->evictions = sv->evictions;
+    out->admit_ms = sv->admit_ms;
+    out->step_ms = sv->step_ms;
   });
 }
 

@@ -94,6 +94,10 @@ def test_plane_wave_oblique_phase_progression():
 
 
 def test_serving_stream_ranges():
-    reqs = W.serving_stream(50, rate_hz=10.0)
-    assert all(8 <= r.n <= 96 and r.n_patch in (24, 48, 72) and 1 <= r.nrhs <= 32 for r in reqs)
+    cat = W.serving_catalogue(12)
+    assert all(8 <= s.n <= 96 and s.n_patch in (24, 48, 72) for s in cat)
+    reqs = W.serving_stream(50, rate_hz=10.0, n_surfaces=len(cat))
+    assert all(0 <= r.surface < 12 and 1 <= r.nrhs <= 32 and len(r.angles) == r.nrhs for r in reqs)
     assert all(reqs[i].arrival_s < reqs[i + 1].arrival_s for i in range(len(reqs) - 1))
+    fast = W.serving_stream(50, rate_hz=20.0, n_surfaces=len(cat))
+    assert np.allclose([2 * f.arrival_s for f in fast], [r.arrival_s for r in reqs])

@@ -193,23 +193,34 @@ def incident_fields(theta: float, pol: str, pts: np.ndarray, k: float = K0):
     return E, H
 
 
+def box_excitation(theta: float, pol: str, geom: BoxGeometry, k: float = K0) -> np.ndarray:
+    """Excitation of the box at the origin: the equivalent incident currents
+    J = n x H_inc and M = -n x E_inc (Love's equivalence, Sec. II-A) at the
+    patch centres, projected on each patch tangent.  complex128 [n_eq]."""
+    E, H = incident_fields(theta, pol, geom.rho, k)
+    nxH = np.cross(geom.normal, H)
+    nxE = np.cross(geom.normal, E)
+    npch = geom.n_patch
+    c = np.zeros(4 * npch, dtype=np.complex128)
+    for a in range(2):
+        t = geom.tan[:, a, :]
+        c[2 * np.arange(npch) + a] = np.sum(t * nxH, axis=-1)
+        c[2 * npch + 2 * np.arange(npch) + a] = np.sum(t * (-nxE), axis=-1)
+    return c
+
+
 def plane_wave_rhs(cfg: Config, geom: BoxGeometry | None = None, pitch: float = PITCH, k: float = K0) -> np.ndarray:
-    """Excitation b sampled at the patch centres: the equivalent incident currents
-    J = n x H_inc and M = -n x E_inc (Love's equivalence, Sec. II-A), projected on
-    each patch tangent.  complex128 [nrhs][ny][nx][n_eq]."""
+    """Excitation b sampled at the patch centres of every element,
+    complex128 [nrhs][ny][nx][n_eq].  A plane wave seen from element m differs
+    from the box at the origin only by the phase exp(-j k k_hat . R_m), so each
+    right-hand side is that phase times the box excitation."""
     geom = geom if geom is not None else box_geometry(cfg.n_patch)
     pos = element_positions(cfg.nx, cfg.ny, pitch)                    # [ny][nx][3]
-    pts = pos[:, :, None, :] + geom.rho[None, None, :, :]            # [ny][nx][p][3]
-    npch = geom.n_patch
-    b = np.zeros((cfg.nrhs, cfg.ny, cfg.nx, 4 * npch), dtype=np.complex128)
+    b = np.empty((cfg.nrhs, cfg.ny, cfg.nx, geom.n_eq), dtype=np.complex128)
     for r, (theta, pol) in enumerate(cfg.angles):
-        E, H = incident_fields(theta, pol, pts, k)
-        nxH = np.cross(geom.normal[None, None], H)
-        nxE = np.cross(geom.normal[None, None], E)
-        for a in range(2):
-            t = geom.tan[:, a, :][None, None]
-            b[r, :, :, 2 * np.arange(npch) + a] = np.moveaxis(np.sum(t * nxH, axis=-1), -1, 0)
-            b[r, :, :, 2 * npch + 2 * np.arange(npch) + a] = np.moveaxis(np.sum(t * (-nxE), axis=-1), -1, 0)
+        khat = np.array([math.sin(theta), 0.0, -math.cos(theta)])
+        phase = np.exp(-1j * k * (pos @ khat))                         # [ny][nx]
+        np.multiply(phase[:, :, None], box_excitation(theta, pol, geom, k)[None, None, :], out=b[r])
     return b
 
 
@@ -248,30 +259,65 @@ def random_type_map(nx: int, ny: int, n_types: int, seed: int) -> np.ndarray:
 
 # ----------------------------------------------------------------------------- serving
 @dataclasses.dataclass(frozen=True)
+class Surface:
+    """One surface of the serving catalogue: an n x n lattice of boxes with
+    n_patch patches each and its own seeded macromodels and type map."""
+    key: int
+    n: int
+    n_patch: int
+    n_types: int
+    seed: int
+
+    @property
+    def n_eq(self) -> int:
+        return 4 * self.n_patch
+
+    def config(self, angles=((0.0, "TE"),)) -> Config:
+        return Config(5000 + self.key, self.n, self.n, self.n_patch, self.n_types, tuple(angles), 1e-6)
+
+    def s_types(self) -> np.ndarray:
+        return random_types(self.n_types, self.n_eq, seed=self.seed)
+
+    def type_map(self) -> np.ndarray:
+        return random_type_map(self.n, self.n, self.n_types, seed=self.seed)
+
+
+@dataclasses.dataclass(frozen=True)
 class Request:
     rid: int
     arrival_s: float
-    n: int            # lattice is n x n
-    n_patch: int
+    surface: int      # index into the catalogue
     nrhs: int
     angles: tuple
-    type_seed: int
 
 
-def serving_stream(n_requests: int, rate_hz: float, n_min: int = 8, n_max: int = 96,
-                   patches=(24, 48, 72), max_rhs: int = 32, cfg: int = 5):
-    """Poisson arrivals of solve requests: n ~ U{n_min..n_max}, n_eq ~ U{96,192,288},
-    nrhs ~ U{1..max_rhs}, per-request seeded angles/polarisations and cell types."""
-    st = streams(cfg)
-    arr = np.cumsum(st["arrivals"].exponential(1.0 / rate_hz, size=n_requests))
-    par = st["serving"]
+def serving_catalogue(n_surfaces: int = 12, n_min: int = 8, n_max: int = 96, patches=(24, 48, 72),
+                      n_types: int = 16, cfg: int = 5):
+    """Surfaces with lattices n ~ U{n_min..n_max} (n x n), n_eq ~ U{96, 192, 288}."""
+    par = streams(cfg)["serving"]
     out = []
-    for i in range(n_requests):
+    for k in range(n_surfaces):
         n = int(par.integers(n_min, n_max + 1))
         npch = int(par.choice(patches))
+        out.append(Surface(k, n, npch, n_types, int(par.integers(0, 2**31 - 1))))
+    return out
+
+
+def serving_stream(n_requests: int, rate_hz: float, n_surfaces: int, max_rhs: int = 32, cfg: int = 5):
+    """Poisson arrivals of solve requests on a catalogue of surfaces: surface
+    uniform, nrhs ~ U{1..max_rhs}, seeded incidence angles theta ~ U[0, 60 deg]
+    and polarisations.  Arrival times scale with 1 / rate_hz (the same draws
+    for every rate)."""
+    st = streams(cfg)
+    gaps = st["arrivals"].exponential(1.0, size=n_requests)
+    arr = np.cumsum(gaps) / rate_hz
+    par = st["test_blocks"]
+    out = []
+    for i in range(n_requests):
+        k = int(par.integers(0, n_surfaces))
         nrhs = int(par.integers(1, max_rhs + 1))
         th = par.uniform(0.0, math.radians(60.0), size=nrhs)
         pol = par.integers(0, 2, size=nrhs)
         ang = tuple((float(t), "TE" if q == 0 else "TM") for t, q in zip(th, pol))
-        out.append(Request(i, float(arr[i]), n, npch, nrhs, ang, int(par.integers(0, 2**31 - 1))))
+        out.append(Request(i, float(arr[i]), k, nrhs, ang))
     return out
