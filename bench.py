@@ -371,6 +371,20 @@ def main():
                 "GBs": round(2 * nbytes / (cms / 1e3) / 1e9, 1)}
         log(f"copy 2 GiB -> 2 GiB: {cms:.3f} ms, {copy['GBs']} GB/s")
         del a, c
+        # read-only reference: a device reduction over 8 GiB
+        big = torch.ones((8 << 30) // 8, dtype=torch.float64, device=dev)
+        for _ in range(2):
+            big.sum()
+        ev0.record()
+        for _ in range(5):
+            big.sum()
+        ev1.record()
+        torch.cuda.synchronize()
+        rms = ev0.elapsed_time(ev1) / 5
+        copy["read_8GiB_sum_ms"] = round(rms, 4)
+        copy["read_GBs"] = round((8 << 30) / (rms / 1e3) / 1e9, 1)
+        log(f"read 8 GiB (sum): {rms:.3f} ms, {copy['read_GBs']} GB/s")
+        del big
 
     multi = None
     if not args.no_multi:

@@ -194,7 +194,7 @@ emsurf_status emsurf_kernel_times(emsurf_plan plan, double* ms, int64_t* count);
  * right-hand sides per pass (n_eq a multiple of 32, at most 480, and at most
  * 4 wavefronts: ceil(n_eq / 32 / k) <= 4; best for many right-hand sides),
  * keeping 4 pairs of block columns in flight per wavefront; the _DEEP forms
- * keep 8 (more registers, longer latency cover).  FP64 applies always use the
+ * keep 6 (n_eq a multiple of 96) or 8 (more registers, longer latency cover).  FP64 applies always use the
  * GEMV form. */
 #define EMSURF_BP_AUTO (-1)
 #define EMSURF_BP_GEMV 0

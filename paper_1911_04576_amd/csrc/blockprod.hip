@@ -132,6 +132,14 @@ void launch_t(const void* That, const void* xh, void* yh, int n, int nrhs, int64
 // LDS for coalesced stores once every wave is done reading it.
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+// 8-byte non-temporal buffer load (out-of-range offsets read zero)
+__device__ __forceinline__ float2 ld_buf(__amdgpu_buffer_rsrc_t rs, unsigned voff, int soff) {
+  auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 2);
+  float2 f;
+  __builtin_memcpy(&f, &v, sizeof(f));
+  return f;
+}
+
 template <int TPW, int U>
 __global__ void __launch_bounds__(256) block_mfma_kernel(const float2* __restrict__ That,
                                                          const float2* __restrict__ xh, float2* __restrict__ yh,
@@ -160,19 +168,23 @@ __global__ void __launch_bounds__(256) block_mfma_kernel(const float2* __restric
   for (int i = 0; i < TPW; ++i)
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[i][e] = 0.f;
-  const float2* Ak = That + k * (long long)n * n;
-  // per-lane base: column h, row tile*32 + jl (a tile past the end re-reads
-  // tile 0 and its results are dropped)
-  const float2* abase[TPW];
+  // The frequency's block is read through a buffer resource: a uniform base,
+  // per-lane byte offsets that stay fixed (column h, row tile*32 + jl; a tile
+  // past the end re-reads tile 0 and its results are dropped) and a uniform
+  // per-step offset, which keeps address arithmetic out of the vector registers.
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(That + k * (long long)n * n), (short)0, n * n * (int)sizeof(float2), 0x00020000);
+  unsigned aoff[TPW];
 #pragma unroll
-  for (int i = 0; i < TPW; ++i) abase[i] = Ak + (long long)h * n + (tv[i] ? tile[i] * 32 : 0) + jl;
+  for (int i = 0; i < TPW; ++i) aoff[i] = (unsigned)((h * n + (tv[i] ? tile[i] * 32 : 0) + jl) * sizeof(float2));
+  const int step_bytes = 2 * n * (int)sizeof(float2);   // two block columns
   // first block columns are requested before the spectral columns are staged,
   // so the two latencies overlap
   float2 acur[U][TPW], anxt[U][TPW];
 #pragma unroll
   for (int st = 0; st < U; ++st)
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) acur[st][i] = ld_nt(abase[i] + (long long)(2 * st) * n);
+    for (int i = 0; i < TPW; ++i) acur[st][i] = ld_buf(rs, aoff[i], st * step_bytes);
   const float2* xk = xh + k * (long long)nrhs * n + (long long)r0 * n;
   for (int i = threadIdx.x; i < NR * n; i += blockDim.x) {
     const int r = i / n, v = i - r * n;
@@ -180,13 +192,13 @@ __global__ void __launch_bounds__(256) block_mfma_kernel(const float2* __restric
   }
   __syncthreads();
   for (int v0 = 0; v0 < n; v0 += 2 * U) {
-    const bool more = v0 + 2 * U < n;
-    if (more) {
+    // the last prefetch runs past the block: buffer loads out of range read 0
 #pragma unroll
-      for (int st = 0; st < U; ++st)
+    for (int st = 0; st < U; ++st)
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) anxt[st][i] = ld_nt(abase[i] + (long long)(v0 + 2 * U + 2 * st) * n);
-    }
+      for (int i = 0; i < TPW; ++i) anxt[st][i] = ld_buf(rs, aoff[i], (v0 / 2 + U + st) * step_bytes);
+    // keep the prefetch ahead of this step's MFMAs
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int st = 0; st < U; ++st) {
       const int v = v0 + 2 * st + h;
@@ -198,12 +210,10 @@ __global__ void __launch_bounds__(256) block_mfma_kernel(const float2* __restric
 #pragma unroll
       for (int i = 0; i < TPW; ++i) acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(acur[st][i].y, bim, acc[i], 0, 0, 0);
     }
-    if (more) {
 #pragma unroll
-      for (int st = 0; st < U; ++st)
+    for (int st = 0; st < U; ++st)
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) acur[st][i] = anxt[st][i];
-    }
+      for (int i = 0; i < TPW; ++i) acur[st][i] = anxt[st][i];
   }
   // stage outputs in LDS as [r][u] complex, then store the frequency's panel
   __syncthreads();
@@ -246,7 +256,8 @@ void launch_mfma(const void* That, const void* xh, void* yh, int n, int nrhs, in
 bool block_mfma_supported(int n, int nrhs) { return n % 32 == 0 && n >= 32 && n <= 480 && nrhs >= 1; }
 
 // variant 1..4: k = variant row tiles per wave, 4 K steps prefetched;
-// variant 5..8: k = variant - 4 row tiles per wave, 8 K steps prefetched
+// variant 5..8: k = variant - 4 row tiles per wave, 6 (n_eq % 96 == 0) or 8
+// K steps prefetched
 static int variant_tiles(int variant) { return variant <= BP_MFMA_T4 ? variant : variant - BP_MFMA_T4; }
 
 bool block_variant_supported(int variant, int n, int nrhs) {
@@ -274,10 +285,23 @@ void launch_block_product_variant(Cx t, int variant, const void* That, const voi
         case BP_MFMA_T2: launch_mfma<2, 4>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
         case BP_MFMA_T3: launch_mfma<3, 4>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
         case BP_MFMA_T4: launch_mfma<4, 4>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
-        case BP_MFMA_T1D: launch_mfma<1, 8>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
-        case BP_MFMA_T2D: launch_mfma<2, 8>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
-        case BP_MFMA_T3D: launch_mfma<3, 8>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
-        default: launch_mfma<4, 8>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
+        // deep prefetch: 6 steps when n_eq / 2 is a multiple of 6, else 8
+        case BP_MFMA_T1D:
+          if (n % 96 == 0) launch_mfma<1, 6>(That, xh, yh, n, nrhs, r0, nr, P, s);
+          else launch_mfma<1, 8>(That, xh, yh, n, nrhs, r0, nr, P, s);
+          break;
+        case BP_MFMA_T2D:
+          if (n % 96 == 0) launch_mfma<2, 6>(That, xh, yh, n, nrhs, r0, nr, P, s);
+          else launch_mfma<2, 8>(That, xh, yh, n, nrhs, r0, nr, P, s);
+          break;
+        case BP_MFMA_T3D:
+          if (n % 96 == 0) launch_mfma<3, 6>(That, xh, yh, n, nrhs, r0, nr, P, s);
+          else launch_mfma<3, 8>(That, xh, yh, n, nrhs, r0, nr, P, s);
+          break;
+        default:
+          if (n % 96 == 0) launch_mfma<4, 6>(That, xh, yh, n, nrhs, r0, nr, P, s);
+          else launch_mfma<4, 8>(That, xh, yh, n, nrhs, r0, nr, P, s);
+          break;
       }
     }
   }

@@ -124,7 +124,7 @@ void launch_block_product(Cx t, const void* That, const void* xh, void* yh, int 
 // Kernel variants of the FP32 product (FP64 always uses the lane-per-row GEMV):
 // BP_GEMV = lane-per-row streaming GEMV; BP_MFMA_Tk = MFMA GEMM with k row
 // tiles of 32 per wavefront (n_eq a multiple of 32, ceil(n_eq/32/k) <= 4),
-// 4 K steps of block columns in flight; BP_MFMA_TkD the same with 8.
+// 4 K steps of block columns in flight; BP_MFMA_TkD the same with 6 or 8.
 enum BpVariant {
   BP_GEMV = 0, BP_MFMA_T1 = 1, BP_MFMA_T2 = 2, BP_MFMA_T3 = 3, BP_MFMA_T4 = 4,
   BP_MFMA_T1D = 5, BP_MFMA_T2D = 6, BP_MFMA_T3D = 7, BP_MFMA_T4D = 8, BP_NVARIANTS = 9
