@@ -1,0 +1,197 @@
+// Fourier-domain block products on the matrix cores (Sec. IV-B): the
+// many-right-hand-side form of the per-frequency product
+//     yh[k][r][u] = sum_v That[k](u, v) xh[k][r][v]
+// in FP32.  The few-right-hand-side GEMV form and the dispatch between the two
+// live in blockprod.hip.
+#include "internal.h"
+
+namespace emsurf {
+namespace {
+
+// ----------------------------------------------------------------------------- MFMA path
+// Many right-hand sides make each frequency a small dense GEMM.  The complex
+// product y = A x is the real product of the interleaved block (n x 2n real,
+// column index 2v + re/im) with the 2n x 2nrhs real embedding of x:
+//   [Re y_r] = sum_v Ar Br - Ai Bi,   [Im y_r] = sum_v Ar Bi + Ai Br,
+// run on v_mfma_f32_32x32x2f32.  A lane supplies A[row][k] for one row of a
+// 32-row tile and one of two block columns per instruction; with the
+// column-major store ([v][u]) the wave's load of two columns x 32 rows is two
+// contiguous 256-byte runs, fed straight from HBM into operand registers
+// (double-buffered, non-temporal).  Each wave owns TPW row tiles (one group;
+// at most 4 waves) and 16 right-hand sides; the spectral columns sit in LDS
+// (rows padded to spread banks) and the outputs are staged through the same
+// LDS for coalesced stores once every wave is done reading it.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// 8-byte non-temporal buffer load; callers keep every offset inside the buffer
+__device__ __forceinline__ float2 ld_buf(__amdgpu_buffer_rsrc_t rs, unsigned voff, int soff) {
+  auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 2);
+  float2 f;
+  __builtin_memcpy(&f, &v, sizeof(f));
+  return f;
+}
+
+template <int TPW, int U>
+__global__ void __launch_bounds__(256) block_mfma_kernel(const float2* __restrict__ That,
+                                                         const float2* __restrict__ xh, float2* __restrict__ yh,
+                                                         int n, int nrhs, int r0, int nr) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float2* xs = reinterpret_cast<float2*>(smem_raw);     // [16][n + 1]
+  constexpr int NR = 16;
+  const int ld = n + 1;
+  const long long k = blockIdx.x;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5;
+  const int jl = lane & 31;
+  const int ntile = n >> 5;
+  const int rsel = jl >> 1;
+  const bool dimag = (jl & 1) != 0;
+  int tile[TPW];
+  bool tv[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    tile[i] = wave * TPW + i;
+    tv[i] = tile[i] < ntile;
+  }
+  floatx16 acc[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[i][e] = 0.f;
+  // The frequency's block is read through a buffer resource: a uniform base,
+  // per-lane byte offsets that stay fixed (column h, row tile*32 + jl; a tile
+  // past the end re-reads tile 0 and its results are dropped) and a uniform
+  // per-step offset, which keeps address arithmetic out of the vector registers.
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(That + k * (long long)n * n), (short)0, n * n * (int)sizeof(float2), 0x00020000);
+  unsigned aoff[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) aoff[i] = (unsigned)((h * n + (tv[i] ? tile[i] * 32 : 0) + jl) * sizeof(float2));
+  const int step_bytes = 2 * n * (int)sizeof(float2);   // two block columns
+  // first block columns are requested before the spectral columns are staged,
+  // so the two latencies overlap
+  float2 acur[U][TPW], anxt[U][TPW];
+#pragma unroll
+  for (int st = 0; st < U; ++st)
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) acur[st][i] = ld_buf(rs, aoff[i], st * step_bytes);
+  const float2* xk = xh + k * (long long)nrhs * n + (long long)r0 * n;
+  for (int i = threadIdx.x; i < NR * n; i += blockDim.x) {
+    const int r = i / n, v = i - r * n;
+    xs[r * ld + v] = (r < nr) ? xk[(long long)r * n + v] : float2{0.f, 0.f};
+  }
+  __syncthreads();
+  const int last_step = n / 2 - 1;
+  for (int v0 = 0; v0 < n; v0 += 2 * U) {
+    // the final prefetch would run past the block: its step index is clamped
+    // to the last column pair (a uniform min), so every load stays inside the
+    // block whatever the hardware range check covers; those values are unused
+#pragma unroll
+    for (int st = 0; st < U; ++st) {
+      const int step = v0 / 2 + U + st < last_step ? v0 / 2 + U + st : last_step;
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) anxt[st][i] = ld_buf(rs, aoff[i], step * step_bytes);
+    }
+    // keep the prefetch ahead of this step's MFMAs
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int st = 0; st < U; ++st) {
+      const int v = v0 + 2 * st + h;
+      const float2 xv = xs[rsel * ld + v];
+      const float bre = dimag ? xv.y : xv.x;
+      const float bim = dimag ? xv.x : -xv.y;
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(acur[st][i].x, bre, acc[i], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(acur[st][i].y, bim, acc[i], 0, 0, 0);
+    }
+#pragma unroll
+    for (int st = 0; st < U; ++st)
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) acur[st][i] = anxt[st][i];
+  }
+  // stage outputs in LDS as [r][u] complex, then store the frequency's panel
+  __syncthreads();
+  float* ysf = reinterpret_cast<float*>(xs);
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    if (!tv[i]) continue;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int u = tile[i] * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+      ysf[2 * (rsel * ld + u) + (dimag ? 1 : 0)] = acc[i][e];
+    }
+  }
+  __syncthreads();
+  float2* yk = yh + k * (long long)nrhs * n + (long long)r0 * n;
+  for (int i = threadIdx.x; i < nr * n; i += blockDim.x) {
+    const int r = i / n, u = i - r * n;
+    yk[(long long)r * n + u] = xs[r * ld + u];
+  }
+}
+
+// row-tile groups (= wavefronts) for TPW tiles per wave
+inline int mfma_waves(int n, int tpw) { return (n / 32 + tpw - 1) / tpw; }
+
+template <int TPW, int U>
+void launch_mfma(const void* That, const void* xh, void* yh, int n, int nrhs, int r0, int nr, int64_t P,
+                 hipStream_t s) {
+  const int waves = mfma_waves(n, TPW);
+  EMS_CHECK_ARG(waves >= 1 && waves <= 4, "MFMA variant needs at most 4 wavefronts per frequency");
+  EMS_CHECK_ARG((n / 2) % U == 0, "MFMA variant needs n_eq / 2 divisible by its prefetch depth");
+  const size_t shm = (size_t)16 * (n + 1) * sizeof(float2);
+  EMS_CHECK_ARG(shm <= 65536, "MFMA variant needs n_eq <= 480");
+  hipLaunchKernelGGL((block_mfma_kernel<TPW, U>), dim3((unsigned)P), dim3(64 * waves), shm, s,
+                     static_cast<const float2*>(That), static_cast<const float2*>(xh), static_cast<float2*>(yh), n,
+                     nrhs, r0, nr);
+}
+
+}  // namespace
+
+bool block_mfma_supported(int n, int nrhs) { return n % 32 == 0 && n >= 32 && n <= 480 && nrhs >= 1; }
+
+// variant 1..4: k = variant row tiles per wave, 4 K steps prefetched;
+// variant 5..8: k = variant - 4 row tiles per wave, 6 (n_eq % 96 == 0) or 8
+// K steps prefetched
+static int variant_tiles(int variant) { return variant <= BP_MFMA_T4 ? variant : variant - BP_MFMA_T4; }
+
+bool block_variant_supported(int variant, int n, int nrhs) {
+  if (variant == BP_GEMV) return true;
+  if (variant < BP_MFMA_T1 || variant >= BP_NVARIANTS || !block_mfma_supported(n, nrhs)) return false;
+  return mfma_waves(n, variant_tiles(variant)) <= 4;
+}
+
+void launch_block_mfma(int variant, const void* That, const void* xh, void* yh, int n, int nrhs, int64_t P,
+                       hipStream_t s) {
+  EMS_CHECK_ARG(block_variant_supported(variant, n, nrhs) && variant != BP_GEMV, "unsupported MFMA variant");
+  // 16 right-hand sides per pass
+  for (int r0 = 0; r0 < nrhs; r0 += 16) {
+    const int nr = nrhs - r0 < 16 ? nrhs - r0 : 16;
+    switch (variant) {
+      case BP_MFMA_T1: launch_mfma<1, 4>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
+      case BP_MFMA_T2: launch_mfma<2, 4>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
+      case BP_MFMA_T3: launch_mfma<3, 4>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
+      case BP_MFMA_T4: launch_mfma<4, 4>(That, xh, yh, n, nrhs, r0, nr, P, s); break;
+      // deep prefetch: 6 steps when n_eq / 2 is a multiple of 6, else 8
+      case BP_MFMA_T1D:
+        if (n % 96 == 0) launch_mfma<1, 6>(That, xh, yh, n, nrhs, r0, nr, P, s);
+        else launch_mfma<1, 8>(That, xh, yh, n, nrhs, r0, nr, P, s);
+        break;
+      case BP_MFMA_T2D:
+        if (n % 96 == 0) launch_mfma<2, 6>(That, xh, yh, n, nrhs, r0, nr, P, s);
+        else launch_mfma<2, 8>(That, xh, yh, n, nrhs, r0, nr, P, s);
+        break;
+      case BP_MFMA_T3D:
+        if (n % 96 == 0) launch_mfma<3, 6>(That, xh, yh, n, nrhs, r0, nr, P, s);
+        else launch_mfma<3, 8>(That, xh, yh, n, nrhs, r0, nr, P, s);
+        break;
+      default:
+        if (n % 96 == 0) launch_mfma<4, 6>(That, xh, yh, n, nrhs, r0, nr, P, s);
+        else launch_mfma<4, 8>(That, xh, yh, n, nrhs, r0, nr, P, s);
+        break;
+    }
+  }
+}
+
+}  // namespace emsurf

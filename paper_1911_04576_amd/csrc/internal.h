@@ -134,6 +134,10 @@ bool block_mfma_supported(int n, int nrhs);
 bool block_variant_supported(int variant, int n, int nrhs);
 void launch_block_product_variant(Cx t, int variant, const void* That, const void* xh, void* yh, int n, int nrhs,
                                   int64_t P, hipStream_t s);
+// FP32 MFMA variants only (blockprod_mfma.hip); ERR_ARG for a variant that
+// block_variant_supported rejects
+void launch_block_mfma(int variant, const void* That, const void* xh, void* yh, int n, int nrhs, int64_t P,
+                       hipStream_t s);
 
 // ----------------------------------------------------------------------------- S apply
 struct TypeTiles {
