@@ -22,6 +22,7 @@ namespace {
 // (rows padded to spread banks) and the outputs are staged through the same
 // LDS for coalesced stores once every wave is done reading it.
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
 
 // 8-byte non-temporal buffer load; callers keep every offset inside the buffer
 __device__ __forceinline__ float2 ld_buf(__amdgpu_buffer_rsrc_t rs, unsigned voff, int soff) {
@@ -124,10 +125,16 @@ __global__ void __launch_bounds__(256) block_mfma_kernel(const float2* __restric
     }
   }
   __syncthreads();
+  // the panel yk[r][u] (r < nr) is one contiguous run starting on an even
+  // element (n_eq is even): non-temporal 16-byte stores of element pairs,
+  // which never straddle two right-hand sides
   float2* yk = yh + k * (long long)nrhs * n + (long long)r0 * n;
-  for (int i = threadIdx.x; i < nr * n; i += blockDim.x) {
-    const int r = i / n, u = i - r * n;
-    yk[(long long)r * n + u] = xs[r * ld + u];
+  for (int i = threadIdx.x; i < nr * n / 2; i += blockDim.x) {
+    const int e = 2 * i;
+    const int r = e / n, u = e - r * n;
+    const float2 p0 = xs[r * ld + u], p1 = xs[r * ld + u + 1];
+    const fvec4 v = {p0.x, p0.y, p1.x, p1.y};
+    __builtin_nontemporal_store(v, reinterpret_cast<fvec4*>(yk + e));
   }
 }
 
