@@ -101,6 +101,9 @@ extern "C" emsurf_status emsurf_plan_autotune(emsurf_plan plan, int32_t nrhs, do
     const int n = plan->d.n_eq;
     EMS_HIP(hipEventCreate(&e0));
     EMS_HIP(hipEventCreate(&e1));
+    // time every candidate on the same defined input (the spectral workspace
+    // may hold anything, including values that slow the arithmetic)
+    EMS_HIP(hipMemsetAsync(w.X.p, 0, w.X.bytes, s));
     int best = BP_GEMV;
     double best_ms = 1e300;
     for (int v = 0; v < BP_NVARIANTS; ++v) {
