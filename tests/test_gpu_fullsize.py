@@ -1,0 +1,117 @@
+"""Full-size GPU parity on sampled outputs: the 32x32, 64x64 and 128x128
+lattices at their benchmark shapes, in the launch configuration bench.py times
+(default stream; the heuristic kernel for 4 RHS, the autotuned kernel for 16),
+checked element by element against the oracle's on-the-fly row evaluation
+(every block of the sampled row regenerated in FP64, no FFT).
+
+Bars: FP64 1e-12 and FP32 2e-5 relative per sampled element (normwise over its
+unknowns and right-hand sides); the FP32 + FP64-refinement solve must reach its
+1e-6 tolerance, and the oracle's residual at sampled elements must agree."""
+import numpy as np
+import pytest
+
+import workload as W
+from oracle import coupling as C
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 2e-5
+
+
+def E():
+    import paper_1911_04576_amd as mod
+    mod.lib()
+    return mod
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def build(cfg_id):
+    e = E()
+    c = W.config(cfg_id)
+    g = W.box_geometry(c.n_patch)
+    S, tm = W.s_types(c), W.type_map(c)
+    geom = e.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)
+    plan = e.emsurf_plan_create_green(c.nx, c.ny, c.n_types, c.nrhs, geom, S, tm)
+    return e, c, g, S, tm, plan
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def sampled_rows(c, g, x, elems):
+    return C.apply_T_elements(g.rho, g.area, g.tan, W.PITCH, W.K0, x, elems, chunk_rows=8)
+
+
+@pytest.mark.parametrize("cfg_id,elems", [
+    (2, [(0, 0), (11, 20), (31, 31)]),
+    (4, [(0, 127), (42, 64)]),
+])
+def test_fullsize_apply_T_sampled(cfg_id, elems):
+    e, c, g, S, tm, plan = build(cfg_id)
+    say(f"full-size apply_T: {c.nx}x{c.ny}, n_eq {c.n_eq}, {c.nrhs} RHS, elements {elems}")
+    b = W.plane_wave_rhs(c, g)
+    b64 = torch.from_numpy(b).to("cuda")
+    y64 = torch.empty_like(b64)
+    e.emsurf_apply_T(plan, e.EMSURF_FP64, c.nrhs, b64, y64)
+    x32 = b64.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    e.emsurf_apply_T(plan, e.EMSURF_FP32, c.nrhs, x32, y32)
+    torch.cuda.synchronize()
+    ref = sampled_rows(c, g, b, elems)                      # [e][r][n]
+    got64 = y64.cpu().numpy()
+    got32 = y32.cpu().numpy().astype(np.complex128)
+    for i, (iy, ix) in enumerate(elems):
+        e64 = rel(got64[:, iy, ix], ref[i])
+        e32 = rel(got32[:, iy, ix], ref[i])
+        say(f"  element ({iy},{ix}): FP64 {e64:.2e}, FP32 {e32:.2e}")
+        assert e64 <= FP64_TOL
+        assert e32 <= FP32_TOL
+    plan.destroy()
+
+
+def test_fullsize_64x64_multi_rhs_autotuned():
+    e, c, g, S, tm, plan = build(3)
+    best, ms = e.emsurf_plan_autotune(plan, c.nrhs)
+    say(f"full-size multi-RHS: {c.nx}x{c.ny}, n_eq {c.n_eq}, {c.nrhs} RHS, kernel {e.BP_NAMES[best]}")
+    assert best != 0, "16 RHS at n_eq 288 should run on the matrix cores"
+    b = W.plane_wave_rhs(c, g)
+    x32 = torch.from_numpy(b).to("cuda").to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    e.emsurf_apply_T(plan, e.EMSURF_FP32, c.nrhs, x32, y32)
+    torch.cuda.synchronize()
+    elems = [(63, 0), (21, 40)]
+    ref = sampled_rows(c, g, b, elems)
+    got = y32.cpu().numpy().astype(np.complex128)
+    for i, (iy, ix) in enumerate(elems):
+        err = rel(got[:, iy, ix], ref[i])
+        say(f"  element ({iy},{ix}): FP32 {err:.2e}")
+        assert err <= FP32_TOL
+    plan.destroy()
+
+
+def test_fullsize_128x128_fp32_ir_solve_sampled_residual():
+    e, c, g, S, tm, plan = build(4)
+    say(f"full-size FP32+IR solve: {c.nx}x{c.ny}, n_eq {c.n_eq}, {c.nrhs} RHS, tol {c.tol}")
+    b = W.plane_wave_rhs(c, g)
+    b64 = torch.from_numpy(b).to("cuda")
+    x = torch.zeros_like(b64)
+    st, info = e.emsurf_solve(plan, e.solve_opts(e.EMSURF_FP32_IR, tol=c.tol), c.nrhs, b64, x)
+    torch.cuda.synchronize()
+    say(f"  status {e.emsurf_status_str(st)}, {info}")
+    assert st == e.EMSURF_OK
+    assert all(i["converged"] and i["rel_res_true"] <= c.tol for i in info)
+    xs = x.cpu().numpy()
+    elems = [(5, 77), (127, 0)]
+    tx = sampled_rows(c, g, xs, elems)                       # (T x) at the sampled elements
+    for i, (iy, ix) in enumerate(elems):
+        Ax = xs[:, iy, ix] - tx[i] @ S[tm[iy, ix]].T        # (x - S T x) at the element
+        r = rel(Ax, b[:, iy, ix])
+        say(f"  element ({iy},{ix}): oracle residual {r:.2e}")
+        assert r <= 50 * c.tol
+    plan.destroy()
