@@ -71,12 +71,26 @@ typedef enum {
 
 typedef struct emsurf_plan_s* emsurf_plan;
 
+/* Form of the coupling operator a plan holds.
+ *  EMSURF_T_DENSE: opaque dense n_eq x n_eq blocks T(d).
+ *  EMSURF_T_LK:    the outer operator in the paper's structured form (eq.
+ *                  (blockZo) with eqs. (SIE_TEFIE1_Outer)/(SIE_TMFIE1_Outer)):
+ *                  T(d) = [[a L(d), b K(d)], [c K(d), e L(d)]] with the
+ *                  discretised L and K operators (n_h x n_h, n_h = n_eq / 2,
+ *                  J unknowns first) shared by the four quadrants; the plan
+ *                  stores the Fourier transforms of L and K only, the storage
+ *                  of Sec. IV-C (half the bytes of dense blocks). */
+#define EMSURF_T_DENSE 0
+#define EMSURF_T_LK 1
+
 typedef struct {
   int32_t nx, ny;      /* lattice size, 1..512 each */
-  int32_t n_eq;        /* unknowns per element, 1 <= n_eq <= 512 */
+  int32_t n_eq;        /* unknowns per element, 1 <= n_eq <= 512 (even for EMSURF_T_LK) */
   int32_t n_types;     /* number of macromodel cell types, >= 1 */
   int32_t max_rhs;     /* largest nrhs any apply or solve on this plan uses, 1..64 */
   uint32_t store;      /* EMSURF_STORE_* mask, non-zero */
+  int32_t form;        /* EMSURF_T_DENSE (0) or EMSURF_T_LK (1) */
+  double coef[8];      /* EMSURF_T_LK: a, b, c, e as (re, im) pairs, finite; ignored for dense */
 } emsurf_plan_desc;
 
 /* Geometry of one box for the synthetic point-sampled coupling fill: the
@@ -113,7 +127,7 @@ typedef struct {
 } emsurf_solve_info;
 
 typedef struct {
-  int32_t Lx, Ly;           /* padded FFT lengths (>= 2n-1, powers of two) */
+  int32_t Lx, Ly;           /* padded FFT lengths (>= 2n-1, of the form 2^a or 3 * 2^a) */
   int64_t n_freq;           /* Lx * Ly */
   size_t bytes_that64;      /* FP64 Fourier-domain store, 0 if absent */
   size_t bytes_that32;      /* FP32 store, 0 if absent */
@@ -127,7 +141,9 @@ size_t emsurf_plan_bytes(const emsurf_plan_desc* desc);
 
 /* Build a plan from caller-supplied coupling blocks (Sec. IV-B: circulant
  * embedding of every block, kernel FFT, products later in the Fourier domain).
- *   T_blocks    c128 [2ny-1][2nx-1][n_eq][n_eq] (layout above); host memory if
+ *   T_blocks    EMSURF_T_DENSE: c128 [2ny-1][2nx-1][n_eq][n_eq] (layout above);
+ *               EMSURF_T_LK: c128 [2ny-1][2nx-1][2][n_h][n_h], L(d) then K(d)
+ *               for each offset, row = test, column = source.  Host memory if
  *               T_is_device == 0, device memory otherwise.  Read during the
  *               call only; the caller keeps ownership.
  *   S_types     host c128 [n_types][n_eq][n_eq], row-major, y_u = sum_v S[u][v] x_v.
@@ -139,7 +155,9 @@ emsurf_status emsurf_plan_create(const emsurf_plan_desc* desc, const void* T_blo
 
 /* Build a plan whose coupling blocks are the synthetic point-sampled fill of
  * `geom`, computed on the device straight into the padded kernel layout (no
- * [2ny-1][2nx-1] intermediate).  desc->n_eq must equal 4 * geom->n_patch. */
+ * [2ny-1][2nx-1] intermediate).  desc->n_eq must equal 4 * geom->n_patch.
+ * EMSURF_T_DENSE uses the scalar fill described at emsurf_geom; EMSURF_T_LK
+ * the structured fill described at emsurf_fill_LK_point_green. */
 emsurf_status emsurf_plan_create_green(const emsurf_plan_desc* desc, const emsurf_geom* geom,
                                        const void* S_types, const int32_t* elem_type, void* stream,
                                        emsurf_plan* out);
@@ -148,6 +166,16 @@ emsurf_status emsurf_plan_create_green(const emsurf_plan_desc* desc, const emsur
  * into T_blocks_dev (c128 [2ny-1][2nx-1][n_eq][n_eq], caller-allocated, device). */
 emsurf_status emsurf_fill_T_point_green(const emsurf_geom* geom, int32_t nx, int32_t ny,
                                         void* T_blocks_dev, void* stream);
+
+/* Write the synthetic structured blocks of `geom` (outer operator of Sec.
+ * III-B, point-matched at the test patch centre, one-point quadrature over
+ * the source patch, R = rho_p - rho_q + pitch (dx, dy, 0), g = exp(-jkR)/(4 pi R)):
+ *     L(d)[(p,a),(q,b)] = A_q t_pa . (I + grad grad / k^2) g(R) . t_qb
+ *     K(d)[(p,a),(q,b)] = A_q t_pa . (grad g(R) x t_qb),   L(0) = K(0) = 0,
+ * local index 2p + a, into LK_blocks_dev (c128 [2ny-1][2nx-1][2][n_h][n_h],
+ * n_h = 2 * n_patch, caller-allocated, device). */
+emsurf_status emsurf_fill_LK_point_green(const emsurf_geom* geom, int32_t nx, int32_t ny,
+                                         void* LK_blocks_dev, void* stream);
 
 /* y = T x over nrhs right-hand sides (1 <= nrhs <= max_rhs).  x_dev and y_dev
  * are c128 for EMSURF_FP64 and c64 for EMSURF_FP32, [nrhs][ny][nx][n_eq]; they

@@ -95,3 +95,24 @@ def lk_assemble(L: np.ndarray, K: np.ndarray, coef) -> np.ndarray:
     top = np.concatenate([a * L, b * K], axis=-1)
     bot = np.concatenate([c * K, e * L], axis=-1)
     return np.concatenate([top, bot], axis=-2)
+
+
+def apply_T_elements_lk(rho, area, tan, pitch: float, k: float, coef, x: np.ndarray, elems, chunk_rows: int = 1):
+    """Rows of y = T x at sampled output elements, every L and K block of the
+    row generated on the fly and assembled into [[a L, b K], [c K, e L]]:
+    y[m] = sum_{m'} T(m - m') x[m'].  x: [nrhs][ny][nx][n_eq]; returns
+    complex128 [len(elems)][nrhs][n_eq]."""
+    nrhs, ny, nx, n = x.shape
+    out = np.zeros((len(elems), nrhs, n), dtype=np.complex128)
+    jx = np.arange(nx)
+    for e, (iy, ix) in enumerate(elems):
+        acc = np.zeros((nrhs, n), dtype=np.complex128)
+        for jy0 in range(0, ny, chunk_rows):
+            jys = np.arange(jy0, min(ny, jy0 + chunk_rows))
+            offs = np.stack(np.broadcast_arrays((iy - jys)[:, None], (ix - jx)[None, :]), axis=-1).reshape(-1, 2)
+            L, K = lk_blocks_at(rho, area, tan, offs, pitch, k)
+            blk = lk_assemble(L, K, coef)                                  # [o][n][n]
+            src = x[:, jys, :, :].reshape(nrhs, -1, n)                     # [r][o][n]
+            acc += np.einsum("ouv,rov->ru", blk, src)
+        out[e] = acc
+    return out

@@ -32,6 +32,9 @@ EMSURF_FP32_IR = 2
 EMSURF_STORE_FP64 = 1
 EMSURF_STORE_FP32 = 2
 
+EMSURF_T_DENSE = 0
+EMSURF_T_LK = 1
+
 EMSURF_BP_AUTO = -1
 EMSURF_BP_GEMV = 0
 EMSURF_BP_MFMA_T1 = 1
@@ -61,7 +64,8 @@ class EmsurfError(RuntimeError):
 
 class emsurf_plan_desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("n_eq", ctypes.c_int32),
-                ("n_types", ctypes.c_int32), ("max_rhs", ctypes.c_int32), ("store", ctypes.c_uint32)]
+                ("n_types", ctypes.c_int32), ("max_rhs", ctypes.c_int32), ("store", ctypes.c_uint32),
+                ("form", ctypes.c_int32), ("coef", ctypes.c_double * 8)]
 
 
 class emsurf_geom(ctypes.Structure):
@@ -105,6 +109,7 @@ _SIGS = {
     "emsurf_plan_create_green": (ctypes.c_int, [ctypes.POINTER(emsurf_plan_desc), ctypes.POINTER(emsurf_geom), _P,
                                                 _P, _P, ctypes.POINTER(_P)]),
     "emsurf_fill_T_point_green": (ctypes.c_int, [ctypes.POINTER(emsurf_geom), ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "emsurf_fill_LK_point_green": (ctypes.c_int, [ctypes.POINTER(emsurf_geom), ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "emsurf_apply_T": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
     "emsurf_apply_S": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
     "emsurf_apply_A": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
@@ -230,19 +235,27 @@ class Plan:
         return emsurf_plan_query(self)
 
 
-def _desc(nx, ny, n_eq, n_types, max_rhs, store):
-    return emsurf_plan_desc(int(nx), int(ny), int(n_eq), int(n_types), int(max_rhs), int(store))
+def _desc(nx, ny, n_eq, n_types, max_rhs, store, form=EMSURF_T_DENSE, coef=None):
+    """coef: the four complex constants (a, b, c, e) of EMSURF_T_LK."""
+    c8 = (ctypes.c_double * 8)()
+    if coef is not None:
+        for i, z in enumerate(coef):
+            c8[2 * i], c8[2 * i + 1] = complex(z).real, complex(z).imag
+    return emsurf_plan_desc(int(nx), int(ny), int(n_eq), int(n_types), int(max_rhs), int(store), int(form), c8)
 
 
-def emsurf_plan_bytes(nx, ny, n_eq, n_types, max_rhs, store=EMSURF_STORE_FP64 | EMSURF_STORE_FP32) -> int:
-    d = _desc(nx, ny, n_eq, n_types, max_rhs, store)
+def emsurf_plan_bytes(nx, ny, n_eq, n_types, max_rhs, store=EMSURF_STORE_FP64 | EMSURF_STORE_FP32,
+                      form=EMSURF_T_DENSE) -> int:
+    d = _desc(nx, ny, n_eq, n_types, max_rhs, store, form, (0, 0, 0, 0) if form == EMSURF_T_LK else None)
     return int(lib().emsurf_plan_bytes(ctypes.byref(d)))
 
 
 def emsurf_plan_create(nx, ny, n_eq, n_types, max_rhs, T_blocks, S_types, elem_type,
-                       store=EMSURF_STORE_FP64 | EMSURF_STORE_FP32, stream=None) -> Plan:
-    """T_blocks: numpy complex128 [2ny-1][2nx-1][n][n] (host) or a device tensor."""
-    d = _desc(nx, ny, n_eq, n_types, max_rhs, store)
+                       store=EMSURF_STORE_FP64 | EMSURF_STORE_FP32, stream=None, form=EMSURF_T_DENSE,
+                       coef=None) -> Plan:
+    """T_blocks: numpy complex128 [2ny-1][2nx-1][n][n] (dense) or [2ny-1][2nx-1][2][n/2][n/2]
+    (EMSURF_T_LK: L then K), host array or device tensor."""
+    d = _desc(nx, ny, n_eq, n_types, max_rhs, store, form, coef)
     if isinstance(T_blocks, np.ndarray):
         tb, ptb = _host(T_blocks, np.complex128)
         is_dev = 0
@@ -256,8 +269,9 @@ def emsurf_plan_create(nx, ny, n_eq, n_types, max_rhs, T_blocks, S_types, elem_t
 
 
 def emsurf_plan_create_green(nx, ny, n_types, max_rhs, geom: Geometry, S_types, elem_type,
-                             store=EMSURF_STORE_FP64 | EMSURF_STORE_FP32, stream=None) -> Plan:
-    d = _desc(nx, ny, 4 * geom.n_patch, n_types, max_rhs, store)
+                             store=EMSURF_STORE_FP64 | EMSURF_STORE_FP32, stream=None, form=EMSURF_T_DENSE,
+                             coef=None) -> Plan:
+    d = _desc(nx, ny, 4 * geom.n_patch, n_types, max_rhs, store, form, coef)
     S, pS = _host(S_types, np.complex128)
     et, pet = _host(elem_type, np.int32)
     out = ctypes.c_void_p()
@@ -269,6 +283,11 @@ def emsurf_plan_create_green(nx, ny, n_types, max_rhs, geom: Geometry, S_types, 
 def emsurf_fill_T_point_green(geom: Geometry, nx, ny, T_blocks_dev, stream=None):
     _check(lib().emsurf_fill_T_point_green(ctypes.byref(geom.c), int(nx), int(ny), _dptr(T_blocks_dev),
                                            _stream(stream)))
+
+
+def emsurf_fill_LK_point_green(geom: Geometry, nx, ny, LK_blocks_dev, stream=None):
+    _check(lib().emsurf_fill_LK_point_green(ctypes.byref(geom.c), int(nx), int(ny), _dptr(LK_blocks_dev),
+                                            _stream(stream)))
 
 
 def emsurf_apply_T(plan: Plan, prec, nrhs, x_dev, y_dev, stream=None):

@@ -1,12 +1,15 @@
 // Plan-time kernels: circulant embedding of the coupling blocks (Sec. IV-B,
 // eq. (LJV3): block T(d) goes to padded slot d mod L on each lattice axis, all
-// other slots stay zero), the synthetic point-sampled coupling fill, and the
+// other slots stay zero), the synthetic point-sampled coupling fills (dense
+// blocks, or the L and K operators of the structured form), and the
 // scatter of transformed kernel columns into the resident Fourier-domain
 // store (FP64 and/or FP32 rounded to nearest).
 //
-// The padded kernel chunk holds columns c in [c0, c0 + nc) of the n*n batch,
-// c = v*n + u (source v, test u), as a dense [Ly][Lx][nc] array, so that after
-// the 2-D transform every frequency's block is stored column-major.
+// The padded kernel chunk holds columns c in [c0, c0 + nc) of the per-frequency
+// batch, c = v*n + u (source v, test u) for dense blocks and
+// c = part*n_h^2 + v*n_h + u for the structured form (part 0 = L, 1 = K), as a
+// dense [Ly][Lx][nc] array, so that after the 2-D transform every frequency's
+// blocks are stored column-major.
 #include "internal.h"
 
 namespace emsurf {
@@ -19,9 +22,14 @@ __device__ __forceinline__ int slot_to_offset(int s, int L, int N, bool* ok) {
   return 0;
 }
 
-__global__ void pad_blocks_kernel(const double2* __restrict__ Tb, int nx, int ny, int n, int Lx, int Ly,
+// Caller blocks hold `parts` square nb x nb matrices per offset, row-major
+// (row = test, column = source): parts = 1, nb = n_eq for dense blocks;
+// parts = 2 (L then K), nb = n_h for the structured operator.  Kernel column
+// c = part * nb^2 + v * nb + u.
+__global__ void pad_blocks_kernel(const double2* __restrict__ Tb, int nx, int ny, int nb, int parts, int Lx, int Ly,
                                   long long c0, long long nc, double2* __restrict__ K) {
   const long long total = (long long)Ly * Lx * nc;
+  const long long nbb = (long long)nb * nb;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
     const long long j = i % nc;
@@ -33,9 +41,11 @@ __global__ void pad_blocks_kernel(const double2* __restrict__ Tb, int nx, int ny
     double2 val{0.0, 0.0};
     if (okx && oky) {
       const long long c = c0 + j;
-      const int v = (int)(c / n), u = (int)(c - (long long)v * n);
+      const long long part = c / nbb;
+      const long long rem = c - part * nbb;
+      const int v = (int)(rem / nb), u = (int)(rem - (long long)v * nb);
       const long long blk = (long long)(dy + ny - 1) * (2 * nx - 1) + (dx + nx - 1);
-      val = Tb[blk * n * n + (long long)u * n + v];
+      val = Tb[(blk * parts + part) * nbb + (long long)u * nb + v];
     }
     K[i] = val;
   }
@@ -63,6 +73,49 @@ __device__ __forceinline__ double2 green_entry(const double* __restrict__ rho, c
   sincos(k * R, &sn, &cs);
   const double w = dot * area[q] / (4.0 * 3.14159265358979323846 * R);
   return double2{w * cs, -w * sn};
+}
+
+// Structured fill (outer EFIE/MFIE operators, Sec. III-B), local index 2p + a:
+//   part 0: L = A_q t_pa . (I + grad grad / k^2) g(R) . t_qb
+//   part 1: K = A_q t_pa . (grad g(R) x t_qb)
+// with R = rho_p - rho_q + pitch (dx, dy, 0) and g = exp(-jkR)/(4 pi R); the
+// radial derivatives g' = -(jk + 1/R) g and g'' = ((jk + 1/R)^2 + 1/R^2) g
+// give grad g = g' Rhat and grad grad g = g'' Rhat Rhat + (g'/R)(I - Rhat Rhat).
+__device__ __forceinline__ double2 lk_entry(const double* __restrict__ rho, const double* __restrict__ area,
+                                            const double* __restrict__ tan, double pitch, double k, int dx,
+                                            int dy, int part, int u, int v) {
+  if (dx == 0 && dy == 0) return double2{0.0, 0.0};
+  const int p = u >> 1, a = u & 1, q = v >> 1, b = v & 1;
+  const double* tp = tan + (p * 2 + a) * 3;
+  const double* tq = tan + (q * 2 + b) * 3;
+  const double ex = rho[3 * p + 0] - rho[3 * q + 0] + pitch * dx;
+  const double ey = rho[3 * p + 1] - rho[3 * q + 1] + pitch * dy;
+  const double ez = rho[3 * p + 2] - rho[3 * q + 2];
+  const double R = sqrt(ex * ex + ey * ey + ez * ez);
+  const double iR = 1.0 / R;
+  const double hx = ex * iR, hy = ey * iR, hz = ez * iR;
+  double sn, cs;
+  sincos(k * R, &sn, &cs);
+  const double g0 = iR / (4.0 * 3.14159265358979323846);
+  const double gr = g0 * cs, gi = -g0 * sn;                         // g
+  // g' = -(1/R + jk) g
+  const double g1r = -(iR * gr - k * gi), g1i = -(iR * gi + k * gr);
+  const double Aq = area[q];
+  if (part == 1) {
+    // t_p . (Rhat x t_q)
+    const double cx = hy * tq[2] - hz * tq[1], cy = hz * tq[0] - hx * tq[2], cz = hx * tq[1] - hy * tq[0];
+    const double trip = tp[0] * cx + tp[1] * cy + tp[2] * cz;
+    return double2{Aq * trip * g1r, Aq * trip * g1i};
+  }
+  // g'' = ((1/R + jk)^2 + 1/R^2) g = (2/R^2 - k^2 + 2jk/R) g
+  const double wr = 2.0 * iR * iR - k * k, wi = 2.0 * k * iR;
+  const double g2r = wr * gr - wi * gi, g2i = wr * gi + wi * gr;
+  const double ik2 = 1.0 / (k * k);
+  const double isor = gr + g1r * iR * ik2, isoi = gi + g1i * iR * ik2;     // g + g'/(k^2 R)
+  const double radr = (g2r - g1r * iR) * ik2, radi = (g2i - g1i * iR) * ik2;  // (g'' - g'/R)/k^2
+  const double tt = tp[0] * tq[0] + tp[1] * tq[1] + tp[2] * tq[2];
+  const double pr = (tp[0] * hx + tp[1] * hy + tp[2] * hz) * (tq[0] * hx + tq[1] * hy + tq[2] * hz);
+  return double2{Aq * (isor * tt + radr * pr), Aq * (isoi * tt + radi * pr)};
 }
 
 __global__ void green_padded_kernel(const double* __restrict__ rho, const double* __restrict__ area,
@@ -105,6 +158,51 @@ __global__ void green_blocks_kernel(const double* __restrict__ rho, const double
   }
 }
 
+__global__ void lk_padded_kernel(const double* __restrict__ rho, const double* __restrict__ area,
+                                 const double* __restrict__ tan, int P, double pitch, double k, int nx, int ny,
+                                 int Lx, int Ly, long long c0, long long nc, double2* __restrict__ K) {
+  const int nh = 2 * P;
+  const long long nhh = (long long)nh * nh;
+  const long long total = (long long)Ly * Lx * nc;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long j = i % nc;
+    const long long sxy = i / nc;
+    const int sx = (int)(sxy % Lx), sy = (int)(sxy / Lx);
+    bool okx, oky;
+    const int dx = slot_to_offset(sx, Lx, nx, &okx);
+    const int dy = slot_to_offset(sy, Ly, ny, &oky);
+    double2 val{0.0, 0.0};
+    if (okx && oky) {
+      const long long c = c0 + j;
+      const int part = (int)(c / nhh);
+      const long long rem = c - part * nhh;
+      const int v = (int)(rem / nh), u = (int)(rem - (long long)v * nh);
+      val = lk_entry(rho, area, tan, pitch, k, dx, dy, part, u, v);
+    }
+    K[i] = val;
+  }
+}
+
+__global__ void lk_blocks_kernel(const double* __restrict__ rho, const double* __restrict__ area,
+                                 const double* __restrict__ tan, int P, double pitch, double k, int nx, int ny,
+                                 double2* __restrict__ Tb) {
+  const int nh = 2 * P;
+  const long long nhh = (long long)nh * nh;
+  const long long total = (long long)(2 * ny - 1) * (2 * nx - 1) * 2 * nhh;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long blk = i / (2 * nhh);
+    const long long r2 = i - blk * 2 * nhh;
+    const int part = (int)(r2 / nhh);
+    const int rem = (int)(r2 - part * nhh);
+    const int u = rem / nh, v = rem - u * nh;
+    const int dx = (int)(blk % (2 * nx - 1)) - (nx - 1);
+    const int dy = (int)(blk / (2 * nx - 1)) - (ny - 1);
+    Tb[i] = lk_entry(rho, area, tan, pitch, k, dx, dy, part, u, v);
+  }
+}
+
 __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, long long nn, long long c0,
                                    long long nc, double2* __restrict__ t64, float2* __restrict__ t32) {
   const long long total = P * nc;
@@ -135,12 +233,12 @@ unsigned grid_for(long long total, int threads) {
 
 }  // namespace
 
-void launch_pad_blocks(const void* T_blocks_dev, int nx, int ny, int n, int Lx, int Ly, int64_t c0, int64_t nc,
-                       void* K, hipStream_t s) {
+void launch_pad_blocks(const void* T_blocks_dev, int nx, int ny, int nb, int parts, int Lx, int Ly, int64_t c0,
+                       int64_t nc, void* K, hipStream_t s) {
   const long long total = (long long)Ly * Lx * nc;
   hipLaunchKernelGGL(pad_blocks_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s,
-                     static_cast<const double2*>(T_blocks_dev), nx, ny, n, Lx, Ly, (long long)c0, (long long)nc,
-                     static_cast<double2*>(K));
+                     static_cast<const double2*>(T_blocks_dev), nx, ny, nb, parts, Lx, Ly, (long long)c0,
+                     (long long)nc, static_cast<double2*>(K));
   EMS_LAUNCH_CHECK();
 }
 
@@ -150,6 +248,24 @@ void launch_green_padded(const GreenGeomDev& g, int nx, int ny, int Lx, int Ly, 
   hipLaunchKernelGGL(green_padded_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, g.rho.as<const double>(),
                      g.area.as<const double>(), g.tan.as<const double>(), g.n_patch, g.pitch, g.k, nx, ny, Lx, Ly,
                      (long long)c0, (long long)nc, static_cast<double2*>(K));
+  EMS_LAUNCH_CHECK();
+}
+
+void launch_lk_padded(const GreenGeomDev& g, int nx, int ny, int Lx, int Ly, int64_t c0, int64_t nc, void* K,
+                      hipStream_t s) {
+  const long long total = (long long)Ly * Lx * nc;
+  hipLaunchKernelGGL(lk_padded_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, g.rho.as<const double>(),
+                     g.area.as<const double>(), g.tan.as<const double>(), g.n_patch, g.pitch, g.k, nx, ny, Lx, Ly,
+                     (long long)c0, (long long)nc, static_cast<double2*>(K));
+  EMS_LAUNCH_CHECK();
+}
+
+void launch_lk_blocks(const GreenGeomDev& g, int nx, int ny, void* LK_blocks, hipStream_t s) {
+  const long long nh = 2LL * g.n_patch;
+  const long long total = (long long)(2 * ny - 1) * (2 * nx - 1) * 2 * nh * nh;
+  hipLaunchKernelGGL(lk_blocks_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, g.rho.as<const double>(),
+                     g.area.as<const double>(), g.tan.as<const double>(), g.n_patch, g.pitch, g.k, nx, ny,
+                     static_cast<double2*>(LK_blocks));
   EMS_LAUNCH_CHECK();
 }
 

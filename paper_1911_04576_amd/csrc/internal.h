@@ -134,6 +134,12 @@ bool block_mfma_supported(int n, int nrhs);
 bool block_variant_supported(int variant, int n, int nrhs);
 void launch_block_product_variant(Cx t, int variant, const void* That, const void* xh, void* yh, int n, int nrhs,
                                   int64_t P, hipStream_t s);
+// Structured outer operator (EMSURF_T_LK): That per frequency holds L then K,
+// each n_h x n_h column-major ([k][2][v][u]);
+//   yh[k][r][u] = a L xJ + b K xM (u < n_h),  yh[k][r][n_h + u] = c K xJ + e L xM,
+// xJ = xh[k][r][0:n_h], xM = xh[k][r][n_h:2 n_h]; coef = (a, b, c, e) as (re, im).
+void launch_block_product_lk(Cx t, const void* That, const void* xh, void* yh, int nh, int nrhs, int64_t P,
+                             const double* coef, hipStream_t s);
 // FP32 MFMA variants only (blockprod_mfma.hip); ERR_ARG for a variant that
 // block_variant_supported rejects
 void launch_block_mfma(int variant, const void* That, const void* xh, void* yh, int n, int nrhs, int64_t P,
@@ -158,8 +164,13 @@ struct GreenGeomDev {
   int n_patch = 0;
   double pitch = 0, k = 0;
 };
-void launch_pad_blocks(const void* T_blocks_dev, int nx, int ny, int n, int Lx, int Ly, int64_t c0, int64_t nc,
-                       void* K, hipStream_t s);
+// caller blocks: `parts` row-major nb x nb matrices per offset (1 x n_eq dense; 2 x n_h for L, K)
+void launch_pad_blocks(const void* T_blocks_dev, int nx, int ny, int nb, int parts, int Lx, int Ly, int64_t c0,
+                       int64_t nc, void* K, hipStream_t s);
+// structured (L, K) fill into the padded layout / into [2ny-1][2nx-1][2][n_h][n_h]
+void launch_lk_padded(const GreenGeomDev& g, int nx, int ny, int Lx, int Ly, int64_t c0, int64_t nc, void* K,
+                      hipStream_t s);
+void launch_lk_blocks(const GreenGeomDev& g, int nx, int ny, void* LK_blocks, hipStream_t s);
 void launch_green_padded(const GreenGeomDev& g, int nx, int ny, int Lx, int Ly, int64_t c0, int64_t nc, void* K,
                          hipStream_t s);
 void launch_green_blocks(const GreenGeomDev& g, int nx, int ny, void* T_blocks, hipStream_t s);
@@ -218,4 +229,10 @@ void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* 
 void apply_A_typed(emsurf_plan p, Cx tx, Cx tc, Cx ty, int nrhs, const void* x, void* y, hipStream_t s,
                    int variant = -1);
 inline size_t cx_bytes(Cx t) { return t == Cx::C128 ? 16 : 8; }
+// kernel columns (complex entries) of one frequency's Fourier-domain record:
+// n_eq^2 for dense blocks, 2 (n_eq/2)^2 for the L and K operators
+inline int64_t kernel_cols(const emsurf_plan_desc& d) {
+  const int64_t n = d.n_eq;
+  return d.form == EMSURF_T_LK ? 2 * (n / 2) * (n / 2) : n * n;
+}
 }  // namespace emsurf

@@ -24,6 +24,11 @@ void validate_desc(const emsurf_plan_desc* d) {
   EMS_CHECK_ARG((d->store & (EMSURF_STORE_FP64 | EMSURF_STORE_FP32)) != 0 &&
                     (d->store & ~(EMSURF_STORE_FP64 | EMSURF_STORE_FP32)) == 0,
                 "store must be a non-empty mask of EMSURF_STORE_FP64 | EMSURF_STORE_FP32");
+  EMS_CHECK_ARG(d->form == EMSURF_T_DENSE || d->form == EMSURF_T_LK, "form must be EMSURF_T_DENSE or EMSURF_T_LK");
+  if (d->form == EMSURF_T_LK) {
+    EMS_CHECK_ARG(d->n_eq % 2 == 0, "EMSURF_T_LK needs an even n_eq (J and M halves)");
+    for (double c : d->coef) EMS_CHECK_ARG(std::isfinite(c), "EMSURF_T_LK coefficients must be finite");
+  }
 }
 
 struct Sizes {
@@ -40,8 +45,9 @@ Sizes sizes_of(const emsurf_plan_desc* d) {
   z.M = (int64_t)d->nx * d->ny;
   z.n = d->n_eq;
   z.nn = z.n * z.n;
-  z.that64 = (d->store & EMSURF_STORE_FP64) ? (size_t)(z.P * z.nn) * 16 : 0;
-  z.that32 = (d->store & EMSURF_STORE_FP32) ? (size_t)(z.P * z.nn) * 8 : 0;
+  const int64_t kc = kernel_cols(*d);
+  z.that64 = (d->store & EMSURF_STORE_FP64) ? (size_t)(z.P * kc) * 16 : 0;
+  z.that32 = (d->store & EMSURF_STORE_FP32) ? (size_t)(z.P * kc) * 8 : 0;
   z.S = (size_t)d->n_types * z.nn * (16 + 8);
   z.tiles = (size_t)z.M * 4 + (size_t)(z.M + d->n_types) * 12;
   const int64_t B = (int64_t)d->max_rhs * z.n;
@@ -132,8 +138,12 @@ void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* 
 
   // Fourier-domain block products
   timer_begin(p, 2, s, &e);
-  const int v = tc == Cx::C64 ? (variant >= 0 ? variant : choose_variant(p, nrhs)) : BP_GEMV;
-  launch_block_product_variant(tc, v, That, w.X.p, w.Y.p, n, nrhs, p->P, s);
+  if (p->d.form == EMSURF_T_LK) {
+    launch_block_product_lk(tc, That, w.X.p, w.Y.p, n / 2, nrhs, p->P, p->d.coef, s);
+  } else {
+    const int v = tc == Cx::C64 ? (variant >= 0 ? variant : choose_variant(p, nrhs)) : BP_GEMV;
+    launch_block_product_variant(tc, v, That, w.X.p, w.Y.p, n, nrhs, p->P, s);
+  }
   timer_end(e, s);
 
   // inverse along y, keep rows iy < Ny
@@ -243,7 +253,7 @@ void upload_S(emsurf_plan p, const void* S_types, hipStream_t s) {
 // Kernel FFT of the padded blocks, in column chunks, into the resident stores.
 template <typename FillChunk>
 void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill) {
-  const int64_t nn = (int64_t)p->d.n_eq * p->d.n_eq;
+  const int64_t nn = kernel_cols(p->d);
   const int64_t P = p->P;
   if (p->d.store & EMSURF_STORE_FP64) p->that64.alloc((size_t)(P * nn) * 16);
   if (p->d.store & EMSURF_STORE_FP32) p->that32.alloc((size_t)(P * nn) * 8);
@@ -353,7 +363,9 @@ emsurf_status emsurf_plan_create(const emsurf_plan_desc* desc, const void* T_blo
     hipStream_t s = static_cast<hipStream_t>(stream);
     p = new_plan(desc);
     const int nx = desc->nx, ny = desc->ny, n = desc->n_eq;
-    const size_t tb_bytes = (size_t)(2 * ny - 1) * (2 * nx - 1) * n * n * 16;
+    const bool lk = desc->form == EMSURF_T_LK;
+    const int nb = lk ? n / 2 : n, parts = lk ? 2 : 1;
+    const size_t tb_bytes = (size_t)(2 * ny - 1) * (2 * nx - 1) * parts * nb * nb * 16;
     DevBuf Tdev;
     const void* Tb = T_blocks;
     if (!T_is_device) {
@@ -362,7 +374,7 @@ emsurf_status emsurf_plan_create(const emsurf_plan_desc* desc, const void* T_blo
       Tb = Tdev.p;
     }
     build_that(p, s, [&](int64_t c0, int64_t cnt, void* K) {
-      launch_pad_blocks(Tb, nx, ny, n, p->Lx, p->Ly, c0, cnt, K, s);
+      launch_pad_blocks(Tb, nx, ny, nb, parts, p->Lx, p->Ly, c0, cnt, K, s);
     });
     upload_S(p, S_types, s);
     build_tiles(p, elem_type, s);
@@ -385,11 +397,15 @@ emsurf_status emsurf_plan_create_green(const emsurf_plan_desc* desc, const emsur
     hipStream_t s = static_cast<hipStream_t>(stream);
     validate_desc(desc);
     EMS_CHECK_ARG(geom != nullptr && desc->n_eq == 4 * geom->n_patch, "n_eq must equal 4 * geom->n_patch");
+    EMS_CHECK_ARG(desc->form != EMSURF_T_LK || geom->k > 0, "the structured fill needs a wavenumber k > 0");
     GreenGeomDev g;
     upload_geom(geom, g);
     p = new_plan(desc);
     build_that(p, s, [&](int64_t c0, int64_t cnt, void* K) {
-      launch_green_padded(g, desc->nx, desc->ny, p->Lx, p->Ly, c0, cnt, K, s);
+      if (desc->form == EMSURF_T_LK)
+        launch_lk_padded(g, desc->nx, desc->ny, p->Lx, p->Ly, c0, cnt, K, s);
+      else
+        launch_green_padded(g, desc->nx, desc->ny, p->Lx, p->Ly, c0, cnt, K, s);
     });
     upload_S(p, S_types, s);
     build_tiles(p, elem_type, s);
@@ -413,6 +429,20 @@ emsurf_status emsurf_fill_T_point_green(const emsurf_geom* geom, int32_t nx, int
     upload_geom(geom, g);
     launch_green_blocks(g, nx, ny, T_blocks_dev, s);
     // the geometry buffers are freed on return: finish using them first
+    EMS_HIP(hipStreamSynchronize(s));
+  });
+}
+
+emsurf_status emsurf_fill_LK_point_green(const emsurf_geom* geom, int32_t nx, int32_t ny, void* LK_blocks_dev,
+                                         void* stream) {
+  return guarded([&] {
+    EMS_CHECK_ARG(LK_blocks_dev != nullptr, "LK_blocks_dev is NULL");
+    EMS_CHECK_ARG(geom != nullptr && geom->k > 0, "the structured fill needs a wavenumber k > 0");
+    EMS_CHECK_ARG(nx >= 1 && ny >= 1 && nx <= 512 && ny <= 512, "lattice sizes must be in [1, 512]");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GreenGeomDev g;
+    upload_geom(geom, g);
+    launch_lk_blocks(g, nx, ny, LK_blocks_dev, s);
     EMS_HIP(hipStreamSynchronize(s));
   });
 }

@@ -74,6 +74,10 @@ extern "C" emsurf_status emsurf_plan_set_variant(emsurf_plan plan, int32_t nrhs,
     EMS_CHECK_ARG(plan != nullptr, "plan is NULL");
     EMS_CHECK_ARG(nrhs >= 1 && nrhs <= plan->d.max_rhs, "nrhs must be in [1, max_rhs]");
     EMS_CHECK_ARG(variant >= -1 && variant < BP_NVARIANTS, "unknown block-product variant");
+    if (variant > BP_GEMV && plan->d.form == EMSURF_T_LK) {
+      set_error("structured (L, K) plans have a single block-product kernel");
+      throw Err{EMSURF_ERR_UNSUPPORTED};
+    }
     if (variant > BP_GEMV && !block_variant_supported(variant, plan->d.n_eq, nrhs)) {
       set_error("this MFMA block-product variant needs n_eq a multiple of 32 (<= 480) and at most 4 "
                 "wavefronts of row tiles");
@@ -106,14 +110,21 @@ extern "C" emsurf_status emsurf_plan_autotune(emsurf_plan plan, int32_t nrhs, do
     EMS_HIP(hipMemsetAsync(w.X.p, 0, w.X.bytes, s));
     int best = BP_GEMV;
     double best_ms = 1e300;
+    // a structured (L, K) plan has one kernel; it is reported as variant 0
+    const bool structured = plan->d.form == EMSURF_T_LK;
+    auto run = [&](int v) {
+      if (structured)
+        launch_block_product_lk(Cx::C64, plan->that32.p, w.X.p, w.Y.p, n / 2, nrhs, plan->P, plan->d.coef, s);
+      else
+        launch_block_product_variant(Cx::C64, v, plan->that32.p, w.X.p, w.Y.p, n, nrhs, plan->P, s);
+    };
     for (int v = 0; v < BP_NVARIANTS; ++v) {
       double ms = -1.0;
-      if (block_variant_supported(v, n, nrhs)) {
-        launch_block_product_variant(Cx::C64, v, plan->that32.p, w.X.p, w.Y.p, n, nrhs, plan->P, s);  // warm-up
+      if (structured ? v == BP_GEMV : block_variant_supported(v, n, nrhs)) {
+        run(v);  // warm-up
         const int reps = 3;
         EMS_HIP(hipEventRecord(e0, s));
-        for (int i = 0; i < reps; ++i)
-          launch_block_product_variant(Cx::C64, v, plan->that32.p, w.X.p, w.Y.p, n, nrhs, plan->P, s);
+        for (int i = 0; i < reps; ++i) run(v);
         EMS_HIP(hipEventRecord(e1, s));
         EMS_HIP(hipEventSynchronize(e1));
         float f = 0;
@@ -125,7 +136,7 @@ extern "C" emsurf_status emsurf_plan_autotune(emsurf_plan plan, int32_t nrhs, do
     }
     plan->bp_variant[nrhs] = best;
     if (best_out) *best_out = best;
-    {
+    if (!structured) {
       std::lock_guard<std::mutex> lk(g_cache_mu);
       load_cache_locked();
       g_cache[{n, nrhs}] = best;

@@ -1,0 +1,196 @@
+"""GPU parity of the structured outer operator (EMSURF_T_LK: the plan stores
+the Fourier transforms of L and K only, Sec. IV-C) against the FP64 oracle,
+through the C ABI: the device fill, applies on the physical fill and on random
+dense L and K blocks with random constants (every pass width and the ragged
+and radix-3 padded lengths), solves against dense LU, argument errors, and a
+full-size 128 x 128 apply on sampled rows.  Bars: FP64 1e-12, FP32 2e-5."""
+import numpy as np
+import pytest
+
+import workload as W
+from oracle import coupling as C
+from oracle import coupling_lk as LK
+from oracle import krylov as K
+from oracle import macromodel as MM
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 2e-5
+
+
+def E():
+    import paper_1911_04576_amd as mod
+    mod.lib()
+    return mod
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def rel(a, b):
+    """Largest normwise relative error over right-hand sides; a zero reference
+    must be matched exactly (0, else inf)."""
+    a = np.asarray(a).reshape(b.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    num = np.linalg.norm(a - b, axis=1)
+    den = np.linalg.norm(b, axis=1)
+    return float(np.max(np.where(den > 0, num / np.where(den > 0, den, 1.0), np.where(num == 0, 0.0, np.inf))))
+
+
+def apply_both(e, plan, x, nrhs):
+    x64 = dev(x)
+    y64 = torch.empty_like(x64)
+    e.emsurf_apply_T(plan, e.EMSURF_FP64, nrhs, x64, y64)
+    x32 = x64.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    e.emsurf_apply_T(plan, e.EMSURF_FP32, nrhs, x32, y32)
+    torch.cuda.synchronize()
+    return y64.cpu().numpy(), y32.cpu().numpy().astype(np.complex128)
+
+
+@pytest.mark.parametrize("npch,nx,ny", [(24, 1, 1), (24, 3, 2), (48, 2, 3)])
+def test_lk_fill_matches_oracle(npch, nx, ny):
+    e = E()
+    g = W.box_geometry(npch)
+    geom = e.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)
+    nh = 2 * npch
+    out = torch.zeros((2 * ny - 1, 2 * nx - 1, 2, nh, nh), dtype=torch.complex128, device="cuda")
+    e.emsurf_fill_LK_point_green(geom, nx, ny, out)
+    torch.cuda.synchronize()
+    Lb, Kb = LK.lk_blocks(g.rho, g.area, g.tan, nx, ny, W.PITCH, W.K0)
+    got = out.cpu().numpy()
+    for part, ref in ((0, Lb), (1, Kb)):
+        scale = np.abs(ref).max() if np.any(ref) else 1.0
+        assert np.abs(got[:, :, part] - ref).max() <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("nx,ny,npch,nrhs", [(1, 1, 24, 1), (4, 4, 24, 1), (3, 5, 24, 3), (5, 2, 48, 4),
+                                             (10, 3, 24, 2), (2, 13, 24, 5), (6, 6, 48, 9)])
+def test_apply_T_lk_physical(nx, ny, npch, nrhs):
+    e = E()
+    g = W.box_geometry(npch)
+    n = 4 * npch
+    say(f"LK apply (fill): {nx}x{ny}, n_eq {n}, {nrhs} RHS")
+    S = W.random_types(2, n, seed=1)
+    tm = W.random_type_map(nx, ny, 2, seed=1)
+    geom = e.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)
+    plan = e.emsurf_plan_create_green(nx, ny, 2, nrhs, geom, S, tm, form=e.EMSURF_T_LK, coef=W.OUTER_COEF)
+    st = plan.stats()
+    nh = n // 2
+    assert st.bytes_that64 == st.Lx * st.Ly * 2 * nh * nh * 16
+    x = W.random_vectors(nrhs, nx, ny, n, seed=nx * 7 + ny)
+    Lb, Kb = LK.lk_blocks(g.rho, g.area, g.tan, nx, ny, W.PITCH, W.K0)
+    blocks = LK.lk_assemble(Lb, Kb, W.OUTER_COEF)
+    ref = C.apply_T_direct(lambda dy, dx: blocks[dy + ny - 1, dx + nx - 1], x)
+    y64, y32 = apply_both(e, plan, x, nrhs)
+    e64, e32 = rel(y64, ref), rel(y32, ref)
+    say(f"  FP64 {e64:.2e}  FP32 {e32:.2e}")
+    assert e64 <= FP64_TOL and e32 <= FP32_TOL
+    plan.destroy()
+
+
+@pytest.mark.parametrize("nx,ny,nh,nrhs", [(1, 1, 3, 1), (2, 3, 5, 2), (4, 3, 17, 3), (7, 2, 8, 8),
+                                           (12, 1, 6, 1), (3, 3, 64, 4), (2, 2, 100, 6), (5, 4, 33, 13)])
+def test_apply_T_lk_random_blocks(nx, ny, nh, nrhs):
+    e = E()
+    n = 2 * nh
+    say(f"LK apply (random L, K): {nx}x{ny}, n_h {nh}, {nrhs} RHS")
+    Lb = W.random_blocks(nx, ny, nh, seed=11 + nh)
+    Kb = W.random_blocks(nx, ny, nh, seed=12 + nh)
+    rng = np.random.default_rng(nh)
+    coef = tuple(complex(a, b) for a, b in rng.standard_normal((4, 2)))
+    S = W.random_types(3, n, seed=2)
+    tm = W.random_type_map(nx, ny, 3, seed=2)
+    T_in = np.stack([Lb, Kb], axis=2)                       # [2ny-1][2nx-1][2][nh][nh]
+    plan = e.emsurf_plan_create(nx, ny, n, 3, nrhs, T_in, S, tm, form=e.EMSURF_T_LK, coef=coef)
+    x = W.random_vectors(nrhs, nx, ny, n, seed=5)
+    blocks = LK.lk_assemble(Lb, Kb, coef)
+    ref = C.apply_T_direct(lambda dy, dx: blocks[dy + ny - 1, dx + nx - 1], x)
+    y64, y32 = apply_both(e, plan, x, nrhs)
+    e64, e32 = rel(y64, ref), rel(y32, ref)
+    say(f"  FP64 {e64:.2e}  FP32 {e32:.2e}")
+    assert e64 <= FP64_TOL and e32 <= FP32_TOL
+    # the same plan built from device blocks
+    plan2 = e.emsurf_plan_create(nx, ny, n, 3, nrhs, dev(T_in), S, tm, form=e.EMSURF_T_LK, coef=coef)
+    y64b, _ = apply_both(e, plan2, x, nrhs)
+    assert np.array_equal(y64b, y64)
+    plan.destroy()
+    plan2.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir"])
+def test_solve_lk_matches_lu(prec):
+    e = E()
+    nx, ny, npch = 4, 3, 24
+    g = W.box_geometry(npch)
+    n = 4 * npch
+    S = W.random_types(3, n, seed=4)
+    tm = W.random_type_map(nx, ny, 3, seed=4)
+    geom = e.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)
+    plan = e.emsurf_plan_create_green(nx, ny, 3, 2, geom, S, tm, form=e.EMSURF_T_LK, coef=W.OUTER_COEF)
+    Lb, Kb = LK.lk_blocks(g.rho, g.area, g.tan, nx, ny, W.PITCH, W.K0)
+    A = np.eye(nx * ny * n) - MM.dense_S(S, tm) @ C.dense_T(LK.lk_assemble(Lb, Kb, W.OUTER_COEF), nx, ny)
+    b = W.random_vectors(2, nx, ny, n, seed=9)
+    xref = K.solve_dense(A, b.reshape(2, -1).T).T.reshape(b.shape)
+    tol = 1e-10 if prec == "fp64" else 1e-6
+    p = e.EMSURF_FP64 if prec == "fp64" else e.EMSURF_FP32_IR
+    x = torch.zeros_like(dev(b))
+    st, info = e.emsurf_solve(plan, e.solve_opts(p, tol=tol), 2, dev(b), x)
+    say(f"LK solve {prec}: {info}")
+    assert st == e.EMSURF_OK and all(i["converged"] for i in info)
+    err = rel(x.cpu().numpy(), xref)
+    assert err <= 10 * tol * np.linalg.cond(A)
+    plan.destroy()
+
+
+def test_lk_argument_errors_and_tuning():
+    e = E()
+    g = W.box_geometry(24)
+    geom = e.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)
+    S = W.random_types(1, 96, seed=0)
+    tm = np.zeros((2, 2), np.int32)
+    with pytest.raises(e.EmsurfError):                        # odd n_eq
+        e.emsurf_plan_create(2, 2, 7, 1, 1, np.zeros((3, 3, 2, 3, 3), complex), W.random_types(1, 7, seed=0),
+                             tm, form=e.EMSURF_T_LK, coef=(1, 0, 0, 1))
+    with pytest.raises(e.EmsurfError):                        # non-finite constant
+        e.emsurf_plan_create_green(2, 2, 1, 1, geom, S, tm, form=e.EMSURF_T_LK, coef=(np.nan, 1, -1, 1))
+    with pytest.raises(e.EmsurfError):                        # unknown form
+        e.emsurf_plan_create_green(2, 2, 1, 1, geom, S, tm, form=7)
+    plan = e.emsurf_plan_create_green(2, 2, 1, 16, geom, S, tm, form=e.EMSURF_T_LK, coef=W.OUTER_COEF)
+    with pytest.raises(e.EmsurfError):                        # MFMA variants belong to dense plans
+        e.emsurf_plan_set_variant(plan, 16, e.EMSURF_BP_MFMA_T3)
+    best, ms = e.emsurf_plan_autotune(plan, 16)
+    assert best == 0 and ms[e.BP_NAMES[0]] is not None
+    assert all(v is None for k, v in ms.items() if k != e.BP_NAMES[0])
+    dense = e.emsurf_plan_bytes(64, 64, 192, 16, 4)
+    lk = e.emsurf_plan_bytes(64, 64, 192, 16, 4, form=e.EMSURF_T_LK)
+    assert lk < dense
+    plan.destroy()
+
+
+def test_lk_fullsize_128x128_sampled():
+    e = E()
+    c = W.config(4)
+    g = W.box_geometry(c.n_patch)
+    S, tm = W.s_types(c), W.type_map(c)
+    geom = e.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)
+    plan = e.emsurf_plan_create_green(c.nx, c.ny, c.n_types, c.nrhs, geom, S, tm, form=e.EMSURF_T_LK,
+                                      coef=W.OUTER_COEF)
+    say(f"LK full size: {c.nx}x{c.ny}, n_eq {c.n_eq}, {c.nrhs} RHS, store {plan.stats().bytes_that32 / 1e9:.2f} GB FP32")
+    b = W.plane_wave_rhs(c, g)
+    y64, y32 = apply_both(e, plan, b, c.nrhs)
+    elems = [(0, 0), (77, 31)]
+    ref = LK.apply_T_elements_lk(g.rho, g.area, g.tan, W.PITCH, W.K0, W.OUTER_COEF, b, elems, chunk_rows=8)
+    for i, (iy, ix) in enumerate(elems):
+        e64 = float(np.linalg.norm(y64[:, iy, ix] - ref[i]) / np.linalg.norm(ref[i]))
+        e32 = float(np.linalg.norm(y32[:, iy, ix] - ref[i]) / np.linalg.norm(ref[i]))
+        say(f"  element ({iy},{ix}): FP64 {e64:.2e}, FP32 {e32:.2e}")
+        assert e64 <= FP64_TOL and e32 <= FP32_TOL
+    plan.destroy()

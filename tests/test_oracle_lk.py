@@ -116,3 +116,22 @@ def test_lk_blocks_index_convention():
     Lb, Kb = LK.lk_blocks(*G, 3, 2, W.PITCH, W.K0)
     L1, K1 = LK.lk_blocks_at(*G, [(1, -2)], W.PITCH, W.K0)
     assert np.array_equal(Lb[1 + 1, -2 + 2], L1[0]) and np.array_equal(Kb[1 + 1, -2 + 2], K1[0])
+
+
+def test_workload_constants_are_the_paper_reading():
+    assert np.allclose(W.OUTER_COEF, LK.paper_coefficients(W.K0), rtol=0, atol=0)
+
+
+def test_sampled_rows_match_dense_assembly():
+    # the on-the-fly row evaluator equals the dense Toeplitz matrix of the
+    # assembled blocks (a different summation path through coupling.dense_T)
+    g, G = _geom(24)
+    nx, ny = 3, 4
+    Lb, Kb = LK.lk_blocks(*G, nx, ny, W.PITCH, W.K0)
+    T = C.dense_T(LK.lk_assemble(Lb, Kb, W.OUTER_COEF), nx, ny)
+    x = W.random_vectors(2, nx, ny, g.n_eq, seed=3)
+    y = (x.reshape(2, -1) @ T.T).reshape(x.shape)
+    elems = [(0, 0), (2, 1), (3, 2)]
+    rows = LK.apply_T_elements_lk(*G, W.PITCH, W.K0, W.OUTER_COEF, x, elems, chunk_rows=2)
+    for i, (iy, ix) in enumerate(elems):
+        assert np.abs(rows[i] - y[:, iy, ix]).max() <= 1e-13 * np.abs(y).max()

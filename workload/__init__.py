@@ -38,6 +38,11 @@ PITCH = 0.5
 BOX_A = 0.45                    # box edge along x and y
 BOX_H = 0.10                    # box height along z
 
+# Constants (a, b, c, e) of the structured outer operator
+# T = [[a L, b K], [c K, e L]]: the outer EFIE and MFIE scale L by -j omega mu0
+# and +j omega eps0 and K by +1 and -1; with eta = 1 both products are k.
+OUTER_COEF = (-1j * K0, 1.0 + 0j, -1.0 + 0j, 1j * K0)
+
 # (n_t, s_a, s_h) patch grids -> 24, 48, 72 patches per box
 PATCH_GRIDS = {24: (2, 2, 2), 48: (4, 4, 1), 72: (4, 5, 2)}
 
