@@ -7,9 +7,9 @@
 //
 // The padded kernel chunk holds columns c in [c0, c0 + nc) of the per-frequency
 // batch, c = v*n + u (source v, test u) for dense blocks and
-// c = part*n_h^2 + v*n_h + u for the structured form (part 0 = L, 1 = K), as a
-// dense [Ly][Lx][nc] array, so that after the 2-D transform every frequency's
-// blocks are stored column-major.
+// c = v*n + part*n_h + u for the structured form (the stacked n x n_h matrix
+// [L; K], part 0 = L, 1 = K), as a dense [Ly][Lx][nc] array, so that after the
+// 2-D transform every frequency's record is stored column-major.
 #include "internal.h"
 
 namespace emsurf {
@@ -24,8 +24,9 @@ __device__ __forceinline__ int slot_to_offset(int s, int L, int N, bool* ok) {
 
 // Caller blocks hold `parts` square nb x nb matrices per offset, row-major
 // (row = test, column = source): parts = 1, nb = n_eq for dense blocks;
-// parts = 2 (L then K), nb = n_h for the structured operator.  Kernel column
-// c = part * nb^2 + v * nb + u.
+// parts = 2 (L then K), nb = n_h for the structured operator.  The kernel
+// columns are those of the stacked (parts * nb) x nb matrix, column-major:
+// c = v * (parts * nb) + part * nb + u.
 __global__ void pad_blocks_kernel(const double2* __restrict__ Tb, int nx, int ny, int nb, int parts, int Lx, int Ly,
                                   long long c0, long long nc, double2* __restrict__ K) {
   const long long total = (long long)Ly * Lx * nc;
@@ -41,9 +42,10 @@ __global__ void pad_blocks_kernel(const double2* __restrict__ Tb, int nx, int ny
     double2 val{0.0, 0.0};
     if (okx && oky) {
       const long long c = c0 + j;
-      const long long part = c / nbb;
-      const long long rem = c - part * nbb;
-      const int v = (int)(rem / nb), u = (int)(rem - (long long)v * nb);
+      const int rows = parts * nb;
+      const int v = (int)(c / rows);
+      const int w = (int)(c - (long long)v * rows);
+      const int part = w / nb, u = w - part * nb;
       const long long blk = (long long)(dy + ny - 1) * (2 * nx - 1) + (dx + nx - 1);
       val = Tb[(blk * parts + part) * nbb + (long long)u * nb + v];
     }
@@ -162,7 +164,6 @@ __global__ void lk_padded_kernel(const double* __restrict__ rho, const double* _
                                  const double* __restrict__ tan, int P, double pitch, double k, int nx, int ny,
                                  int Lx, int Ly, long long c0, long long nc, double2* __restrict__ K) {
   const int nh = 2 * P;
-  const long long nhh = (long long)nh * nh;
   const long long total = (long long)Ly * Lx * nc;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
@@ -175,9 +176,9 @@ __global__ void lk_padded_kernel(const double* __restrict__ rho, const double* _
     double2 val{0.0, 0.0};
     if (okx && oky) {
       const long long c = c0 + j;
-      const int part = (int)(c / nhh);
-      const long long rem = c - part * nhh;
-      const int v = (int)(rem / nh), u = (int)(rem - (long long)v * nh);
+      const int v = (int)(c / (2 * nh));
+      const int w = (int)(c - (long long)v * 2 * nh);
+      const int part = w / nh, u = w - part * nh;
       val = lk_entry(rho, area, tan, pitch, k, dx, dy, part, u, v);
     }
     K[i] = val;

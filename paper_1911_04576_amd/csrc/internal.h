@@ -134,8 +134,8 @@ bool block_mfma_supported(int n, int nrhs);
 bool block_variant_supported(int variant, int n, int nrhs);
 void launch_block_product_variant(Cx t, int variant, const void* That, const void* xh, void* yh, int n, int nrhs,
                                   int64_t P, hipStream_t s);
-// Structured outer operator (EMSURF_T_LK): That per frequency holds L then K,
-// each n_h x n_h column-major ([k][2][v][u]);
+// Structured outer operator (EMSURF_T_LK): That per frequency holds the
+// stacked n x n_h matrix [L; K] column-major ([k][v][L|K][u]);
 //   yh[k][r][u] = a L xJ + b K xM (u < n_h),  yh[k][r][n_h + u] = c K xJ + e L xM,
 // xJ = xh[k][r][0:n_h], xM = xh[k][r][n_h:2 n_h]; coef = (a, b, c, e) as (re, im).
 void launch_block_product_lk(Cx t, const void* That, const void* xh, void* yh, int nh, int nrhs, int64_t P,
