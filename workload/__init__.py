@@ -326,3 +326,27 @@ def serving_stream(n_requests: int, rate_hz: float, n_surfaces: int, max_rhs: in
         ang = tuple((float(t), "TE" if q == 0 else "TM") for t, q in zip(th, pol))
         out.append(Request(i, float(arr[i]), k, nrhs, ang))
     return out
+
+def cell_interiors(n_types: int, n_eq: int, n_int: int, seed: int):
+    """Synthetic discretised cells for macromodel generation: per cell type the
+    reduced system [[Z_eq,eq, Z_eq,int], [Z_int,eq, Z_int,int]] (complex128
+    [n_types][N][N], N = n_eq + n_int, equivalent-surface unknowns first) and
+    the box self block Z_o^self ([n_eq][n_eq], shared by every type).  Diagonally
+    dominant interior and surface blocks with weak coupling, so that the
+    resulting S = -(Z~ + Z_self)^-1 has norm about 0.5 like the direct S draws."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 80, seed])))
+    N = n_eq + n_int
+
+    def cn(*shape):
+        return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+    Z = np.zeros((n_types, N, N), dtype=np.complex128)
+    for t in range(n_types):
+        Z[t, :n_eq, :n_eq] = 2.0 * np.eye(n_eq) + 0.25 * cn(n_eq, n_eq) / math.sqrt(n_eq)
+        if n_int:
+            c = 0.3 / math.sqrt(math.sqrt(n_eq * n_int))
+            Z[t, :n_eq, n_eq:] = c * cn(n_eq, n_int)
+            Z[t, n_eq:, :n_eq] = c * cn(n_int, n_eq)
+            Z[t, n_eq:, n_eq:] = (1.0 + 0.5j) * np.eye(n_int) + 0.3 * cn(n_int, n_int) / math.sqrt(n_int)
+    Zself = 0.2 * cn(n_eq, n_eq) / math.sqrt(n_eq)
+    return Z, Zself
