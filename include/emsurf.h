@@ -177,6 +177,28 @@ emsurf_status emsurf_fill_T_point_green(const emsurf_geom* geom, int32_t nx, int
 emsurf_status emsurf_fill_LK_point_green(const emsurf_geom* geom, int32_t nx, int32_t ny,
                                          void* LK_blocks_dev, void* stream);
 
+/* Macromodel generation for unique cells (Sec. II-D, eq. (Zmacromodel)): for
+ * every cell type t the interior unknowns are eliminated with the Schur
+ * complement (LU with partial pivoting of Z_int,int),
+ *     Z~_t = Z_eq,eq - Z_eq,int Z_int,int^-1 Z_int,eq,
+ * and the element operator of the solve (block-Jacobi form of Sec. III-C) is
+ *     S_t = -(Z~_t + Z_self)^-1.
+ *   Z_dev      c128 [n_types][N][N], N = n_eq + n_int, row-major, the reduced
+ *              cell system [[Z_eq,eq, Z_eq,int], [Z_int,eq, Z_int,int]]
+ *              (equivalent-surface unknowns first); read only.
+ *   Zself_dev  c128 [n_eq][n_eq], the box self block of the outer operator,
+ *              shared by all types; NULL means zero.
+ *   S_dev      c128 [n_types][n_eq][n_eq] output, row-major (the S_types
+ *              layout of emsurf_plan_create once copied to the host).
+ *   Zt_dev     c128 [n_types][n_eq][n_eq] output of Z~, or NULL.
+ * 1 <= n_types <= 4096, 1 <= n_eq <= 512, 0 <= n_int <= 4096.  Workspaces of
+ * n_types ((n_eq + n_int)^2 + 4 n_eq^2) complex values are allocated for the
+ * call.  Blocks on `stream`; a singular Z_int,int or Z~ + Z_self (a zero
+ * pivot column) returns EMSURF_ERR_ARG naming the cell type, with the outputs
+ * unspecified. */
+emsurf_status emsurf_macromodels(int32_t n_types, int32_t n_eq, int32_t n_int, const void* Z_dev,
+                                 const void* Zself_dev, void* S_dev, void* Zt_dev, void* stream);
+
 /* y = T x over nrhs right-hand sides (1 <= nrhs <= max_rhs).  x_dev and y_dev
  * are c128 for EMSURF_FP64 and c64 for EMSURF_FP32, [nrhs][ny][nx][n_eq]; they
  * must not overlap.  Requires the matching store in the plan. */

@@ -110,6 +110,7 @@ _SIGS = {
                                                 _P, _P, ctypes.POINTER(_P)]),
     "emsurf_fill_T_point_green": (ctypes.c_int, [ctypes.POINTER(emsurf_geom), ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "emsurf_fill_LK_point_green": (ctypes.c_int, [ctypes.POINTER(emsurf_geom), ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "emsurf_macromodels": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "emsurf_apply_T": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
     "emsurf_apply_S": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
     "emsurf_apply_A": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
@@ -288,6 +289,13 @@ def emsurf_fill_T_point_green(geom: Geometry, nx, ny, T_blocks_dev, stream=None)
 def emsurf_fill_LK_point_green(geom: Geometry, nx, ny, LK_blocks_dev, stream=None):
     _check(lib().emsurf_fill_LK_point_green(ctypes.byref(geom.c), int(nx), int(ny), _dptr(LK_blocks_dev),
                                             _stream(stream)))
+
+
+def emsurf_macromodels(n_types, n_eq, n_int, Z_dev, Zself_dev, S_dev, Zt_dev=None, stream=None):
+    """Device tensors: Z [T][N][N], Zself [n][n] or None, S out [T][n][n], Zt out or None."""
+    _check(lib().emsurf_macromodels(int(n_types), int(n_eq), int(n_int), _dptr(Z_dev),
+                                    None if Zself_dev is None else _dptr(Zself_dev), _dptr(S_dev),
+                                    None if Zt_dev is None else _dptr(Zt_dev), _stream(stream)))
 
 
 def emsurf_apply_T(plan: Plan, prec, nrhs, x_dev, y_dev, stream=None):

@@ -1,0 +1,320 @@
+// Macromodel generation for unique cells (Sec. II-D, eq. (Zmacromodel)): the
+// interior unknowns of a cell are eliminated with the Schur complement
+//     Z~ = Z_eq,eq - Z_eq,int Z_int,int^-1 Z_int,eq,
+// which takes an LU factorisation of Z_int,int; cells are independent.  The
+// operator of the solve then needs S = -(Z~ + Z_self)^-1 (block-Jacobi form
+// of Sec. III-C).
+//
+// Both steps are one operation, the partial elimination of the leading K x K
+// block of an N x N matrix, after which the trailing block holds
+// A22 - A21 A11^-1 A12:
+//   step 1: [[Z_int,int, Z_int,eq], [Z_eq,int, Z_eq,eq]], K = n_int  ->  Z~
+//   step 2: [[Z~ + Z_self, I], [I, 0]],                  K = n_eq   ->  -(Z~ + Z_self)^-1 = S
+// The elimination is right-looking and blocked (panels of 32 columns) with
+// partial pivoting among the leading rows (trailing rows never move, so the
+// trailing block is exactly the Schur complement); every matrix of the batch
+// (one per cell type) runs in the same launches, and the trailing update of a
+// panel spreads over many workgroups per matrix.  FP64 complex throughout;
+// row-major storage, matrix b at A + b N^2.
+#include <vector>
+
+#include "internal.h"
+
+namespace emsurf {
+namespace {
+
+constexpr int PANEL = 32;
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ double2 csub_mul(double2 c, double2 a, double2 b) {
+  // c - a b with fused multiply-adds
+  return double2{__builtin_fma(-a.x, b.x, __builtin_fma(a.y, b.y, c.x)),
+                 __builtin_fma(-a.x, b.y, __builtin_fma(-a.y, b.x, c.y))};
+}
+__device__ __forceinline__ double2 cinv(double2 a) {
+  const double d = a.x * a.x + a.y * a.y;
+  return double2{a.x / d, -a.y / d};
+}
+
+// Panel columns [k0, k0 + kb) over rows [k0, N): pivot, swap (panel columns
+// only), multipliers, update inside the panel.  One workgroup per matrix.
+// info[b] receives 1 + the first column whose pivot candidates are all zero.
+__global__ void __launch_bounds__(256) panel_kernel(double2* __restrict__ A, int N, int K, int k0, int kb,
+                                                    int* __restrict__ piv, int* __restrict__ info) {
+  const int b = blockIdx.x;
+  double2* M = A + (long long)b * N * N;
+  __shared__ double best_v[256];
+  __shared__ int best_i[256];
+  __shared__ double2 prow[PANEL];
+  for (int kk = k0; kk < k0 + kb; ++kk) {
+    // pivot: largest |a|^2 among the leading rows [kk, K), first index on ties
+    double bv = -1.0;
+    int bi = kk;
+    for (int i = kk + threadIdx.x; i < K; i += blockDim.x) {
+      const double2 a = M[(long long)i * N + kk];
+      const double v = a.x * a.x + a.y * a.y;
+      if (v > bv) { bv = v; bi = i; }
+    }
+    best_v[threadIdx.x] = bv;
+    best_i[threadIdx.x] = bi;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) {
+        const double ov = best_v[threadIdx.x + s];
+        const int oi = best_i[threadIdx.x + s];
+        if (ov > best_v[threadIdx.x] || (ov == best_v[threadIdx.x] && oi < best_i[threadIdx.x])) {
+          best_v[threadIdx.x] = ov;
+          best_i[threadIdx.x] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int p = best_i[0];
+    const bool singular = !(best_v[0] > 0.0);
+    if (threadIdx.x == 0) {
+      piv[(long long)b * K + kk] = p;
+      if (singular && info[b] == 0) info[b] = kk + 1;
+    }
+    // swap rows kk and p in the panel columns, keep the pivot row segment
+    for (int j = k0 + threadIdx.x; j < k0 + kb; j += blockDim.x) {
+      const double2 t = M[(long long)p * N + j];
+      if (p != kk) M[(long long)p * N + j] = M[(long long)kk * N + j];
+      M[(long long)kk * N + j] = t;
+      prow[j - k0] = t;
+    }
+    __syncthreads();
+    const double2 inv = singular ? double2{0.0, 0.0} : cinv(prow[kk - k0]);
+    for (int i = kk + 1 + threadIdx.x; i < N; i += blockDim.x) {
+      double2* row = M + (long long)i * N;
+      const double2 l = cmul(row[kk], inv);
+      row[kk] = l;
+      for (int j = kk + 1; j < k0 + kb; ++j) row[j] = csub_mul(row[j], l, prow[j - k0]);
+    }
+    __syncthreads();
+  }
+}
+
+// Columns j >= k0 + kb: apply the panel's row swaps, then U12 = L11^-1 A12
+// (unit lower triangular L11 of the panel).  One thread per column.
+__global__ void __launch_bounds__(64) swap_trsm_kernel(double2* __restrict__ A, int N, int K, int k0, int kb,
+                                                       const int* __restrict__ piv) {
+  const int b = blockIdx.y;
+  double2* M = A + (long long)b * N * N;
+  __shared__ double2 L[PANEL][PANEL + 1];
+  for (int t = threadIdx.x; t < kb * kb; t += blockDim.x) {
+    const int i = t / kb, l = t - i * kb;
+    L[i][l] = M[(long long)(k0 + i) * N + k0 + l];
+  }
+  __syncthreads();
+  const int j = k0 + kb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  for (int kk = k0; kk < k0 + kb; ++kk) {
+    const int p = piv[(long long)b * K + kk];
+    if (p != kk) {
+      const double2 t = M[(long long)p * N + j];
+      M[(long long)p * N + j] = M[(long long)kk * N + j];
+      M[(long long)kk * N + j] = t;
+    }
+  }
+  double2 x[PANEL];
+#pragma unroll
+  for (int i = 0; i < PANEL; ++i)
+    if (i < kb) x[i] = M[(long long)(k0 + i) * N + j];
+#pragma unroll
+  for (int i = 1; i < PANEL; ++i) {
+    if (i < kb) {
+      double2 v = x[i];
+#pragma unroll
+      for (int l = 0; l < PANEL; ++l)
+        if (l < i) v = csub_mul(v, L[i][l], x[l]);
+      x[i] = v;
+    }
+  }
+#pragma unroll
+  for (int i = 1; i < PANEL; ++i)
+    if (i < kb) M[(long long)(k0 + i) * N + j] = x[i];
+}
+
+// Trailing update A22 -= L21 U12 over rows and columns [k0 + kb, N): 32 x 32
+// output tiles, 256 threads each owning 4 outputs of one row.
+constexpr int TT = 32;
+__global__ void __launch_bounds__(256) update_kernel(double2* __restrict__ A, int N, int k0, int kb) {
+  const int b = blockIdx.z;
+  double2* M = A + (long long)b * N * N;
+  const int r0 = k0 + kb + blockIdx.y * TT;
+  const int c0 = k0 + kb + blockIdx.x * TT;
+  __shared__ double2 Ls[TT][PANEL + 1];
+  __shared__ double2 Us[PANEL][TT + 1];
+  for (int t = threadIdx.x; t < TT * PANEL; t += blockDim.x) {
+    const int i = t / PANEL, l = t - i * PANEL;
+    const int gi = r0 + i;
+    Ls[i][l] = (gi < N && l < kb) ? M[(long long)gi * N + k0 + l] : double2{0.0, 0.0};
+  }
+  for (int t = threadIdx.x; t < PANEL * TT; t += blockDim.x) {
+    const int l = t / TT, jj = t - l * TT;
+    const int gj = c0 + jj;
+    Us[l][jj] = (gj < N && l < kb) ? M[(long long)(k0 + l) * N + gj] : double2{0.0, 0.0};
+  }
+  __syncthreads();
+  const int i = threadIdx.x / 8;           // tile row
+  const int jb = (threadIdx.x % 8) * 4;    // first of 4 tile columns
+  const int gi = r0 + i;
+  if (gi >= N) return;
+  double2 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = double2{0.0, 0.0};
+  for (int l = 0; l < kb; ++l) {
+    const double2 a = Ls[i][l];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double2 u = Us[l][jb + q];
+      acc[q].x = __builtin_fma(a.x, u.x, __builtin_fma(-a.y, u.y, acc[q].x));
+      acc[q].y = __builtin_fma(a.x, u.y, __builtin_fma(a.y, u.x, acc[q].y));
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int gj = c0 + jb + q;
+    if (gj < N) {
+      double2* c = M + (long long)gi * N + gj;
+      *c = double2{c->x - acc[q].x, c->y - acc[q].y};
+    }
+  }
+}
+
+// A1[t] = [[Z_int,int, Z_int,eq], [Z_eq,int, Z_eq,eq]] from Z[t] = [[Z_eq,eq, ...]]
+__global__ void interior_first_kernel(const double2* __restrict__ Z, int n, int m, int T,
+                                      double2* __restrict__ A) {
+  const int N = n + m;
+  const long long total = (long long)T * N * N;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long t = e / ((long long)N * N);
+    const int r = (int)(e - t * N * N);
+    const int i = r / N, j = r - i * N;
+    const int si = i < m ? n + i : i - m;
+    const int sj = j < m ? n + j : j - m;
+    A[e] = Z[t * N * N + (long long)si * N + sj];
+  }
+}
+
+// A2[t] = [[Zt[t] + Z_self, I], [I, 0]] (2n x 2n), Zt read from the trailing
+// block of A1 (row stride N1, offset m)
+__global__ void inverse_setup_kernel(const double2* __restrict__ A1, int N1, int m, const double2* __restrict__ Zself,
+                                     int n, int T, double2* __restrict__ A2) {
+  const int N2 = 2 * n;
+  const long long total = (long long)T * N2 * N2;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long t = e / ((long long)N2 * N2);
+    const int r = (int)(e - t * N2 * N2);
+    const int i = r / N2, j = r - i * N2;
+    double2 v{0.0, 0.0};
+    if (i < n && j < n) {
+      v = A1[t * N1 * N1 + (long long)(m + i) * N1 + (m + j)];
+      if (Zself) {
+        const double2 s = Zself[(long long)i * n + j];
+        v.x += s.x;
+        v.y += s.y;
+      }
+    } else if ((i < n && j == i + n) || (i >= n && j == i - n)) {
+      v = double2{1.0, 0.0};
+    }
+    A2[e] = v;
+  }
+}
+
+// out[t][i][j] = A[t][off + i][off + j] (trailing n x n block)
+__global__ void trailing_copy_kernel(const double2* __restrict__ A, int N, int off, int n, int T,
+                                     double2* __restrict__ out) {
+  const long long total = (long long)T * n * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long t = e / ((long long)n * n);
+    const int r = (int)(e - t * n * n);
+    const int i = r / n, j = r - i * n;
+    out[e] = A[t * N * N + (long long)(off + i) * N + (off + j)];
+  }
+}
+
+unsigned grid1(long long total) {
+  long long g = (total + 255) / 256;
+  if (g > 65536LL * 4) g = 65536LL * 4;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// Leading K x K elimination of T matrices N x N at A (see the file header).
+void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t s) {
+  for (int k0 = 0; k0 < K; k0 += PANEL) {
+    const int kb = K - k0 < PANEL ? K - k0 : PANEL;
+    hipLaunchKernelGGL(panel_kernel, dim3((unsigned)T), dim3(256), 0, s, A, N, K, k0, kb, piv, info);
+    const int rest = N - k0 - kb;
+    if (rest > 0) {
+      hipLaunchKernelGGL(swap_trsm_kernel, dim3((unsigned)((rest + 63) / 64), (unsigned)T), dim3(64), 0, s, A, N, K,
+                         k0, kb, piv);
+      const unsigned tiles = (unsigned)((rest + TT - 1) / TT);
+      hipLaunchKernelGGL(update_kernel, dim3(tiles, tiles, (unsigned)T), dim3(256), 0, s, A, N, k0, kb);
+    }
+    EMS_LAUNCH_CHECK();
+  }
+}
+
+}  // namespace
+}  // namespace emsurf
+
+using namespace emsurf;
+
+extern "C" emsurf_status emsurf_macromodels(int32_t n_types, int32_t n_eq, int32_t n_int, const void* Z_dev,
+                                            const void* Zself_dev, void* S_dev, void* Zt_dev, void* stream) {
+  try {
+    EMS_CHECK_ARG(n_types >= 1 && n_types <= 4096, "n_types must be in [1, 4096]");
+    EMS_CHECK_ARG(n_eq >= 1 && n_eq <= 512, "n_eq must be in [1, 512]");
+    EMS_CHECK_ARG(n_int >= 0 && n_int <= 4096, "n_int must be in [0, 4096]");
+    EMS_CHECK_ARG(Z_dev != nullptr && S_dev != nullptr, "Z_dev and S_dev must be non-NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int n = n_eq, m = n_int, N1 = n + m, N2 = 2 * n, T = n_types;
+    DevBuf A1((size_t)T * N1 * N1 * 16), A2((size_t)T * N2 * N2 * 16);
+    const int Kmax = m > n ? m : n;
+    DevBuf piv((size_t)T * (Kmax > 0 ? Kmax : 1) * 4), info((size_t)T * 4);
+    EMS_HIP(hipMemsetAsync(info.p, 0, info.bytes, s));
+    hipLaunchKernelGGL(interior_first_kernel, dim3(grid1((long long)T * N1 * N1)), dim3(256), 0, s,
+                       static_cast<const double2*>(Z_dev), n, m, T, A1.as<double2>());
+    EMS_LAUNCH_CHECK();
+    if (m > 0) eliminate(A1.as<double2>(), N1, m, T, piv.as<int>(), info.as<int>(), s);
+    if (Zt_dev) {
+      hipLaunchKernelGGL(trailing_copy_kernel, dim3(grid1((long long)T * n * n)), dim3(256), 0, s,
+                         A1.as<const double2>(), N1, m, n, T, static_cast<double2*>(Zt_dev));
+      EMS_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(inverse_setup_kernel, dim3(grid1((long long)T * N2 * N2)), dim3(256), 0, s,
+                       A1.as<const double2>(), N1, m, static_cast<const double2*>(Zself_dev), n, T,
+                       A2.as<double2>());
+    EMS_LAUNCH_CHECK();
+    // the interior step's singular flags are kept apart from the inverse step's
+    std::vector<int> info1(T), info2(T);
+    EMS_HIP(hipMemcpyAsync(info1.data(), info.p, (size_t)T * 4, hipMemcpyDeviceToHost, s));
+    EMS_HIP(hipStreamSynchronize(s));
+    EMS_HIP(hipMemsetAsync(info.p, 0, info.bytes, s));
+    eliminate(A2.as<double2>(), N2, n, T, piv.as<int>(), info.as<int>(), s);
+    hipLaunchKernelGGL(trailing_copy_kernel, dim3(grid1((long long)T * n * n)), dim3(256), 0, s,
+                       A2.as<const double2>(), N2, n, n, T, static_cast<double2*>(S_dev));
+    EMS_LAUNCH_CHECK();
+    EMS_HIP(hipMemcpyAsync(info2.data(), info.p, (size_t)T * 4, hipMemcpyDeviceToHost, s));
+    EMS_HIP(hipStreamSynchronize(s));
+    for (int t = 0; t < T; ++t) {
+      if (info1[t]) {
+        set_error("cell type " + std::to_string(t) + ": interior block Z_int,int is singular");
+        throw Err{EMSURF_ERR_ARG};
+      }
+      if (info2[t]) {
+        set_error("cell type " + std::to_string(t) + ": Z~ + Z_self is singular");
+        throw Err{EMSURF_ERR_ARG};
+      }
+    }
+    return EMSURF_OK;
+  } catch (const Err& e) {
+    return e.st;
+  }
+}
