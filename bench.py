@@ -219,6 +219,38 @@ def structured_section(E, W, torch, np, steps):
     return sec
 
 
+def macromodel_section(E, W, torch, np):
+    """Macromodel generation (Schur complement of every cell type's interior,
+    then S = -(Z~ + Z_self)^-1) at the 64x64 and 128x128 workloads' cell
+    shapes, interior twice the surface unknowns."""
+    out = {}
+    for label, T, n in (("64x64_types", 32, 288), ("128x128_types", 16, 192)):
+        m = 2 * n
+        Z, Zself = W.cell_interiors(T, n, m, seed=1)
+        Zd = torch.from_numpy(Z).to("cuda")
+        Zs = torch.from_numpy(Zself).to("cuda")
+        S = torch.empty((T, n, n), dtype=torch.complex128, device="cuda")
+        E.emsurf_macromodels(T, n, m, Zd, Zs, S)          # warm-up
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            E.emsurf_macromodels(T, n, m, Zd, Zs, S)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        N = n + m
+        # complex multiply-adds of the two eliminations: sum over eliminated
+        # columns k of (N - k - 1)^2 (trailing update incl. multipliers)
+        cmac = sum((N - k - 1) ** 2 for k in range(m)) + sum((2 * n - k - 1) ** 2 for k in range(n))
+        flop = 8.0 * cmac * T
+        out[label] = {"types": T, "n_eq": n, "n_int": m, "ms": round(ms, 3),
+                      "fp64_TFs": round(flop / (ms / 1e3) / 1e12, 3),
+                      "frac_fp64_peak": round(flop / (ms / 1e3) / 1e12 / 78.6, 4)}
+        del Zd, Zs, S
+    log(f"macromodel generation: {out}")
+    return out
+
+
 def serving_section(E, W, np, n_requests, budget_gb, n_surfaces=12, load=0.7):
     """Poisson stream of solve requests over a catalogue of surfaces (lattices
     8..96, n_eq 96/192/288, 1..32 RHS each), FP32 inner / FP64 refinement to
@@ -330,6 +362,7 @@ def main():
     ap.add_argument("--copy-cal", action="store_true", help="also time a plain 2 GiB device copy")
     ap.add_argument("--no-multi", action="store_true", help="skip the 64x64, 16-RHS MFMA section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--no-macromodels", action="store_true", help="skip the macromodel-generation timing")
     ap.add_argument("--no-structured", action="store_true",
                     help="skip the structured (L, K) operator section at 128x128")
     ap.add_argument("--serving-requests", type=int, default=200)
@@ -472,6 +505,10 @@ def main():
     if not args.no_multi:
         multi = multi_rhs_section(E, W, torch, np, not args.no_cpu)
 
+    macromodels = None
+    if not args.no_macromodels:
+        macromodels = macromodel_section(E, W, torch, np)
+
     structured = None
     if not args.no_structured:
         plan.destroy()
@@ -523,6 +560,7 @@ def main():
         "copy_reference": copy,
         "multi_rhs_64x64": multi,
         "structured_lk_128x128": structured,
+        "macromodel_generation": macromodels,
         "serving": serving,
         "solve": solve,
         "cpu_baseline": cpu,

@@ -39,14 +39,15 @@ __device__ __forceinline__ double2 cinv(double2 a) {
 }
 
 // Panel columns [k0, k0 + kb) over rows [k0, N): pivot, swap (panel columns
-// only), multipliers, update inside the panel.  One workgroup per matrix.
+// only), multipliers, update inside the panel.  One workgroup of 512 threads
+// per matrix.
 // info[b] receives 1 + the first column whose pivot candidates are all zero.
-__global__ void __launch_bounds__(256) panel_kernel(double2* __restrict__ A, int N, int K, int k0, int kb,
+__global__ void __launch_bounds__(512) panel_kernel(double2* __restrict__ A, int N, int K, int k0, int kb,
                                                     int* __restrict__ piv, int* __restrict__ info) {
   const int b = blockIdx.x;
   double2* M = A + (long long)b * N * N;
-  __shared__ double best_v[256];
-  __shared__ int best_i[256];
+  __shared__ double best_v[512];
+  __shared__ int best_i[512];
   __shared__ double2 prow[PANEL];
   for (int kk = k0; kk < k0 + kb; ++kk) {
     // pivot: largest |a|^2 among the leading rows [kk, K), first index on ties
@@ -88,9 +89,19 @@ __global__ void __launch_bounds__(256) panel_kernel(double2* __restrict__ A, int
     const double2 inv = singular ? double2{0.0, 0.0} : cinv(prow[kk - k0]);
     for (int i = kk + 1 + threadIdx.x; i < N; i += blockDim.x) {
       double2* row = M + (long long)i * N;
-      const double2 l = cmul(row[kk], inv);
-      row[kk] = l;
-      for (int j = kk + 1; j < k0 + kb; ++j) row[j] = csub_mul(row[j], l, prow[j - k0]);
+      row[kk] = cmul(row[kk], inv);
+    }
+    __syncthreads();
+    // rank-1 update of the rest of the panel, one (row, column) pair per thread
+    const int w = k0 + kb - kk - 1;
+    if (w > 0) {
+      const long long pairs = (long long)(N - kk - 1) * w;
+      for (long long t = threadIdx.x; t < pairs; t += blockDim.x) {
+        const int i = kk + 1 + (int)(t / w);
+        const int j = kk + 1 + (int)(t - (long long)(i - kk - 1) * w);
+        double2* row = M + (long long)i * N;
+        row[j] = csub_mul(row[j], row[kk], prow[j - k0]);
+      }
     }
     __syncthreads();
   }
@@ -249,7 +260,7 @@ unsigned grid1(long long total) {
 void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t s) {
   for (int k0 = 0; k0 < K; k0 += PANEL) {
     const int kb = K - k0 < PANEL ? K - k0 : PANEL;
-    hipLaunchKernelGGL(panel_kernel, dim3((unsigned)T), dim3(256), 0, s, A, N, K, k0, kb, piv, info);
+    hipLaunchKernelGGL(panel_kernel, dim3((unsigned)T), dim3(512), 0, s, A, N, K, k0, kb, piv, info);
     const int rest = N - k0 - kb;
     if (rest > 0) {
       hipLaunchKernelGGL(swap_trsm_kernel, dim3((unsigned)((rest + 63) / 64), (unsigned)T), dim3(64), 0, s, A, N, K,
