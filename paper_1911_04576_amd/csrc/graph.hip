@@ -56,7 +56,7 @@ extern "C" emsurf_status emsurf_graph_create(emsurf_plan plan, int32_t op, emsur
     EMS_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
     *out = g;
     return EMSURF_OK;
-  } catch (const Err& e) {
+  } catch (...) {
     if (capturing) {
       hipGraph_t junk = nullptr;
       (void)hipStreamEndCapture(s, &junk);
@@ -64,7 +64,7 @@ extern "C" emsurf_status emsurf_graph_create(emsurf_plan plan, int32_t op, emsur
     }
     if (plan) plan->timer.enabled = timer_was;
     delete g;
-    return e.st;
+    return current_exception_status();
   }
 }
 
@@ -73,8 +73,8 @@ extern "C" emsurf_status emsurf_graph_launch(emsurf_graph g, void* stream) {
     EMS_CHECK_ARG(g != nullptr && g->exec != nullptr, "graph is NULL");
     EMS_HIP(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
     return EMSURF_OK;
-  } catch (const Err& e) {
-    return e.st;
+  } catch (...) {
+    return current_exception_status();
   }
 }
 

@@ -8,6 +8,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/emsurf.h"
@@ -21,6 +22,20 @@ const char* last_error();
 struct Err {
   emsurf_status st;
 };
+// Status of the exception being handled (call only inside a catch block): the
+// library's own errors carry their status, host allocation failures map to
+// EMSURF_ERR_OOM and anything else to EMSURF_ERR_DEVICE, so that no exception
+// crosses the C interface.
+emsurf_status current_exception_status();
+template <typename F>
+emsurf_status guarded_call(F&& f) {
+  try {
+    f();
+    return EMSURF_OK;
+  } catch (...) {
+    return current_exception_status();
+  }
+}
 
 #define EMS_HIP(call)                                                                      \
   do {                                                                                     \

@@ -58,6 +58,23 @@ Sizes sizes_of(const emsurf_plan_desc* d) {
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+emsurf_status current_exception_status() {
+  try {
+    throw;
+  } catch (const Err& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return EMSURF_ERR_OOM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return EMSURF_ERR_DEVICE;
+  } catch (...) {
+    set_error("unknown error");
+    return EMSURF_ERR_DEVICE;
+  }
+}
 const char* last_error() { return g_last_error.c_str(); }
 
 // Workspaces: one per stream, sized for max_rhs at FP64 width.
@@ -191,21 +208,7 @@ namespace {
 
 template <typename F>
 emsurf_status guarded(F&& f) {
-  try {
-    f();
-    return EMSURF_OK;
-  } catch (const Err& e) {
-    return e.st;
-  } catch (const std::bad_alloc&) {
-    set_error("host allocation failed");
-    return EMSURF_ERR_OOM;
-  } catch (const std::exception& e) {
-    set_error(e.what());
-    return EMSURF_ERR_DEVICE;
-  } catch (...) {
-    set_error("unknown error");
-    return EMSURF_ERR_DEVICE;
-  }
+  return guarded_call(std::forward<F>(f));
 }
 
 void build_tiles(emsurf_plan p, const int32_t* elem_type, hipStream_t s) {

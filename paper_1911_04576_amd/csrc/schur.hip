@@ -325,7 +325,7 @@ extern "C" emsurf_status emsurf_macromodels(int32_t n_types, int32_t n_eq, int32
       }
     }
     return EMSURF_OK;
-  } catch (const Err& e) {
-    return e.st;
+  } catch (...) {
+    return current_exception_status();
   }
 }

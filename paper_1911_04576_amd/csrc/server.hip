@@ -254,15 +254,7 @@ void harvest(emsurf_server sv) {
 
 template <typename F>
 emsurf_status vguard(F&& f) {
-  try {
-    f();
-    return EMSURF_OK;
-  } catch (const Err& e) {
-    return e.st;
-  } catch (const std::bad_alloc&) {
-    set_error("host allocation failed");
-    return EMSURF_ERR_OOM;
-  }
+  return guarded_call(std::forward<F>(f));
 }
 
 }  // namespace

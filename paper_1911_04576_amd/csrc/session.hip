@@ -345,15 +345,7 @@ namespace {
 
 template <typename F>
 emsurf_status sguard(F&& f) {
-  try {
-    f();
-    return EMSURF_OK;
-  } catch (const Err& e) {
-    return e.st;
-  } catch (const std::bad_alloc&) {
-    set_error("host allocation failed");
-    return EMSURF_ERR_OOM;
-  }
+  return guarded_call(std::forward<F>(f));
 }
 
 void check_session_opts(emsurf_plan plan, const emsurf_solve_opts* o, int max_slots) {

@@ -349,11 +349,8 @@ extern "C" emsurf_status emsurf_solve(emsurf_plan plan, const emsurf_solve_opts*
       }
     }
     EMS_HIP(hipStreamSynchronize(s));
-  } catch (const Err& e) {
-    return e.st;
-  } catch (const std::bad_alloc&) {
-    set_error("host allocation failed");
-    return EMSURF_ERR_OOM;
+  } catch (...) {
+    return current_exception_status();
   }
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   for (int r = 0; r < nrhs; ++r) {

@@ -85,8 +85,8 @@ extern "C" emsurf_status emsurf_plan_set_variant(emsurf_plan plan, int32_t nrhs,
     }
     plan->bp_variant[nrhs] = variant;
     return EMSURF_OK;
-  } catch (const Err& e) {
-    return e.st;
+  } catch (...) {
+    return current_exception_status();
   }
 }
 
@@ -145,9 +145,9 @@ extern "C" emsurf_status emsurf_plan_autotune(emsurf_plan plan, int32_t nrhs, do
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return EMSURF_OK;
-  } catch (const Err& e) {
+  } catch (...) {
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    return e.st;
+    return current_exception_status();
   }
 }
