@@ -194,3 +194,66 @@ def test_lk_fullsize_128x128_sampled():
         say(f"  element ({iy},{ix}): FP64 {e64:.2e}, FP32 {e32:.2e}")
         assert e64 <= FP64_TOL and e32 <= FP32_TOL
     plan.destroy()
+
+
+def test_lk_graph_replay_and_session_alone_equals_mix():
+    # the structured plan under the HIP-graph capture of apply_A (replays with
+    # eager work between them) and under continuous batching (a right-hand side
+    # bitwise the same alone and joining a busy session)
+    e = E()
+    nx, ny, npch, nt = 4, 3, 24, 2
+    g = W.box_geometry(npch)
+    n = 4 * npch
+    S = W.random_types(nt, n, seed=8)
+    tm = W.random_type_map(nx, ny, nt, seed=8)
+    geom = e.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)
+    plan = e.emsurf_plan_create_green(nx, ny, nt, 4, geom, S, tm, form=e.EMSURF_T_LK, coef=W.OUTER_COEF)
+    Lb, Kb = LK.lk_blocks(g.rho, g.area, g.tan, nx, ny, W.PITCH, W.K0)
+    blocks = LK.lk_assemble(Lb, Kb, W.OUTER_COEF)
+    Tf = lambda v: C.apply_T_direct(lambda dy, dx: blocks[dy + ny - 1, dx + nx - 1], v)
+    s = torch.cuda.Stream()
+    xg = torch.empty((1, ny, nx, n), dtype=torch.complex128, device="cuda")
+    yg = torch.empty_like(xg)
+    gr = e.emsurf_graph_create(plan, e.EMSURF_OP_A, e.EMSURF_FP64, 1, xg, yg, s)
+    for rep in range(3):
+        x = W.random_vectors(1, nx, ny, n, seed=40 + rep)
+        with torch.cuda.stream(s):
+            xg.copy_(dev(x))
+        gr.launch(s)
+        s.synchronize()
+        ye = torch.empty_like(xg)
+        e.emsurf_apply_A(plan, e.EMSURF_FP64, 1, xg, ye)
+        torch.cuda.synchronize()
+        assert rel(yg.cpu().numpy(), MM.apply_A(Tf, S, tm, x)) <= FP64_TOL
+        assert np.array_equal(yg.cpu().numpy(), ye.cpu().numpy())
+    gr.destroy()
+    opts = e.solve_opts(e.EMSURF_FP32_IR, tol=1e-6, restart=5)
+    bs = W.random_vectors(3, nx, ny, n, seed=12)
+    shape = (ny, nx, n)
+
+    def run(schedule):
+        sess = e.emsurf_session_create(plan, 4, opts)
+        out, slot_tag = {}, {}
+        for step in range(400):
+            for tag in schedule.get(step, []):
+                slot_tag[e.emsurf_session_submit(sess, dev(bs[tag]), tag)] = tag
+            if not slot_tag and step > max(schedule):
+                break
+            e.emsurf_session_step(sess)
+            for slot, tag in e.emsurf_session_finished(sess):
+                x = torch.empty(shape, dtype=torch.complex128, device="cuda")
+                info = e.emsurf_session_collect(sess, slot, x)
+                out[tag] = (x.cpu().numpy(), info)
+                del slot_tag[slot]
+        sess.destroy()
+        return out
+
+    alone = run({0: [0]})
+    mix = run({0: [1, 2], 2: [0]})
+    assert np.array_equal(alone[0][0], mix[0][0]) and alone[0][1]["converged"]
+    A = np.eye(nx * ny * n) - MM.dense_S(S, tm) @ C.dense_T(blocks, nx, ny)
+    for t in range(3):
+        x, info = mix[t]
+        res = np.linalg.norm(A @ x.ravel() - bs[t].ravel()) / np.linalg.norm(bs[t])
+        assert info["converged"] and res <= 1e-6
+    plan.destroy()
