@@ -217,14 +217,16 @@ void launch_lk_t(const void* That, const void* xh, void* yh, int nh, int nrhs, i
 
 }  // namespace
 
-void launch_block_product_lk(Cx t, const void* That, const void* xh, void* yh, int nh, int nrhs, int64_t P,
-                             const double* coef, hipStream_t s) {
+void launch_block_product_lk(Cx t, int variant, const void* That, const void* xh, void* yh, int nh, int nrhs,
+                             int64_t P, const double* coef, hipStream_t s) {
   EMS_CHECK_ARG(nh >= 1 && nh <= 256, "structured block product supports 1 <= n_eq / 2 <= 256");
   EMS_CHECK_ARG(nrhs >= 1 && nrhs <= 64, "block product supports 1 <= nrhs <= 64");
   EMS_CHECK_ARG(P >= 1 && P <= 0x7fffffffLL, "frequency count out of range");
   const Coef4 cf{{coef[0], coef[1]}, {coef[2], coef[3]}, {coef[4], coef[5]}, {coef[6], coef[7]}};
   if (t == Cx::C128)
     launch_lk_t<double2>(That, xh, yh, nh, nrhs, P, cf, s);
+  else if (variant != BP_GEMV && block_variant_supported_lk(variant, 2 * nh, nrhs))
+    launch_block_mfma_lk(variant, That, xh, yh, nh, nrhs, P, coef, s);
   else
     launch_lk_t<float2>(That, xh, yh, nh, nrhs, P, cf, s);
   EMS_LAUNCH_CHECK();

@@ -153,8 +153,13 @@ void launch_block_product_variant(Cx t, int variant, const void* That, const voi
 // stacked n x n_h matrix [L; K] column-major ([k][v][L|K][u]);
 //   yh[k][r][u] = a L xJ + b K xM (u < n_h),  yh[k][r][n_h + u] = c K xJ + e L xM,
 // xJ = xh[k][r][0:n_h], xM = xh[k][r][n_h:2 n_h]; coef = (a, b, c, e) as (re, im).
-void launch_block_product_lk(Cx t, const void* That, const void* xh, void* yh, int nh, int nrhs, int64_t P,
-                             const double* coef, hipStream_t s);
+// variant: BP_GEMV (lane-per-row stream, FP32 or FP64) or an FP32 MFMA variant
+// (as for dense blocks, two operand blocks per step); FP64 always streams.
+void launch_block_product_lk(Cx t, int variant, const void* That, const void* xh, void* yh, int nh, int nrhs,
+                             int64_t P, const double* coef, hipStream_t s);
+bool block_variant_supported_lk(int variant, int n, int nrhs);
+void launch_block_mfma_lk(int variant, const void* That, const void* xh, void* yh, int nh, int nrhs, int64_t P,
+                          const double* coef, hipStream_t s);
 // FP32 MFMA variants only (blockprod_mfma.hip); ERR_ARG for a variant that
 // block_variant_supported rejects
 void launch_block_mfma(int variant, const void* That, const void* xh, void* yh, int n, int nrhs, int64_t P,

@@ -155,12 +155,11 @@ void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* 
 
   // Fourier-domain block products
   timer_begin(p, 2, s, &e);
-  if (p->d.form == EMSURF_T_LK) {
-    launch_block_product_lk(tc, That, w.X.p, w.Y.p, n / 2, nrhs, p->P, p->d.coef, s);
-  } else {
-    const int v = tc == Cx::C64 ? (variant >= 0 ? variant : choose_variant(p, nrhs)) : BP_GEMV;
+  const int v = tc == Cx::C64 ? (variant >= 0 ? variant : choose_variant(p, nrhs)) : BP_GEMV;
+  if (p->d.form == EMSURF_T_LK)
+    launch_block_product_lk(tc, v, That, w.X.p, w.Y.p, n / 2, nrhs, p->P, p->d.coef, s);
+  else
     launch_block_product_variant(tc, v, That, w.X.p, w.Y.p, n, nrhs, p->P, s);
-  }
   timer_end(e, s);
 
   // inverse along y, keep rows iy < Ny

@@ -43,11 +43,11 @@ void save_cache_locked() {
   for (auto& kv : g_cache) f << kv.first.first << " " << kv.first.second << " " << kv.second << "\n";
 }
 
-int heuristic(int n, int nrhs) {
+int heuristic(int n, int nrhs, bool structured) {
   if (!block_mfma_supported(n, nrhs) || nrhs < 8) return BP_GEMV;
   // deep prefetch, fewest row tiles per wave that fits in 4 wavefronts
   for (int v = BP_MFMA_T1D; v <= BP_MFMA_T4D; ++v)
-    if (block_variant_supported(v, n, nrhs)) return v;
+    if (structured ? block_variant_supported_lk(v, n, nrhs) : block_variant_supported(v, n, nrhs)) return v;
   return BP_GEMV;
 }
 
@@ -56,13 +56,15 @@ int heuristic(int n, int nrhs) {
 int choose_variant(emsurf_plan p, int nrhs) {
   const int n = p->d.n_eq;
   if (nrhs >= 1 && nrhs <= 64 && p->bp_variant[nrhs] >= 0) return p->bp_variant[nrhs];
+  // the persisted cache holds dense-block choices only
+  if (p->d.form == EMSURF_T_LK) return heuristic(n, nrhs, true);
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     load_cache_locked();
     auto it = g_cache.find({n, nrhs});
     if (it != g_cache.end()) return it->second;
   }
-  return heuristic(n, nrhs);
+  return heuristic(n, nrhs, false);
 }
 
 }  // namespace emsurf
@@ -74,11 +76,9 @@ extern "C" emsurf_status emsurf_plan_set_variant(emsurf_plan plan, int32_t nrhs,
     EMS_CHECK_ARG(plan != nullptr, "plan is NULL");
     EMS_CHECK_ARG(nrhs >= 1 && nrhs <= plan->d.max_rhs, "nrhs must be in [1, max_rhs]");
     EMS_CHECK_ARG(variant >= -1 && variant < BP_NVARIANTS, "unknown block-product variant");
-    if (variant > BP_GEMV && plan->d.form == EMSURF_T_LK) {
-      set_error("structured (L, K) plans have a single block-product kernel");
-      throw Err{EMSURF_ERR_UNSUPPORTED};
-    }
-    if (variant > BP_GEMV && !block_variant_supported(variant, plan->d.n_eq, nrhs)) {
+    const bool structured = plan->d.form == EMSURF_T_LK;
+    if (variant > BP_GEMV && !(structured ? block_variant_supported_lk(variant, plan->d.n_eq, nrhs)
+                                          : block_variant_supported(variant, plan->d.n_eq, nrhs))) {
       set_error("this MFMA block-product variant needs n_eq a multiple of 32 (<= 480) and at most 4 "
                 "wavefronts of row tiles");
       throw Err{EMSURF_ERR_UNSUPPORTED};
@@ -110,17 +110,17 @@ extern "C" emsurf_status emsurf_plan_autotune(emsurf_plan plan, int32_t nrhs, do
     EMS_HIP(hipMemsetAsync(w.X.p, 0, w.X.bytes, s));
     int best = BP_GEMV;
     double best_ms = 1e300;
-    // a structured (L, K) plan has one kernel; it is reported as variant 0
+    // structured (L, K) plans time their own kernels under the same variant numbers
     const bool structured = plan->d.form == EMSURF_T_LK;
     auto run = [&](int v) {
       if (structured)
-        launch_block_product_lk(Cx::C64, plan->that32.p, w.X.p, w.Y.p, n / 2, nrhs, plan->P, plan->d.coef, s);
+        launch_block_product_lk(Cx::C64, v, plan->that32.p, w.X.p, w.Y.p, n / 2, nrhs, plan->P, plan->d.coef, s);
       else
         launch_block_product_variant(Cx::C64, v, plan->that32.p, w.X.p, w.Y.p, n, nrhs, plan->P, s);
     };
     for (int v = 0; v < BP_NVARIANTS; ++v) {
       double ms = -1.0;
-      if (structured ? v == BP_GEMV : block_variant_supported(v, n, nrhs)) {
+      if (structured ? block_variant_supported_lk(v, n, nrhs) : block_variant_supported(v, n, nrhs)) {
         run(v);  // warm-up
         const int reps = 3;
         EMS_HIP(hipEventRecord(e0, s));

@@ -163,12 +163,21 @@ def test_lk_argument_errors_and_tuning():
         e.emsurf_plan_create_green(2, 2, 1, 1, geom, S, tm, form=e.EMSURF_T_LK, coef=(np.nan, 1, -1, 1))
     with pytest.raises(e.EmsurfError):                        # unknown form
         e.emsurf_plan_create_green(2, 2, 1, 1, geom, S, tm, form=7)
-    plan = e.emsurf_plan_create_green(2, 2, 1, 16, geom, S, tm, form=e.EMSURF_T_LK, coef=W.OUTER_COEF)
-    with pytest.raises(e.EmsurfError):                        # MFMA variants belong to dense plans
-        e.emsurf_plan_set_variant(plan, 16, e.EMSURF_BP_MFMA_T3)
-    best, ms = e.emsurf_plan_autotune(plan, 16)
+    # n_eq = 10 is no multiple of 32: only the streaming kernel applies
+    Lb = W.random_blocks(2, 2, 5, seed=1)
+    plan10 = e.emsurf_plan_create(2, 2, 10, 1, 16, np.stack([Lb, Lb], axis=2), W.random_types(1, 10, seed=1), tm,
+                                  form=e.EMSURF_T_LK, coef=(1, 0.5, -0.5, 1))
+    with pytest.raises(e.EmsurfError):
+        e.emsurf_plan_set_variant(plan10, 16, e.EMSURF_BP_MFMA_T3)
+    best, ms = e.emsurf_plan_autotune(plan10, 16)
     assert best == 0 and ms[e.BP_NAMES[0]] is not None
     assert all(v is None for k, v in ms.items() if k != e.BP_NAMES[0])
+    plan10.destroy()
+    # n_eq = 96: the matrix-core variants are timed too
+    plan = e.emsurf_plan_create_green(2, 2, 1, 16, geom, S, tm, form=e.EMSURF_T_LK, coef=W.OUTER_COEF)
+    e.emsurf_plan_set_variant(plan, 16, e.EMSURF_BP_MFMA_T3)
+    best, ms = e.emsurf_plan_autotune(plan, 16)
+    assert ms[e.BP_NAMES[e.EMSURF_BP_MFMA_T3]] is not None and ms[e.BP_NAMES[best]] is not None
     dense = e.emsurf_plan_bytes(64, 64, 192, 16, 4)
     lk = e.emsurf_plan_bytes(64, 64, 192, 16, 4, form=e.EMSURF_T_LK)
     assert lk < dense
@@ -256,4 +265,38 @@ def test_lk_graph_replay_and_session_alone_equals_mix():
         x, info = mix[t]
         res = np.linalg.norm(A @ x.ravel() - bs[t].ravel()) / np.linalg.norm(bs[t])
         assert info["converged"] and res <= 1e-6
+    plan.destroy()
+
+
+@pytest.mark.parametrize("nx,ny,nh,nrhs", [(3, 3, 48, 16), (2, 3, 96, 8), (4, 2, 144, 16), (3, 2, 16, 20),
+                                           (2, 2, 48, 33)])
+def test_lk_mfma_variants_match_oracle(nx, ny, nh, nrhs):
+    e = E()
+    n = 2 * nh
+    Lb = W.random_blocks(nx, ny, nh, seed=21 + nh)
+    Kb = W.random_blocks(nx, ny, nh, seed=22 + nh)
+    rng = np.random.default_rng(nrhs)
+    coef = tuple(complex(a, b) for a, b in rng.standard_normal((4, 2)))
+    S = W.random_types(2, n, seed=3)
+    tm = W.random_type_map(nx, ny, 2, seed=3)
+    plan = e.emsurf_plan_create(nx, ny, n, 2, nrhs, np.stack([Lb, Kb], axis=2), S, tm, form=e.EMSURF_T_LK,
+                                coef=coef)
+    x = W.random_vectors(nrhs, nx, ny, n, seed=6)
+    blocks = LK.lk_assemble(Lb, Kb, coef)
+    ref = C.apply_T_direct(lambda dy, dx: blocks[dy + ny - 1, dx + nx - 1], x)
+    x32 = dev(x).to(torch.complex64)
+    ran = []
+    for v in range(e.EMSURF_BP_NVARIANTS):
+        try:
+            e.emsurf_plan_set_variant(plan, nrhs, v)
+        except e.EmsurfError:
+            continue
+        y = torch.empty_like(x32)
+        e.emsurf_apply_T(plan, e.EMSURF_FP32, nrhs, x32, y)
+        torch.cuda.synchronize()
+        err = rel(y.cpu().numpy().astype(np.complex128), ref)
+        say(f"  {nx}x{ny} n_h {nh} {nrhs} RHS variant {e.BP_NAMES[v]}: {err:.2e}")
+        assert err <= FP32_TOL
+        ran.append(v)
+    assert 0 in ran and any(v > 0 for v in ran)
     plan.destroy()
