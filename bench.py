@@ -141,6 +141,35 @@ def multi_rhs_section(E, W, torch, np, with_oracle):
         ys = C.apply_T_elements(g.rho, g.area, g.tan, W.PITCH, W.K0, b, [e], chunk_rows=4)[0]
         sec["fp64_sampled_rel_err_vs_oracle"] = float(np.linalg.norm(ref[:, e[0], e[1]] - ys) / np.linalg.norm(ys))
         sec["fp32_sampled_rel_err_vs_oracle"] = float(np.linalg.norm(out[:, e[0], e[1]] - ys) / np.linalg.norm(ys))
+    plan.destroy()
+    # the same lattice with the structured outer operator (L and K stored)
+    plan = E.emsurf_plan_create_green(cfg.nx, cfg.ny, cfg.n_types, nrhs, geom, S, tm, form=E.EMSURF_T_LK,
+                                      coef=W.OUTER_COEF)
+    best_lk, ms_lk = E.emsurf_plan_autotune(plan, nrhs)
+    for _ in range(2):
+        E.emsurf_apply_T(plan, E.EMSURF_FP32, nrhs, x32, y32)
+    torch.cuda.synchronize()
+    E.emsurf_kernel_timing(plan, True)
+    E.emsurf_kernel_times(plan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        E.emsurf_apply_T(plan, E.EMSURF_FP32, nrhs, x32, y32)
+    torch.cuda.synchronize()
+    lk_apply_ms = 1e3 * (time.perf_counter() - t0) / reps
+    ph = E.emsurf_kernel_times(plan)
+    E.emsurf_kernel_timing(plan, False)
+    lk_bms = ph["block_product"][0] / max(1, ph["block_product"][1])
+    lk_bytes = P * n * (n // 2) * 8 + 2 * P * nrhs * n * 8
+    sec["structured"] = {
+        "workload": "same lattice, outer operator [[aL, bK], [cK, eL]], FP32 Fourier-domain L and K",
+        "chosen": E.BP_NAMES[best_lk],
+        "block_product_variants_autotuner": {k: (None if v is None else round(v, 4)) for k, v in ms_lk.items()},
+        "block_product_ms": round(lk_bms, 4), "block_product_TFs": round(flops / (lk_bms / 1e3) / 1e12, 2),
+        "frac_fp32_mfma_peak": round(flops / (lk_bms / 1e3) / 1e12 / MFMA_FP32_PEAK_TFS, 4),
+        "block_product_GBs": round(lk_bytes / (lk_bms / 1e3) / 1e9, 1),
+        "apply_T_ms": round(lk_apply_ms, 4),
+        "unknowns_rhs_per_s": cfg.n_unknowns * nrhs / (lk_apply_ms / 1e3)}
     log(f"64x64 multi-RHS: {sec}")
     plan.destroy()
     return sec
