@@ -280,11 +280,15 @@ def macromodel_section(E, W, torch, np):
     return out
 
 
-def serving_section(E, W, np, n_requests, budget_gb, n_surfaces=12, load=0.7):
+def serving_section(E, W, np, n_requests, budget_gb, n_surfaces=12, load=0.7, structured=False):
     """Poisson stream of solve requests over a catalogue of surfaces (lattices
     8..96, n_eq 96/192/288, 1..32 RHS each), FP32 inner / FP64 refinement to
     1e-6.  A closed-loop pass (every request queued at once) measures capacity;
-    the open-loop pass then offers `load` x that rate and reports latency."""
+    the open-loop pass then offers `load` x that rate and reports latency.
+    `structured`: every surface uses the structured outer operator (plans hold
+    L and K only)."""
+    form = E.EMSURF_T_LK if structured else E.EMSURF_T_DENSE
+    coef = W.OUTER_COEF if structured else None
     tol = 1e-6
     opts = E.solve_opts(E.EMSURF_FP32_IR, tol=tol, restart=8, inner_tol=1e-6)
     cat = W.serving_catalogue(n_surfaces)
@@ -334,7 +338,7 @@ def serving_section(E, W, np, n_requests, budget_gb, n_surfaces=12, load=0.7):
                 pending.pop(0)
                 sf = cat[r.surface]
                 geom, S, tm, g = inputs[r.surface]
-                rid = E.emsurf_server_submit(srv, sf.key, sf.n, sf.n, sf.n_types, geom, S, tm, b)
+                rid = E.emsurf_server_submit(srv, sf.key, sf.n, sf.n, sf.n_types, geom, S, tm, b, form, coef)
                 arrive[rid] = (0.0 if closed else r.arrival_s, r.nrhs * sf.n * sf.n * sf.n_eq)
                 nxt += 1
             st = E.emsurf_server_query(srv)
@@ -366,7 +370,8 @@ def serving_section(E, W, np, n_requests, budget_gb, n_surfaces=12, load=0.7):
     log(f"serving closed loop: {n_requests} requests in {wall_c:.2f} s ({cap_rps:.1f} req/s, "
         f"{unk_c / wall_c:.3e} unknowns*RHS/s), stats {st_c}")
     lat, wall, unk, bad, st = run(rate, closed=False)
-    sec = {"workload": f"{n_surfaces} surfaces (n x n lattices, n in 8..96; n_eq 96/192/288; 16 types each), "
+    sec = {"workload": f"{n_surfaces} surfaces (n x n lattices, n in 8..96; n_eq 96/192/288; 16 types each"
+                       f"{'; structured outer operator, L and K stored' if structured else ''}), "
                        f"{n_requests} requests of 1..32 RHS, Poisson arrivals at {rate:.2f} req/s "
                        f"(= {load} x closed-loop capacity {cap_rps:.2f} req/s), FP32 inner + FP64 refinement "
                        f"to {tol}, HBM budget {budget_gb} GB, 32 slots per surface",
@@ -392,6 +397,8 @@ def main():
     ap.add_argument("--no-multi", action="store_true", help="skip the 64x64, 16-RHS MFMA section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--no-macromodels", action="store_true", help="skip the macromodel-generation timing")
+    ap.add_argument("--serving-structured", action="store_true",
+                    help="also run the serving section with structured (L, K) plans")
     ap.add_argument("--no-structured", action="store_true",
                     help="skip the structured (L, K) operator section at 128x128")
     ap.add_argument("--serving-requests", type=int, default=200)
@@ -552,6 +559,14 @@ def main():
             plan = None
         torch.cuda.empty_cache()
         serving = serving_section(E, W, np, args.serving_requests, args.serving_budget_gb)
+    serving_structured = None
+    if args.serving_structured:
+        if plan is not None:
+            plan.destroy()
+            plan = None
+        torch.cuda.empty_cache()
+        serving_structured = serving_section(E, W, np, args.serving_requests, args.serving_budget_gb,
+                                             structured=True)
 
     cpu = None
     parity = None
@@ -591,6 +606,7 @@ def main():
         "structured_lk_128x128": structured,
         "macromodel_generation": macromodels,
         "serving": serving,
+        "serving_structured": serving_structured,
         "solve": solve,
         "cpu_baseline": cpu,
         "parity_sampled_fp64_rel_err": parity,

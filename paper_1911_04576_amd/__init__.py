@@ -493,9 +493,10 @@ def emsurf_server_create(budget_bytes, max_slots, opts, store=EMSURF_STORE_FP64 
     return Server(out.value)
 
 
-def emsurf_server_submit(srv: Server, key, nx, ny, n_types, geom: Geometry, S_types, elem_type, b) -> int:
+def emsurf_server_submit(srv: Server, key, nx, ny, n_types, geom: Geometry, S_types, elem_type, b,
+                         form=EMSURF_T_DENSE, coef=None) -> int:
     """b: numpy complex128 [nrhs][ny][nx][n_eq] (host)."""
-    d = _desc(nx, ny, 4 * geom.n_patch, n_types, 1, EMSURF_STORE_FP64)
+    d = _desc(nx, ny, 4 * geom.n_patch, n_types, 1, EMSURF_STORE_FP64, form, coef)
     S, pS = _host(S_types, np.complex128)
     et, pet = _host(elem_type, np.int32)
     bb, pb = _host(b, np.complex128)
