@@ -37,9 +37,11 @@ __global__ void __launch_bounds__(256) block_mfma_kernel(const float2* __restric
                                                          const float2* __restrict__ xh, float2* __restrict__ yh,
                                                          int n, int nrhs, int r0, int nr) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  float2* xs = reinterpret_cast<float2*>(smem_raw);     // [16][n + 1]
+  float2* xs = reinterpret_cast<float2*>(smem_raw);     // [16][n/2 + 1], then [8][n + 1]
   constexpr int NR = 16;
-  const int ld = n + 1;
+  const int hn = n / 2;
+  const int ld = hn + 1;          // spectral columns: one half of the source index at a time
+  const int ldo = n + 1;          // outputs: eight right-hand sides at a time
   const long long k = blockIdx.x;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -78,63 +80,86 @@ __global__ void __launch_bounds__(256) block_mfma_kernel(const float2* __restric
 #pragma unroll
     for (int i = 0; i < TPW; ++i) acur[st][i] = ld_buf(rs, aoff[i], st * step_bytes);
   const float2* xk = xh + k * (long long)nrhs * n + (long long)r0 * n;
-  for (int i = threadIdx.x; i < NR * n; i += blockDim.x) {
-    const int r = i / n, v = i - r * n;
-    xs[r * ld + v] = (r < nr) ? xk[(long long)r * n + v] : float2{0.f, 0.f};
-  }
-  __syncthreads();
+  // spectral columns of source indices [base, base + n/2) into LDS
+  auto stage = [&](int base) {
+    for (int i = threadIdx.x; i < NR * hn; i += blockDim.x) {
+      const int r = i / hn, v = i - r * hn;
+      xs[r * ld + v] = (r < nr) ? xk[(long long)r * n + base + v] : float2{0.f, 0.f};
+    }
+  };
   const int last_step = n / 2 - 1;
-  for (int v0 = 0; v0 < n; v0 += 2 * U) {
-    // the final prefetch would run past the block: its step index is clamped
-    // to the last column pair (a uniform min), so every load stays inside the
-    // block whatever the hardware range check covers; those values are unused
+  // column pairs of source indices [vstart, vend), spectral columns in LDS
+  // starting at source index vbase
+  auto sweep = [&](int vstart, int vend, int vbase) {
+    for (int v0 = vstart; v0 < vend; v0 += 2 * U) {
+      // the final prefetch would run past the block: its step index is clamped
+      // to the last column pair (a uniform min), so every load stays inside the
+      // block whatever the hardware range check covers; those values are unused
 #pragma unroll
-    for (int st = 0; st < U; ++st) {
-      const int step = v0 / 2 + U + st < last_step ? v0 / 2 + U + st : last_step;
+      for (int st = 0; st < U; ++st) {
+        const int step = v0 / 2 + U + st < last_step ? v0 / 2 + U + st : last_step;
 #pragma unroll
-      for (int i = 0; i < TPW; ++i) anxt[st][i] = ld_buf(rs, aoff[i], step * step_bytes);
+        for (int i = 0; i < TPW; ++i) anxt[st][i] = ld_buf(rs, aoff[i], step * step_bytes);
+      }
+      // keep the prefetch ahead of this step's MFMAs
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int st = 0; st < U; ++st) {
+        const float2 xv = xs[rsel * ld + (v0 - vbase) + 2 * st + h];
+        const float bre = dimag ? xv.y : xv.x;
+        const float bim = dimag ? xv.x : -xv.y;
+#pragma unroll
+        for (int i = 0; i < TPW; ++i)
+          acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(acur[st][i].x, bre, acc[i], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < TPW; ++i)
+          acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(acur[st][i].y, bim, acc[i], 0, 0, 0);
+      }
+#pragma unroll
+      for (int st = 0; st < U; ++st)
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) acur[st][i] = anxt[st][i];
     }
-    // keep the prefetch ahead of this step's MFMAs
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int st = 0; st < U; ++st) {
-      const int v = v0 + 2 * st + h;
-      const float2 xv = xs[rsel * ld + v];
-      const float bre = dimag ? xv.y : xv.x;
-      const float bim = dimag ? xv.x : -xv.y;
-#pragma unroll
-      for (int i = 0; i < TPW; ++i) acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(acur[st][i].x, bre, acc[i], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < TPW; ++i) acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(acur[st][i].y, bim, acc[i], 0, 0, 0);
-    }
-#pragma unroll
-    for (int st = 0; st < U; ++st)
-#pragma unroll
-      for (int i = 0; i < TPW; ++i) acur[st][i] = anxt[st][i];
-  }
-  // stage outputs in LDS as [r][u] complex, then store the frequency's panel
+  };
+  // first half of the source index, then the second (n/2 is a multiple of
+  // 2U, so each half is a whole number of loop steps)
+  stage(0);
   __syncthreads();
+  sweep(0, hn, 0);
+  __syncthreads();
+  stage(hn);
+  __syncthreads();
+  sweep(hn, n, hn);
+  // outputs in two halves of eight right-hand sides: stage [r][u] complex in
+  // LDS, then non-temporal 16-byte stores of element pairs (the run of a
+  // right-hand side starts on an even element because n_eq is even)
   float* ysf = reinterpret_cast<float*>(xs);
-#pragma unroll
-  for (int i = 0; i < TPW; ++i) {
-    if (!tv[i]) continue;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int u = tile[i] * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
-      ysf[2 * (rsel * ld + u) + (dimag ? 1 : 0)] = acc[i][e];
-    }
-  }
-  __syncthreads();
-  // the panel yk[r][u] (r < nr) is one contiguous run starting on an even
-  // element (n_eq is even): non-temporal 16-byte stores of element pairs,
-  // which never straddle two right-hand sides
   float2* yk = yh + k * (long long)nrhs * n + (long long)r0 * n;
-  for (int i = threadIdx.x; i < nr * n / 2; i += blockDim.x) {
-    const int e = 2 * i;
-    const int r = e / n, u = e - r * n;
-    const float2 p0 = xs[r * ld + u], p1 = xs[r * ld + u + 1];
-    const fvec4 v = {p0.x, p0.y, p1.x, p1.y};
-    __builtin_nontemporal_store(v, reinterpret_cast<fvec4*>(yk + e));
+  for (int half = 0; half < 2; ++half) {
+    const int rlo = 8 * half;
+    const int cnt = nr - rlo < 8 ? nr - rlo : 8;
+    if (cnt <= 0) break;
+    __syncthreads();
+    if ((rsel >> 3) == half) {
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        if (!tv[i]) continue;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int u = tile[i] * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+          ysf[2 * ((rsel - rlo) * ldo + u) + (dimag ? 1 : 0)] = acc[i][e];
+        }
+      }
+    }
+    __syncthreads();
+    float2* yo = yk + (long long)rlo * n;
+    for (int i = threadIdx.x; i < cnt * n / 2; i += blockDim.x) {
+      const int e = 2 * i;
+      const int r = e / n, u = e - r * n;
+      const float2 p0 = xs[r * ldo + u], p1 = xs[r * ldo + u + 1];
+      const fvec4 v = {p0.x, p0.y, p1.x, p1.y};
+      __builtin_nontemporal_store(v, reinterpret_cast<fvec4*>(yo + e));
+    }
   }
 }
 
@@ -146,8 +171,9 @@ void launch_mfma(const void* That, const void* xh, void* yh, int n, int nrhs, in
                  hipStream_t s) {
   const int waves = mfma_waves(n, TPW);
   EMS_CHECK_ARG(waves >= 1 && waves <= 4, "MFMA variant needs at most 4 wavefronts per frequency");
-  EMS_CHECK_ARG((n / 2) % U == 0, "MFMA variant needs n_eq / 2 divisible by its prefetch depth");
-  const size_t shm = (size_t)16 * (n + 1) * sizeof(float2);
+  EMS_CHECK_ARG((n / 2) % (2 * U) == 0, "MFMA variant needs n_eq / 2 divisible by twice its prefetch depth");
+  const size_t a = (size_t)16 * (n / 2 + 1) * sizeof(float2), b = (size_t)8 * (n + 1) * sizeof(float2);
+  const size_t shm = a > b ? a : b;
   EMS_CHECK_ARG(shm <= 65536, "MFMA variant needs n_eq <= 480");
   hipLaunchKernelGGL((block_mfma_kernel<TPW, U>), dim3((unsigned)P), dim3(64 * waves), shm, s,
                      static_cast<const float2*>(That), static_cast<const float2*>(xh), static_cast<float2*>(yh), n,
