@@ -199,6 +199,28 @@ emsurf_status emsurf_fill_LK_point_green(const emsurf_geom* geom, int32_t nx, in
 emsurf_status emsurf_macromodels(int32_t n_types, int32_t n_eq, int32_t n_int, const void* Z_dev,
                                  const void* Zself_dev, void* S_dev, void* Zt_dev, void* stream);
 
+/* Far field radiated by the equivalent currents of every box (Sec. II-A:
+ * the equivalent J and M on each fictitious surface radiate the exterior
+ * field; Sec. III: they are the solved unknowns), with the point-sampled
+ * currents of the coupling fill (patch q of element (ix, iy) carries
+ * J = sum_a x_J[q, a] t_qa at rho_q + pitch (ix, iy, 0), M likewise) and
+ * eta = 1, common factor -jk e^{-jkr} / (4 pi r) dropped:
+ *     E_theta = N . theta^ + L . phi^,   E_phi = N . phi^ - L . theta^,
+ *     N = sum A_q J e^{jk rhat . r'},    L = sum A_q M e^{jk rhat . r'}.
+ * Directions are the bins of an Lu x Lv lattice DFT: bin (q, p) has direction
+ * cosines u = 2 pi p' / (Lu k pitch), v = 2 pi q' / (Lv k pitch), with p', q'
+ * the signed bin indices (p' = p for p < Lu/2, else p - Lu), w = cos(theta) =
+ * sqrt(1 - u^2 - v^2) >= 0 (upper half space, phi = 0 at the zenith).
+ *   x_dev   c128 [nrhs][ny][nx][n_eq], n_eq = 4 * geom->n_patch (J unknowns first).
+ *   E_dev   c128 [nrhs][Lv][Lu][2] output (E_theta, E_phi) per bin; bins with
+ *           u^2 + v^2 >= 1 (no real direction) are set to zero.
+ * Lu >= nx and Lv >= ny must be supported FFT lengths (2^a <= 1024 or
+ * 3 * 2^a <= 768); larger ones sample the pattern more finely.  Workspaces of
+ * nrhs * n_eq * Lu * (ny + Lv) complex values are allocated for the call,
+ * which synchronises `stream` before returning. */
+emsurf_status emsurf_far_field(const emsurf_geom* geom, int32_t nx, int32_t ny, int32_t nrhs, int32_t Lu,
+                               int32_t Lv, const void* x_dev, void* E_dev, void* stream);
+
 /* y = T x over nrhs right-hand sides (1 <= nrhs <= max_rhs).  x_dev and y_dev
  * are c128 for EMSURF_FP64 and c64 for EMSURF_FP32, [nrhs][ny][nx][n_eq]; they
  * must not overlap.  Requires the matching store in the plan. */

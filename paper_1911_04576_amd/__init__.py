@@ -111,6 +111,8 @@ _SIGS = {
     "emsurf_fill_T_point_green": (ctypes.c_int, [ctypes.POINTER(emsurf_geom), ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "emsurf_fill_LK_point_green": (ctypes.c_int, [ctypes.POINTER(emsurf_geom), ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "emsurf_macromodels": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P]),
+    "emsurf_far_field": (ctypes.c_int, [ctypes.POINTER(emsurf_geom), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
     "emsurf_apply_T": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
     "emsurf_apply_S": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
     "emsurf_apply_A": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
@@ -296,6 +298,12 @@ def emsurf_macromodels(n_types, n_eq, n_int, Z_dev, Zself_dev, S_dev, Zt_dev=Non
     _check(lib().emsurf_macromodels(int(n_types), int(n_eq), int(n_int), _dptr(Z_dev),
                                     None if Zself_dev is None else _dptr(Zself_dev), _dptr(S_dev),
                                     None if Zt_dev is None else _dptr(Zt_dev), _stream(stream)))
+
+
+def emsurf_far_field(geom: Geometry, nx, ny, nrhs, Lu, Lv, x_dev, E_dev, stream=None):
+    """x_dev c128 [nrhs][ny][nx][n_eq]; E_dev c128 [nrhs][Lv][Lu][2] (E_theta, E_phi)."""
+    _check(lib().emsurf_far_field(ctypes.byref(geom.c), int(nx), int(ny), int(nrhs), int(Lu), int(Lv),
+                                  _dptr(x_dev), _dptr(E_dev), _stream(stream)))
 
 
 def emsurf_apply_T(plan: Plan, prec, nrhs, x_dev, y_dev, stream=None):

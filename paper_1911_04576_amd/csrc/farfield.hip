@@ -1,0 +1,131 @@
+// Far field radiated by the equivalent currents of every box (Sec. II-A: the
+// equivalent J and M on a fictitious surface radiate the exterior field;
+// Sec. III: they are the solved unknowns).  With the point-sampled currents of
+// the coupling fill (patch q of element m carries J = sum_a xJ t_qa at
+// rho_q + pitch (ix, iy, 0), M likewise) and eta = 1,
+//     E_theta = N . theta^ + L . phi^,   E_phi = N . phi^ - L . theta^,
+//     N = sum A_q J e^{jk rhat . r'},    L = sum A_q M e^{jk rhat . r'}
+// (common factor -jk e^{-jkr}/(4 pi r) dropped).  At the direction cosines of
+// the bins of an Lu x Lv lattice DFT, k pitch u = 2 pi p' / Lu (p' the signed
+// bin), the sum over elements is the zero-padded 2-D DFT with kernel
+// e^{+j 2 pi (p ix / Lu + q iy / Lv)} of the lattice data: two Stockham
+// passes of sign +1 (the passes of the coupling apply), then one projection
+// per bin over the patches of a box.
+#include "internal.h"
+
+namespace emsurf {
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// One thread per (bin q, bin p, right-hand side r).  X[q][p][r][u] holds the
+// lattice DFT of the unknowns; E[r][q][p][2] receives (E_theta, E_phi), zero
+// outside the visible region u^2 + v^2 < 1.
+__global__ void far_field_kernel(const double2* __restrict__ X, const double* __restrict__ rho,
+                                 const double* __restrict__ area, const double* __restrict__ tan, int P, double pitch,
+                                 double k, int Lu, int Lv, int nrhs, double2* __restrict__ E) {
+  const long long total = (long long)Lv * Lu * nrhs;
+  const int n = 4 * P;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(t % nrhs);
+    const long long bin = t / nrhs;
+    const int p = (int)(bin % Lu), q = (int)(bin / Lu);
+    const int ps = p < (Lu + 1) / 2 ? p : p - Lu;
+    const int qs = q < (Lv + 1) / 2 ? q : q - Lv;
+    const double u = 2.0 * 3.14159265358979323846 * ps / (Lu * k * pitch);
+    const double v = 2.0 * 3.14159265358979323846 * qs / (Lv * k * pitch);
+    double2* out = E + (((long long)r * Lv + q) * Lu + p) * 2;
+    const double s2 = u * u + v * v;
+    if (!(s2 < 1.0)) {
+      out[0] = double2{0.0, 0.0};
+      out[1] = double2{0.0, 0.0};
+      continue;
+    }
+    const double w = sqrt(1.0 - s2), st = sqrt(s2);
+    const double cp = st > 0.0 ? u / st : 1.0, sp = st > 0.0 ? v / st : 0.0;
+    const double th[3] = {w * cp, w * sp, -st};
+    const double ph[3] = {-sp, cp, 0.0};
+    const double2* xb = X + (bin * nrhs + r) * n;
+    double2 N[3] = {{0, 0}, {0, 0}, {0, 0}}, L[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int i = 0; i < P; ++i) {
+      double sn, cs;
+      sincos(k * (u * rho[3 * i] + v * rho[3 * i + 1] + w * rho[3 * i + 2]), &sn, &cs);
+      const double2 ph_i{area[i] * cs, area[i] * sn};
+      const double2 j0 = cmul(ph_i, xb[2 * i]), j1 = cmul(ph_i, xb[2 * i + 1]);
+      const double2 m0 = cmul(ph_i, xb[2 * P + 2 * i]), m1 = cmul(ph_i, xb[2 * P + 2 * i + 1]);
+      const double* t0 = tan + 6 * i;
+      const double* t1 = t0 + 3;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        N[c].x += j0.x * t0[c] + j1.x * t1[c];
+        N[c].y += j0.y * t0[c] + j1.y * t1[c];
+        L[c].x += m0.x * t0[c] + m1.x * t1[c];
+        L[c].y += m0.y * t0[c] + m1.y * t1[c];
+      }
+    }
+    double2 et{0, 0}, ep{0, 0};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      et.x += N[c].x * th[c] + L[c].x * ph[c];
+      et.y += N[c].y * th[c] + L[c].y * ph[c];
+      ep.x += N[c].x * ph[c] - L[c].x * th[c];
+      ep.y += N[c].y * ph[c] - L[c].y * th[c];
+    }
+    out[0] = et;
+    out[1] = ep;
+  }
+}
+
+}  // namespace
+}  // namespace emsurf
+
+using namespace emsurf;
+
+extern "C" emsurf_status emsurf_far_field(const emsurf_geom* geom, int32_t nx, int32_t ny, int32_t nrhs, int32_t Lu,
+                                          int32_t Lv, const void* x_dev, void* E_dev, void* stream) {
+  try {
+    EMS_CHECK_ARG(x_dev != nullptr && E_dev != nullptr, "x_dev and E_dev must be non-NULL");
+    EMS_CHECK_ARG(nx >= 1 && ny >= 1 && nx <= 1024 && ny <= 1024, "lattice sizes must be in [1, 1024]");
+    EMS_CHECK_ARG(nrhs >= 1 && nrhs <= 64, "nrhs must be in [1, 64]");
+    EMS_CHECK_ARG(fft_length_supported(Lu) && fft_length_supported(Lv) && Lu >= nx && Lv >= ny,
+                  "Lu, Lv must be supported FFT lengths (2^a <= 1024 or 3 * 2^a <= 768) with Lu >= nx, Lv >= ny");
+    EMS_CHECK_ARG(geom != nullptr && geom->k > 0, "the far field needs a wavenumber k > 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GreenGeomDev g;
+    upload_geom(geom, g);
+    const int n = 4 * g.n_patch;
+    const int64_t B = (int64_t)nrhs * n, M = (int64_t)nx * ny;
+    DevBuf W((size_t)ny * Lu * B * 16), X((size_t)Lv * Lu * B * 16);
+    // along x: lines (r, iy); x[r][iy][ix][u] -> W[iy][p][r][u]
+    FftPass fx;
+    fx.L = Lu; fx.n_in = nx; fx.n_out = Lu; fx.batch = n;
+    fx.n_lines = nrhs * ny; fx.nl0 = ny;
+    fx.in_s1 = M * n; fx.in_s0 = (int64_t)nx * n; fx.in_pt = n;
+    fx.out_s1 = n; fx.out_s0 = (int64_t)Lu * B; fx.out_pt = B;
+    fx.sign = +1;
+    launch_fft_pass(fx, Cx::C128, Cx::C128, Cx::C128, x_dev, W.p, twiddle_table(Lu, Cx::C128), s);
+    // along y: lines p; W[iy][p][b] -> X[q][p][b]
+    FftPass fy;
+    fy.L = Lv; fy.n_in = ny; fy.n_out = Lv; fy.batch = (int)B;
+    fy.n_lines = Lu; fy.nl0 = Lu;
+    fy.in_s0 = B; fy.in_pt = (int64_t)Lu * B;
+    fy.out_s0 = B; fy.out_pt = (int64_t)Lu * B;
+    fy.sign = +1;
+    launch_fft_pass(fy, Cx::C128, Cx::C128, Cx::C128, W.p, X.p, twiddle_table(Lv, Cx::C128), s);
+    const long long total = (long long)Lv * Lu * nrhs;
+    long long grid = (total + 255) / 256;
+    if (grid > 65536) grid = 65536;
+    hipLaunchKernelGGL(far_field_kernel, dim3((unsigned)grid), dim3(256), 0, s, X.as<const double2>(),
+                       g.rho.as<const double>(), g.area.as<const double>(), g.tan.as<const double>(), g.n_patch,
+                       g.pitch, g.k, Lu, Lv, nrhs, static_cast<double2*>(E_dev));
+    EMS_LAUNCH_CHECK();
+    // the workspaces and geometry are freed on return
+    EMS_HIP(hipStreamSynchronize(s));
+    return EMSURF_OK;
+  } catch (...) {
+    return current_exception_status();
+  }
+}

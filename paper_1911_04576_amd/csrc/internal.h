@@ -184,6 +184,8 @@ struct GreenGeomDev {
   int n_patch = 0;
   double pitch = 0, k = 0;
 };
+// validate a box geometry (finite pitch > 0, areas > 0) and copy it to the device
+void upload_geom(const emsurf_geom* g, GreenGeomDev& d);
 // caller blocks: `parts` row-major nb x nb matrices per offset (1 x n_eq dense; 2 x n_h for L, K)
 void launch_pad_blocks(const void* T_blocks_dev, int nx, int ny, int nb, int parts, int Lx, int Ly, int64_t c0,
                        int64_t nc, void* K, hipStream_t s);

@@ -190,6 +190,23 @@ void apply_A_typed(emsurf_plan p, Cx tx, Cx tc, Cx ty, int nrhs, const void* x, 
   launch_apply_S(tc, tc, ty, S, p->tiles, p->d.n_eq, p->M, nrhs, w.t.p, x, y, s);
 }
 
+void upload_geom(const emsurf_geom* g, GreenGeomDev& d) {
+  EMS_CHECK_ARG(g != nullptr && g->rho && g->area && g->tan, "geometry pointers must be non-NULL");
+  EMS_CHECK_ARG(g->n_patch >= 1, "n_patch must be >= 1");
+  EMS_CHECK_ARG(std::isfinite(g->pitch) && g->pitch > 0 && std::isfinite(g->k), "pitch must be > 0, k finite");
+  const int P = g->n_patch;
+  for (int i = 0; i < P; ++i) EMS_CHECK_ARG(g->area[i] > 0 && std::isfinite(g->area[i]), "patch areas must be > 0");
+  d.n_patch = P;
+  d.pitch = g->pitch;
+  d.k = g->k;
+  d.rho.alloc((size_t)P * 3 * 8);
+  d.area.alloc((size_t)P * 8);
+  d.tan.alloc((size_t)P * 6 * 8);
+  EMS_HIP(hipMemcpy(d.rho.p, g->rho, (size_t)P * 3 * 8, hipMemcpyHostToDevice));
+  EMS_HIP(hipMemcpy(d.area.p, g->area, (size_t)P * 8, hipMemcpyHostToDevice));
+  EMS_HIP(hipMemcpy(d.tan.p, g->tan, (size_t)P * 6 * 8, hipMemcpyHostToDevice));
+}
+
 }  // namespace emsurf
 
 emsurf_plan_s::~emsurf_plan_s() {
@@ -286,23 +303,6 @@ void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill) {
     launch_store_chunk(K.p, P, nn, c0, cnt, p->that64.p, p->that32.p, s);
   }
   EMS_HIP(hipStreamSynchronize(s));
-}
-
-void upload_geom(const emsurf_geom* g, GreenGeomDev& d) {
-  EMS_CHECK_ARG(g != nullptr && g->rho && g->area && g->tan, "geometry pointers must be non-NULL");
-  EMS_CHECK_ARG(g->n_patch >= 1, "n_patch must be >= 1");
-  EMS_CHECK_ARG(std::isfinite(g->pitch) && g->pitch > 0 && std::isfinite(g->k), "pitch must be > 0, k finite");
-  const int P = g->n_patch;
-  for (int i = 0; i < P; ++i) EMS_CHECK_ARG(g->area[i] > 0 && std::isfinite(g->area[i]), "patch areas must be > 0");
-  d.n_patch = P;
-  d.pitch = g->pitch;
-  d.k = g->k;
-  d.rho.alloc((size_t)P * 3 * 8);
-  d.area.alloc((size_t)P * 8);
-  d.tan.alloc((size_t)P * 6 * 8);
-  EMS_HIP(hipMemcpy(d.rho.p, g->rho, (size_t)P * 3 * 8, hipMemcpyHostToDevice));
-  EMS_HIP(hipMemcpy(d.area.p, g->area, (size_t)P * 8, hipMemcpyHostToDevice));
-  EMS_HIP(hipMemcpy(d.tan.p, g->tan, (size_t)P * 6 * 8, hipMemcpyHostToDevice));
 }
 
 // Workspace of the creating stream and every twiddle table the applies need are
