@@ -501,6 +501,20 @@ def main():
         solve["speedup_fp32_ir_vs_fp64"] = round(solve["fp64"]["ms"] / solve["fp32_ir"]["ms"], 3)
         solve["tol"] = cfg.tol
 
+    # far field of the solved currents (the last FP64 solve's x) at the bins of a 256 x 256 lattice DFT
+    far = None
+    if solve is not None:
+        geom_ff = geom
+        Eff = torch.empty((nrhs, 256, 256, 2), dtype=torch.complex128, device=dev)
+        E.emsurf_far_field(geom_ff, cfg.nx, cfg.ny, nrhs, 256, 256, x, Eff)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            E.emsurf_far_field(geom_ff, cfg.nx, cfg.ny, nrhs, 256, 256, x, Eff)
+        far = {"bins": [256, 256], "nrhs": nrhs, "ms": round(1e3 * (time.perf_counter() - t0) / 3, 3),
+               "peak_abs_E": round(float(Eff.abs().max().item()), 4)}
+        log(f"far field: {far}")
+        del Eff
+
     # plain device copy of a known size (bandwidth reference and counter calibration)
     copy = None
     if args.copy_cal:
@@ -605,6 +619,7 @@ def main():
         "multi_rhs_64x64": multi,
         "structured_lk_128x128": structured,
         "macromodel_generation": macromodels,
+        "far_field_128x128": far,
         "serving": serving,
         "serving_structured": serving_structured,
         "solve": solve,
