@@ -61,12 +61,16 @@ def cpu_baseline(cfg, b, y_gpu, budget_s=15.0):
     }, max(errs)
 
 
-def measured_traffic():
+def measured_traffic(recip=True):
     """HBM bytes per FP32 block-product launch from the committed counter summary,
     or None if the kernel source changed since the counters were taken."""
     import hashlib
-    rec = os.path.join(ROOT, "profiles", "block_product_128x128_n192_rhs4_fp32_traffic.txt")
-    src = os.path.join(ROOT, "paper_1911_04576_amd", "csrc", "blockprod.hip")
+    if recip:
+        rec = os.path.join(ROOT, "profiles", "block_product_pair_128x128_n192_rhs4_fp32_traffic.txt")
+        src = os.path.join(ROOT, "paper_1911_04576_amd", "csrc", "blockprod_pair.hip")
+    else:
+        rec = os.path.join(ROOT, "profiles", "block_product_128x128_n192_rhs4_fp32_traffic.txt")
+        src = os.path.join(ROOT, "paper_1911_04576_amd", "csrc", "blockprod.hip")
     try:
         kv = dict(l.strip().split("=", 1) for l in open(rec) if "=" in l and not l.startswith("#"))
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -401,6 +405,8 @@ def main():
                     help="also run the serving section with structured (L, K) plans")
     ap.add_argument("--no-structured", action="store_true",
                     help="skip the structured (L, K) operator section at 128x128")
+    ap.add_argument("--full-store", action="store_true",
+                    help="time the headline apply on a plan that stores every frequency (no reciprocal pairing)")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--serving-budget-gb", type=float, default=230.0)
     args = ap.parse_args()
@@ -426,13 +432,14 @@ def main():
     log(f"plan: {cfg.nx}x{cfg.ny} lattice, n_eq {n}, {cfg.n_unknowns} unknowns, {nrhs} RHS")
     t0 = time.perf_counter()
     geom = E.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)
-    plan = E.emsurf_plan_create_green(cfg.nx, cfg.ny, cfg.n_types, nrhs, geom, S, tm, stream=stream)
+    recip = 0 if args.full_store else 1
+    plan = E.emsurf_plan_create_green(cfg.nx, cfg.ny, cfg.n_types, nrhs, geom, S, tm, stream=stream, recip=recip)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     st = plan.stats()
-    P, Lx, Ly = st.n_freq, st.Lx, st.Ly
-    log(f"plan built in {plan_s:.2f} s: padded {Lx}x{Ly}, FP32 store {st.bytes_that32 / 1e9:.2f} GB, "
-        f"total {st.bytes_total / 1e9:.2f} GB")
+    P, Ps, Lx, Ly = st.n_freq, st.n_stored, st.Lx, st.Ly
+    log(f"plan built in {plan_s:.2f} s: padded {Lx}x{Ly}, {Ps} stored blocks (reciprocal {recip}), "
+        f"FP32 store {st.bytes_that32 / 1e9:.2f} GB, total {st.bytes_total / 1e9:.2f} GB")
 
     b64 = torch.from_numpy(b).to(dev)
     x32 = b64.to(torch.complex64)
@@ -459,8 +466,8 @@ def main():
     # algorithmic bytes (FP32: 8-byte complex)
     sT = sv = 8
     B = nrhs * n
-    bp_bytes = P * n * n * sT + 2 * P * B * sv          # That once, spectral x read, spectral y written
-    apply_bytes = 4 * M * n * n * sT + 18 * M * n * nrhs * sv
+    bp_bytes = Ps * n * n * sT + 2 * P * B * sv         # stored blocks once, spectral x read, spectral y written
+    apply_bytes = Ps * n * n * sT + 18 * M * n * nrhs * sv
     bp_ms, bp_cnt = phases["block_product"]
     bp_avg = bp_ms / max(1, bp_cnt)
     bp_gbs = bp_bytes / (bp_avg / 1e3) / 1e9
@@ -479,6 +486,40 @@ def main():
     torch.cuda.synchronize()
     ms64 = 1e3 * (time.perf_counter() - t0) / k64
     log(f"T-apply fp64: {ms64:.3f} ms/step")
+
+    # the same operator on a plan that stores every frequency (reference)
+    full = None
+    if recip:
+        pf = E.emsurf_plan_create_green(cfg.nx, cfg.ny, cfg.n_types, nrhs, geom, S, tm, stream=stream,
+                                        store=E.EMSURF_STORE_FP32)
+        yf = torch.empty_like(x32)
+        for _ in range(3):
+            E.emsurf_apply_T(pf, E.EMSURF_FP32, nrhs, x32, yf, stream)
+        torch.cuda.synchronize()
+        E.emsurf_kernel_timing(pf, True)
+        E.emsurf_kernel_times(pf)
+        t0 = time.perf_counter()
+        kf = max(5, args.steps // 2)
+        for _ in range(kf):
+            E.emsurf_apply_T(pf, E.EMSURF_FP32, nrhs, x32, yf, stream)
+        torch.cuda.synchronize()
+        msf = 1e3 * (time.perf_counter() - t0) / kf
+        phf = E.emsurf_kernel_times(pf)
+        bpf_ms, bpf_cnt = phf["block_product"]
+        bpf_avg = bpf_ms / max(1, bpf_cnt)
+        bpf_bytes = P * n * n * sT + 2 * P * B * sv
+        diff = float((yf - y32).abs().max().item() / y32.abs().max().item())
+        full = {"ms_per_step": round(msf, 4), "value": cfg.n_unknowns * nrhs / (msf / 1e3),
+                "block_product": {"kernel": "block_gemv_kernel<float2,4,8>", "avg_launch_ms": round(bpf_avg, 4),
+                                  "bytes_per_launch": bpf_bytes,
+                                  "GBs": round(bpf_bytes / (bpf_avg / 1e3) / 1e9, 1),
+                                  "traffic": measured_traffic(recip=False)},
+                "store_GB": round(pf.stats().bytes_that32 / 1e9, 2),
+                "max_rel_diff_vs_reciprocal": float(f"{diff:.3e}")}
+        log(f"full-store T-apply fp32: {msf:.3f} ms/step ({full})")
+        pf.destroy()
+        del yf
+        torch.cuda.empty_cache()
 
     # ---- GMRES solves on the same plan
     solve = None
@@ -604,12 +645,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": "128x128 lattice, n_eq 192 (48 patches/box), 3145728 unknowns, 4 RHS "
                                "(theta 0/30 deg x TE/TM), 16 cell types, FP32 Fourier-domain blocks, "
-                               f"{Lx}x{Ly} padded FFT", "lattice": [cfg.nx, cfg.ny], "n_eq": n, "nrhs": nrhs,
-                   "unknowns": cfg.n_unknowns, "padded_fft": [Lx, Ly], "parallelism": "1 GPU"},
-        "roofline": {"kernel": "block_gemv_kernel<float2,4,8> (Fourier-domain block product)", "bound": "hbm",
+                               f"{Lx}x{Ly} padded FFT, "
+                               + ("reciprocal store (one block per frequency pair)" if recip else "full store"),
+                   "lattice": [cfg.nx, cfg.ny], "n_eq": n, "nrhs": nrhs,
+                   "unknowns": cfg.n_unknowns, "padded_fft": [Lx, Ly], "stored_blocks": Ps,
+                   "parallelism": "1 GPU"},
+        "roofline": {"kernel": ("pair_gemv_kernel<float2,6,4> (paired Fourier-domain block product)" if recip
+                                else "block_gemv_kernel<float2,4,8> (Fourier-domain block product)"),
+                     "bound": "hbm",
                      "achieved": round(bp_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(bp_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                     "frac": round(bp_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(bool(recip)),
                      "bytes_per_launch": bp_bytes, "avg_launch_ms": round(bp_avg, 4)},
+        "full_store_apply": full,
         "apply_T": {"algorithmic_bytes": apply_bytes,
                     "effective_GBs": round(apply_bytes / (ms_step / 1e3) / 1e9, 1),
                     "frac_of_hbm_peak": round(apply_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),

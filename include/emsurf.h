@@ -90,6 +90,9 @@ typedef struct {
   int32_t max_rhs;     /* largest nrhs any apply or solve on this plan uses, 1..64 */
   uint32_t store;      /* EMSURF_STORE_* mask, non-zero */
   int32_t form;        /* EMSURF_T_DENSE (0) or EMSURF_T_LK (1) */
+  int32_t recip;       /* 1: reciprocal operator, store one Fourier-domain block per
+                          frequency pair {k, -k} (see emsurf_plan_create_reciprocal);
+                          EMSURF_T_DENSE only; 0: store every frequency */
   double coef[8];      /* EMSURF_T_LK: a, b, c, e as (re, im) pairs, finite; ignored for dense */
 } emsurf_plan_desc;
 
@@ -132,6 +135,7 @@ typedef struct {
   size_t bytes_that64;      /* FP64 Fourier-domain store, 0 if absent */
   size_t bytes_that32;      /* FP32 store, 0 if absent */
   size_t bytes_total;       /* all device memory the plan holds */
+  int64_t n_stored;         /* Fourier-domain blocks per store: n_freq, or the pair count of a reciprocal plan */
 } emsurf_plan_stats;
 
 /* Device bytes a plan with this descriptor will hold (Fourier-domain stores,
@@ -152,6 +156,36 @@ size_t emsurf_plan_bytes(const emsurf_plan_desc* desc);
 emsurf_status emsurf_plan_create(const emsurf_plan_desc* desc, const void* T_blocks, int32_t T_is_device,
                                  const void* S_types, const int32_t* elem_type, void* stream,
                                  emsurf_plan* out);
+
+/* Reciprocal plans (desc->recip = 1, EMSURF_T_DENSE).  Reciprocity of the
+ * Green's function (Sec. II: a source and a test point may trade places) makes
+ * the blocks of Sec. IV-A satisfy T(-d) = W^-1 T(d)^T W for a diagonal W of
+ * per-unknown weights (the source patch areas of the point-sampled fill); the
+ * circulant embedding of Sec. IV-B turns this into That[-k] = W^-1 That[k]^T W.
+ * A reciprocal plan stores one block per frequency pair {k, -k} (about half the
+ * bytes) and its block products read each stored block once for both
+ * frequencies.  Results equal those of a full plan up to rounding.
+ *   weights  host double [n_eq], finite and non-zero; NULL means all ones
+ *            (T(-d) = T(d)^T).
+ * The blocks are checked before the transform: the call fails with
+ * EMSURF_ERR_ARG if max |T(-d) - W^-1 T(d)^T W| exceeds 1e-9 max |T(d)|, or if
+ * desc->recip != 1.  Other arguments as for emsurf_plan_create (which itself
+ * treats desc->recip = 1 as weights = NULL).  emsurf_plan_create_green with
+ * desc->recip = 1 takes W from the geometry (the source patch area of each
+ * unknown); its fill is reciprocal by construction. */
+emsurf_status emsurf_plan_create_reciprocal(const emsurf_plan_desc* desc, const void* T_blocks,
+                                            int32_t T_is_device, const double* weights,
+                                            const void* S_types, const int32_t* elem_type, void* stream,
+                                            emsurf_plan* out);
+
+/* Stored frequencies of a reciprocal plan with padded lengths Lx, Ly: pair s
+ * of the store holds That[pairs[2s]] and serves k = pairs[2s] and
+ * -k = pairs[2s + 1] (k = ky * Lx + kx, -k = ((Ly - ky) % Ly) * Lx + (Lx - kx) % Lx,
+ * k <= -k; the two are equal for self-paired frequencies).  Pure host
+ * function: writes min(*count, total) pairs into `pairs` (host int32
+ * [2 * capacity], may be NULL with *count = 0) and sets *count to the total,
+ * (Lx Ly + s) / 2 with s the number of self-paired frequencies. */
+emsurf_status emsurf_spectrum_pairs(int32_t Lx, int32_t Ly, int32_t* pairs, int64_t* count);
 
 /* Build a plan whose coupling blocks are the synthetic point-sampled fill of
  * `geom`, computed on the device straight into the padded kernel layout (no
@@ -286,14 +320,17 @@ emsurf_status emsurf_kernel_times(emsurf_plan plan, double* ms, int64_t* count);
  * choice for that nrhs and, if the environment variable EMSURF_TUNE_CACHE names
  * a file, record it there ("n_eq nrhs variant" lines) for later processes.
  * ms_out (may be NULL): EMSURF_BP_NVARIANTS entries, -1 for unsupported
- * variants.  best_out (may be NULL) receives the chosen variant.  Blocks. */
+ * variants.  best_out (may be NULL) receives the chosen variant.  A reciprocal
+ * plan has one kernel, the paired product, timed as variant 0 (no cache
+ * entry).  Blocks. */
 emsurf_status emsurf_plan_autotune(emsurf_plan plan, int32_t nrhs, double* ms_out, int32_t* best_out,
                                    void* stream);
 
 /* Force the FP32 block-product variant used for `nrhs` right-hand sides
  * (EMSURF_BP_AUTO restores: tuned cache entry, else for nrhs >= 8 the deep
  * MFMA variant with the fewest row tiles that fits, else GEMV).
- * EMSURF_ERR_UNSUPPORTED for an MFMA variant this n_eq cannot run. */
+ * EMSURF_ERR_UNSUPPORTED for an MFMA variant this n_eq cannot run, and for
+ * any MFMA variant on a reciprocal plan. */
 emsurf_status emsurf_plan_set_variant(emsurf_plan plan, int32_t nrhs, int32_t variant);
 
 /* ---- HIP-graph capture of an apply ----

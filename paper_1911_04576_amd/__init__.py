@@ -65,7 +65,7 @@ class EmsurfError(RuntimeError):
 class emsurf_plan_desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("n_eq", ctypes.c_int32),
                 ("n_types", ctypes.c_int32), ("max_rhs", ctypes.c_int32), ("store", ctypes.c_uint32),
-                ("form", ctypes.c_int32), ("coef", ctypes.c_double * 8)]
+                ("form", ctypes.c_int32), ("recip", ctypes.c_int32), ("coef", ctypes.c_double * 8)]
 
 
 class emsurf_geom(ctypes.Structure):
@@ -98,7 +98,7 @@ class emsurf_server_stats(ctypes.Structure):
 class emsurf_plan_stats(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("n_freq", ctypes.c_int64),
                 ("bytes_that64", ctypes.c_size_t), ("bytes_that32", ctypes.c_size_t),
-                ("bytes_total", ctypes.c_size_t)]
+                ("bytes_total", ctypes.c_size_t), ("n_stored", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p
@@ -108,6 +108,9 @@ _SIGS = {
                                           ctypes.POINTER(_P)]),
     "emsurf_plan_create_green": (ctypes.c_int, [ctypes.POINTER(emsurf_plan_desc), ctypes.POINTER(emsurf_geom), _P,
                                                 _P, _P, ctypes.POINTER(_P)]),
+    "emsurf_plan_create_reciprocal": (ctypes.c_int, [ctypes.POINTER(emsurf_plan_desc), _P, ctypes.c_int32, _P, _P,
+                                                     _P, _P, ctypes.POINTER(_P)]),
+    "emsurf_spectrum_pairs": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_int64)]),
     "emsurf_fill_T_point_green": (ctypes.c_int, [ctypes.POINTER(emsurf_geom), ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "emsurf_fill_LK_point_green": (ctypes.c_int, [ctypes.POINTER(emsurf_geom), ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "emsurf_macromodels": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P]),
@@ -238,32 +241,37 @@ class Plan:
         return emsurf_plan_query(self)
 
 
-def _desc(nx, ny, n_eq, n_types, max_rhs, store, form=EMSURF_T_DENSE, coef=None):
-    """coef: the four complex constants (a, b, c, e) of EMSURF_T_LK."""
+def _desc(nx, ny, n_eq, n_types, max_rhs, store, form=EMSURF_T_DENSE, coef=None, recip=0):
+    """coef: the four complex constants (a, b, c, e) of EMSURF_T_LK; recip: 1 for
+    a reciprocal plan (one stored block per frequency pair)."""
     c8 = (ctypes.c_double * 8)()
     if coef is not None:
         for i, z in enumerate(coef):
             c8[2 * i], c8[2 * i + 1] = complex(z).real, complex(z).imag
-    return emsurf_plan_desc(int(nx), int(ny), int(n_eq), int(n_types), int(max_rhs), int(store), int(form), c8)
+    return emsurf_plan_desc(int(nx), int(ny), int(n_eq), int(n_types), int(max_rhs), int(store), int(form),
+                            int(recip), c8)
 
 
 def emsurf_plan_bytes(nx, ny, n_eq, n_types, max_rhs, store=EMSURF_STORE_FP64 | EMSURF_STORE_FP32,
-                      form=EMSURF_T_DENSE) -> int:
-    d = _desc(nx, ny, n_eq, n_types, max_rhs, store, form, (0, 0, 0, 0) if form == EMSURF_T_LK else None)
+                      form=EMSURF_T_DENSE, recip=0) -> int:
+    d = _desc(nx, ny, n_eq, n_types, max_rhs, store, form, (0, 0, 0, 0) if form == EMSURF_T_LK else None, recip)
     return int(lib().emsurf_plan_bytes(ctypes.byref(d)))
+
+
+def _blocks_arg(T_blocks):
+    if isinstance(T_blocks, np.ndarray):
+        tb, ptb = _host(T_blocks, np.complex128)
+        return tb, ptb, 0
+    return T_blocks, _dptr(T_blocks), 1
 
 
 def emsurf_plan_create(nx, ny, n_eq, n_types, max_rhs, T_blocks, S_types, elem_type,
                        store=EMSURF_STORE_FP64 | EMSURF_STORE_FP32, stream=None, form=EMSURF_T_DENSE,
-                       coef=None) -> Plan:
+                       coef=None, recip=0) -> Plan:
     """T_blocks: numpy complex128 [2ny-1][2nx-1][n][n] (dense) or [2ny-1][2nx-1][2][n/2][n/2]
     (EMSURF_T_LK: L then K), host array or device tensor."""
-    d = _desc(nx, ny, n_eq, n_types, max_rhs, store, form, coef)
-    if isinstance(T_blocks, np.ndarray):
-        tb, ptb = _host(T_blocks, np.complex128)
-        is_dev = 0
-    else:
-        tb, ptb, is_dev = T_blocks, _dptr(T_blocks), 1
+    d = _desc(nx, ny, n_eq, n_types, max_rhs, store, form, coef, recip)
+    tb, ptb, is_dev = _blocks_arg(T_blocks)
     S, pS = _host(S_types, np.complex128)
     et, pet = _host(elem_type, np.int32)
     out = ctypes.c_void_p()
@@ -271,10 +279,37 @@ def emsurf_plan_create(nx, ny, n_eq, n_types, max_rhs, T_blocks, S_types, elem_t
     return Plan(out.value, d)
 
 
+def emsurf_plan_create_reciprocal(nx, ny, n_eq, n_types, max_rhs, T_blocks, weights, S_types, elem_type,
+                                  store=EMSURF_STORE_FP64 | EMSURF_STORE_FP32, stream=None, recip=1) -> Plan:
+    """Dense blocks with T(-d) = W^-1 T(d)^T W; weights: n_eq reals or None (all ones)."""
+    d = _desc(nx, ny, n_eq, n_types, max_rhs, store, EMSURF_T_DENSE, None, recip)
+    tb, ptb, is_dev = _blocks_arg(T_blocks)
+    if weights is None:
+        wt, pw = None, None
+    else:
+        wt, pw = _host(weights, np.float64)
+    S, pS = _host(S_types, np.complex128)
+    et, pet = _host(elem_type, np.int32)
+    out = ctypes.c_void_p()
+    _check(lib().emsurf_plan_create_reciprocal(ctypes.byref(d), ptb, is_dev, pw, pS, pet, _stream(stream),
+                                               ctypes.byref(out)))
+    return Plan(out.value, d)
+
+
+def emsurf_spectrum_pairs(Lx, Ly) -> np.ndarray:
+    """Stored frequency pairs (k, -k) of a reciprocal plan: int32 [count][2]."""
+    cnt = ctypes.c_int64(0)
+    _check(lib().emsurf_spectrum_pairs(int(Lx), int(Ly), None, ctypes.byref(cnt)))
+    out = np.zeros((cnt.value, 2), dtype=np.int32)
+    if cnt.value:
+        _check(lib().emsurf_spectrum_pairs(int(Lx), int(Ly), out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(cnt)))
+    return out
+
+
 def emsurf_plan_create_green(nx, ny, n_types, max_rhs, geom: Geometry, S_types, elem_type,
                              store=EMSURF_STORE_FP64 | EMSURF_STORE_FP32, stream=None, form=EMSURF_T_DENSE,
-                             coef=None) -> Plan:
-    d = _desc(nx, ny, 4 * geom.n_patch, n_types, max_rhs, store, form, coef)
+                             coef=None, recip=0) -> Plan:
+    d = _desc(nx, ny, 4 * geom.n_patch, n_types, max_rhs, store, form, coef, recip)
     S, pS = _host(S_types, np.complex128)
     et, pet = _host(elem_type, np.int32)
     out = ctypes.c_void_p()
@@ -502,9 +537,9 @@ def emsurf_server_create(budget_bytes, max_slots, opts, store=EMSURF_STORE_FP64 
 
 
 def emsurf_server_submit(srv: Server, key, nx, ny, n_types, geom: Geometry, S_types, elem_type, b,
-                         form=EMSURF_T_DENSE, coef=None) -> int:
+                         form=EMSURF_T_DENSE, coef=None, recip=0) -> int:
     """b: numpy complex128 [nrhs][ny][nx][n_eq] (host)."""
-    d = _desc(nx, ny, 4 * geom.n_patch, n_types, 1, EMSURF_STORE_FP64, form, coef)
+    d = _desc(nx, ny, 4 * geom.n_patch, n_types, 1, EMSURF_STORE_FP64, form, coef, recip)
     S, pS = _host(S_types, np.complex128)
     et, pet = _host(elem_type, np.int32)
     bb, pb = _host(b, np.complex128)

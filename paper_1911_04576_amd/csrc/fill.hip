@@ -205,15 +205,69 @@ __global__ void lk_blocks_kernel(const double* __restrict__ rho, const double* _
 }
 
 __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, long long nn, long long c0,
-                                   long long nc, double2* __restrict__ t64, float2* __restrict__ t32) {
+                                   long long nc, const int* __restrict__ slot_of, int n, double2* __restrict__ t64,
+                                   float2* __restrict__ t32) {
   const long long total = P * nc;
+  const long long blk64 = pair_block_entries64(n), blk32 = pair_block_entries32(n);
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
     const long long kf = i / nc, j = i - kf * nc;
     const double2 v = Kc[i];
-    const long long dst = kf * nn + c0 + j;
-    if (t64) t64[dst] = v;
-    if (t32) t32[dst] = float2{(float)v.x, (float)v.y};
+    if (!slot_of) {
+      const long long dst = kf * nn + c0 + j;
+      if (t64) t64[dst] = v;
+      if (t32) t32[dst] = float2{(float)v.x, (float)v.y};
+      continue;
+    }
+    const long long slot = slot_of[kf];
+    if (slot < 0) continue;
+    const long long col = c0 + j;
+    const int cv = (int)(col / n), u = (int)(col - (long long)cv * n);
+    if (t64) t64[slot * blk64 + pair_offset64(n, u, cv)] = v;
+    if (t32) t32[slot * blk32 + pair_offset32(n, u, cv)] = float2{(float)v.x, (float)v.y};
+  }
+}
+
+// Reciprocity check of dense caller blocks: out[0] = max |T(-d)[u][v] -
+// T(d)[v][u] w[v] / w[u]|, out[1] = max |T(d)[u][v]| (non-negative doubles
+// combined as their bit patterns, which order like the values).
+__global__ void __launch_bounds__(256) recip_check_kernel(const double2* __restrict__ T, int nx, int ny, int n,
+                                                          const double* __restrict__ w,
+                                                          unsigned long long* __restrict__ out) {
+  const long long nn = (long long)n * n;
+  const int wx = 2 * nx - 1, wy = 2 * ny - 1;
+  const long long total = (long long)wx * wy * nn;
+  double dmax = 0.0, mmax = 0.0;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long blk = e / nn;
+    const int r = (int)(e - blk * nn);
+    const int u = r / n, v = r - u * n;
+    const int dyi = (int)(blk / wx), dxi = (int)(blk - (long long)dyi * wx);
+    const long long mirror = (long long)(wy - 1 - dyi) * wx + (wx - 1 - dxi);
+    const double2 a = T[e];
+    const double2 b = T[mirror * nn + (long long)v * n + u];
+    const double f = w[v] / w[u];
+    const double dx = a.x - b.x * f, dy = a.y - b.y * f;
+    const double d = sqrt(dx * dx + dy * dy), m = sqrt(a.x * a.x + a.y * a.y);
+    dmax = (d > dmax || d != d) ? d : dmax;
+    mmax = (m > mmax || m != m) ? m : mmax;
+  }
+  __shared__ double sd[256], sm[256];
+  sd[threadIdx.x] = dmax;
+  sm[threadIdx.x] = mmax;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      const double o = sd[threadIdx.x + st], q = sm[threadIdx.x + st];
+      if (o > sd[threadIdx.x] || o != o) sd[threadIdx.x] = o;
+      if (q > sm[threadIdx.x] || q != q) sm[threadIdx.x] = q;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(out, (unsigned long long)__double_as_longlong(sd[0]));
+    atomicMax(out + 1, (unsigned long long)__double_as_longlong(sm[0]));
   }
 }
 
@@ -279,11 +333,22 @@ void launch_green_blocks(const GreenGeomDev& g, int nx, int ny, void* T_blocks, 
   EMS_LAUNCH_CHECK();
 }
 
-void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, void* that64, void* that32,
-                        hipStream_t s) {
+void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, const int* slot_of, int n,
+                        void* that64, void* that32, hipStream_t s) {
   hipLaunchKernelGGL(store_chunk_kernel, dim3(grid_for((long long)P * nc, 256)), dim3(256), 0, s,
                      static_cast<const double2*>(Kc), (long long)P, (long long)nn, (long long)c0, (long long)nc,
-                     static_cast<double2*>(that64), static_cast<float2*>(that32));
+                     slot_of, n, static_cast<double2*>(that64), static_cast<float2*>(that32));
+  EMS_LAUNCH_CHECK();
+}
+
+void launch_recip_check(const void* T_blocks_dev, int nx, int ny, int n, const double* w_dev, double* out,
+                        hipStream_t s) {
+  EMS_HIP(hipMemsetAsync(out, 0, 2 * sizeof(double), s));
+  const long long total = (long long)(2 * nx - 1) * (2 * ny - 1) * n * n;
+  long long g = (total + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(recip_check_kernel, dim3((unsigned)g), dim3(256), 0, s, static_cast<const double2*>(T_blocks_dev),
+                     nx, ny, n, w_dev, reinterpret_cast<unsigned long long*>(out));
   EMS_LAUNCH_CHECK();
 }
 

@@ -149,6 +149,35 @@ bool block_mfma_supported(int n, int nrhs);
 bool block_variant_supported(int variant, int n, int nrhs);
 void launch_block_product_variant(Cx t, int variant, const void* That, const void* xh, void* yh, int n, int nrhs,
                                   int64_t P, hipStream_t s);
+// Block layouts of the reciprocal store (the last row panel / column tile
+// zero-padded):
+//  FP64: row panels of 4 rows, entry (u, v) at ((u / 4) n + v) 4 + u % 4;
+//  FP32: tiles of 8 rows x 32 columns in [row panel][column tile] order, each
+//        tile row-major: entry (u, v) at ((u / 8 * ct + v / 32) 8 + u % 8) 32 + v % 32,
+//        ct = ceil(n / 32) column tiles.
+constexpr int PAIR_PANEL_FP64 = 4, PAIR_TILE_ROWS = 8, PAIR_TILE_COLS = 32;
+__host__ __device__ inline int pair_col_tiles(int n) { return (n + PAIR_TILE_COLS - 1) / PAIR_TILE_COLS; }
+__host__ __device__ inline int64_t pair_block_entries64(int n) {
+  return (int64_t)((n + PAIR_PANEL_FP64 - 1) / PAIR_PANEL_FP64) * PAIR_PANEL_FP64 * n;
+}
+__host__ __device__ inline int64_t pair_block_entries32(int n) {
+  return (int64_t)((n + PAIR_TILE_ROWS - 1) / PAIR_TILE_ROWS) * PAIR_TILE_ROWS * pair_col_tiles(n) * PAIR_TILE_COLS;
+}
+__host__ __device__ inline int64_t pair_offset64(int n, int u, int v) {
+  return ((int64_t)(u / PAIR_PANEL_FP64) * n + v) * PAIR_PANEL_FP64 + u % PAIR_PANEL_FP64;
+}
+__host__ __device__ inline int64_t pair_offset32(int n, int u, int v) {
+  return (((int64_t)(u / PAIR_TILE_ROWS) * pair_col_tiles(n) + v / PAIR_TILE_COLS) * PAIR_TILE_ROWS + u % PAIR_TILE_ROWS) *
+             PAIR_TILE_COLS + v % PAIR_TILE_COLS;
+}
+// Reciprocal plans: one block per frequency pair {k, -k}; pairs = int [Ps][2]
+// (k, -k), w / winv the per-unknown weights and their inverses in the compute
+// precision.  yh[k] = That[s] xh[k], yh[-k] = W^-1 That[s]^T W xh[-k].
+void launch_block_product_pair(Cx t, const void* That, const void* pairs, const void* w, const void* winv,
+                               const void* xh, void* yh, int n, int nrhs, int64_t Ps, hipStream_t s);
+// pairs (k, -k) with k <= -k in increasing k, flattened; slot_of[k] = pair index or -1
+void spectrum_pairs(int Lx, int Ly, std::vector<int>& pairs, std::vector<int>& slot_of);
+
 // Structured outer operator (EMSURF_T_LK): That per frequency holds the
 // stacked n x n_h matrix [L; K] column-major ([k][v][L|K][u]);
 //   yh[k][r][u] = a L xJ + b K xM (u < n_h),  yh[k][r][n_h + u] = c K xJ + e L xM,
@@ -197,7 +226,15 @@ void launch_green_padded(const GreenGeomDev& g, int nx, int ny, int Lx, int Ly, 
                          hipStream_t s);
 void launch_green_blocks(const GreenGeomDev& g, int nx, int ny, void* T_blocks, hipStream_t s);
 // Scatter a [P][nc] chunk into the [P][n*n] store at column offset c0 (FP64 and/or FP32 rounded).
-void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, void* that64, void* that32,
+// slot_of (device int [P], or NULL for the identity) maps a frequency to its
+// stored block, -1 for frequencies that are not stored; with slot_of the
+// blocks (n x n, kernel column v n + u) go to the row-panel layout of the
+// reciprocal store, else to [k][v][u].
+void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, const int* slot_of, int n,
+                        void* that64, void* that32, hipStream_t s);
+// max |T(-d)[u][v] - T(d)[v][u] w[v] / w[u]| and max |T(d)| over dense caller
+// blocks [2ny-1][2nx-1][n][n] (device), written to out (device double [2]).
+void launch_recip_check(const void* T_blocks_dev, int nx, int ny, int n, const double* w_dev, double* out,
                         hipStream_t s);
 
 // ----------------------------------------------------------------------------- vector ops (GMRES)
@@ -226,7 +263,10 @@ struct emsurf_plan_s {
   int Lx = 0, Ly = 0;
   int64_t P = 0;
   int M = 0;
-  emsurf::DevBuf that64, that32;  // [P][v][u]
+  emsurf::DevBuf that64, that32;  // [Ps][v][u]
+  int64_t Ps = 0;                 // stored blocks: P, or the pair count of a reciprocal plan
+  emsurf::DevBuf pairs;           // reciprocal plans: int [Ps][2]
+  emsurf::DevBuf w64, winv64, w32, winv32;  // reciprocal weights and inverses [n]
   emsurf::DevBuf S64, S32;        // [n_types][n][n] row-major
   emsurf::TypeTiles tiles;
   std::mutex mu;

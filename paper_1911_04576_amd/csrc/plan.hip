@@ -29,11 +29,22 @@ void validate_desc(const emsurf_plan_desc* d) {
     EMS_CHECK_ARG(d->n_eq % 2 == 0, "EMSURF_T_LK needs an even n_eq (J and M halves)");
     for (double c : d->coef) EMS_CHECK_ARG(std::isfinite(c), "EMSURF_T_LK coefficients must be finite");
   }
+  EMS_CHECK_ARG(d->recip == 0 || d->recip == 1, "recip must be 0 or 1");
+  EMS_CHECK_ARG(d->recip == 0 || d->form == EMSURF_T_DENSE, "reciprocal storage is supported for EMSURF_T_DENSE only");
+}
+
+// stored blocks: every frequency, or one per pair {k, -k} (a length L has one
+// self-paired index, 0, when odd and two, 0 and L/2, when even)
+int64_t stored_blocks(int Lx, int Ly, bool recip) {
+  const int64_t P = (int64_t)Lx * Ly;
+  if (!recip) return P;
+  const int64_t self = (Lx % 2 == 0 ? 2 : 1) * (Ly % 2 == 0 ? 2 : 1);
+  return (P + self) / 2;
 }
 
 struct Sizes {
   int Lx, Ly;
-  int64_t P, M, n, nn;
+  int64_t P, Ps, M, n, nn;
   size_t that64, that32, S, tiles, ws;
 };
 
@@ -42,14 +53,18 @@ Sizes sizes_of(const emsurf_plan_desc* d) {
   z.Lx = fft_length_at_least(2 * d->nx - 1);
   z.Ly = fft_length_at_least(2 * d->ny - 1);
   z.P = (int64_t)z.Lx * z.Ly;
+  z.Ps = stored_blocks(z.Lx, z.Ly, d->recip == 1);
   z.M = (int64_t)d->nx * d->ny;
   z.n = d->n_eq;
   z.nn = z.n * z.n;
   const int64_t kc = kernel_cols(*d);
-  z.that64 = (d->store & EMSURF_STORE_FP64) ? (size_t)(z.P * kc) * 16 : 0;
-  z.that32 = (d->store & EMSURF_STORE_FP32) ? (size_t)(z.P * kc) * 8 : 0;
+  const int64_t kc64 = d->recip ? pair_block_entries64(d->n_eq) : kc;
+  const int64_t kc32 = d->recip ? pair_block_entries32(d->n_eq) : kc;
+  z.that64 = (d->store & EMSURF_STORE_FP64) ? (size_t)(z.Ps * kc64) * 16 : 0;
+  z.that32 = (d->store & EMSURF_STORE_FP32) ? (size_t)(z.Ps * kc32) * 8 : 0;
   z.S = (size_t)d->n_types * z.nn * (16 + 8);
   z.tiles = (size_t)z.M * 4 + (size_t)(z.M + d->n_types) * 12;
+  if (d->recip) z.tiles += (size_t)z.Ps * 8 + (size_t)z.n * 24;  // pair list and weights
   const int64_t B = (int64_t)d->max_rhs * z.n;
   z.ws = (size_t)(d->ny * (int64_t)z.Lx * B) * 16 + 2 * (size_t)(z.P * B) * 16 + (size_t)(B * z.M) * 16;
   return z;
@@ -155,8 +170,11 @@ void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* 
 
   // Fourier-domain block products
   timer_begin(p, 2, s, &e);
-  const int v = tc == Cx::C64 ? (variant >= 0 ? variant : choose_variant(p, nrhs)) : BP_GEMV;
-  if (p->d.form == EMSURF_T_LK)
+  const int v = tc == Cx::C64 && !p->d.recip ? (variant >= 0 ? variant : choose_variant(p, nrhs)) : BP_GEMV;
+  if (p->d.recip)
+    launch_block_product_pair(tc, That, p->pairs.p, tc == Cx::C128 ? p->w64.p : p->w32.p,
+                              tc == Cx::C128 ? p->winv64.p : p->winv32.p, w.X.p, w.Y.p, n, nrhs, p->Ps, s);
+  else if (p->d.form == EMSURF_T_LK)
     launch_block_product_lk(tc, v, That, w.X.p, w.Y.p, n / 2, nrhs, p->P, p->d.coef, s);
   else
     launch_block_product_variant(tc, v, That, w.X.p, w.Y.p, n, nrhs, p->P, s);
@@ -274,8 +292,25 @@ template <typename FillChunk>
 void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill) {
   const int64_t nn = kernel_cols(p->d);
   const int64_t P = p->P;
-  if (p->d.store & EMSURF_STORE_FP64) p->that64.alloc((size_t)(P * nn) * 16);
-  if (p->d.store & EMSURF_STORE_FP32) p->that32.alloc((size_t)(P * nn) * 8);
+  const int n = p->d.n_eq;
+  const int64_t kc64 = p->d.recip ? pair_block_entries64(n) : nn;
+  const int64_t kc32 = p->d.recip ? pair_block_entries32(n) : nn;
+  if (p->d.store & EMSURF_STORE_FP64) p->that64.alloc((size_t)(p->Ps * kc64) * 16);
+  if (p->d.store & EMSURF_STORE_FP32) p->that32.alloc((size_t)(p->Ps * kc32) * 8);
+  // the padding rows of the last panel of a reciprocal store stay zero
+  if (p->d.recip && kc64 != nn && p->that64.p) EMS_HIP(hipMemsetAsync(p->that64.p, 0, p->that64.bytes, s));
+  if (p->d.recip && kc32 != nn && p->that32.p) EMS_HIP(hipMemsetAsync(p->that32.p, 0, p->that32.bytes, s));
+  // reciprocal plans keep the representative of each pair {k, -k}
+  DevBuf slot_dev;
+  if (p->d.recip) {
+    std::vector<int> pairs, slot_of;
+    spectrum_pairs(p->Lx, p->Ly, pairs, slot_of);
+    EMS_CHECK_ARG((int64_t)pairs.size() == 2 * p->Ps, "internal: pair count mismatch");
+    p->pairs.alloc(pairs.size() * sizeof(int));
+    slot_dev.alloc(slot_of.size() * sizeof(int));
+    EMS_HIP(hipMemcpyAsync(p->pairs.p, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    EMS_HIP(hipMemcpyAsync(slot_dev.p, slot_of.data(), slot_of.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  }
   // two chunk buffers of at most ~512 MB each
   int64_t nc = (int64_t)((512ull << 20) / ((size_t)P * 16));
   nc = std::max<int64_t>(1, std::min<int64_t>(nc, nn));
@@ -300,7 +335,7 @@ void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill) {
     fy.out_s0 = cnt; fy.out_pt = (int64_t)p->Lx * cnt;
     fy.sign = -1;
     launch_fft_pass(fy, Cx::C128, Cx::C128, Cx::C128, tmp.p, K.p, twy, s);
-    launch_store_chunk(K.p, P, nn, c0, cnt, p->that64.p, p->that32.p, s);
+    launch_store_chunk(K.p, P, nn, c0, cnt, slot_dev.as<const int>(), n, p->that64.p, p->that32.p, s);
   }
   EMS_HIP(hipStreamSynchronize(s));
 }
@@ -324,8 +359,33 @@ emsurf_plan new_plan(const emsurf_plan_desc* desc) {
   p->Lx = z.Lx;
   p->Ly = z.Ly;
   p->P = z.P;
+  p->Ps = z.Ps;
   p->M = (int)z.M;
   return p;
+}
+
+// Reciprocity weights of the unknowns (host, n values): checked and kept on
+// the device in both precisions with their inverses.
+void set_weights(emsurf_plan p, const std::vector<double>& w, hipStream_t s) {
+  const int n = p->d.n_eq;
+  std::vector<double> inv(n);
+  std::vector<float> w32(n), inv32(n);
+  for (int u = 0; u < n; ++u) {
+    EMS_CHECK_ARG(std::isfinite(w[u]) && w[u] != 0.0 && std::isfinite(1.0 / w[u]),
+                  "reciprocity weights must be finite and non-zero");
+    inv[u] = 1.0 / w[u];
+    w32[u] = (float)w[u];
+    inv32[u] = (float)inv[u];
+  }
+  p->w64.alloc((size_t)n * 8);
+  p->winv64.alloc((size_t)n * 8);
+  p->w32.alloc((size_t)n * 4);
+  p->winv32.alloc((size_t)n * 4);
+  EMS_HIP(hipMemcpyAsync(p->w64.p, w.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+  EMS_HIP(hipMemcpyAsync(p->winv64.p, inv.data(), (size_t)n * 8, hipMemcpyHostToDevice, s));
+  EMS_HIP(hipMemcpyAsync(p->w32.p, w32.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+  EMS_HIP(hipMemcpyAsync(p->winv32.p, inv32.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+  EMS_HIP(hipStreamSynchronize(s));
 }
 
 Cx prec_type(emsurf_prec prec) {
@@ -356,8 +416,13 @@ size_t emsurf_plan_bytes(const emsurf_plan_desc* desc) {
   return out;
 }
 
-emsurf_status emsurf_plan_create(const emsurf_plan_desc* desc, const void* T_blocks, int32_t T_is_device,
-                                 const void* S_types, const int32_t* elem_type, void* stream, emsurf_plan* out) {
+}  // extern "C"
+
+namespace {
+
+emsurf_status create_from_blocks(const emsurf_plan_desc* desc, const void* T_blocks, int32_t T_is_device,
+                                 const double* weights, const void* S_types, const int32_t* elem_type, void* stream,
+                                 emsurf_plan* out) {
   emsurf_plan p = nullptr;
   emsurf_status st = guarded([&] {
     EMS_CHECK_ARG(out != nullptr, "out is NULL");
@@ -375,6 +440,21 @@ emsurf_status emsurf_plan_create(const emsurf_plan_desc* desc, const void* T_blo
       EMS_HIP(hipMemcpyAsync(Tdev.p, T_blocks, tb_bytes, hipMemcpyHostToDevice, s));
       Tb = Tdev.p;
     }
+    if (desc->recip) {
+      std::vector<double> w(n, 1.0);
+      if (weights) w.assign(weights, weights + n);
+      set_weights(p, w, s);
+      DevBuf res(2 * sizeof(double));
+      launch_recip_check(Tb, nx, ny, n, p->w64.as<const double>(), res.as<double>(), s);
+      double h[2];
+      EMS_HIP(hipMemcpyAsync(h, res.p, sizeof(h), hipMemcpyDeviceToHost, s));
+      EMS_HIP(hipStreamSynchronize(s));
+      if (!(h[0] <= 1e-9 * h[1])) {
+        set_error("T_blocks are not reciprocal under the given weights: max |T(-d) - W^-1 T(d)^T W| = " +
+                  std::to_string(h[0]) + ", max |T(d)| = " + std::to_string(h[1]));
+        throw Err{EMSURF_ERR_ARG};
+      }
+    }
     build_that(p, s, [&](int64_t c0, int64_t cnt, void* K) {
       launch_pad_blocks(Tb, nx, ny, nb, parts, p->Lx, p->Ly, c0, cnt, K, s);
     });
@@ -390,6 +470,39 @@ emsurf_status emsurf_plan_create(const emsurf_plan_desc* desc, const void* T_blo
   return EMSURF_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+emsurf_status emsurf_plan_create(const emsurf_plan_desc* desc, const void* T_blocks, int32_t T_is_device,
+                                 const void* S_types, const int32_t* elem_type, void* stream, emsurf_plan* out) {
+  return create_from_blocks(desc, T_blocks, T_is_device, nullptr, S_types, elem_type, stream, out);
+}
+
+emsurf_status emsurf_plan_create_reciprocal(const emsurf_plan_desc* desc, const void* T_blocks, int32_t T_is_device,
+                                            const double* weights, const void* S_types, const int32_t* elem_type,
+                                            void* stream, emsurf_plan* out) {
+  if (desc && desc->recip != 1) {
+    set_error("emsurf_plan_create_reciprocal needs desc->recip = 1");
+    return EMSURF_ERR_ARG;
+  }
+  return create_from_blocks(desc, T_blocks, T_is_device, weights, S_types, elem_type, stream, out);
+}
+
+emsurf_status emsurf_spectrum_pairs(int32_t Lx, int32_t Ly, int32_t* pairs, int64_t* count) {
+  return guarded([&] {
+    EMS_CHECK_ARG(count != nullptr, "count is NULL");
+    EMS_CHECK_ARG(Lx >= 1 && Ly >= 1 && (int64_t)Lx * Ly <= (1LL << 30), "Lx, Ly must be >= 1 with Lx Ly <= 2^30");
+    EMS_CHECK_ARG(*count >= 0 && (*count == 0 || pairs != nullptr), "pairs is NULL with a non-zero capacity");
+    std::vector<int> pr, slot_of;
+    spectrum_pairs(Lx, Ly, pr, slot_of);
+    const int64_t total = (int64_t)pr.size() / 2;
+    const int64_t m = std::min(*count, total);
+    for (int64_t i = 0; i < 2 * m; ++i) pairs[i] = pr[(size_t)i];
+    *count = total;
+  });
+}
+
 emsurf_status emsurf_plan_create_green(const emsurf_plan_desc* desc, const emsurf_geom* geom, const void* S_types,
                                        const int32_t* elem_type, void* stream, emsurf_plan* out) {
   emsurf_plan p = nullptr;
@@ -403,6 +516,13 @@ emsurf_status emsurf_plan_create_green(const emsurf_plan_desc* desc, const emsur
     GreenGeomDev g;
     upload_geom(geom, g);
     p = new_plan(desc);
+    if (desc->recip) {
+      // the fill weights each source by its patch area: W = that area per unknown
+      const int P2 = 2 * geom->n_patch;
+      std::vector<double> w(desc->n_eq);
+      for (int u = 0; u < desc->n_eq; ++u) w[u] = geom->area[(u % P2) / 2];
+      set_weights(p, w, s);
+    }
     build_that(p, s, [&](int64_t c0, int64_t cnt, void* K) {
       if (desc->form == EMSURF_T_LK)
         launch_lk_padded(g, desc->nx, desc->ny, p->Lx, p->Ly, c0, cnt, K, s);
@@ -495,8 +615,10 @@ emsurf_status emsurf_plan_query(emsurf_plan plan, emsurf_plan_stats* out) {
     out->n_freq = plan->P;
     out->bytes_that64 = plan->that64.bytes;
     out->bytes_that32 = plan->that32.bytes;
+    out->n_stored = plan->Ps;
     size_t tot = plan->that64.bytes + plan->that32.bytes + plan->S64.bytes + plan->S32.bytes +
-                 plan->tiles.elem_sorted.bytes + plan->tiles.tiles.bytes;
+                 plan->tiles.elem_sorted.bytes + plan->tiles.tiles.bytes + plan->pairs.bytes + plan->w64.bytes +
+                 plan->winv64.bytes + plan->w32.bytes + plan->winv32.bytes;
     std::lock_guard<std::mutex> lk(plan->mu);
     for (auto& kv : plan->ws) tot += kv.second->W.bytes + kv.second->X.bytes + kv.second->Y.bytes + kv.second->t.bytes;
     out->bytes_total = tot;

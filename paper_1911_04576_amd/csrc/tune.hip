@@ -77,6 +77,10 @@ extern "C" emsurf_status emsurf_plan_set_variant(emsurf_plan plan, int32_t nrhs,
     EMS_CHECK_ARG(nrhs >= 1 && nrhs <= plan->d.max_rhs, "nrhs must be in [1, max_rhs]");
     EMS_CHECK_ARG(variant >= -1 && variant < BP_NVARIANTS, "unknown block-product variant");
     const bool structured = plan->d.form == EMSURF_T_LK;
+    if (variant > BP_GEMV && plan->d.recip) {
+      set_error("reciprocal plans have a single (paired) block-product kernel");
+      throw Err{EMSURF_ERR_UNSUPPORTED};
+    }
     if (variant > BP_GEMV && !(structured ? block_variant_supported_lk(variant, plan->d.n_eq, nrhs)
                                           : block_variant_supported(variant, plan->d.n_eq, nrhs))) {
       set_error("this MFMA block-product variant needs n_eq a multiple of 32 (<= 480) and at most 4 "
@@ -112,15 +116,22 @@ extern "C" emsurf_status emsurf_plan_autotune(emsurf_plan plan, int32_t nrhs, do
     double best_ms = 1e300;
     // structured (L, K) plans time their own kernels under the same variant numbers
     const bool structured = plan->d.form == EMSURF_T_LK;
+    // reciprocal plans have one kernel, the paired product, timed as variant 0
+    const bool recip = plan->d.recip != 0;
     auto run = [&](int v) {
-      if (structured)
+      if (recip)
+        launch_block_product_pair(Cx::C64, plan->that32.p, plan->pairs.p, plan->w32.p, plan->winv32.p, w.X.p, w.Y.p,
+                                  n, nrhs, plan->Ps, s);
+      else if (structured)
         launch_block_product_lk(Cx::C64, v, plan->that32.p, w.X.p, w.Y.p, n / 2, nrhs, plan->P, plan->d.coef, s);
       else
         launch_block_product_variant(Cx::C64, v, plan->that32.p, w.X.p, w.Y.p, n, nrhs, plan->P, s);
     };
     for (int v = 0; v < BP_NVARIANTS; ++v) {
       double ms = -1.0;
-      if (structured ? block_variant_supported_lk(v, n, nrhs) : block_variant_supported(v, n, nrhs)) {
+      const bool ok = recip ? v == BP_GEMV
+                            : structured ? block_variant_supported_lk(v, n, nrhs) : block_variant_supported(v, n, nrhs);
+      if (ok) {
         run(v);  // warm-up
         const int reps = 3;
         EMS_HIP(hipEventRecord(e0, s));
@@ -136,7 +147,7 @@ extern "C" emsurf_status emsurf_plan_autotune(emsurf_plan plan, int32_t nrhs, do
     }
     plan->bp_variant[nrhs] = best;
     if (best_out) *best_out = best;
-    if (!structured) {
+    if (!structured && !recip) {
       std::lock_guard<std::mutex> lk(g_cache_mu);
       load_cache_locked();
       g_cache[{n, nrhs}] = best;

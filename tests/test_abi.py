@@ -2,6 +2,8 @@
 (no compute calls: runs without a GPU)."""
 import ctypes
 import os
+
+import numpy as np
 import re
 
 import pytest
@@ -44,3 +46,36 @@ def test_host_only_calls():
     assert b32 > 256 * 256 * 192 * 192 * 8
     assert E.emsurf_plan_bytes(0, 4, 96, 4, 1) == 0
     assert E.emsurf_plan_bytes(4, 4, 96, 4, 65) == 0
+
+
+@pytest.mark.parametrize("Lx,Ly", [(1, 1), (2, 1), (3, 1), (1, 4), (3, 3), (4, 6), (12, 8), (6, 3), (256, 256)])
+def test_spectrum_pairs_cover_every_frequency_once(Lx, Ly):
+    import paper_1911_04576_amd as E
+    if not os.path.exists(E.LIB_PATH):
+        pytest.skip("library not built")
+    pr = E.emsurf_spectrum_pairs(Lx, Ly)
+    P = Lx * Ly
+    self_paired = (2 if Lx % 2 == 0 else 1) * (2 if Ly % 2 == 0 else 1)
+    assert pr.shape == ((P + self_paired) // 2, 2)
+    k, kb = pr[:, 0].astype(np.int64), pr[:, 1].astype(np.int64)
+    ky, kx = k // Lx, k % Lx
+    assert np.array_equal(kb, ((Ly - ky) % Ly) * Lx + (Lx - kx) % Lx)
+    assert np.all(k <= kb) and np.all(np.diff(k) > 0)
+    seen = np.zeros(P, np.int64)
+    np.add.at(seen, k, 1)
+    np.add.at(seen, kb[kb != k], 1)
+    assert np.all(seen == 1)
+    assert int(np.sum(k == kb)) == self_paired
+
+
+def test_reciprocal_plan_bytes_and_desc_checks():
+    import paper_1911_04576_amd as E
+    if not os.path.exists(E.LIB_PATH):
+        pytest.skip("library not built")
+    full = E.emsurf_plan_bytes(128, 128, 192, 16, 4, store=E.EMSURF_STORE_FP32)
+    half = E.emsurf_plan_bytes(128, 128, 192, 16, 4, store=E.EMSURF_STORE_FP32, recip=1)
+    store = 256 * 256 * 192 * 192 * 8
+    assert abs((full - half) - (store // 2 - 2 * 192 * 192 * 8 - (256 * 256 // 2 + 2) * 8 - 192 * 24)) <= 0
+    # reciprocal storage is for dense blocks only; recip must be 0 or 1
+    assert E.emsurf_plan_bytes(8, 8, 96, 4, 1, form=E.EMSURF_T_LK, recip=1) == 0
+    assert E.emsurf_plan_bytes(8, 8, 96, 4, 1, recip=2) == 0

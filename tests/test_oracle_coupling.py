@@ -254,3 +254,45 @@ def test_paper_1d_example_first_row_reading_fails():
     good = C5 @ Ja
     wrong = np.fft.ifft(np.fft.fft(C5[0, :]) * np.fft.fft(Ja))
     assert np.linalg.norm(wrong[:3] - good[:3]) > 1e-2 * np.linalg.norm(good[:3])
+
+
+@pytest.mark.parametrize("nx,ny,Lx,Ly", [(3, 2, 6, 4), (2, 2, 3, 3), (5, 3, 12, 6), (4, 1, 8, 1)])
+def test_spectral_reciprocity_of_the_circulant_embedding(nx, ny, Lx, Ly):
+    # With T(-d) = W^-1 T(d)^T W the kernel spectrum obeys That[-k] = W^-1 That[k]^T W
+    # (library FFT of the zero-padded circulant embedding, padded lengths even and
+    # odd); this is what lets a plan keep one block per pair {k, -k}.
+    g, G = _geom(24)
+    B = C.coupling_blocks(*G, nx, ny, W.PITCH, W.K0)
+    w = np.tile(np.repeat(g.area, 2), 2)
+    n = B.shape[-1]
+    K = np.zeros((Ly, Lx, n, n), dtype=np.complex128)
+    for dy in range(-(ny - 1), ny):
+        for dx in range(-(nx - 1), nx):
+            K[dy % Ly, dx % Lx] = B[dy + ny - 1, dx + nx - 1]
+    Kh = np.fft.fft2(K, axes=(0, 1))
+    scale = np.abs(Kh).max()
+    for ky in range(Ly):
+        for kx in range(Lx):
+            mine = Kh[(-ky) % Ly, (-kx) % Lx]
+            mirrored = (Kh[ky, kx].T * w[None, :]) / w[:, None]
+            assert np.abs(mine - mirrored).max() <= 1e-13 * scale
+    # a non-reciprocal operator does not have the property
+    Bn = W.random_blocks(nx, ny, n, seed=3)
+    Kn = np.zeros_like(K)
+    for dy in range(-(ny - 1), ny):
+        for dx in range(-(nx - 1), nx):
+            Kn[dy % Ly, dx % Lx] = Bn[dy + ny - 1, dx + nx - 1]
+    Knh = np.fft.fft2(Kn, axes=(0, 1))
+    if nx * ny > 1:
+        assert np.abs(Knh[(-1) % Ly, (-1) % Lx] - Knh[1 % Ly, 1 % Lx].T).max() > 1e-3
+
+
+def test_reciprocal_workload_blocks_satisfy_the_identity():
+    # the seeded reciprocal generator used by the GPU tests honours its contract
+    w = W.random_weights(9, seed=2)
+    B = W.random_reciprocal_blocks(4, 3, 9, w, seed=5, zero_self=False)
+    for dy in range(-2, 3):
+        for dx in range(-3, 4):
+            T, Tm = B[dy + 2, dx + 3], B[-dy + 2, -dx + 3]
+            assert np.abs(Tm - np.diag(1 / w) @ T.T @ np.diag(w)).max() <= 1e-15
+    assert np.abs(B[2, 3]).max() > 0

@@ -135,3 +135,23 @@ def test_sampled_rows_match_dense_assembly():
     rows = LK.apply_T_elements_lk(*G, W.PITCH, W.K0, W.OUTER_COEF, x, elems, chunk_rows=2)
     for i, (iy, ix) in enumerate(elems):
         assert np.abs(rows[i] - y[:, iy, ix]).max() <= 1e-13 * np.abs(y).max()
+
+
+def test_structured_operator_reciprocity_needs_the_signed_weights():
+    # With the paper's constants (b = -c) the assembled outer operator satisfies
+    # T(-d) = W^-1 T(d)^T W with W = diag(A, -A) (J half, M half); with b = c it
+    # would take W = diag(A, A).  A reciprocal store of the structured form
+    # therefore needs the sign.
+    g, G = _geom()
+    d = (1, 2)
+    L, K = LK.lk_blocks_at(*G, [d, (-d[0], -d[1])], W.PITCH, W.K0)
+    a = np.repeat(g.area, 2)
+    for coef, w in [(W.OUTER_COEF, np.concatenate([a, -a])),
+                    ((W.OUTER_COEF[0], 1.0, 1.0, W.OUTER_COEF[3]), np.concatenate([a, a]))]:
+        T = LK.lk_assemble(L[None, None, 0], K[None, None, 0], coef)[0, 0]
+        Tm = LK.lk_assemble(L[None, None, 1], K[None, None, 1], coef)[0, 0]
+        assert np.abs(Tm - (T.T * w[None, :]) / w[:, None]).max() <= 1e-13 * np.abs(T).max()
+    T = LK.lk_assemble(L[None, None, 0], K[None, None, 0], W.OUTER_COEF)[0, 0]
+    Tm = LK.lk_assemble(L[None, None, 1], K[None, None, 1], W.OUTER_COEF)[0, 0]
+    wrong = np.concatenate([a, a])
+    assert np.abs(Tm - (T.T * wrong[None, :]) / wrong[:, None]).max() > 1e-3 * np.abs(T).max()

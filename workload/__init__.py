@@ -242,6 +242,38 @@ def random_blocks(nx: int, ny: int, n_eq: int, seed: int, zero_self: bool = True
     return t
 
 
+def random_weights(n_eq: int, seed: int, signed: bool = True) -> np.ndarray:
+    """Per-unknown reciprocity weights in [0.5, 2) with random signs (or all
+    positive)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 81, seed])))
+    w = 0.5 * 4.0 ** rng.random(n_eq)
+    if signed:
+        w *= np.where(rng.random(n_eq) < 0.5, -1.0, 1.0)
+    return w
+
+
+def random_reciprocal_blocks(nx: int, ny: int, n_eq: int, w: np.ndarray, seed: int,
+                             zero_self: bool = True) -> np.ndarray:
+    """Random blocks with T(-d) = W^-1 T(d)^T W, W = diag(w): T(d) is drawn for
+    the offsets after (0, 0) in [dy][dx] order and mirrored onto -d; T(0) =
+    W^-1 Q with Q complex symmetric (zero if `zero_self`).  Same layout and
+    scale as random_blocks."""
+    t = random_blocks(nx, ny, n_eq, seed, zero_self=True)
+    w = np.asarray(w, dtype=np.float64)
+    cy, cx = ny - 1, nx - 1
+    for dy in range(-(ny - 1), ny):
+        for dx in range(-(nx - 1), nx):
+            if (dy, dx) <= (0, 0):
+                continue
+            t[cy - dy, cx - dx] = (t[cy + dy, cx + dx].T * w[None, :]) / w[:, None]
+    if not zero_self:
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 82, seed])))
+        q = rng.standard_normal((n_eq, n_eq)) + 1j * rng.standard_normal((n_eq, n_eq))
+        q = (q + q.T) * (0.25 / math.sqrt(n_eq * max(1, nx * ny)))
+        t[cy, cx] = q / w[:, None]
+    return t
+
+
 def random_vectors(nrhs: int, nx: int, ny: int, n_eq: int, seed: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 78, seed])))
     shape = (nrhs, ny, nx, n_eq)
