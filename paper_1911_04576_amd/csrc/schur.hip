@@ -40,19 +40,17 @@ __device__ __forceinline__ double2 cinv(double2 a) {
 
 // Panel columns [k0, k0 + kb) over rows [k0, N): pivot, swap (panel columns
 // only), multipliers, update inside the panel.  One workgroup of 512 threads
-// (16 half-wavefronts of 32 lanes, one lane per panel column) per matrix.
+// per matrix.
 // info[b] receives 1 + the first column whose pivot candidates are all zero.
 __global__ void __launch_bounds__(512) panel_kernel(double2* __restrict__ A, int N, int K, int k0, int kb,
                                                     int* __restrict__ piv, int* __restrict__ info) {
   const int b = blockIdx.x;
   double2* M = A + (long long)b * N * N;
-  __shared__ double wave_v[8];
-  __shared__ int wave_i[8];
+  __shared__ double best_v[512];
+  __shared__ int best_i[512];
   __shared__ double2 prow[PANEL];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   for (int kk = k0; kk < k0 + kb; ++kk) {
-    // pivot: largest |a|^2 among the leading rows [kk, K), first index on ties;
-    // reduced within each wavefront by shuffles, then across wavefronts
+    // pivot: largest |a|^2 among the leading rows [kk, K), first index on ties
     double bv = -1.0;
     int bi = kk;
     for (int i = kk + threadIdx.x; i < K; i += blockDim.x) {
@@ -60,22 +58,22 @@ __global__ void __launch_bounds__(512) panel_kernel(double2* __restrict__ A, int
       const double v = a.x * a.x + a.y * a.y;
       if (v > bv) { bv = v; bi = i; }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(bv, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-    }
-    if (lane == 0) {
-      wave_v[wid] = bv;
-      wave_i[wid] = bi;
-    }
+    best_v[threadIdx.x] = bv;
+    best_i[threadIdx.x] = bi;
     __syncthreads();
-    double gv = wave_v[0];
-    int p = wave_i[0];
-    for (int q = 1; q < nwave; ++q) {
-      if (wave_v[q] > gv || (wave_v[q] == gv && wave_i[q] < p)) { gv = wave_v[q]; p = wave_i[q]; }
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) {
+        const double ov = best_v[threadIdx.x + s];
+        const int oi = best_i[threadIdx.x + s];
+        if (ov > best_v[threadIdx.x] || (ov == best_v[threadIdx.x] && oi < best_i[threadIdx.x])) {
+          best_v[threadIdx.x] = ov;
+          best_i[threadIdx.x] = oi;
+        }
+      }
+      __syncthreads();
     }
-    const bool singular = !(gv > 0.0);
+    const int p = best_i[0];
+    const bool singular = !(best_v[0] > 0.0);
     if (threadIdx.x == 0) {
       piv[(long long)b * K + kk] = p;
       if (singular && info[b] == 0) info[b] = kk + 1;
@@ -89,32 +87,20 @@ __global__ void __launch_bounds__(512) panel_kernel(double2* __restrict__ A, int
     }
     __syncthreads();
     const double2 inv = singular ? double2{0.0, 0.0} : cinv(prow[kk - k0]);
-    // multipliers l = a_i,kk / pivot and the rank-1 update of the rest of the
-    // panel, fused: half-wavefront g takes rows kk + 1 + g + ng t, its lane c
-    // column kk + c (c = 0 stores the multiplier).  All lanes of a row sit in
-    // one wavefront and load a_i,kk before lane 0 overwrites it.
-    const int w = k0 + kb - kk;
-    const int c = threadIdx.x & 31, g = threadIdx.x >> 5, ng = blockDim.x >> 5;
-    if (c < w) {
-      const double2 u = prow[kk - k0 + c];
-      for (int i0 = kk + 1 + g; i0 < N; i0 += 4 * ng) {
-        double2 a[4], v[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int i = i0 + ng * q;
-          if (i < N) {
-            a[q] = M[(long long)i * N + kk];
-            v[q] = M[(long long)i * N + kk + c];
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int i = i0 + ng * q;
-          if (i < N) {
-            const double2 l = cmul(a[q], inv);
-            M[(long long)i * N + kk + c] = c == 0 ? l : csub_mul(v[q], l, u);
-          }
-        }
+    for (int i = kk + 1 + threadIdx.x; i < N; i += blockDim.x) {
+      double2* row = M + (long long)i * N;
+      row[kk] = cmul(row[kk], inv);
+    }
+    __syncthreads();
+    // rank-1 update of the rest of the panel, one (row, column) pair per thread
+    const int w = k0 + kb - kk - 1;
+    if (w > 0) {
+      const long long pairs = (long long)(N - kk - 1) * w;
+      for (long long t = threadIdx.x; t < pairs; t += blockDim.x) {
+        const int i = kk + 1 + (int)(t / w);
+        const int j = kk + 1 + (int)(t - (long long)(i - kk - 1) * w);
+        double2* row = M + (long long)i * N;
+        row[j] = csub_mul(row[j], row[kk], prow[j - k0]);
       }
     }
     __syncthreads();
@@ -162,18 +148,16 @@ __global__ void __launch_bounds__(64) swap_trsm_kernel(double2* __restrict__ A, 
     if (i < kb) M[(long long)(k0 + i) * N + j] = x[i];
 }
 
-// Trailing update A22 -= L21 U12 over rows and columns [k0 + kb, N): 64 x 64
-// output tiles, 256 threads each owning a 4 x 4 block of outputs (rows
-// ty + 16 a, columns tx + 16 b), so that every pair of LDS reads feeds 16
-// complex multiply-adds.
-constexpr int TT = 64;
+// Trailing update A22 -= L21 U12 over rows and columns [k0 + kb, N): 32 x 32
+// output tiles, 256 threads each owning 4 outputs of one row.
+constexpr int TT = 32;
 __global__ void __launch_bounds__(256) update_kernel(double2* __restrict__ A, int N, int k0, int kb) {
   const int b = blockIdx.z;
   double2* M = A + (long long)b * N * N;
   const int r0 = k0 + kb + blockIdx.y * TT;
   const int c0 = k0 + kb + blockIdx.x * TT;
   __shared__ double2 Ls[TT][PANEL + 1];
-  __shared__ double2 Us[PANEL][TT];
+  __shared__ double2 Us[PANEL][TT + 1];
   for (int t = threadIdx.x; t < TT * PANEL; t += blockDim.x) {
     const int i = t / PANEL, l = t - i * PANEL;
     const int gi = r0 + i;
@@ -185,38 +169,28 @@ __global__ void __launch_bounds__(256) update_kernel(double2* __restrict__ A, in
     Us[l][jj] = (gj < N && l < kb) ? M[(long long)(k0 + l) * N + gj] : double2{0.0, 0.0};
   }
   __syncthreads();
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  double2 acc[4][4];
+  const int i = threadIdx.x / 8;           // tile row
+  const int jb = (threadIdx.x % 8) * 4;    // first of 4 tile columns
+  const int gi = r0 + i;
+  if (gi >= N) return;
+  double2 acc[4];
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[p][q] = double2{0.0, 0.0};
-#pragma unroll 4
+  for (int q = 0; q < 4; ++q) acc[q] = double2{0.0, 0.0};
   for (int l = 0; l < kb; ++l) {
-    double2 a[4], u[4];
-#pragma unroll
-    for (int p = 0; p < 4; ++p) a[p] = Ls[ty + 16 * p][l];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) u[q] = Us[l][tx + 16 * q];
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        acc[p][q].x = __builtin_fma(a[p].x, u[q].x, __builtin_fma(-a[p].y, u[q].y, acc[p][q].x));
-        acc[p][q].y = __builtin_fma(a[p].x, u[q].y, __builtin_fma(a[p].y, u[q].x, acc[p][q].y));
-      }
-  }
-#pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const int gi = r0 + ty + 16 * p;
-    if (gi >= N) continue;
+    const double2 a = Ls[i][l];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int gj = c0 + tx + 16 * q;
-      if (gj < N) {
-        double2* c = M + (long long)gi * N + gj;
-        *c = double2{c->x - acc[p][q].x, c->y - acc[p][q].y};
-      }
+      const double2 u = Us[l][jb + q];
+      acc[q].x = __builtin_fma(a.x, u.x, __builtin_fma(-a.y, u.y, acc[q].x));
+      acc[q].y = __builtin_fma(a.x, u.y, __builtin_fma(a.y, u.x, acc[q].y));
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int gj = c0 + jb + q;
+    if (gj < N) {
+      double2* c = M + (long long)gi * N + gj;
+      *c = double2{c->x - acc[q].x, c->y - acc[q].y};
     }
   }
 }
