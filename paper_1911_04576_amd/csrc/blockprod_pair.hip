@@ -217,186 +217,206 @@ void launch_pair(const void* That, const void* pairs, const void* w, const void*
                      static_cast<const T*>(winv), static_cast<const V*>(xh), static_cast<V*>(yh), n, nrhs, r0, nr);
 }
 
-// ---- FP32: half-wavefront rows
+// ---- FP32: matrix cores (v_mfma_f32_16x16x4f32)
+//
+// Real embedding of the complex products: for an A operand of 16 rows x 4
+// k-slots the slots are (source index pair, real / imaginary part), and the B
+// operand columns are the real parts (columns r < NR) and imaginary parts
+// (NR <= column < 2 NR) of the outputs:
+//     part 0 (re M): B = [ xr | xi ],   part 1 (im M): B = [ -xi | xr ].
+// Wavefront w owns u tiles w, w + 4, ... (TPW of them) and visits every v tile;
+// for tile (t, q) it runs 8 MFMAs of the first product (A = the tile with rows
+// u, read straight from HBM in the lane order of the store) into the tile's
+// row accumulator, and 8 of the transposed product (A = the tile transposed,
+// staged through LDS) into the v tile's column sums, which are added into
+// LDS once per v tile.  Up to 8 right-hand sides per pass (2 NR <= 16 MFMA
+// columns).
 
-template <int K> __device__ __forceinline__ float dpp_ror(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x120 + K, 0xF, 0xF, false));
-}
-// sum over the 32 lanes of a half-wavefront, returned in every lane: rotations
-// by 8, 4, 2, 1 within each 16-lane row, then the two rows exchanged
-__device__ __forceinline__ float half_wave_sum(float v) {
-  v += dpp_ror<8>(v);
-  v += dpp_ror<4>(v);
-  v += dpp_ror<2>(v);
-  v += dpp_ror<1>(v);
-  return v + __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4v ld_tile(__amdgpu_buffer_rsrc_t rs, unsigned voff, int soff) {
+  return __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 2));
 }
 
-// CC column tiles (32 CC >= n, CC = ceil(n / 32)); NR right-hand sides per
-// pass, nr <= NR of them valid.  LDS: W xh[-k] as [rows_pad][NR], xh[k] as NR
-// planes of 32 CC, row sums and column sums as [NR][n][2].
-template <int CC, int NR>
-__global__ void __launch_bounds__(PNT, 4) pair_f32_kernel(const float2* __restrict__ That, const int2* __restrict__ pairs,
+// TPW u tiles per wavefront; NRW right-hand sides per pass (4 or 8: the
+// MFMA columns used, 2 NRW of 16)
+template <int TPW, int NRW>
+__global__ void __launch_bounds__(PNT, 2) pair_f32_kernel(const float* __restrict__ That, const int2* __restrict__ pairs,
                                                           const float* __restrict__ w, const float* __restrict__ winv,
                                                           const float2* __restrict__ xh, float2* __restrict__ yh, int n,
                                                           int nrhs, int r0, int nr) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int RR = (n + PAIR_TILE_ROWS - 1) / PAIR_TILE_ROWS, rows_pad = PAIR_TILE_ROWS * RR;
-  constexpr int cols_pad = PAIR_TILE_COLS * CC;
-  float2* xt = reinterpret_cast<float2*>(smem_raw);        // [rows_pad][NR]: W xh[-k]
-  float2* xs = xt + rows_pad * NR;                         // [NR][cols_pad]: xh[k]
-  float* ys = reinterpret_cast<float*>(xs + NR * cols_pad);  // [NR][n][2]: yh[k]
-  float* zs = ys + 2 * NR * n;                             // [NR][n][2]: W yh[-k]
+  const int nt = pair_tiles(n), np = nt * PAIR_TILE;
+  float* xs = reinterpret_cast<float*>(smem_raw);  // [np][NRW][2]: xh[k]
+  float* xt = xs + np * NRW * 2;                 // [np][NRW][2]: W xh[-k]
+  float* zs = xt + np * NRW * 2;                 // [np][2 NRW]: column sums
+  float* tiles = zs + np * 2 * NRW;              // [4 waves][2 stages][512]
   const long long slot = blockIdx.x;
   const int2 pr = pairs[slot];
   const long long k = pr.x, kb = pr.y;
   const bool self = k == kb;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, c = lane & 31, g = 2 * wv + (lane >> 5);
-  const long long blk = (long long)rows_pad * cols_pad;
+  const int l = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ntw = (nt - wv + 3) / 4;  // u tiles of this wavefront (<= TPW)
+  const long long blk = (long long)nt * nt * 2 * PAIR_TILE * PAIR_TILE;  // floats
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(That + slot * blk), (short)0, (int)(blk * (long long)sizeof(float2)), 0x00020000);
-  // a wavefront's 64 lanes read tile rows 2 wv and 2 wv + 1: 512 contiguous bytes
-  const unsigned voff = (unsigned)((64 * wv + lane) * (int)sizeof(float2));
-  auto fetch = [&](float2 (&a)[CC], int i) {
-#pragma unroll
-    for (int j = 0; j < CC; ++j) a[j] = ld_elem<float2>(rs, voff, (i * CC + j) * (PAIR_TILE_ROWS * PAIR_TILE_COLS * 8));
+      (void*)(That + slot * blk), (short)0, (int)(blk * (long long)sizeof(float)), 0x00020000);
+  const unsigned voff = (unsigned)(l * 32);
+  auto tile_off = [&](int t, int q) { return (t * nt + q) * (2 * PAIR_TILE * PAIR_TILE * 4); };
+  // tiles of this wavefront in visiting order it = q * ntw + ta (t = wv + 4 ta)
+  const int nvisit = ntw * nt;
+  auto visit = [&](int it, int& t, int& q) {
+    if (it > nvisit - 1) it = nvisit - 1;
+    q = it / ntw;
+    t = wv + 4 * (it - q * ntw);
   };
-  float2 a0[CC], a1[CC];
-  fetch(a0, 0);
+  // two tiles in flight: p (current) and nx (next)
+  f4v p0{0, 0, 0, 0}, p1{0, 0, 0, 0}, nx0{0, 0, 0, 0}, nx1{0, 0, 0, 0};
+  if (ntw > 0) {
+    int t, q;
+    visit(0, t, q);
+    p0 = ld_tile(rs, voff, tile_off(t, q));
+    p1 = ld_tile(rs, voff + 16, tile_off(t, q));
+    visit(1, t, q);
+    nx0 = ld_tile(rs, voff, tile_off(t, q));
+    nx1 = ld_tile(rs, voff + 16, tile_off(t, q));
+  }
   const float2* x0 = xh + k * (long long)nrhs * n + (long long)r0 * n;
   const float2* x1 = xh + kb * (long long)nrhs * n + (long long)r0 * n;
-  for (int e = threadIdx.x; e < NR * cols_pad; e += PNT) {
-    const int r = e / cols_pad, v = e - r * cols_pad;
-    xs[e] = (r < nr && v < n) ? x0[(long long)r * n + v] : float2{0, 0};
-  }
-  for (int e = threadIdx.x; e < NR * rows_pad; e += PNT) {
-    const int r = e / rows_pad, u = e - r * rows_pad;
-    float2 val{0, 0};
-    if (r < nr && u < n) {
-      const float2 x = x1[(long long)r * n + u];
-      val = float2{w[u] * x.x, w[u] * x.y};
+  for (int e = threadIdx.x; e < np * NRW; e += PNT) {
+    const int r = e / np, v = e - r * np;
+    float2 a{0, 0}, b{0, 0};
+    if (r < nr && v < n) {
+      a = x0[(long long)r * n + v];
+      const float2 c = x1[(long long)r * n + v];
+      b = float2{w[v] * c.x, w[v] * c.y};
     }
-    xt[u * NR + r] = val;
+    xs[(v * NRW + r) * 2] = a.x;
+    xs[(v * NRW + r) * 2 + 1] = a.y;
+    xt[(v * NRW + r) * 2] = b.x;
+    xt[(v * NRW + r) * 2 + 1] = b.y;
   }
-  for (int e = threadIdx.x; e < 4 * NR * n; e += PNT) ys[e] = 0;  // ys and zs
+  for (int e = threadIdx.x; e < np * 2 * NRW; e += PNT) zs[e] = 0.f;
   __syncthreads();
-  float zr[CC][NR], zi[CC][NR];
-#pragma unroll
-  for (int j = 0; j < CC; ++j)
-#pragma unroll
-    for (int r = 0; r < NR; ++r) { zr[j][r] = 0; zi[j][r] = 0; }
-  auto row = [&](const float2 (&a)[CC], int i) {
-    const int u = g + PAIR_TILE_ROWS * i;
-    float2 xr[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) xr[r] = xt[u * NR + r];
-    float yr[NR], yi[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) { yr[r] = 0; yi[r] = 0; }
-#pragma unroll
-    for (int j = 0; j < CC; ++j) {
-      const float2 av = a[j];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const float2 x = xs[r * cols_pad + c + PAIR_TILE_COLS * j];
-        yr[r] = fma_r(av.x, x.x, yr[r]);
-        yr[r] = fma_r(-av.y, x.y, yr[r]);
-        yi[r] = fma_r(av.x, x.y, yi[r]);
-        yi[r] = fma_r(av.y, x.x, yi[r]);
-        zr[j][r] = fma_r(av.x, xr[r].x, zr[j][r]);
-        zr[j][r] = fma_r(-av.y, xr[r].y, zr[j][r]);
-        zi[j][r] = fma_r(av.x, xr[r].y, zi[j][r]);
-        zi[j][r] = fma_r(av.y, xr[r].x, zi[j][r]);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      yr[r] = half_wave_sum(yr[r]);
-      yi[r] = half_wave_sum(yi[r]);
-    }
-    if (c == 0 && u < n) {
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        ys[2 * (r * n + u)] = yr[r];
-        ys[2 * (r * n + u) + 1] = yi[r];
-      }
-    }
+  // lane roles: k-slot kk = l / 16 -> (pair offset off, part); column jj = l % 16
+  const int kk = l >> 4, jj = l & 15, off = kk >> 1, part = kk & 1, a16 = l & 15;
+  const bool jre = jj < NRW, jok = jj < 2 * NRW;
+  const int rj = jre ? jj : (jok ? jj - NRW : 0);
+  auto bval = [&](const float* x, int idx) {
+    const float xr = x[(idx * NRW + rj) * 2], xi = x[(idx * NRW + rj) * 2 + 1];
+    const float val = part == 0 ? (jre ? xr : xi) : (jre ? -xi : xr);
+    return jok ? val : 0.f;
   };
-  for (int i = 0; i < RR; i += 2) {
-    fetch(a1, i + 1 < RR ? i + 1 : RR - 1);
-    __builtin_amdgcn_sched_barrier(0);
-    row(a0, i);
-    fetch(a0, i + 2 < RR ? i + 2 : RR - 1);
-    __builtin_amdgcn_sched_barrier(0);
-    if (i + 1 < RR) row(a1, i + 1);
+  float b2[TPW][8];
+#pragma unroll
+  for (int ta = 0; ta < TPW; ++ta)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) b2[ta][s] = ta < ntw ? bval(xt, (wv + 4 * ta) * PAIR_TILE + 2 * s + off) : 0.f;
+  f4v acc[TPW];
+#pragma unroll
+  for (int ta = 0; ta < TPW; ++ta) acc[ta] = f4v{0, 0, 0, 0};
+  // transposed staging: value s of this lane, entry (u = a16, v = 2 s + off, part), goes to
+  // ((v * 2 + part) * 2 + u % 2) * 8 + u / 2; lane l then reads its 8 transposed operands
+  // (u = 2 s + off, v = a16, part) as 8 consecutive floats
+  const int wbase = (part * 2 + (a16 & 1)) * 8 + (a16 >> 1);
+  const int rbase = ((a16 * 2 + part) * 2 + off) * 8;
+  float* tw = tiles + wv * 2 * 512;
+  int stage = 0;
+  for (int q = 0; q < nt; ++q) {
+    float b1[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) b1[s] = bval(xs, q * PAIR_TILE + 2 * s + off);
+    f4v zq{0, 0, 0, 0};
+#pragma unroll
+    for (int ta = 0; ta < TPW; ++ta) {
+      if (ta < ntw) {
+        const float a1[8] = {p0[0], p0[1], p0[2], p0[3], p1[0], p1[1], p1[2], p1[3]};
+        float* T = tw + stage * 512;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) T[(2 * s + off) * 32 + wbase] = a1[s];
+        __builtin_amdgcn_wave_barrier();
+        const f4v c0 = *reinterpret_cast<const f4v*>(T + rbase), c1 = *reinterpret_cast<const f4v*>(T + rbase + 4);
+        int tn, qn;
+        visit(q * ntw + ta + 2, tn, qn);
+        p0 = nx0;
+        p1 = nx1;
+        nx0 = ld_tile(rs, voff, tile_off(tn, qn));
+        nx1 = ld_tile(rs, voff + 16, tile_off(tn, qn));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) acc[ta] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[s], b1[s], acc[ta], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        const float a2[8] = {c0[0], c0[1], c0[2], c0[3], c1[0], c1[1], c1[2], c1[3]};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) zq = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[s], b2[ta][s], zq, 0, 0, 0);
+        stage ^= 1;
+      }
+    }
+    // D layout: register e of lane l holds row 4 (l / 16) + e, column l % 16
+    if (!self && ntw > 0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (jok) atomicAdd(&zs[(q * PAIR_TILE + 4 * (l >> 4) + e) * 2 * NRW + jj], zq[e]);
+    }
   }
-  if (!self) {
+  // first product: rows of this wavefront's u tiles
+  float2* y0 = yh + k * (long long)nrhs * n + (long long)r0 * n;
+  float* y0f = reinterpret_cast<float*>(y0);
 #pragma unroll
-    for (int j = 0; j < CC; ++j) {
-      const int v = c + PAIR_TILE_COLS * j;
-      if (v < n) {
+  for (int ta = 0; ta < TPW; ++ta) {
+    if (ta < ntw) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          atomicAdd(zs + 2 * (r * n + v), zr[j][r]);
-          atomicAdd(zs + 2 * (r * n + v) + 1, zi[j][r]);
-        }
+      for (int e = 0; e < 4; ++e) {
+        const int u = (wv + 4 * ta) * PAIR_TILE + 4 * (l >> 4) + e;
+        if (u < n && jok && rj < nr) y0f[2 * ((long long)rj * n + u) + (jre ? 0 : 1)] = acc[ta][e];
       }
     }
   }
   __syncthreads();
-  float2* y0 = yh + k * (long long)nrhs * n + (long long)r0 * n;
-  for (int e = threadIdx.x; e < nr * n; e += PNT) y0[e] = float2{ys[2 * e], ys[2 * e + 1]};
   if (!self) {
     float2* y1 = yh + kb * (long long)nrhs * n + (long long)r0 * n;
     for (int e = threadIdx.x; e < nr * n; e += PNT) {
-      const int v = e % n;
-      y1[e] = float2{zs[2 * e] * winv[v], zs[2 * e + 1] * winv[v]};
+      const int r = e / n, v = e - r * n;
+      y1[e] = float2{zs[v * 2 * NRW + r] * winv[v], zs[v * 2 * NRW + NRW + r] * winv[v]};
     }
   }
 }
 
-template <int CC, int NR>
+template <int TPW, int NRW>
 void launch_f32(const void* That, const void* pairs, const void* w, const void* winv, const void* xh, void* yh, int n,
                 int nrhs, int r0, int nr, int64_t Ps, hipStream_t s) {
-  const int rows_pad = (n + PAIR_TILE_ROWS - 1) / PAIR_TILE_ROWS * PAIR_TILE_ROWS;
-  const size_t shm = (size_t)(rows_pad + PAIR_TILE_COLS * CC) * NR * sizeof(float2) + (size_t)4 * NR * n * sizeof(float);
-  hipLaunchKernelGGL((pair_f32_kernel<CC, NR>), dim3((unsigned)Ps), dim3(PNT), shm, s,
-                     static_cast<const float2*>(That), static_cast<const int2*>(pairs), static_cast<const float*>(w),
-                     static_cast<const float*>(winv), static_cast<const float2*>(xh), static_cast<float2*>(yh), n, nrhs,
-                     r0, nr);
+  const int np = pair_tiles(n) * PAIR_TILE;
+  const size_t shm = (size_t)(np * NRW * 2 * 3 + 4 * 2 * 512) * sizeof(float);
+  hipLaunchKernelGGL((pair_f32_kernel<TPW, NRW>), dim3((unsigned)Ps), dim3(PNT), shm, s, static_cast<const float*>(That),
+                     static_cast<const int2*>(pairs), static_cast<const float*>(w), static_cast<const float*>(winv),
+                     static_cast<const float2*>(xh), static_cast<float2*>(yh), n, nrhs, r0, nr);
 }
 
-// FP32 right-hand sides per pass: column sums take CC x NR complex registers,
-// at most 24
-constexpr int f32_nr_max(int CC) { return CC <= 2 ? 8 : CC <= 6 ? 4 : CC <= 12 ? 2 : 1; }
-
-template <int CC>
-void launch_f32_cc(int NR, const void* That, const void* pairs, const void* w, const void* winv, const void* xh,
-                   void* yh, int n, int nrhs, int r0, int nr, int64_t Ps, hipStream_t s) {
-  switch (NR) {
-    case 1: launch_f32<CC, 1>(That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s); break;
-    case 2: if constexpr (f32_nr_max(CC) >= 2) launch_f32<CC, 2>(That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s); break;
-    case 4: if constexpr (f32_nr_max(CC) >= 4) launch_f32<CC, 4>(That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s); break;
-    default: if constexpr (f32_nr_max(CC) >= 8) launch_f32<CC, 8>(That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s); break;
-  }
-}
-
-template <int... C>
-void launch_f32_dispatch(std::integer_sequence<int, C...>, int CC, int NR, const void* That, const void* pairs,
-                         const void* w, const void* winv, const void* xh, void* yh, int n, int nrhs, int r0, int nr,
-                         int64_t Ps, hipStream_t s) {
-  ((CC == C + 1 ? launch_f32_cc<C + 1>(NR, That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s) : void()), ...);
+template <int TPW>
+void launch_f32_tpw(int nrw, const void* That, const void* pairs, const void* w, const void* winv, const void* xh,
+                    void* yh, int n, int nrhs, int r0, int nr, int64_t Ps, hipStream_t s) {
+  if (nrw == 4)
+    launch_f32<TPW, 4>(That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s);
+  else
+    launch_f32<TPW, 8>(That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s);
 }
 
 void launch_pair_f32(const void* That, const void* pairs, const void* w, const void* winv, const void* xh, void* yh,
                      int n, int nrhs, int64_t Ps, hipStream_t s) {
-  const int CC = pair_col_tiles(n);
-  int NR = 1;
-  while (NR < nrhs && NR * 2 <= f32_nr_max(CC)) NR *= 2;
-  for (int r0 = 0; r0 < nrhs; r0 += NR) {
-    const int nr = nrhs - r0 < NR ? nrhs - r0 : NR;
-    launch_f32_dispatch(std::make_integer_sequence<int, 16>{}, CC, NR, That, pairs, w, winv, xh, yh, n, nrhs, r0, nr,
-                        Ps, s);
+  const int tpw = (pair_tiles(n) + 3) / 4;
+  // 4-wide passes for at most 4 right-hand sides (less LDS, more workgroups per CU)
+  const int nrw = nrhs <= 4 ? 4 : 8;
+  for (int r0 = 0; r0 < nrhs; r0 += nrw) {
+    const int nr = nrhs - r0 < nrw ? nrhs - r0 : nrw;
+    switch (tpw) {
+      case 1: launch_f32_tpw<1>(nrw, That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s); break;
+      case 2: launch_f32_tpw<2>(nrw, That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s); break;
+      case 3: launch_f32_tpw<3>(nrw, That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s); break;
+      case 4: launch_f32_tpw<4>(nrw, That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s); break;
+      case 5: launch_f32_tpw<5>(nrw, That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s); break;
+      case 6: launch_f32_tpw<6>(nrw, That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s); break;
+      case 7: launch_f32_tpw<7>(nrw, That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s); break;
+      default: launch_f32_tpw<8>(nrw, That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s); break;
+    }
   }
 }
 

@@ -224,7 +224,11 @@ __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, 
     const long long col = c0 + j;
     const int cv = (int)(col / n), u = (int)(col - (long long)cv * n);
     if (t64) t64[slot * blk64 + pair_offset64(n, u, cv)] = v;
-    if (t32) t32[slot * blk32 + pair_offset32(n, u, cv)] = float2{(float)v.x, (float)v.y};
+    if (t32) {
+      float* f = reinterpret_cast<float*>(t32) + slot * blk32 * 2;
+      f[pair_float_offset32(n, u, cv, 0)] = (float)v.x;
+      f[pair_float_offset32(n, u, cv, 1)] = (float)v.y;
+    }
   }
 }
 

@@ -149,26 +149,31 @@ bool block_mfma_supported(int n, int nrhs);
 bool block_variant_supported(int variant, int n, int nrhs);
 void launch_block_product_variant(Cx t, int variant, const void* That, const void* xh, void* yh, int n, int nrhs,
                                   int64_t P, hipStream_t s);
-// Block layouts of the reciprocal store (the last row panel / column tile
-// zero-padded):
+// Block layouts of the reciprocal store (padding zero):
 //  FP64: row panels of 4 rows, entry (u, v) at ((u / 4) n + v) 4 + u % 4;
-//  FP32: tiles of 8 rows x 32 columns in [row panel][column tile] order, each
-//        tile row-major: entry (u, v) at ((u / 8 * ct + v / 32) 8 + u % 8) 32 + v % 32,
-//        ct = ceil(n / 32) column tiles.
-constexpr int PAIR_PANEL_FP64 = 4, PAIR_TILE_ROWS = 8, PAIR_TILE_COLS = 32;
-__host__ __device__ inline int pair_col_tiles(int n) { return (n + PAIR_TILE_COLS - 1) / PAIR_TILE_COLS; }
+//  FP32: 16 x 16 tiles in [u tile][v tile] order (nt = ceil(n / 16) per side),
+//        512 floats per tile, real and imaginary parts apart: the part p of
+//        tile entry (a, b) is float (a + 16 p + 32 (b % 2)) 8 + b / 2 -- the
+//        order in which a wavefront's lanes hold the A operand of the
+//        first product on the matrix cores (lane a + 16 p + 32 (b % 2),
+//        register b / 2).
+constexpr int PAIR_PANEL_FP64 = 4, PAIR_TILE = 16;
+__host__ __device__ inline int pair_tiles(int n) { return (n + PAIR_TILE - 1) / PAIR_TILE; }
 __host__ __device__ inline int64_t pair_block_entries64(int n) {
   return (int64_t)((n + PAIR_PANEL_FP64 - 1) / PAIR_PANEL_FP64) * PAIR_PANEL_FP64 * n;
 }
+// complex entries (= floats / 2) of one FP32 block
 __host__ __device__ inline int64_t pair_block_entries32(int n) {
-  return (int64_t)((n + PAIR_TILE_ROWS - 1) / PAIR_TILE_ROWS) * PAIR_TILE_ROWS * pair_col_tiles(n) * PAIR_TILE_COLS;
+  return (int64_t)pair_tiles(n) * pair_tiles(n) * PAIR_TILE * PAIR_TILE;
 }
 __host__ __device__ inline int64_t pair_offset64(int n, int u, int v) {
   return ((int64_t)(u / PAIR_PANEL_FP64) * n + v) * PAIR_PANEL_FP64 + u % PAIR_PANEL_FP64;
 }
-__host__ __device__ inline int64_t pair_offset32(int n, int u, int v) {
-  return (((int64_t)(u / PAIR_TILE_ROWS) * pair_col_tiles(n) + v / PAIR_TILE_COLS) * PAIR_TILE_ROWS + u % PAIR_TILE_ROWS) *
-             PAIR_TILE_COLS + v % PAIR_TILE_COLS;
+// float offset of part p (0 real, 1 imaginary) of entry (u, v) within an FP32 block
+__host__ __device__ inline int64_t pair_float_offset32(int n, int u, int v, int p) {
+  const int a = u % PAIR_TILE, b = v % PAIR_TILE;
+  return ((int64_t)(u / PAIR_TILE) * pair_tiles(n) + v / PAIR_TILE) * (2 * PAIR_TILE * PAIR_TILE) +
+         (a + 16 * p + 32 * (b % 2)) * 8 + b / 2;
 }
 // Reciprocal plans: one block per frequency pair {k, -k}; pairs = int [Ps][2]
 // (k, -k), w / winv the per-unknown weights and their inverses in the compute
