@@ -261,24 +261,20 @@ __global__ void __launch_bounds__(PNT, 2) pair_f32_kernel(const float* __restric
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(That + slot * blk), (short)0, (int)(blk * (long long)sizeof(float)), 0x00020000);
   const unsigned voff = (unsigned)(l * 32);
-  auto tile_off = [&](int t, int q) { return (t * nt + q) * (2 * PAIR_TILE * PAIR_TILE * 4); };
-  // tiles of this wavefront in visiting order it = q * ntw + ta (t = wv + 4 ta)
-  const int nvisit = ntw * nt;
-  auto visit = [&](int it, int& t, int& q) {
+  // this wavefront's tiles are stored contiguously in visiting order
+  // it = q * ntw + ta (u tile wv + 4 ta, v tile q)
+  const int nvisit = ntw * nt, wbase_tile = pair_wave_base(nt, wv);
+  auto visit_off = [&](int it) {
     if (it > nvisit - 1) it = nvisit - 1;
-    q = it / ntw;
-    t = wv + 4 * (it - q * ntw);
+    return (wbase_tile + it) * (2 * PAIR_TILE * PAIR_TILE * 4);
   };
   // two tiles in flight: p (current) and nx (next)
   f4v p0{0, 0, 0, 0}, p1{0, 0, 0, 0}, nx0{0, 0, 0, 0}, nx1{0, 0, 0, 0};
   if (ntw > 0) {
-    int t, q;
-    visit(0, t, q);
-    p0 = ld_tile(rs, voff, tile_off(t, q));
-    p1 = ld_tile(rs, voff + 16, tile_off(t, q));
-    visit(1, t, q);
-    nx0 = ld_tile(rs, voff, tile_off(t, q));
-    nx1 = ld_tile(rs, voff + 16, tile_off(t, q));
+    p0 = ld_tile(rs, voff, visit_off(0));
+    p1 = ld_tile(rs, voff + 16, visit_off(0));
+    nx0 = ld_tile(rs, voff, visit_off(1));
+    nx1 = ld_tile(rs, voff + 16, visit_off(1));
   }
   const float2* x0 = xh + k * (long long)nrhs * n + (long long)r0 * n;
   const float2* x1 = xh + kb * (long long)nrhs * n + (long long)r0 * n;
@@ -321,10 +317,17 @@ __global__ void __launch_bounds__(PNT, 2) pair_f32_kernel(const float* __restric
   const int rbase = ((a16 * 2 + part) * 2 + off) * 8;
   float* tw = tiles + wv * 2 * 512;
   int stage = 0;
+  // B operands of the first product for v tile q, built one v tile ahead
+  float b1n[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) b1n[s] = bval(xs, 2 * s + off);
   for (int q = 0; q < nt; ++q) {
     float b1[8];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) b1[s] = bval(xs, q * PAIR_TILE + 2 * s + off);
+    for (int s = 0; s < 8; ++s) b1[s] = b1n[s];
+    const int qn = q + 1 < nt ? q + 1 : q;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) b1n[s] = bval(xs, qn * PAIR_TILE + 2 * s + off);
     f4v zq{0, 0, 0, 0};
 #pragma unroll
     for (int ta = 0; ta < TPW; ++ta) {
@@ -335,12 +338,11 @@ __global__ void __launch_bounds__(PNT, 2) pair_f32_kernel(const float* __restric
         for (int s = 0; s < 8; ++s) T[(2 * s + off) * 32 + wbase] = a1[s];
         __builtin_amdgcn_wave_barrier();
         const f4v c0 = *reinterpret_cast<const f4v*>(T + rbase), c1 = *reinterpret_cast<const f4v*>(T + rbase + 4);
-        int tn, qn;
-        visit(q * ntw + ta + 2, tn, qn);
+        const int noff = visit_off(q * ntw + ta + 2);
         p0 = nx0;
         p1 = nx1;
-        nx0 = ld_tile(rs, voff, tile_off(tn, qn));
-        nx1 = ld_tile(rs, voff + 16, tile_off(tn, qn));
+        nx0 = ld_tile(rs, voff, noff);
+        nx1 = ld_tile(rs, voff + 16, noff);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s = 0; s < 8; ++s) acc[ta] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[s], b1[s], acc[ta], 0, 0, 0);

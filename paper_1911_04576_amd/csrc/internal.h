@@ -151,12 +151,16 @@ void launch_block_product_variant(Cx t, int variant, const void* That, const voi
                                   int64_t P, hipStream_t s);
 // Block layouts of the reciprocal store (padding zero):
 //  FP64: row panels of 4 rows, entry (u, v) at ((u / 4) n + v) 4 + u % 4;
-//  FP32: 16 x 16 tiles in [u tile][v tile] order (nt = ceil(n / 16) per side),
-//        512 floats per tile, real and imaginary parts apart: the part p of
-//        tile entry (a, b) is float (a + 16 p + 32 (b % 2)) 8 + b / 2 -- the
-//        order in which a wavefront's lanes hold the A operand of the
-//        first product on the matrix cores (lane a + 16 p + 32 (b % 2),
-//        register b / 2).
+//  FP32: 16 x 16 tiles (nt = ceil(n / 16) per side), 512 floats per tile, in
+//        the order the four wavefronts of the paired product visit them:
+//        u tile t belongs to wavefront t % 4, which walks v tiles q outer and
+//        its own u tiles inner, so tile (t, q) sits at
+//        base(t % 4) + q ntw(t % 4) + t / 4, with ntw(w) = (nt - w + 3) / 4
+//        and base(w) = nt sum_{w' < w} ntw(w').  Within a tile, real and
+//        imaginary parts apart: part p of tile entry (a, b) is float
+//        (a + 16 p + 32 (b % 2)) 8 + b / 2 -- the order in which a
+//        wavefront's lanes hold the A operand of the first product on the
+//        matrix cores (lane a + 16 p + 32 (b % 2), register b / 2).
 constexpr int PAIR_PANEL_FP64 = 4, PAIR_TILE = 16;
 __host__ __device__ inline int pair_tiles(int n) { return (n + PAIR_TILE - 1) / PAIR_TILE; }
 __host__ __device__ inline int64_t pair_block_entries64(int n) {
@@ -169,10 +173,22 @@ __host__ __device__ inline int64_t pair_block_entries32(int n) {
 __host__ __device__ inline int64_t pair_offset64(int n, int u, int v) {
   return ((int64_t)(u / PAIR_PANEL_FP64) * n + v) * PAIR_PANEL_FP64 + u % PAIR_PANEL_FP64;
 }
+// u tiles of wavefront w, and the first tile position of wavefront w
+__host__ __device__ inline int pair_wave_tiles(int nt, int w) { return (nt - w + 3) / 4; }
+__host__ __device__ inline int pair_wave_base(int nt, int w) {
+  int b = 0;
+  for (int x = 0; x < w; ++x) b += pair_wave_tiles(nt, x) * nt;
+  return b;
+}
+// tile position of (u tile t, v tile q) within an FP32 block
+__host__ __device__ inline int pair_tile_pos(int nt, int t, int q) {
+  const int w = t % 4;
+  return pair_wave_base(nt, w) + q * pair_wave_tiles(nt, w) + t / 4;
+}
 // float offset of part p (0 real, 1 imaginary) of entry (u, v) within an FP32 block
 __host__ __device__ inline int64_t pair_float_offset32(int n, int u, int v, int p) {
   const int a = u % PAIR_TILE, b = v % PAIR_TILE;
-  return ((int64_t)(u / PAIR_TILE) * pair_tiles(n) + v / PAIR_TILE) * (2 * PAIR_TILE * PAIR_TILE) +
+  return (int64_t)pair_tile_pos(pair_tiles(n), u / PAIR_TILE, v / PAIR_TILE) * (2 * PAIR_TILE * PAIR_TILE) +
          (a + 16 * p + 32 * (b % 2)) * 8 + b / 2;
 }
 // Reciprocal plans: one block per frequency pair {k, -k}; pairs = int [Ps][2]
