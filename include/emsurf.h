@@ -276,7 +276,12 @@ emsurf_status emsurf_apply_A(emsurf_plan plan, emsurf_prec prec, int32_t nrhs, c
  * the solve starts from x_dev's content.  info_host: nrhs entries (may be
  * NULL).  Blocks until done.  Returns EMSURF_ERR_NOT_CONVERGED (x holds the
  * best iterate, info filled) if any RHS missed tol; EMSURF_ERR_ARG if b has a
- * non-finite entry.  A zero RHS returns x = 0, converged, 0 iterations. */
+ * non-finite entry.  A zero RHS returns x = 0, converged, 0 iterations.
+ * The GMRES workspace ((restart + 1) nrhs basis vectors of c128 and a few
+ * vectors more) is kept in the plan for the stream after the first solve on
+ * it, grows to the largest nrhs and restart used, is reused by later solves
+ * on that stream and freed with the plan (counted in emsurf_plan_query's
+ * bytes_total); concurrent solves on one plan must use distinct streams. */
 emsurf_status emsurf_solve(emsurf_plan plan, const emsurf_solve_opts* opts, int32_t nrhs,
                            const void* b_dev, void* x_dev, emsurf_solve_info* info_host, void* stream);
 

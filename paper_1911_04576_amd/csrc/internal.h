@@ -81,6 +81,10 @@ struct DevBuf {
     p = nullptr;
     bytes = 0;
   }
+  // keep the buffer if it already holds n bytes, else reallocate
+  void reserve(size_t n) {
+    if (n > bytes) alloc(n);
+  }
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
@@ -97,6 +101,9 @@ struct PinnedBuf {
     if (n == 0) return;
     EMS_HIP(hipHostMalloc(&p, n, hipHostMallocDefault));
     bytes = n;
+  }
+  void reserve(size_t n) {
+    if (n > bytes) alloc(n);
   }
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
@@ -269,6 +276,11 @@ struct Workspace {
   DevBuf t;     // T x result for A-apply [nrhs][M][n] (widest type)
 };
 
+// GMRES workspace of emsurf_solve (csrc/solver.hip), kept per stream in the plan
+struct SolveWork;
+void destroy_solve_work(SolveWork* w);
+size_t solve_work_bytes(const SolveWork* w);
+
 struct KernelTimer {
   bool enabled = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[5];
@@ -292,6 +304,7 @@ struct emsurf_plan_s {
   emsurf::TypeTiles tiles;
   std::mutex mu;
   std::map<hipStream_t, emsurf::Workspace*> ws;
+  std::map<hipStream_t, emsurf::SolveWork*> solve_ws;  // created by the first solve on a stream
   emsurf::KernelTimer timer;
   hipStream_t timer_stream = nullptr;
   int bp_variant[65];             // FP32 block-product variant per nrhs, -1 = automatic

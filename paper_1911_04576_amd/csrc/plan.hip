@@ -229,6 +229,7 @@ void upload_geom(const emsurf_geom* g, GreenGeomDev& d) {
 
 emsurf_plan_s::~emsurf_plan_s() {
   for (auto& kv : ws) delete kv.second;
+  for (auto& kv : solve_ws) emsurf::destroy_solve_work(kv.second);
   for (int ph = 0; ph < 5; ++ph)
     for (auto& pr : timer.ev[ph]) {
       (void)hipEventDestroy(pr.first);
@@ -621,6 +622,7 @@ emsurf_status emsurf_plan_query(emsurf_plan plan, emsurf_plan_stats* out) {
                  plan->winv64.bytes + plan->w32.bytes + plan->winv32.bytes;
     std::lock_guard<std::mutex> lk(plan->mu);
     for (auto& kv : plan->ws) tot += kv.second->W.bytes + kv.second->X.bytes + kv.second->Y.bytes + kv.second->t.bytes;
+    for (auto& kv : plan->solve_ws) tot += emsurf::solve_work_bytes(kv.second);
     out->bytes_total = tot;
   });
 }

@@ -28,6 +28,10 @@ namespace {
 
 using cd = std::complex<double>;
 
+}  // namespace
+
+// Buffers grow to the largest (nrhs, restart) a stream has used and are reused
+// by later solves on that stream.
 struct SolveWork {
   int nrhs = 0, m = 0;
   long long N = 0;
@@ -39,6 +43,7 @@ struct SolveWork {
   DevBuf scale;    // nrhs doubles
   DevBuf ycoef;    // nrhs x m complex
   DevBuf mask;     // nrhs ints
+  DevBuf ir_r, ir_d, ir_t;  // refinement residual, correction, operator output: nrhs x N each
   PinnedBuf h_red, h_scale, h_y, h_mask;
   void init(int nrhs_, int m_, long long N_) {
     nrhs = nrhs_;
@@ -46,21 +51,35 @@ struct SolveWork {
     N = N_;
     nblk = dot_blocks(N);
     rstride = 2 * (m + 2) + 4;
-    V.alloc((size_t)(m + 1) * nrhs * N * 16);
-    r.alloc((size_t)nrhs * N * 16);
-    t.alloc((size_t)nrhs * N * 16);
-    partial.alloc((size_t)nrhs * nblk * (m + 2) * 16);
-    red.alloc((size_t)nrhs * rstride * 16);
-    scale.alloc((size_t)nrhs * 8);
-    ycoef.alloc((size_t)nrhs * m * 16);
-    mask.alloc((size_t)nrhs * 4);
-    h_red.alloc(red.bytes);
-    h_scale.alloc(scale.bytes);
-    h_y.alloc(ycoef.bytes);
-    h_mask.alloc(mask.bytes);
+    V.reserve((size_t)(m + 1) * nrhs * N * 16);
+    r.reserve((size_t)nrhs * N * 16);
+    t.reserve((size_t)nrhs * N * 16);
+    partial.reserve((size_t)nrhs * nblk * (m + 2) * 16);
+    red.reserve((size_t)nrhs * rstride * 16);
+    scale.reserve((size_t)nrhs * 8);
+    ycoef.reserve((size_t)nrhs * m * 16);
+    mask.reserve((size_t)nrhs * 4);
+    h_red.reserve((size_t)nrhs * rstride * 16);
+    h_scale.reserve((size_t)nrhs * 8);
+    h_y.reserve((size_t)nrhs * m * 16);
+    h_mask.reserve((size_t)nrhs * 4);
   }
   double2* Vp(int l) const { return V.as<double2>() + (size_t)l * nrhs * N; }
+  void init_refinement() {
+    ir_r.reserve((size_t)nrhs * N * 16);
+    ir_d.reserve((size_t)nrhs * N * 16);
+    ir_t.reserve((size_t)nrhs * N * 16);
+  }
+  size_t bytes() const {
+    return V.bytes + r.bytes + t.bytes + partial.bytes + red.bytes + scale.bytes + ycoef.bytes + mask.bytes +
+           ir_r.bytes + ir_d.bytes + ir_t.bytes;
+  }
 };
+
+void destroy_solve_work(SolveWork* w) { delete w; }
+size_t solve_work_bytes(const SolveWork* w) { return w ? w->bytes() : 0; }
+
+namespace {
 
 using OpFn = void (*)(emsurf_plan, int, const void*, void*, hipStream_t);
 
@@ -74,7 +93,7 @@ void op_fp32(emsurf_plan p, int nrhs, const void* x, void* y, hipStream_t s) {
 // per-RHS norms of vec ([nrhs][N]) into host array
 void norms(SolveWork& w, const void* vec, std::vector<double>& out, hipStream_t s) {
   launch_dot(nullptr, 0, 0, vec, w.N, w.nrhs, w.partial.p, w.nblk, w.red.p, w.rstride, 0, s);
-  EMS_HIP(hipMemcpyAsync(w.h_red.p, w.red.p, w.red.bytes, hipMemcpyDeviceToHost, s));
+  EMS_HIP(hipMemcpyAsync(w.h_red.p, w.red.p, (size_t)w.nrhs * w.rstride * 16, hipMemcpyDeviceToHost, s));
   EMS_HIP(hipStreamSynchronize(s));
   const double2* h = w.h_red.as<double2>();
   out.resize(w.nrhs);
@@ -164,7 +183,7 @@ void gmres(emsurf_plan p, OpFn op, SolveWork& w, int nrhs, const double2* b, dou
       launch_dot(w.V.p, vstride, nv, wv, N, nrhs, w.partial.p, w.nblk, w.red.p, w.rstride, o2, s);
       launch_update(w.V.p, vstride, nv, w.red.p, w.rstride, o2, wv, N, nrhs, s);
       launch_dot(nullptr, 0, 0, wv, N, nrhs, w.partial.p, w.nblk, w.red.p, w.rstride, o3, s);
-      EMS_HIP(hipMemcpyAsync(w.h_red.p, w.red.p, w.red.bytes, hipMemcpyDeviceToHost, s));
+      EMS_HIP(hipMemcpyAsync(w.h_red.p, w.red.p, (size_t)w.nrhs * w.rstride * 16, hipMemcpyDeviceToHost, s));
       EMS_HIP(hipStreamSynchronize(s));
       const double2* hr = w.h_red.as<double2>();
       bool all_stopped = true;
@@ -271,7 +290,14 @@ extern "C" emsurf_status emsurf_solve(emsurf_plan plan, const emsurf_solve_opts*
     EMS_CHECK_ARG(b_dev != x_dev, "b and x must be distinct buffers");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const long long N = (long long)plan->M * plan->d.n_eq;
-    SolveWork w;
+    SolveWork* wp = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(plan->mu);
+      auto it = plan->solve_ws.find(s);
+      if (it == plan->solve_ws.end()) it = plan->solve_ws.emplace(s, new SolveWork()).first;
+      wp = it->second;
+    }
+    SolveWork& w = *wp;
     w.init(nrhs, opts->restart, N);
     // finiteness and norms of b
     int* hm = w.h_mask.as<int>();
@@ -301,7 +327,8 @@ extern "C" emsurf_status emsurf_solve(emsurf_plan plan, const emsurf_solve_opts*
       for (int r = 0; r < nrhs; ++r) outer = std::max(outer, st[r].cycles);
     } else {
       // outer refinement: residual in FP64, correction from an FP32 inner solve
-      DevBuf rr((size_t)nrhs * N * 16), d((size_t)nrhs * N * 16), tt((size_t)nrhs * N * 16);
+      w.init_refinement();
+      DevBuf &rr = w.ir_r, &d = w.ir_d, &tt = w.ir_t;
       std::vector<RhsState> inner(nrhs);
       for (outer = 0;; ++outer) {
         for (int r = 0; r < nrhs; ++r) hm[r] = st[r].done ? 0 : 1;
@@ -338,7 +365,7 @@ extern "C" emsurf_status emsurf_solve(emsurf_plan plan, const emsurf_solve_opts*
           if (st[r].done || rn[r] == 0.0) { inner[r].done = true; inner[r].converged = true; continue; }
           itol[r] = std::min(0.5, std::max(opts->inner_tol, 0.5 * opts->tol * st[r].bnorm / rn[r]));
         }
-        EMS_HIP(hipMemsetAsync(d.p, 0, d.bytes, s));
+        EMS_HIP(hipMemsetAsync(d.p, 0, (size_t)nrhs * N * 16, s));
         int budget = 0;
         for (int r = 0; r < nrhs; ++r)
           if (!st[r].done) budget = std::max(budget, opts->max_iter - st[r].iters);

@@ -189,3 +189,27 @@ def test_fp32_ir_reaches_1e6_and_fp32_solve():
     res = max(np.linalg.norm(A @ x[r].ravel() - b[r].ravel()) / np.linalg.norm(b[r]) for r in range(2))
     say(f"fp32 solve: residual vs FP64 operator {res:.2e}")
     assert st == e.EMSURF_OK and res <= 1e-4
+
+
+def test_solve_workspace_reused_across_calls():
+    # the GMRES workspace stays in the plan per stream: solves with a growing and
+    # then shrinking nrhs and restart on one plan each match LU, and the plan
+    # reports the cached bytes after the first solve
+    e = E()
+    nx, ny = 3, 2
+    plan, g, S, tm = physical(nx, ny, max_rhs=4, seed=7)
+    A, _ = dense_A(g, S, tm, nx, ny)
+    before = plan.stats().bytes_total
+    for nrhs, restart, prec in [(1, 5, e.EMSURF_FP64), (4, 12, e.EMSURF_FP32_IR), (2, 3, e.EMSURF_FP64),
+                                (4, 30, e.EMSURF_FP64), (1, 8, e.EMSURF_FP32_IR)]:
+        b = W.random_vectors(nrhs, nx, ny, 4 * g.n_patch, seed=nrhs * 10 + restart)
+        x = torch.zeros_like(dev(b))
+        st, info = e.emsurf_solve(plan, e.solve_opts(prec, tol=1e-10, restart=restart), nrhs, dev(b), x)
+        assert st == e.EMSURF_OK
+        xs = x.cpu().numpy()
+        for r in range(nrhs):
+            xref = K.solve_dense(A, b[r].ravel())
+            err = float(np.linalg.norm(xs[r].ravel() - xref) / np.linalg.norm(xref))
+            say(f"reused workspace: nrhs {nrhs} restart {restart} prec {prec} rhs {r}: error vs LU {err:.2e}")
+            assert err <= 1e-8
+    assert plan.stats().bytes_total > before
