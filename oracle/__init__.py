@@ -16,6 +16,9 @@ What it computes, each function citing the passage it follows:
   operator A = I - S T.
 * ``krylov`` -- restarted GMRES with classical Gram-Schmidt applied twice and
   complex Givens rotations, plus a dense LU reference solve.
+* ``split_bf16`` -- the split-bfloat16 definition of the reduced-precision
+  block products (a = a_hi + a_lo, three or one real products per entry),
+  combined exactly in FP64.
 
 Every function is plain numpy in complex128.  The parity status of each is
 listed in its docstring: the pins live in ``tests/test_oracle_*.py``.
