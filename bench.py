@@ -82,18 +82,20 @@ def measured_traffic(recip=True):
 MFMA_FP32_PEAK_TFS = 157.3
 
 
-def multi_rhs_section(E, W, torch, np, with_oracle):
+def multi_rhs_section(E, W, torch, np):
     """64 x 64 lattice, n_eq 288, 16 RHS: Fourier-domain products as MFMA GEMMs.
     Autotunes the FP32 block-product variants, times the chosen one inside a
-    full T-apply, and reports the FP32 error against the FP64 path (itself
-    checked against the oracle at a sampled element)."""
+    full T-apply, and reports the FP32 and split-BF16 errors against the FP64
+    path.  The outputs at one element are kept (key "_sample") for the CPU leg,
+    which checks them against the oracle."""
     cfg = W.config(3)
     g = W.box_geometry(cfg.n_patch)
     S, tm = W.s_types(cfg), W.type_map(cfg)
     b = W.plane_wave_rhs(cfg, g)
     nrhs, n = cfg.nrhs, cfg.n_eq
     geom = E.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)
-    plan = E.emsurf_plan_create_green(cfg.nx, cfg.ny, cfg.n_types, nrhs, geom, S, tm)
+    plan = E.emsurf_plan_create_green(cfg.nx, cfg.ny, cfg.n_types, nrhs, geom, S, tm,
+                                      store=E.EMSURF_STORE_FP64 | E.EMSURF_STORE_FP32 | E.EMSURF_STORE_BF16)
     st = plan.stats()
     P = st.n_freq
     best, ms = E.emsurf_plan_autotune(plan, nrhs)
@@ -128,8 +130,45 @@ def multi_rhs_section(E, W, torch, np, with_oracle):
     torch.cuda.synchronize()
     ref = y64.cpu().numpy()
     out = y32.cpu().numpy().astype(np.complex128)
-    err32 = float(np.max(np.linalg.norm((out - ref).reshape(nrhs, -1), axis=1) /
-                         np.linalg.norm(ref.reshape(nrhs, -1), axis=1)))
+
+    def err_vs(o):
+        return float(np.max(np.linalg.norm((o - ref).reshape(nrhs, -1), axis=1) /
+                            np.linalg.norm(ref.reshape(nrhs, -1), axis=1)))
+
+    err32 = err_vs(out)
+    # split-bfloat16 products (three or one matrix-core products per entry) on
+    # the split store: same FP32 FFTs, timed the same way
+    split = {}
+    for prec, name, terms, store_bytes in ((E.EMSURF_BF16X3, "bf16x3", 3, 8), (E.EMSURF_BF16, "bf16", 1, 4)):
+        ys = torch.empty_like(x32)
+        for _ in range(2):
+            E.emsurf_apply_T(plan, prec, nrhs, x32, ys)
+        torch.cuda.synchronize()
+        E.emsurf_kernel_timing(plan, True)
+        E.emsurf_kernel_times(plan)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            E.emsurf_apply_T(plan, prec, nrhs, x32, ys)
+        torch.cuda.synchronize()
+        s_apply = 1e3 * (time.perf_counter() - t0) / reps
+        ph = E.emsurf_kernel_times(plan)
+        E.emsurf_kernel_timing(plan, False)
+        s_bms = ph["block_product"][0] / max(1, ph["block_product"][1])
+        s_bytes = P * n * n * store_bytes + 2 * P * nrhs * n * 8
+        s_out = ys.cpu().numpy().astype(np.complex128)
+        split[name] = {
+            "kernel": f"block_bf16_kernel<3, 2, {'true' if terms == 3 else 'false'}>",
+            "block_product_ms": round(s_bms, 4),
+            "block_product_GBs": round(s_bytes / (s_bms / 1e3) / 1e9, 1),
+            "frac_hbm_peak": round(s_bytes / (s_bms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "bf16_mfma_TFs": round(terms * flops / (s_bms / 1e3) / 1e12, 1),
+            "apply_T_ms": round(s_apply, 4),
+            "unknowns_rhs_per_s": cfg.n_unknowns * nrhs / (s_apply / 1e3),
+            "rel_err_vs_fp64": err_vs(s_out),
+            "_out": s_out}
+        log(f"64x64 {name}: block product {s_bms:.3f} ms, apply {s_apply:.3f} ms, "
+            f"rel err vs FP64 {split[name]['rel_err_vs_fp64']:.2e}")
     sec = {"workload": "64x64 lattice, n_eq 288 (72 patches/box), 16 RHS (8 seeded theta x TE/TM), 32 types, "
                        "128x128 padded FFT, FP32 blocks",
            "block_product_variants_autotuner": variants, "chosen": E.BP_NAMES[best],
@@ -138,13 +177,14 @@ def multi_rhs_section(E, W, torch, np, with_oracle):
            "block_product_GBs": round(bytes_bp / (bms / 1e3) / 1e9, 1),
            "apply_T_ms": round(apply_ms, 4),
            "unknowns_rhs_per_s": cfg.n_unknowns * nrhs / (apply_ms / 1e3),
-           "fp32_rel_err_vs_fp64": err32}
-    if with_oracle:
-        from oracle import coupling as C
-        e = (cfg.ny // 3, cfg.nx // 2)
-        ys = C.apply_T_elements(g.rho, g.area, g.tan, W.PITCH, W.K0, b, [e], chunk_rows=4)[0]
-        sec["fp64_sampled_rel_err_vs_oracle"] = float(np.linalg.norm(ref[:, e[0], e[1]] - ys) / np.linalg.norm(ys))
-        sec["fp32_sampled_rel_err_vs_oracle"] = float(np.linalg.norm(out[:, e[0], e[1]] - ys) / np.linalg.norm(ys))
+           "fp32_rel_err_vs_fp64": err32,
+           "split_bf16": split}
+    e = (cfg.ny // 3, cfg.nx // 2)
+    sec["_sample"] = {"element": e, "b": b, "geom": g,
+                      "outputs": {"fp64": ref[:, e[0], e[1]], "fp32": out[:, e[0], e[1]],
+                                  **{name: d["_out"][:, e[0], e[1]] for name, d in split.items()}}}
+    for d in split.values():
+        d.pop("_out")
     plan.destroy()
     # the same lattice with the structured outer operator (L and K stored)
     plan = E.emsurf_plan_create_green(cfg.nx, cfg.ny, cfg.n_types, nrhs, geom, S, tm, form=E.EMSURF_T_LK,
@@ -174,7 +214,7 @@ def multi_rhs_section(E, W, torch, np, with_oracle):
         "block_product_GBs": round(lk_bytes / (lk_bms / 1e3) / 1e9, 1),
         "apply_T_ms": round(lk_apply_ms, 4),
         "unknowns_rhs_per_s": cfg.n_unknowns * nrhs / (lk_apply_ms / 1e3)}
-    log(f"64x64 multi-RHS: {sec}")
+    log(f"64x64 multi-RHS: { {k: v for k, v in sec.items() if k != '_sample'} }")
     plan.destroy()
     return sec
 
@@ -594,7 +634,7 @@ def main():
 
     multi = None
     if not args.no_multi:
-        multi = multi_rhs_section(E, W, torch, np, not args.no_cpu)
+        multi = multi_rhs_section(E, W, torch, np)
 
     macromodels = None
     if not args.no_macromodels:
@@ -629,6 +669,17 @@ def main():
         y_gpu = y64.cpu().numpy()
         cpu, parity = cpu_baseline(cfg, b, y_gpu, args.cpu_budget)
         log(f"cpu baseline: {cpu['value']:.3e} unknowns*RHS/s; sampled FP64 GPU vs oracle rel err {parity:.2e}")
+        if multi is not None:
+            # the 64x64 outputs at one element against the oracle's row evaluation
+            from oracle import coupling as C
+            smp = multi["_sample"]
+            (iy, ix), g3 = smp["element"], smp["geom"]
+            ys = C.apply_T_elements(g3.rho, g3.area, g3.tan, W.PITCH, W.K0, smp["b"], [(iy, ix)], chunk_rows=4)[0]
+            errs = {k: float(np.linalg.norm(v - ys) / np.linalg.norm(ys)) for k, v in smp["outputs"].items()}
+            multi["sampled_rel_err_vs_oracle"] = {"element": [iy, ix], **errs}
+            log(f"64x64 sampled errors vs oracle: {errs}")
+    if multi is not None:
+        multi.pop("_sample", None)
 
     out = {
         "metric": "coupled unknowns*RHS/s per T-apply at 128x128 lattice; GMRES solve time",

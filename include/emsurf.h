@@ -62,12 +62,23 @@ typedef enum {
 typedef enum {
   EMSURF_FP64 = 0,     /* FP64 FFTs and products on the FP64 Fourier-domain store */
   EMSURF_FP32 = 1,     /* FP32 FFTs and products on the FP32 store (rounded from FP64) */
-  EMSURF_FP32_IR = 2   /* solve only: FP32 inner GMRES, FP64 residual refinement */
+  EMSURF_FP32_IR = 2,  /* solve only: FP32 inner GMRES, FP64 residual refinement */
+  EMSURF_BF16X3 = 3,   /* applies only: FP32 FFTs, block products on the split-BF16 store with
+                          three matrix-core products per entry, a b ~ a_hi b_hi + a_hi b_lo +
+                          a_lo b_hi accumulated in FP32 (a = a_hi + a_lo, both bfloat16 rounded
+                          to nearest even, a_lo = bf16(a - a_hi); the FP32 spectral input is
+                          split the same way); per-product error about 3 * 2^-16 |a||b| */
+  EMSURF_BF16 = 4      /* applies only: as EMSURF_BF16X3 with a_hi b_hi alone, reading half the
+                          store; per-product error about 2^-7 |a||b| */
 } emsurf_prec;
 
 /* bit mask of Fourier-domain block stores kept resident in a plan */
 #define EMSURF_STORE_FP64 1u
 #define EMSURF_STORE_FP32 2u
+/* split-BF16 store (for EMSURF_BF16X3 / EMSURF_BF16): per frequency a hi plane
+ * then a lo plane of the FP32-rounded block, 8 n_eq^2 bytes in all.  Dense,
+ * non-reciprocal plans with n_eq a multiple of 32 in [32, 480] only. */
+#define EMSURF_STORE_BF16 4u
 
 typedef struct emsurf_plan_s* emsurf_plan;
 
@@ -136,6 +147,7 @@ typedef struct {
   size_t bytes_that32;      /* FP32 store, 0 if absent */
   size_t bytes_total;       /* all device memory the plan holds */
   int64_t n_stored;         /* Fourier-domain blocks per store: n_freq, or the pair count of a reciprocal plan */
+  size_t bytes_that16;      /* split-BF16 store (hi and lo planes), 0 if absent */
 } emsurf_plan_stats;
 
 /* Device bytes a plan with this descriptor will hold (Fourier-domain stores,
@@ -256,14 +268,17 @@ emsurf_status emsurf_far_field(const emsurf_geom* geom, int32_t nx, int32_t ny, 
                                int32_t Lv, const void* x_dev, void* E_dev, void* stream);
 
 /* y = T x over nrhs right-hand sides (1 <= nrhs <= max_rhs).  x_dev and y_dev
- * are c128 for EMSURF_FP64 and c64 for EMSURF_FP32, [nrhs][ny][nx][n_eq]; they
- * must not overlap.  Requires the matching store in the plan. */
+ * are c128 for EMSURF_FP64 and c64 for EMSURF_FP32, EMSURF_BF16X3 and
+ * EMSURF_BF16, [nrhs][ny][nx][n_eq]; they must not overlap.  Requires the
+ * matching store in the plan (EMSURF_STORE_BF16 for the split-BF16 forms,
+ * which run the FFTs in FP32).  EMSURF_FP32_IR is rejected (EMSURF_ERR_ARG). */
 emsurf_status emsurf_apply_T(emsurf_plan plan, emsurf_prec prec, int32_t nrhs, const void* x_dev,
                              void* y_dev, void* stream);
 
-/* y = S x (block-diagonal macromodel apply).  Same types and layout as apply_T;
- * x_dev and y_dev may be the same buffer only if they are identical pointers
- * (then the call is out-of-place internally). */
+/* y = S x (block-diagonal macromodel apply).  Same types and layout as apply_T
+ * (the split-BF16 precisions apply S in FP32); x_dev and y_dev may be the same
+ * buffer only if they are identical pointers (then the call is out-of-place
+ * internally). */
 emsurf_status emsurf_apply_S(emsurf_plan plan, emsurf_prec prec, int32_t nrhs, const void* x_dev,
                              void* y_dev, void* stream);
 
@@ -344,7 +359,8 @@ emsurf_status emsurf_plan_set_variant(emsurf_plan plan, int32_t nrhs, int32_t va
  * `stream` (must not be the null stream) and instantiates it.  Launching the
  * graph on any stream then recomputes y from the current content of x.  The
  * graph uses the workspace belonging to `stream`: do not overlap a graph
- * launch with other applies issued on that stream. */
+ * launch with other applies issued on that stream.  prec: EMSURF_FP64,
+ * EMSURF_FP32, EMSURF_BF16X3 or EMSURF_BF16, as for the applies. */
 typedef struct emsurf_graph_s* emsurf_graph;
 #define EMSURF_OP_T 0
 #define EMSURF_OP_S 1

@@ -28,9 +28,12 @@ EMSURF_ERR_UNSUPPORTED = 6
 EMSURF_FP64 = 0
 EMSURF_FP32 = 1
 EMSURF_FP32_IR = 2
+EMSURF_BF16X3 = 3
+EMSURF_BF16 = 4
 
 EMSURF_STORE_FP64 = 1
 EMSURF_STORE_FP32 = 2
+EMSURF_STORE_BF16 = 4
 
 EMSURF_T_DENSE = 0
 EMSURF_T_LK = 1
@@ -98,7 +101,8 @@ class emsurf_server_stats(ctypes.Structure):
 class emsurf_plan_stats(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("n_freq", ctypes.c_int64),
                 ("bytes_that64", ctypes.c_size_t), ("bytes_that32", ctypes.c_size_t),
-                ("bytes_total", ctypes.c_size_t), ("n_stored", ctypes.c_int64)]
+                ("bytes_total", ctypes.c_size_t), ("n_stored", ctypes.c_int64),
+                ("bytes_that16", ctypes.c_size_t)]
 
 
 _P = ctypes.c_void_p

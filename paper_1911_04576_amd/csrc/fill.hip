@@ -206,7 +206,7 @@ __global__ void lk_blocks_kernel(const double* __restrict__ rho, const double* _
 
 __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, long long nn, long long c0,
                                    long long nc, const int* __restrict__ slot_of, int n, double2* __restrict__ t64,
-                                   float2* __restrict__ t32) {
+                                   float2* __restrict__ t32, __bf16* __restrict__ t16) {
   const long long total = P * nc;
   const long long blk64 = pair_block_entries64(n), blk32 = pair_block_entries32(n);
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
@@ -217,6 +217,21 @@ __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, 
       const long long dst = kf * nn + c0 + j;
       if (t64) t64[dst] = v;
       if (t32) t32[dst] = float2{(float)v.x, (float)v.y};
+      if (t16) {
+        // split of the FP32-rounded entry: hi = bf16(a), lo = bf16(a - hi),
+        // both round to nearest even (a - hi is exact in FP32)
+        const long long col = c0 + j;
+        const int cv = (int)(col / n), u = (int)(col - (long long)cv * n);
+        __bf16* hi = t16 + kf * 4 * nn;
+        __bf16* lo = hi + 2 * nn;
+        const float parts[2] = {(float)v.x, (float)v.y};
+        for (int pp = 0; pp < 2; ++pp) {
+          const __bf16 hv = (__bf16)parts[pp];
+          const long long o = bf16_offset(n, u, cv, pp);
+          hi[o] = hv;
+          lo[o] = (__bf16)(parts[pp] - (float)hv);
+        }
+      }
       continue;
     }
     const long long slot = slot_of[kf];
@@ -338,10 +353,12 @@ void launch_green_blocks(const GreenGeomDev& g, int nx, int ny, void* T_blocks, 
 }
 
 void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, const int* slot_of, int n,
-                        void* that64, void* that32, hipStream_t s) {
+                        void* that64, void* that32, void* that16, hipStream_t s) {
+  EMS_CHECK_ARG(!(that16 && slot_of), "internal: the split-BF16 store has no reciprocal layout");
   hipLaunchKernelGGL(store_chunk_kernel, dim3(grid_for((long long)P * nc, 256)), dim3(256), 0, s,
                      static_cast<const double2*>(Kc), (long long)P, (long long)nn, (long long)c0, (long long)nc,
-                     slot_of, n, static_cast<double2*>(that64), static_cast<float2*>(that32));
+                     slot_of, n, static_cast<double2*>(that64), static_cast<float2*>(that32),
+                     static_cast<__bf16*>(that16));
   EMS_LAUNCH_CHECK();
 }
 

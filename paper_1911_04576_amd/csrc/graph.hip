@@ -27,11 +27,12 @@ extern "C" emsurf_status emsurf_graph_create(emsurf_plan plan, int32_t op, emsur
     EMS_CHECK_ARG(plan != nullptr && out != nullptr, "plan and out must be non-NULL");
     EMS_CHECK_ARG(s != nullptr, "graph capture needs a non-null stream");
     EMS_CHECK_ARG(op == EMSURF_OP_T || op == EMSURF_OP_S || op == EMSURF_OP_A, "op must be EMSURF_OP_T/S/A");
-    EMS_CHECK_ARG(prec == EMSURF_FP64 || prec == EMSURF_FP32, "graph precision must be EMSURF_FP64 or EMSURF_FP32");
     EMS_CHECK_ARG(nrhs >= 1 && nrhs <= plan->d.max_rhs, "nrhs must be in [1, max_rhs]");
     EMS_CHECK_ARG(x_dev && y_dev && x_dev != y_dev, "x and y must be distinct non-NULL device buffers");
-    const Cx t = prec == EMSURF_FP64 ? Cx::C128 : Cx::C64;
-    if ((t == Cx::C128 && !plan->that64.p) || (t == Cx::C64 && !plan->that32.p)) {
+    const ApplyPrec ap = apply_prec(prec);
+    const Cx t = ap.t;
+    const void* store = ap.split ? plan->that16.p : t == Cx::C128 ? plan->that64.p : plan->that32.p;
+    if (op != EMSURF_OP_S && !store) {
       set_error("plan lacks the Fourier-domain store for this precision");
       throw Err{EMSURF_ERR_UNSUPPORTED};
     }
@@ -43,9 +44,9 @@ extern "C" emsurf_status emsurf_graph_create(emsurf_plan plan, int32_t op, emsur
     EMS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     capturing = true;
     if (op == EMSURF_OP_T) {
-      apply_T_typed(plan, t, t, t, nrhs, x_dev, y_dev, s);
+      apply_T_typed(plan, t, t, t, nrhs, x_dev, y_dev, s, -1, ap.split);
     } else if (op == EMSURF_OP_A) {
-      apply_A_typed(plan, t, t, t, nrhs, x_dev, y_dev, s);
+      apply_A_typed(plan, t, t, t, nrhs, x_dev, y_dev, s, -1, ap.split);
     } else {
       const void* S = (t == Cx::C128) ? plan->S64.p : plan->S32.p;
       launch_apply_S(t, t, t, S, plan->tiles, plan->d.n_eq, plan->M, nrhs, x_dev, nullptr, y_dev, s);

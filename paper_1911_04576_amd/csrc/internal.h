@@ -221,6 +221,16 @@ void launch_block_mfma_lk(int variant, const void* That, const void* xh, void* y
 // block_variant_supported rejects
 void launch_block_mfma(int variant, const void* That, const void* xh, void* yh, int n, int nrhs, int64_t P,
                        hipStream_t s);
+// Split-BF16 products (blockprod_bf16.hip): split = 3 runs a_hi b_hi + a_hi b_lo
+// + a_lo b_hi, split = 1 a_hi b_hi alone; FP32 spectral input and output.
+// Tb: per frequency a hi plane then a lo plane, entry (u, v) part p at bf16
+// index ((v / 4) n + u) 8 + (v % 4) 2 + p of its plane (bf16_offset).
+bool block_bf16_supported(int n);
+void launch_block_bf16(int split, const void* Tb, const void* xh, void* yh, int n, int nrhs, int64_t P,
+                       hipStream_t s);
+__host__ __device__ inline int64_t bf16_offset(int n, int u, int v, int p) {
+  return ((int64_t)(v / 4) * n + u) * 8 + (v % 4) * 2 + p;
+}
 
 // ----------------------------------------------------------------------------- S apply
 struct TypeTiles {
@@ -258,8 +268,10 @@ void launch_green_blocks(const GreenGeomDev& g, int nx, int ny, void* T_blocks, 
 // stored block, -1 for frequencies that are not stored; with slot_of the
 // blocks (n x n, kernel column v n + u) go to the row-panel layout of the
 // reciprocal store, else to [k][v][u].
+// that16 (or NULL): the split-BF16 store of a full dense plan (slot_of NULL),
+// split from the FP32-rounded entry.
 void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, const int* slot_of, int n,
-                        void* that64, void* that32, hipStream_t s);
+                        void* that64, void* that32, void* that16, hipStream_t s);
 // max |T(-d)[u][v] - T(d)[v][u] w[v] / w[u]| and max |T(d)| over dense caller
 // blocks [2ny-1][2nx-1][n][n] (device), written to out (device double [2]).
 void launch_recip_check(const void* T_blocks_dev, int nx, int ny, int n, const double* w_dev, double* out,
@@ -297,6 +309,7 @@ struct emsurf_plan_s {
   int64_t P = 0;
   int M = 0;
   emsurf::DevBuf that64, that32;  // [Ps][v][u]
+  emsurf::DevBuf that16;          // split-BF16 store: [P][hi | lo plane], bf16_offset order
   int64_t Ps = 0;                 // stored blocks: P, or the pair count of a reciprocal plan
   emsurf::DevBuf pairs;           // reciprocal plans: int [Ps][2]
   emsurf::DevBuf w64, winv64, w32, winv32;  // reciprocal weights and inverses [n]
@@ -319,11 +332,20 @@ Workspace& workspace(emsurf_plan p, hipStream_t s);
 int choose_variant(emsurf_plan p, int nrhs);
 // apply_T with explicit element types: input tin, compute/that type tc, output tout.
 // variant: FP32 block-product variant, -1 = the plan's choice for nrhs.
+// split: 0 = products on the tc store; 1 or 3 = split-BF16 products (tc must
+// be C64) with one or three matrix-core products per entry.
 void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* x, void* y, hipStream_t s,
-                   int variant = -1);
+                   int variant = -1, int split = 0);
 // apply_A with explicit types: x (tx) -> y (ty) = x - S T x, arithmetic in tc.
 void apply_A_typed(emsurf_plan p, Cx tx, Cx tc, Cx ty, int nrhs, const void* x, void* y, hipStream_t s,
-                   int variant = -1);
+                   int variant = -1, int split = 0);
+// element type and split of an apply precision (EMSURF_FP64, EMSURF_FP32,
+// EMSURF_BF16X3, EMSURF_BF16); ERR_ARG for any other
+struct ApplyPrec {
+  Cx t;
+  int split;
+};
+ApplyPrec apply_prec(emsurf_prec prec);
 inline size_t cx_bytes(Cx t) { return t == Cx::C128 ? 16 : 8; }
 // kernel columns (complex entries) of one frequency's Fourier-domain record:
 // n_eq^2 for dense blocks, 2 (n_eq/2)^2 for the L and K operators

@@ -21,9 +21,9 @@ void validate_desc(const emsurf_plan_desc* d) {
   EMS_CHECK_ARG(d->n_eq >= 1 && d->n_eq <= 512, "n_eq must be in [1, 512]");
   EMS_CHECK_ARG(d->n_types >= 1, "n_types must be >= 1");
   EMS_CHECK_ARG(d->max_rhs >= 1 && d->max_rhs <= 64, "max_rhs must be in [1, 64]");
-  EMS_CHECK_ARG((d->store & (EMSURF_STORE_FP64 | EMSURF_STORE_FP32)) != 0 &&
-                    (d->store & ~(EMSURF_STORE_FP64 | EMSURF_STORE_FP32)) == 0,
-                "store must be a non-empty mask of EMSURF_STORE_FP64 | EMSURF_STORE_FP32");
+  const uint32_t all = EMSURF_STORE_FP64 | EMSURF_STORE_FP32 | EMSURF_STORE_BF16;
+  EMS_CHECK_ARG(d->store != 0 && (d->store & ~all) == 0,
+                "store must be a non-empty mask of EMSURF_STORE_FP64 | EMSURF_STORE_FP32 | EMSURF_STORE_BF16");
   EMS_CHECK_ARG(d->form == EMSURF_T_DENSE || d->form == EMSURF_T_LK, "form must be EMSURF_T_DENSE or EMSURF_T_LK");
   if (d->form == EMSURF_T_LK) {
     EMS_CHECK_ARG(d->n_eq % 2 == 0, "EMSURF_T_LK needs an even n_eq (J and M halves)");
@@ -31,6 +31,11 @@ void validate_desc(const emsurf_plan_desc* d) {
   }
   EMS_CHECK_ARG(d->recip == 0 || d->recip == 1, "recip must be 0 or 1");
   EMS_CHECK_ARG(d->recip == 0 || d->form == EMSURF_T_DENSE, "reciprocal storage is supported for EMSURF_T_DENSE only");
+  if (d->store & EMSURF_STORE_BF16) {
+    EMS_CHECK_ARG(d->form == EMSURF_T_DENSE && d->recip == 0,
+                  "the split-BF16 store needs a dense plan that stores every frequency (recip 0)");
+    EMS_CHECK_ARG(block_bf16_supported(d->n_eq), "the split-BF16 store needs n_eq a multiple of 32 in [32, 480]");
+  }
 }
 
 // stored blocks: every frequency, or one per pair {k, -k} (a length L has one
@@ -45,7 +50,7 @@ int64_t stored_blocks(int Lx, int Ly, bool recip) {
 struct Sizes {
   int Lx, Ly;
   int64_t P, Ps, M, n, nn;
-  size_t that64, that32, S, tiles, ws;
+  size_t that64, that32, that16, S, tiles, ws;
 };
 
 Sizes sizes_of(const emsurf_plan_desc* d) {
@@ -62,6 +67,7 @@ Sizes sizes_of(const emsurf_plan_desc* d) {
   const int64_t kc32 = d->recip ? pair_block_entries32(d->n_eq) : kc;
   z.that64 = (d->store & EMSURF_STORE_FP64) ? (size_t)(z.Ps * kc64) * 16 : 0;
   z.that32 = (d->store & EMSURF_STORE_FP32) ? (size_t)(z.Ps * kc32) * 8 : 0;
+  z.that16 = (d->store & EMSURF_STORE_BF16) ? (size_t)(z.P * z.nn) * 8 : 0;
   z.S = (size_t)d->n_types * z.nn * (16 + 8);
   z.tiles = (size_t)z.M * 4 + (size_t)(z.M + d->n_types) * 12;
   if (d->recip) z.tiles += (size_t)z.Ps * 8 + (size_t)z.n * 24;  // pair list and weights
@@ -132,10 +138,12 @@ void timer_end(hipEvent_t e, hipStream_t s) {
 }  // namespace
 
 void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* x, void* y, hipStream_t s,
-                   int variant) {
-  const void* That = (tc == Cx::C128) ? p->that64.p : p->that32.p;
+                   int variant, int split) {
+  EMS_CHECK_ARG(split == 0 || (tc == Cx::C64 && (split == 1 || split == 3)), "internal: bad split-BF16 request");
+  const void* That = split ? p->that16.p : (tc == Cx::C128) ? p->that64.p : p->that32.p;
   if (!That) {
-    set_error(tc == Cx::C128 ? "plan has no FP64 Fourier-domain store" : "plan has no FP32 Fourier-domain store");
+    set_error(split ? "plan has no split-BF16 Fourier-domain store"
+              : tc == Cx::C128 ? "plan has no FP64 Fourier-domain store" : "plan has no FP32 Fourier-domain store");
     throw Err{EMSURF_ERR_UNSUPPORTED};
   }
   Workspace& w = workspace(p, s);
@@ -170,8 +178,11 @@ void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* 
 
   // Fourier-domain block products
   timer_begin(p, 2, s, &e);
-  const int v = tc == Cx::C64 && !p->d.recip ? (variant >= 0 ? variant : choose_variant(p, nrhs)) : BP_GEMV;
-  if (p->d.recip)
+  const int v = tc == Cx::C64 && !p->d.recip && !split ? (variant >= 0 ? variant : choose_variant(p, nrhs))
+                                                       : BP_GEMV;
+  if (split)
+    launch_block_bf16(split, That, w.X.p, w.Y.p, n, nrhs, p->P, s);
+  else if (p->d.recip)
     launch_block_product_pair(tc, That, p->pairs.p, tc == Cx::C128 ? p->w64.p : p->w32.p,
                               tc == Cx::C128 ? p->winv64.p : p->winv32.p, w.X.p, w.Y.p, n, nrhs, p->Ps, s);
   else if (p->d.form == EMSURF_T_LK)
@@ -201,9 +212,9 @@ void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* 
 }
 
 void apply_A_typed(emsurf_plan p, Cx tx, Cx tc, Cx ty, int nrhs, const void* x, void* y, hipStream_t s,
-                   int variant) {
+                   int variant, int split) {
   Workspace& w = workspace(p, s);
-  apply_T_typed(p, tx, tc, tc, nrhs, x, w.t.p, s, variant);
+  apply_T_typed(p, tx, tc, tc, nrhs, x, w.t.p, s, variant, split);
   const void* S = (tc == Cx::C128) ? p->S64.p : p->S32.p;
   launch_apply_S(tc, tc, ty, S, p->tiles, p->d.n_eq, p->M, nrhs, w.t.p, x, y, s);
 }
@@ -298,6 +309,7 @@ void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill) {
   const int64_t kc32 = p->d.recip ? pair_block_entries32(n) : nn;
   if (p->d.store & EMSURF_STORE_FP64) p->that64.alloc((size_t)(p->Ps * kc64) * 16);
   if (p->d.store & EMSURF_STORE_FP32) p->that32.alloc((size_t)(p->Ps * kc32) * 8);
+  if (p->d.store & EMSURF_STORE_BF16) p->that16.alloc((size_t)(P * nn) * 8);
   // the padding rows of the last panel of a reciprocal store stay zero
   if (p->d.recip && kc64 != nn && p->that64.p) EMS_HIP(hipMemsetAsync(p->that64.p, 0, p->that64.bytes, s));
   if (p->d.recip && kc32 != nn && p->that32.p) EMS_HIP(hipMemsetAsync(p->that32.p, 0, p->that32.bytes, s));
@@ -336,7 +348,8 @@ void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill) {
     fy.out_s0 = cnt; fy.out_pt = (int64_t)p->Lx * cnt;
     fy.sign = -1;
     launch_fft_pass(fy, Cx::C128, Cx::C128, Cx::C128, tmp.p, K.p, twy, s);
-    launch_store_chunk(K.p, P, nn, c0, cnt, slot_dev.as<const int>(), n, p->that64.p, p->that32.p, s);
+    launch_store_chunk(K.p, P, nn, c0, cnt, slot_dev.as<const int>(), n, p->that64.p, p->that32.p, p->that16.p,
+                       s);
   }
   EMS_HIP(hipStreamSynchronize(s));
 }
@@ -389,12 +402,23 @@ void set_weights(emsurf_plan p, const std::vector<double>& w, hipStream_t s) {
   EMS_HIP(hipStreamSynchronize(s));
 }
 
-Cx prec_type(emsurf_prec prec) {
-  if (prec == EMSURF_FP64) return Cx::C128;
-  if (prec == EMSURF_FP32) return Cx::C64;
-  set_error("apply precision must be EMSURF_FP64 or EMSURF_FP32");
+}  // namespace
+
+namespace emsurf {
+ApplyPrec apply_prec(emsurf_prec prec) {
+  switch (prec) {
+    case EMSURF_FP64: return {Cx::C128, 0};
+    case EMSURF_FP32: return {Cx::C64, 0};
+    case EMSURF_BF16X3: return {Cx::C64, 3};
+    case EMSURF_BF16: return {Cx::C64, 1};
+    default: break;
+  }
+  set_error("apply precision must be EMSURF_FP64, EMSURF_FP32, EMSURF_BF16X3 or EMSURF_BF16");
   throw Err{EMSURF_ERR_ARG};
 }
+}  // namespace emsurf
+
+namespace {
 
 void check_apply(emsurf_plan plan, int32_t nrhs, const void* x, const void* y) {
   EMS_CHECK_ARG(plan != nullptr, "plan is NULL");
@@ -411,7 +435,7 @@ size_t emsurf_plan_bytes(const emsurf_plan_desc* desc) {
   if (guarded([&] {
         validate_desc(desc);
         auto z = sizes_of(desc);
-        out = z.that64 + z.that32 + z.S + z.tiles + z.ws;
+        out = z.that64 + z.that32 + z.that16 + z.S + z.tiles + z.ws;
       }) != EMSURF_OK)
     return 0;
   return out;
@@ -575,8 +599,8 @@ emsurf_status emsurf_apply_T(emsurf_plan plan, emsurf_prec prec, int32_t nrhs, c
   return guarded([&] {
     check_apply(plan, nrhs, x_dev, y_dev);
     EMS_CHECK_ARG(x_dev != y_dev, "apply_T needs distinct x and y buffers");
-    const Cx t = prec_type(prec);
-    apply_T_typed(plan, t, t, t, nrhs, x_dev, y_dev, static_cast<hipStream_t>(stream));
+    const ApplyPrec ap = apply_prec(prec);
+    apply_T_typed(plan, ap.t, ap.t, ap.t, nrhs, x_dev, y_dev, static_cast<hipStream_t>(stream), -1, ap.split);
   });
 }
 
@@ -584,7 +608,7 @@ emsurf_status emsurf_apply_S(emsurf_plan plan, emsurf_prec prec, int32_t nrhs, c
                              void* stream) {
   return guarded([&] {
     check_apply(plan, nrhs, x_dev, y_dev);
-    const Cx t = prec_type(prec);
+    const Cx t = apply_prec(prec).t;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const void* S = (t == Cx::C128) ? plan->S64.p : plan->S32.p;
     const void* src = x_dev;
@@ -603,8 +627,8 @@ emsurf_status emsurf_apply_A(emsurf_plan plan, emsurf_prec prec, int32_t nrhs, c
   return guarded([&] {
     check_apply(plan, nrhs, x_dev, y_dev);
     EMS_CHECK_ARG(x_dev != y_dev, "apply_A needs distinct x and y buffers");
-    const Cx t = prec_type(prec);
-    apply_A_typed(plan, t, t, t, nrhs, x_dev, y_dev, static_cast<hipStream_t>(stream));
+    const ApplyPrec ap = apply_prec(prec);
+    apply_A_typed(plan, ap.t, ap.t, ap.t, nrhs, x_dev, y_dev, static_cast<hipStream_t>(stream), -1, ap.split);
   });
 }
 
@@ -617,7 +641,8 @@ emsurf_status emsurf_plan_query(emsurf_plan plan, emsurf_plan_stats* out) {
     out->bytes_that64 = plan->that64.bytes;
     out->bytes_that32 = plan->that32.bytes;
     out->n_stored = plan->Ps;
-    size_t tot = plan->that64.bytes + plan->that32.bytes + plan->S64.bytes + plan->S32.bytes +
+    out->bytes_that16 = plan->that16.bytes;
+    size_t tot = plan->that64.bytes + plan->that32.bytes + plan->that16.bytes + plan->S64.bytes + plan->S32.bytes +
                  plan->tiles.elem_sorted.bytes + plan->tiles.tiles.bytes + plan->pairs.bytes + plan->w64.bytes +
                  plan->winv64.bytes + plan->w32.bytes + plan->winv32.bytes;
     std::lock_guard<std::mutex> lk(plan->mu);

@@ -79,3 +79,22 @@ def test_reciprocal_plan_bytes_and_desc_checks():
     # reciprocal storage is for dense blocks only; recip must be 0 or 1
     assert E.emsurf_plan_bytes(8, 8, 96, 4, 1, form=E.EMSURF_T_LK, recip=1) == 0
     assert E.emsurf_plan_bytes(8, 8, 96, 4, 1, recip=2) == 0
+
+
+def test_split_bf16_store_bytes_and_desc_checks():
+    import paper_1911_04576_amd as E
+    if not os.path.exists(E.LIB_PATH):
+        pytest.skip("library not built")
+    # hi and lo bfloat16 planes: 8 bytes per complex entry, as much as the FP32 store
+    b32 = E.emsurf_plan_bytes(64, 64, 288, 32, 16, store=E.EMSURF_STORE_FP32)
+    b16 = E.emsurf_plan_bytes(64, 64, 288, 32, 16, store=E.EMSURF_STORE_BF16)
+    both = E.emsurf_plan_bytes(64, 64, 288, 32, 16, store=E.EMSURF_STORE_FP32 | E.EMSURF_STORE_BF16)
+    store = 128 * 128 * 288 * 288 * 8
+    assert b16 == b32 and both - b32 == store
+    # dense, full (non-reciprocal) plans with n_eq a multiple of 32 in [32, 480] only
+    assert E.emsurf_plan_bytes(8, 8, 96, 4, 1, store=E.EMSURF_STORE_BF16, recip=1) == 0
+    assert E.emsurf_plan_bytes(8, 8, 96, 4, 1, store=E.EMSURF_STORE_BF16, form=E.EMSURF_T_LK) == 0
+    assert E.emsurf_plan_bytes(8, 8, 48, 4, 1, store=E.EMSURF_STORE_BF16) == 0
+    assert E.emsurf_plan_bytes(8, 8, 512, 4, 1, store=E.EMSURF_STORE_BF16) == 0
+    assert E.emsurf_plan_bytes(8, 8, 480, 4, 1, store=E.EMSURF_STORE_BF16) > 0
+    assert E.emsurf_plan_bytes(8, 8, 96, 4, 1, store=8) == 0
