@@ -360,25 +360,43 @@ __global__ void __launch_bounds__(PNT, 2) pair_f32_kernel(const float* __restric
         if (jok) atomicAdd(&zs[(q * PAIR_TILE + 4 * (l >> 4) + e) * 2 * NRW + jj], zq[e]);
     }
   }
-  // first product: rows of this wavefront's u tiles
-  float2* y0 = yh + k * (long long)nrhs * n + (long long)r0 * n;
-  float* y0f = reinterpret_cast<float*>(y0);
+  // outputs: the row sums are staged in LDS over the spectral columns of
+  // xh[k] (no longer read once every wavefront is past its loop), in the
+  // layout of the column sums, and both products leave as coalesced
+  // non-temporal stores, two complex values per 16-byte store when n is even
+  __syncthreads();
+  float* ys = xs;  // [np][2 NRW]: row sums (yh[k])
 #pragma unroll
   for (int ta = 0; ta < TPW; ++ta) {
     if (ta < ntw) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int u = (wv + 4 * ta) * PAIR_TILE + 4 * (l >> 4) + e;
-        if (u < n && jok && rj < nr) y0f[2 * ((long long)rj * n + u) + (jre ? 0 : 1)] = acc[ta][e];
+        if (jok) ys[u * 2 * NRW + jj] = acc[ta][e];
       }
     }
   }
   __syncthreads();
-  if (!self) {
-    float2* y1 = yh + kb * (long long)nrhs * n + (long long)r0 * n;
+  float2* y0 = yh + k * (long long)nrhs * n + (long long)r0 * n;
+  float2* y1 = yh + kb * (long long)nrhs * n + (long long)r0 * n;
+  if ((n & 1) == 0) {
+    for (int e2 = threadIdx.x; e2 < nr * n / 2; e2 += PNT) {
+      const int e = 2 * e2, r = e / n, v = e - r * n;   // v + 1 < n in the same row r
+      const int c0 = v * 2 * NRW + r, c1 = c0 + 2 * NRW;
+      const f4v a = {ys[c0], ys[c0 + NRW], ys[c1], ys[c1 + NRW]};
+      __builtin_nontemporal_store(a, reinterpret_cast<f4v*>(y0 + e));
+      if (!self) {
+        const float w0 = winv[v], w1 = winv[v + 1];
+        const f4v b = {zs[c0] * w0, zs[c0 + NRW] * w0, zs[c1] * w1, zs[c1 + NRW] * w1};
+        __builtin_nontemporal_store(b, reinterpret_cast<f4v*>(y1 + e));
+      }
+    }
+  } else {
     for (int e = threadIdx.x; e < nr * n; e += PNT) {
       const int r = e / n, v = e - r * n;
-      y1[e] = float2{zs[v * 2 * NRW + r] * winv[v], zs[v * 2 * NRW + NRW + r] * winv[v]};
+      const int c0 = v * 2 * NRW + r;
+      y0[e] = float2{ys[c0], ys[c0 + NRW]};
+      if (!self) y1[e] = float2{zs[c0] * winv[v], zs[c0 + NRW] * winv[v]};
     }
   }
 }
