@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(PNT, 2) pair_f32_kernel(const float* __restric
   const long long blk = (long long)nt * nt * 2 * PAIR_TILE * PAIR_TILE;  // floats
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(That + slot * blk), (short)0, (int)(blk * (long long)sizeof(float)), 0x00020000);
-  const unsigned voff = (unsigned)(l * 32);
+  const unsigned voff = (unsigned)(l * 16);   // registers 0-3; registers 4-7 sit 1024 bytes on
   // this wavefront's tiles are stored contiguously in visiting order
   // it = q * ntw + ta (u tile wv + 4 ta, v tile q)
   const int nvisit = ntw * nt, wbase_tile = pair_wave_base(nt, wv);
@@ -272,9 +272,9 @@ __global__ void __launch_bounds__(PNT, 2) pair_f32_kernel(const float* __restric
   f4v p0{0, 0, 0, 0}, p1{0, 0, 0, 0}, nx0{0, 0, 0, 0}, nx1{0, 0, 0, 0};
   if (ntw > 0) {
     p0 = ld_tile(rs, voff, visit_off(0));
-    p1 = ld_tile(rs, voff + 16, visit_off(0));
+    p1 = ld_tile(rs, voff + 1024, visit_off(0));
     nx0 = ld_tile(rs, voff, visit_off(1));
-    nx1 = ld_tile(rs, voff + 16, visit_off(1));
+    nx1 = ld_tile(rs, voff + 1024, visit_off(1));
   }
   const float2* x0 = xh + k * (long long)nrhs * n + (long long)r0 * n;
   const float2* x1 = xh + kb * (long long)nrhs * n + (long long)r0 * n;
@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(PNT, 2) pair_f32_kernel(const float* __restric
         p0 = nx0;
         p1 = nx1;
         nx0 = ld_tile(rs, voff, noff);
-        nx1 = ld_tile(rs, voff + 16, noff);
+        nx1 = ld_tile(rs, voff + 1024, noff);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s = 0; s < 8; ++s) acc[ta] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[s], b1[s], acc[ta], 0, 0, 0);

@@ -164,10 +164,12 @@ void launch_block_product_variant(Cx t, int variant, const void* That, const voi
 //        its own u tiles inner, so tile (t, q) sits at
 //        base(t % 4) + q ntw(t % 4) + t / 4, with ntw(w) = (nt - w + 3) / 4
 //        and base(w) = nt sum_{w' < w} ntw(w').  Within a tile, real and
-//        imaginary parts apart: part p of tile entry (a, b) is float
-//        (a + 16 p + 32 (b % 2)) 8 + b / 2 -- the order in which a
-//        wavefront's lanes hold the A operand of the first product on the
-//        matrix cores (lane a + 16 p + 32 (b % 2), register b / 2).
+//        imaginary parts apart: the first product's A operand on the matrix
+//        cores holds part p of tile entry (a, b) in lane L = a + 16 p +
+//        32 (b % 2), register r = b / 2; the tile stores registers 0-3 of
+//        every lane, then registers 4-7, so that float is
+//        (r / 4) 256 + 4 L + r % 4 and each 16-byte load instruction of a
+//        wavefront reads 1024 contiguous bytes.
 constexpr int PAIR_PANEL_FP64 = 4, PAIR_TILE = 16;
 __host__ __device__ inline int pair_tiles(int n) { return (n + PAIR_TILE - 1) / PAIR_TILE; }
 __host__ __device__ inline int64_t pair_block_entries64(int n) {
@@ -196,7 +198,7 @@ __host__ __device__ inline int pair_tile_pos(int nt, int t, int q) {
 __host__ __device__ inline int64_t pair_float_offset32(int n, int u, int v, int p) {
   const int a = u % PAIR_TILE, b = v % PAIR_TILE;
   return (int64_t)pair_tile_pos(pair_tiles(n), u / PAIR_TILE, v / PAIR_TILE) * (2 * PAIR_TILE * PAIR_TILE) +
-         (a + 16 * p + 32 * (b % 2)) * 8 + b / 2;
+         (b / 8) * 256 + (a + 16 * p + 32 * (b % 2)) * 4 + (b / 2) % 4;
 }
 // Reciprocal plans: one block per frequency pair {k, -k}; pairs = int [Ps][2]
 // (k, -k), w / winv the per-unknown weights and their inverses in the compute
