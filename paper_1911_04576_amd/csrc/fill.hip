@@ -208,7 +208,7 @@ __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, 
                                    long long nc, const int* __restrict__ slot_of, int n, double2* __restrict__ t64,
                                    float2* __restrict__ t32, __bf16* __restrict__ t16) {
   const long long total = P * nc;
-  const long long blk64 = pair_block_entries64(n), blk32 = pair_block_entries32(n);
+  const long long blk = pair_block_entries(n);
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
     const long long kf = i / nc, j = i - kf * nc;
@@ -238,11 +238,15 @@ __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, 
     if (slot < 0) continue;
     const long long col = c0 + j;
     const int cv = (int)(col / n), u = (int)(col - (long long)cv * n);
-    if (t64) t64[slot * blk64 + pair_offset64(n, u, cv)] = v;
+    if (t64) {
+      double* d = reinterpret_cast<double*>(t64) + slot * blk * 2;
+      d[pair_value_offset(n, u, cv, 0, 2)] = v.x;
+      d[pair_value_offset(n, u, cv, 1, 2)] = v.y;
+    }
     if (t32) {
-      float* f = reinterpret_cast<float*>(t32) + slot * blk32 * 2;
-      f[pair_float_offset32(n, u, cv, 0)] = (float)v.x;
-      f[pair_float_offset32(n, u, cv, 1)] = (float)v.y;
+      float* f = reinterpret_cast<float*>(t32) + slot * blk * 2;
+      f[pair_value_offset(n, u, cv, 0, 4)] = (float)v.x;
+      f[pair_value_offset(n, u, cv, 1, 4)] = (float)v.y;
     }
   }
 }

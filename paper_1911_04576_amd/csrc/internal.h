@@ -156,31 +156,23 @@ bool block_mfma_supported(int n, int nrhs);
 bool block_variant_supported(int variant, int n, int nrhs);
 void launch_block_product_variant(Cx t, int variant, const void* That, const void* xh, void* yh, int n, int nrhs,
                                   int64_t P, hipStream_t s);
-// Block layouts of the reciprocal store (padding zero):
-//  FP64: row panels of 4 rows, entry (u, v) at ((u / 4) n + v) 4 + u % 4;
-//  FP32: 16 x 16 tiles (nt = ceil(n / 16) per side), 512 floats per tile, in
-//        the order the four wavefronts of the paired product visit them:
-//        u tile t belongs to wavefront t % 4, which walks v tiles q outer and
-//        its own u tiles inner, so tile (t, q) sits at
-//        base(t % 4) + q ntw(t % 4) + t / 4, with ntw(w) = (nt - w + 3) / 4
-//        and base(w) = nt sum_{w' < w} ntw(w').  Within a tile, real and
-//        imaginary parts apart: the first product's A operand on the matrix
-//        cores holds part p of tile entry (a, b) in lane L = a + 16 p +
-//        32 (b % 2), register r = b / 2; the tile stores registers 0-3 of
-//        every lane, then registers 4-7, so that float is
-//        (r / 4) 256 + 4 L + r % 4 and each 16-byte load instruction of a
-//        wavefront reads 1024 contiguous bytes.
-constexpr int PAIR_PANEL_FP64 = 4, PAIR_TILE = 16;
+// Block layout of the reciprocal store (FP64 and FP32 alike, padding zero):
+// 16 x 16 tiles (nt = ceil(n / 16) per side), 256 complex entries per tile,
+// in the order the four wavefronts of the paired product visit them: u tile t
+// belongs to wavefront t % 4, which walks v tiles q outer and its own u tiles
+// inner, so tile (t, q) sits at base(t % 4) + q ntw(t % 4) + t / 4, with
+// ntw(w) = (nt - w + 3) / 4 and base(w) = nt sum_{w' < w} ntw(w').  Within a
+// tile, real and imaginary parts apart: the first product's A operand on the
+// matrix cores holds part p of tile entry (a, b) in lane L = a + 16 p +
+// 32 (b % 2), register r = b / 2.  With ch = 16 / (bytes of a real) values per
+// 16-byte chunk (4 in FP32, 2 in FP64) the tile stores chunk r / ch of every
+// lane in turn: value offset (r / ch) 64 ch + L ch + r % ch, so that each
+// 16-byte load instruction of a wavefront reads 1024 contiguous bytes.
+constexpr int PAIR_TILE = 16;
 __host__ __device__ inline int pair_tiles(int n) { return (n + PAIR_TILE - 1) / PAIR_TILE; }
-__host__ __device__ inline int64_t pair_block_entries64(int n) {
-  return (int64_t)((n + PAIR_PANEL_FP64 - 1) / PAIR_PANEL_FP64) * PAIR_PANEL_FP64 * n;
-}
-// complex entries (= floats / 2) of one FP32 block
-__host__ __device__ inline int64_t pair_block_entries32(int n) {
+// complex entries (= reals / 2) of one stored block
+__host__ __device__ inline int64_t pair_block_entries(int n) {
   return (int64_t)pair_tiles(n) * pair_tiles(n) * PAIR_TILE * PAIR_TILE;
-}
-__host__ __device__ inline int64_t pair_offset64(int n, int u, int v) {
-  return ((int64_t)(u / PAIR_PANEL_FP64) * n + v) * PAIR_PANEL_FP64 + u % PAIR_PANEL_FP64;
 }
 // u tiles of wavefront w, and the first tile position of wavefront w
 __host__ __device__ inline int pair_wave_tiles(int nt, int w) { return (nt - w + 3) / 4; }
@@ -189,16 +181,18 @@ __host__ __device__ inline int pair_wave_base(int nt, int w) {
   for (int x = 0; x < w; ++x) b += pair_wave_tiles(nt, x) * nt;
   return b;
 }
-// tile position of (u tile t, v tile q) within an FP32 block
+// tile position of (u tile t, v tile q) within a block
 __host__ __device__ inline int pair_tile_pos(int nt, int t, int q) {
   const int w = t % 4;
   return pair_wave_base(nt, w) + q * pair_wave_tiles(nt, w) + t / 4;
 }
-// float offset of part p (0 real, 1 imaginary) of entry (u, v) within an FP32 block
-__host__ __device__ inline int64_t pair_float_offset32(int n, int u, int v, int p) {
+// real-value offset of part p (0 real, 1 imaginary) of entry (u, v) within a
+// block; ch = 4 for FP32, 2 for FP64
+__host__ __device__ inline int64_t pair_value_offset(int n, int u, int v, int p, int ch) {
   const int a = u % PAIR_TILE, b = v % PAIR_TILE;
+  const int L = a + 16 * p + 32 * (b % 2), r = b / 2;
   return (int64_t)pair_tile_pos(pair_tiles(n), u / PAIR_TILE, v / PAIR_TILE) * (2 * PAIR_TILE * PAIR_TILE) +
-         (b / 8) * 256 + (a + 16 * p + 32 * (b % 2)) * 4 + (b / 2) % 4;
+         (r / ch) * 64 * ch + L * ch + r % ch;
 }
 // Reciprocal plans: one block per frequency pair {k, -k}; pairs = int [Ps][2]
 // (k, -k), w / winv the per-unknown weights and their inverses in the compute

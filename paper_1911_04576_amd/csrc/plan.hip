@@ -63,8 +63,8 @@ Sizes sizes_of(const emsurf_plan_desc* d) {
   z.n = d->n_eq;
   z.nn = z.n * z.n;
   const int64_t kc = kernel_cols(*d);
-  const int64_t kc64 = d->recip ? pair_block_entries64(d->n_eq) : kc;
-  const int64_t kc32 = d->recip ? pair_block_entries32(d->n_eq) : kc;
+  const int64_t kc64 = d->recip ? pair_block_entries(d->n_eq) : kc;
+  const int64_t kc32 = d->recip ? pair_block_entries(d->n_eq) : kc;
   z.that64 = (d->store & EMSURF_STORE_FP64) ? (size_t)(z.Ps * kc64) * 16 : 0;
   z.that32 = (d->store & EMSURF_STORE_FP32) ? (size_t)(z.Ps * kc32) * 8 : 0;
   z.that16 = (d->store & EMSURF_STORE_BF16) ? (size_t)(z.P * z.nn) * 8 : 0;
@@ -305,8 +305,8 @@ void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill) {
   const int64_t nn = kernel_cols(p->d);
   const int64_t P = p->P;
   const int n = p->d.n_eq;
-  const int64_t kc64 = p->d.recip ? pair_block_entries64(n) : nn;
-  const int64_t kc32 = p->d.recip ? pair_block_entries32(n) : nn;
+  const int64_t kc64 = p->d.recip ? pair_block_entries(n) : nn;
+  const int64_t kc32 = p->d.recip ? pair_block_entries(n) : nn;
   if (p->d.store & EMSURF_STORE_FP64) p->that64.alloc((size_t)(p->Ps * kc64) * 16);
   if (p->d.store & EMSURF_STORE_FP32) p->that32.alloc((size_t)(p->Ps * kc32) * 8);
   if (p->d.store & EMSURF_STORE_BF16) p->that16.alloc((size_t)(P * nn) * 8);

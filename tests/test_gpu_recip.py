@@ -116,7 +116,11 @@ def test_recip_matches_full_plan(signed, zero_self):
     err = rel_per_rhs(y_r, y_f)
     say(f"reciprocal vs full plan (signed weights {signed}, self block {not zero_self}): {err}")
     assert np.all(err <= FP64_TOL)
-    assert plan.stats().bytes_that64 < 0.6 * full.stats().bytes_that64
+    # one block per pair, n padded to whole 16 x 16 tiles
+    nt = -(-n // 16)
+    st = plan.stats()
+    assert st.bytes_that64 == st.n_stored * nt * nt * 256 * 16
+    assert st.bytes_that32 == st.n_stored * nt * nt * 256 * 8
 
 
 def test_recip_delta_columns():
@@ -235,6 +239,8 @@ def test_recip_fullsize_128x128_sampled():
     plan = e.emsurf_plan_create_green(c.nx, c.ny, c.n_types, c.nrhs, geom, W.s_types(c), W.type_map(c), recip=1)
     st = plan.stats()
     say(f"reciprocal 128x128: {st.n_stored} of {st.n_freq} blocks, FP32 store {st.bytes_that32 / 2**30:.2f} GiB")
+    # n_eq 192 fills whole tiles: the paired stores are half the full ones plus the self-paired blocks
+    assert st.bytes_that32 == st.n_stored * 192 * 192 * 8 and st.bytes_that64 == st.n_stored * 192 * 192 * 16
     b = W.plane_wave_rhs(c, g)
     b64 = torch.from_numpy(b).to("cuda")
     y64 = torch.empty_like(b64)
