@@ -701,7 +701,7 @@ def main():
                    "lattice": [cfg.nx, cfg.ny], "n_eq": n, "nrhs": nrhs,
                    "unknowns": cfg.n_unknowns, "padded_fft": [Lx, Ly], "stored_blocks": Ps,
                    "parallelism": "1 GPU"},
-        "roofline": {"kernel": ("pair_f32_kernel<3, 4> (paired Fourier-domain block product, matrix cores)" if recip
+        "roofline": {"kernel": ("pair_mfma_kernel<float, 3, 4, true> (paired Fourier-domain block product, matrix cores)" if recip
                                 else "block_gemv_kernel<float2,4,8> (Fourier-domain block product)"),
                      "bound": "hbm",
                      "achieved": round(bp_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

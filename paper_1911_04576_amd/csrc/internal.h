@@ -186,13 +186,18 @@ __host__ __device__ inline int pair_tile_pos(int nt, int t, int q) {
   const int w = t % 4;
   return pair_wave_base(nt, w) + q * pair_wave_tiles(nt, w) + t / 4;
 }
+// in-tile real-value offset of part p of tile entry (a, b) (row a, column b
+// of a 16 x 16 tile): lane a + 16 p + 32 (b % 2), register b / 2 of the
+// first operand of v_mfma_*_16x16x4, chunk by chunk (ch reals per 16 bytes)
+__host__ __device__ inline int tile_value_offset(int a, int b, int p, int ch) {
+  const int L = a + 16 * p + 32 * (b % 2), r = b / 2;
+  return (r / ch) * 64 * ch + L * ch + r % ch;
+}
 // real-value offset of part p (0 real, 1 imaginary) of entry (u, v) within a
 // block; ch = 4 for FP32, 2 for FP64
 __host__ __device__ inline int64_t pair_value_offset(int n, int u, int v, int p, int ch) {
-  const int a = u % PAIR_TILE, b = v % PAIR_TILE;
-  const int L = a + 16 * p + 32 * (b % 2), r = b / 2;
   return (int64_t)pair_tile_pos(pair_tiles(n), u / PAIR_TILE, v / PAIR_TILE) * (2 * PAIR_TILE * PAIR_TILE) +
-         (r / ch) * 64 * ch + L * ch + r % ch;
+         tile_value_offset(u % PAIR_TILE, v % PAIR_TILE, p, ch);
 }
 // Reciprocal plans: one block per frequency pair {k, -k}; pairs = int [Ps][2]
 // (k, -k), w / winv the per-unknown weights and their inverses in the compute
