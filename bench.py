@@ -222,7 +222,8 @@ def multi_rhs_section(E, W, torch, np):
 def structured_section(E, W, torch, np, steps):
     """128 x 128 lattice, n_eq 192, 4 RHS with the outer operator in the
     paper's structured form [[a L, b K], [c K, e L]]: the plan stores the
-    Fourier transforms of L and K only (Sec. IV-C), half the dense bytes."""
+    Fourier transforms of L and K only (Sec. IV-C), half the dense bytes; the
+    reciprocal form stores one [L | K] record per frequency pair, a quarter."""
     cfg = W.config(4)
     g = W.box_geometry(cfg.n_patch)
     S, tm = W.s_types(cfg), W.type_map(cfg)
@@ -230,65 +231,83 @@ def structured_section(E, W, torch, np, steps):
     nrhs, n = cfg.nrhs, cfg.n_eq
     nh = n // 2
     geom = E.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)
-    t0 = time.perf_counter()
-    plan = E.emsurf_plan_create_green(cfg.nx, cfg.ny, cfg.n_types, nrhs, geom, S, tm, form=E.EMSURF_T_LK,
-                                      coef=W.OUTER_COEF)
-    torch.cuda.synchronize()
-    plan_s = time.perf_counter() - t0
-    st = plan.stats()
-    P = st.n_freq
     b64 = torch.from_numpy(b).to("cuda")
     x32 = b64.to(torch.complex64)
-    y32 = torch.empty_like(x32)
-    for _ in range(3):
-        E.emsurf_apply_T(plan, E.EMSURF_FP32, nrhs, x32, y32)
-    torch.cuda.synchronize()
-    E.emsurf_kernel_timing(plan, True)
-    E.emsurf_kernel_times(plan)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        E.emsurf_apply_T(plan, E.EMSURF_FP32, nrhs, x32, y32)
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0) / steps
-    phases = E.emsurf_kernel_times(plan)
-    E.emsurf_kernel_timing(plan, False)
-    bp_ms = phases["block_product"][0] / max(1, phases["block_product"][1])
-    bp_bytes = P * 2 * nh * nh * 8 + 2 * P * nrhs * n * 8
-    y64 = torch.empty_like(b64)
-    for _ in range(2):
-        E.emsurf_apply_T(plan, E.EMSURF_FP64, nrhs, b64, y64)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(3):
-        E.emsurf_apply_T(plan, E.EMSURF_FP64, nrhs, b64, y64)
-    torch.cuda.synchronize()
-    ms64 = 1e3 * (time.perf_counter() - t0) / 3
-    solve = {}
-    x = torch.zeros_like(b64)
-    for name, prec in (("fp32_ir", E.EMSURF_FP32_IR), ("fp64", E.EMSURF_FP64)):
-        x.zero_()
-        E.emsurf_solve(plan, E.solve_opts(prec, tol=cfg.tol), nrhs, b64, x)
-        x.zero_()
+
+    def run(recip):
+        t0 = time.perf_counter()
+        plan = E.emsurf_plan_create_green(cfg.nx, cfg.ny, cfg.n_types, nrhs, geom, S, tm, form=E.EMSURF_T_LK,
+                                          coef=W.OUTER_COEF, recip=recip)
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t0
+        st = plan.stats()
+        P, Ps = st.n_freq, st.n_stored
+        y32 = torch.empty_like(x32)
+        for _ in range(3):
+            E.emsurf_apply_T(plan, E.EMSURF_FP32, nrhs, x32, y32)
+        torch.cuda.synchronize()
+        E.emsurf_kernel_timing(plan, True)
+        E.emsurf_kernel_times(plan)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        stt, info = E.emsurf_solve(plan, E.solve_opts(prec, tol=cfg.tol), nrhs, b64, x)
+        for _ in range(steps):
+            E.emsurf_apply_T(plan, E.EMSURF_FP32, nrhs, x32, y32)
         torch.cuda.synchronize()
-        solve[name] = {"ms": round(1e3 * (time.perf_counter() - t0), 3), "status": E.emsurf_status_str(stt),
-                       "iters": [i["iters"] for i in info],
-                       "rel_res_true": [float(f"{i['rel_res_true']:.3e}") for i in info]}
-    sec = {"workload": "128x128 lattice, n_eq 192, 4 RHS, outer operator [[aL, bK], [cK, eL]] (point-sampled "
-                       "dyadic-Green L, curl K; a, b, c, e = -jk, 1, -1, jk), FP32 Fourier-domain L and K",
-           "plan_create_s": round(plan_s, 3), "store_fp32_GB": round(st.bytes_that32 / 1e9, 3),
-           "apply_T_ms": round(ms, 4), "unknowns_rhs_per_s": cfg.n_unknowns * nrhs / (ms / 1e3),
-           "phase_avg_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in phases.items()},
-           "block_product": {"kernel": "block_lk_kernel<float2,4,8>", "bytes_per_launch": bp_bytes,
-                             "avg_launch_ms": round(bp_ms, 4),
-                             "achieved_GBs": round(bp_bytes / (bp_ms / 1e3) / 1e9, 1),
-                             "frac_hbm_peak": round(bp_bytes / (bp_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
-           "apply_T_fp64_ms": round(ms64, 4), "solve": solve}
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        phases = E.emsurf_kernel_times(plan)
+        E.emsurf_kernel_timing(plan, False)
+        bp_ms = phases["block_product"][0] / max(1, phases["block_product"][1])
+        bp_bytes = (Ps * nh * n if recip else P * 2 * nh * nh) * 8 + 2 * P * nrhs * n * 8
+        y64 = torch.empty_like(b64)
+        for _ in range(2):
+            E.emsurf_apply_T(plan, E.EMSURF_FP64, nrhs, b64, y64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            E.emsurf_apply_T(plan, E.EMSURF_FP64, nrhs, b64, y64)
+        torch.cuda.synchronize()
+        ms64 = 1e3 * (time.perf_counter() - t0) / 3
+        solve = {}
+        x = torch.zeros_like(b64)
+        for name, prec in (("fp32_ir", E.EMSURF_FP32_IR), ("fp64", E.EMSURF_FP64)):
+            x.zero_()
+            E.emsurf_solve(plan, E.solve_opts(prec, tol=cfg.tol), nrhs, b64, x)
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            stt, info = E.emsurf_solve(plan, E.solve_opts(prec, tol=cfg.tol), nrhs, b64, x)
+            torch.cuda.synchronize()
+            solve[name] = {"ms": round(1e3 * (time.perf_counter() - t0), 3), "status": E.emsurf_status_str(stt),
+                           "iters": [i["iters"] for i in info],
+                           "rel_res_true": [float(f"{i['rel_res_true']:.3e}") for i in info]}
+        kern = "pair_lk_kernel<float, 6>" if recip else "block_lk_kernel<float2,4,8>"
+        sec = {"plan_create_s": round(plan_s, 3), "store_fp32_GB": round(st.bytes_that32 / 1e9, 3),
+               "stored_records": Ps,
+               "apply_T_ms": round(ms, 4), "unknowns_rhs_per_s": cfg.n_unknowns * nrhs / (ms / 1e3),
+               "phase_avg_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in phases.items()},
+               "block_product": {"kernel": kern, "bytes_per_launch": bp_bytes,
+                                 "avg_launch_ms": round(bp_ms, 4),
+                                 "achieved_GBs": round(bp_bytes / (bp_ms / 1e3) / 1e9, 1),
+                                 "frac_hbm_peak": round(bp_bytes / (bp_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+               "apply_T_fp64_ms": round(ms64, 4), "solve": solve}
+        out = (y32.cpu().numpy().astype(np.complex128), y64.cpu().numpy())
+        plan.destroy()
+        torch.cuda.empty_cache()
+        return sec, out
+
+    sec, (f32, f64) = run(0)
+    sec["workload"] = ("128x128 lattice, n_eq 192, 4 RHS, outer operator [[aL, bK], [cK, eL]] (point-sampled "
+                       "dyadic-Green L, curl K; a, b, c, e = -jk, 1, -1, jk), FP32 Fourier-domain L and K")
+    rsec, (r32, r64) = run(1)
+    rsec["workload"] = "same operator, reciprocal store: one [L | K] record per frequency pair {k, -k}"
+
+    def rdiff(a, ref):
+        return float(np.max(np.linalg.norm((a - ref).reshape(nrhs, -1), axis=1) /
+                            np.linalg.norm(ref.reshape(nrhs, -1), axis=1)))
+
+    rsec["rel_diff_vs_full_store"] = {"fp32": rdiff(r32, f32), "fp64": rdiff(r64, f64)}
+    sec["reciprocal"] = rsec
     log(f"structured L/K 128x128: {sec}")
-    plan.destroy()
     return sec
 
 

@@ -103,7 +103,7 @@ typedef struct {
   int32_t form;        /* EMSURF_T_DENSE (0) or EMSURF_T_LK (1) */
   int32_t recip;       /* 1: reciprocal operator, store one Fourier-domain block per
                           frequency pair {k, -k} (see emsurf_plan_create_reciprocal);
-                          EMSURF_T_DENSE only; 0: store every frequency */
+                          EMSURF_T_LK with n_eq <= 416; 0: store every frequency */
   double coef[8];      /* EMSURF_T_LK: a, b, c, e as (re, im) pairs, finite; ignored for dense */
 } emsurf_plan_desc;
 
@@ -169,7 +169,7 @@ emsurf_status emsurf_plan_create(const emsurf_plan_desc* desc, const void* T_blo
                                  const void* S_types, const int32_t* elem_type, void* stream,
                                  emsurf_plan* out);
 
-/* Reciprocal plans (desc->recip = 1, EMSURF_T_DENSE).  Reciprocity of the
+/* Reciprocal plans (desc->recip = 1).  Reciprocity of the
  * Green's function (Sec. II: a source and a test point may trade places) makes
  * the blocks of Sec. IV-A satisfy T(-d) = W^-1 T(d)^T W for a diagonal W of
  * per-unknown weights (the source patch areas of the point-sampled fill); the
@@ -179,6 +179,11 @@ emsurf_status emsurf_plan_create(const emsurf_plan_desc* desc, const void* T_blo
  * frequencies.  Results equal those of a full plan up to rounding.
  *   weights  host double [n_eq], finite and non-zero; NULL means all ones
  *            (T(-d) = T(d)^T).
+ * EMSURF_T_LK: L and K are reciprocal one by one, X(-d) = D^-1 X(d)^T D for
+ * X = L, K with the n_eq / 2 weights D (`weights` then holds n_eq / 2 values);
+ * a plan stores [L | K] of one frequency per pair and forms
+ * yJ[-k] = D^-1 (a L^T D xJ + b K^T D xM), yM[-k] = D^-1 (c K^T D xJ + e L^T D xM)
+ * from it (a quarter of the dense bytes).  The check covers both L and K.
  * The blocks are checked before the transform: the call fails with
  * EMSURF_ERR_ARG if max |T(-d) - W^-1 T(d)^T W| exceeds 1e-9 max |T(d)|, or if
  * desc->recip != 1.  Other arguments as for emsurf_plan_create (which itself

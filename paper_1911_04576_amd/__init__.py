@@ -284,9 +284,12 @@ def emsurf_plan_create(nx, ny, n_eq, n_types, max_rhs, T_blocks, S_types, elem_t
 
 
 def emsurf_plan_create_reciprocal(nx, ny, n_eq, n_types, max_rhs, T_blocks, weights, S_types, elem_type,
-                                  store=EMSURF_STORE_FP64 | EMSURF_STORE_FP32, stream=None, recip=1) -> Plan:
-    """Dense blocks with T(-d) = W^-1 T(d)^T W; weights: n_eq reals or None (all ones)."""
-    d = _desc(nx, ny, n_eq, n_types, max_rhs, store, EMSURF_T_DENSE, None, recip)
+                                  store=EMSURF_STORE_FP64 | EMSURF_STORE_FP32, stream=None, recip=1,
+                                  form=EMSURF_T_DENSE, coef=None) -> Plan:
+    """Dense blocks with T(-d) = W^-1 T(d)^T W (weights: n_eq reals), or with
+    form=EMSURF_T_LK structured blocks [..][2][n_eq/2][n_eq/2] whose L and K are
+    each reciprocal under n_eq/2 weights; None means all ones."""
+    d = _desc(nx, ny, n_eq, n_types, max_rhs, store, form, coef, recip)
     tb, ptb, is_dev = _blocks_arg(T_blocks)
     if weights is None:
         wt, pw = None, None

@@ -205,10 +205,10 @@ __global__ void lk_blocks_kernel(const double* __restrict__ rho, const double* _
 }
 
 __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, long long nn, long long c0,
-                                   long long nc, const int* __restrict__ slot_of, int n, double2* __restrict__ t64,
-                                   float2* __restrict__ t32, __bf16* __restrict__ t16) {
+                                   long long nc, const int* __restrict__ slot_of, int n, int nh,
+                                   double2* __restrict__ t64, float2* __restrict__ t32, __bf16* __restrict__ t16) {
   const long long total = P * nc;
-  const long long blk = pair_block_entries(n);
+  const long long blk = nh > 0 ? lkpair_block_entries(nh) : pair_block_entries(n);
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
     const long long kf = i / nc, j = i - kf * nc;
@@ -237,39 +237,52 @@ __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, 
     const long long slot = slot_of[kf];
     if (slot < 0) continue;
     const long long col = c0 + j;
-    const int cv = (int)(col / n), u = (int)(col - (long long)cv * n);
+    int u, cv, half = 0;
+    if (nh > 0) {
+      // structured record: column v (2 n_h) + half n_h + u
+      cv = (int)(col / (2 * nh));
+      const int rem = (int)(col - (long long)cv * 2 * nh);
+      half = rem / nh;
+      u = rem - half * nh;
+    } else {
+      cv = (int)(col / n);
+      u = (int)(col - (long long)cv * n);
+    }
     if (t64) {
       double* d = reinterpret_cast<double*>(t64) + slot * blk * 2;
-      d[pair_value_offset(n, u, cv, 0, 2)] = v.x;
-      d[pair_value_offset(n, u, cv, 1, 2)] = v.y;
+      d[nh > 0 ? lkpair_value_offset(nh, u, cv, half, 0, 2) : pair_value_offset(n, u, cv, 0, 2)] = v.x;
+      d[nh > 0 ? lkpair_value_offset(nh, u, cv, half, 1, 2) : pair_value_offset(n, u, cv, 1, 2)] = v.y;
     }
     if (t32) {
       float* f = reinterpret_cast<float*>(t32) + slot * blk * 2;
-      f[pair_value_offset(n, u, cv, 0, 4)] = (float)v.x;
-      f[pair_value_offset(n, u, cv, 1, 4)] = (float)v.y;
+      f[nh > 0 ? lkpair_value_offset(nh, u, cv, half, 0, 4) : pair_value_offset(n, u, cv, 0, 4)] = (float)v.x;
+      f[nh > 0 ? lkpair_value_offset(nh, u, cv, half, 1, 4) : pair_value_offset(n, u, cv, 1, 4)] = (float)v.y;
     }
   }
 }
 
-// Reciprocity check of dense caller blocks: out[0] = max |T(-d)[u][v] -
-// T(d)[v][u] w[v] / w[u]|, out[1] = max |T(d)[u][v]| (non-negative doubles
-// combined as their bit patterns, which order like the values).
+// Reciprocity check of caller blocks (parts n x n matrices per offset):
+// out[0] = max |X(-d)[u][v] - X(d)[v][u] w[v] / w[u]| over every part X,
+// out[1] = max |X(d)[u][v]| (non-negative doubles combined as their bit
+// patterns, which order like the values).
 __global__ void __launch_bounds__(256) recip_check_kernel(const double2* __restrict__ T, int nx, int ny, int n,
-                                                          const double* __restrict__ w,
+                                                          int parts, const double* __restrict__ w,
                                                           unsigned long long* __restrict__ out) {
   const long long nn = (long long)n * n;
   const int wx = 2 * nx - 1, wy = 2 * ny - 1;
-  const long long total = (long long)wx * wy * nn;
+  const long long total = (long long)wx * wy * parts * nn;
   double dmax = 0.0, mmax = 0.0;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
-    const long long blk = e / nn;
-    const int r = (int)(e - blk * nn);
+    const long long bp = e / nn;   // block * parts + part
+    const int r = (int)(e - bp * nn);
     const int u = r / n, v = r - u * n;
+    const long long blk = bp / parts;
+    const int part = (int)(bp - blk * parts);
     const int dyi = (int)(blk / wx), dxi = (int)(blk - (long long)dyi * wx);
     const long long mirror = (long long)(wy - 1 - dyi) * wx + (wx - 1 - dxi);
     const double2 a = T[e];
-    const double2 b = T[mirror * nn + (long long)v * n + u];
+    const double2 b = T[(mirror * parts + part) * nn + (long long)v * n + u];
     const double f = w[v] / w[u];
     const double dx = a.x - b.x * f, dy = a.y - b.y * f;
     const double d = sqrt(dx * dx + dy * dy), m = sqrt(a.x * a.x + a.y * a.y);
@@ -357,23 +370,23 @@ void launch_green_blocks(const GreenGeomDev& g, int nx, int ny, void* T_blocks, 
 }
 
 void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, const int* slot_of, int n,
-                        void* that64, void* that32, void* that16, hipStream_t s) {
+                        int nh, void* that64, void* that32, void* that16, hipStream_t s) {
   EMS_CHECK_ARG(!(that16 && slot_of), "internal: the split-BF16 store has no reciprocal layout");
   hipLaunchKernelGGL(store_chunk_kernel, dim3(grid_for((long long)P * nc, 256)), dim3(256), 0, s,
                      static_cast<const double2*>(Kc), (long long)P, (long long)nn, (long long)c0, (long long)nc,
-                     slot_of, n, static_cast<double2*>(that64), static_cast<float2*>(that32),
+                     slot_of, n, nh, static_cast<double2*>(that64), static_cast<float2*>(that32),
                      static_cast<__bf16*>(that16));
   EMS_LAUNCH_CHECK();
 }
 
-void launch_recip_check(const void* T_blocks_dev, int nx, int ny, int n, const double* w_dev, double* out,
+void launch_recip_check(const void* T_blocks_dev, int nx, int ny, int n, int parts, const double* w_dev, double* out,
                         hipStream_t s) {
   EMS_HIP(hipMemsetAsync(out, 0, 2 * sizeof(double), s));
-  const long long total = (long long)(2 * nx - 1) * (2 * ny - 1) * n * n;
+  const long long total = (long long)(2 * nx - 1) * (2 * ny - 1) * parts * n * n;
   long long g = (total + 255) / 256;
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(recip_check_kernel, dim3((unsigned)g), dim3(256), 0, s, static_cast<const double2*>(T_blocks_dev),
-                     nx, ny, n, w_dev, reinterpret_cast<unsigned long long*>(out));
+                     nx, ny, n, parts, w_dev, reinterpret_cast<unsigned long long*>(out));
   EMS_LAUNCH_CHECK();
 }
 

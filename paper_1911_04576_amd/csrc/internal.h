@@ -199,6 +199,36 @@ __host__ __device__ inline int64_t pair_value_offset(int n, int u, int v, int p,
   return (int64_t)pair_tile_pos(pair_tiles(n), u / PAIR_TILE, v / PAIR_TILE) * (2 * PAIR_TILE * PAIR_TILE) +
          tile_value_offset(u % PAIR_TILE, v % PAIR_TILE, p, ch);
 }
+// Reciprocal structured plans (EMSURF_T_LK): per stored pair the n_h x 2 n_h
+// matrix [L | K] in 16 x 16 tiles, ntr = ceil(n_h / 16) row tiles and 2 ntr
+// column tiles (L in column tiles q < ntr, K in q >= ntr, each half padded to
+// whole tiles), in the order the four wavefronts visit them: column tile q
+// with wavefront q % 4, its row tiles inner, so tile (t, q) sits at
+// base(q % 4) + (q / 4) ntr + t with base(w) = ntr sum_{w' < w} nqw(w'),
+// nqw(w) = (2 ntr - w + 3) / 4 column tiles of wavefront w.
+__host__ __device__ inline int64_t lkpair_block_entries(int nh) {
+  return (int64_t)pair_tiles(nh) * 2 * pair_tiles(nh) * PAIR_TILE * PAIR_TILE;
+}
+__host__ __device__ inline int lkpair_tile_pos(int ntr, int t, int q) {
+  const int w = q % 4, ntc = 2 * ntr;
+  int base = 0;
+  for (int x = 0; x < w; ++x) base += (ntc - x + 3) / 4 * ntr;
+  return base + (q / 4) * ntr + t;
+}
+// real-value offset of part p of entry (u, v) of L (half 0) or K (half 1)
+__host__ __device__ inline int64_t lkpair_value_offset(int nh, int u, int v, int half, int p, int ch) {
+  const int ntr = pair_tiles(nh);
+  const int q = half * ntr + v / PAIR_TILE;
+  return (int64_t)lkpair_tile_pos(ntr, u / PAIR_TILE, q) * (2 * PAIR_TILE * PAIR_TILE) +
+         tile_value_offset(u % PAIR_TILE, v % PAIR_TILE, p, ch);
+}
+// Paired products of a reciprocal structured plan: with L(-d) = D^-1 L(d)^T D
+// and K(-d) = D^-1 K(d)^T D (D = w, n_h weights),
+//   yh[k]  = [[a L, b K], [c K, e L]] xh[k],
+//   yh[-k] = [[a D^-1 L^T D, b D^-1 K^T D], [c D^-1 K^T D, e D^-1 L^T D]] xh[-k].
+void launch_block_product_pair_lk(Cx t, const void* That, const void* pairs, const void* w, const void* winv,
+                                  const void* xh, void* yh, int nh, int nrhs, int64_t Ps, const double* coef,
+                                  hipStream_t s);
 // Reciprocal plans: one block per frequency pair {k, -k}; pairs = int [Ps][2]
 // (k, -k), w / winv the per-unknown weights and their inverses in the compute
 // precision.  yh[k] = That[s] xh[k], yh[-k] = W^-1 That[s]^T W xh[-k].
@@ -271,11 +301,14 @@ void launch_green_blocks(const GreenGeomDev& g, int nx, int ny, void* T_blocks, 
 // reciprocal store, else to [k][v][u].
 // that16 (or NULL): the split-BF16 store of a full dense plan (slot_of NULL),
 // split from the FP32-rounded entry.
+// nh > 0: the columns are those of a structured record (v (2 n_h) + half n_h
+// + u) and a reciprocal store takes the [L | K] pair layout.
 void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, const int* slot_of, int n,
-                        void* that64, void* that32, void* that16, hipStream_t s);
+                        int nh, void* that64, void* that32, void* that16, hipStream_t s);
 // max |T(-d)[u][v] - T(d)[v][u] w[v] / w[u]| and max |T(d)| over dense caller
 // blocks [2ny-1][2nx-1][n][n] (device), written to out (device double [2]).
-void launch_recip_check(const void* T_blocks_dev, int nx, int ny, int n, const double* w_dev, double* out,
+// parts = 2 for structured blocks [..][2][n][n] (L and K, each checked with w).
+void launch_recip_check(const void* T_blocks_dev, int nx, int ny, int n, int parts, const double* w_dev, double* out,
                         hipStream_t s);
 
 // ----------------------------------------------------------------------------- vector ops (GMRES)

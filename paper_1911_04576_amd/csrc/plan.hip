@@ -30,12 +30,18 @@ void validate_desc(const emsurf_plan_desc* d) {
     for (double c : d->coef) EMS_CHECK_ARG(std::isfinite(c), "EMSURF_T_LK coefficients must be finite");
   }
   EMS_CHECK_ARG(d->recip == 0 || d->recip == 1, "recip must be 0 or 1");
-  EMS_CHECK_ARG(d->recip == 0 || d->form == EMSURF_T_DENSE, "reciprocal storage is supported for EMSURF_T_DENSE only");
+  EMS_CHECK_ARG(d->recip == 0 || d->form == EMSURF_T_DENSE || d->n_eq <= 416,
+                "reciprocal storage of the structured form supports n_eq <= 416");
   if (d->store & EMSURF_STORE_BF16) {
     EMS_CHECK_ARG(d->form == EMSURF_T_DENSE && d->recip == 0,
                   "the split-BF16 store needs a dense plan that stores every frequency (recip 0)");
     EMS_CHECK_ARG(block_bf16_supported(d->n_eq), "the split-BF16 store needs n_eq a multiple of 32 in [32, 480]");
   }
+}
+
+// complex entries of one stored block of a reciprocal plan (tile padding included)
+int64_t recip_block_entries(const emsurf_plan_desc& d) {
+  return d.form == EMSURF_T_LK ? lkpair_block_entries(d.n_eq / 2) : pair_block_entries(d.n_eq);
 }
 
 // stored blocks: every frequency, or one per pair {k, -k} (a length L has one
@@ -63,8 +69,8 @@ Sizes sizes_of(const emsurf_plan_desc* d) {
   z.n = d->n_eq;
   z.nn = z.n * z.n;
   const int64_t kc = kernel_cols(*d);
-  const int64_t kc64 = d->recip ? pair_block_entries(d->n_eq) : kc;
-  const int64_t kc32 = d->recip ? pair_block_entries(d->n_eq) : kc;
+  const int64_t kc64 = d->recip ? recip_block_entries(*d) : kc;
+  const int64_t kc32 = kc64;
   z.that64 = (d->store & EMSURF_STORE_FP64) ? (size_t)(z.Ps * kc64) * 16 : 0;
   z.that32 = (d->store & EMSURF_STORE_FP32) ? (size_t)(z.Ps * kc32) * 8 : 0;
   z.that16 = (d->store & EMSURF_STORE_BF16) ? (size_t)(z.P * z.nn) * 8 : 0;
@@ -182,6 +188,10 @@ void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* 
                                                        : BP_GEMV;
   if (split)
     launch_block_bf16(split, That, w.X.p, w.Y.p, n, nrhs, p->P, s);
+  else if (p->d.recip && p->d.form == EMSURF_T_LK)
+    launch_block_product_pair_lk(tc, That, p->pairs.p, tc == Cx::C128 ? p->w64.p : p->w32.p,
+                                 tc == Cx::C128 ? p->winv64.p : p->winv32.p, w.X.p, w.Y.p, n / 2, nrhs, p->Ps,
+                                 p->d.coef, s);
   else if (p->d.recip)
     launch_block_product_pair(tc, That, p->pairs.p, tc == Cx::C128 ? p->w64.p : p->w32.p,
                               tc == Cx::C128 ? p->winv64.p : p->winv32.p, w.X.p, w.Y.p, n, nrhs, p->Ps, s);
@@ -305,8 +315,8 @@ void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill) {
   const int64_t nn = kernel_cols(p->d);
   const int64_t P = p->P;
   const int n = p->d.n_eq;
-  const int64_t kc64 = p->d.recip ? pair_block_entries(n) : nn;
-  const int64_t kc32 = p->d.recip ? pair_block_entries(n) : nn;
+  const int64_t kc64 = p->d.recip ? recip_block_entries(p->d) : nn;
+  const int64_t kc32 = kc64;
   if (p->d.store & EMSURF_STORE_FP64) p->that64.alloc((size_t)(p->Ps * kc64) * 16);
   if (p->d.store & EMSURF_STORE_FP32) p->that32.alloc((size_t)(p->Ps * kc32) * 8);
   if (p->d.store & EMSURF_STORE_BF16) p->that16.alloc((size_t)(P * nn) * 8);
@@ -348,8 +358,8 @@ void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill) {
     fy.out_s0 = cnt; fy.out_pt = (int64_t)p->Lx * cnt;
     fy.sign = -1;
     launch_fft_pass(fy, Cx::C128, Cx::C128, Cx::C128, tmp.p, K.p, twy, s);
-    launch_store_chunk(K.p, P, nn, c0, cnt, slot_dev.as<const int>(), n, p->that64.p, p->that32.p, p->that16.p,
-                       s);
+    launch_store_chunk(K.p, P, nn, c0, cnt, slot_dev.as<const int>(), n, p->d.form == EMSURF_T_LK ? n / 2 : 0,
+                       p->that64.p, p->that32.p, p->that16.p, s);
   }
   EMS_HIP(hipStreamSynchronize(s));
 }
@@ -466,11 +476,15 @@ emsurf_status create_from_blocks(const emsurf_plan_desc* desc, const void* T_blo
       Tb = Tdev.p;
     }
     if (desc->recip) {
+      // n weights for dense blocks; n / 2 for the structured form (the weights
+      // of L and K, stored twice so that both halves have theirs)
       std::vector<double> w(n, 1.0);
-      if (weights) w.assign(weights, weights + n);
+      if (weights) {
+        for (int u = 0; u < n; ++u) w[u] = weights[u % nb];
+      }
       set_weights(p, w, s);
       DevBuf res(2 * sizeof(double));
-      launch_recip_check(Tb, nx, ny, n, p->w64.as<const double>(), res.as<double>(), s);
+      launch_recip_check(Tb, nx, ny, nb, parts, p->w64.as<const double>(), res.as<double>(), s);
       double h[2];
       EMS_HIP(hipMemcpyAsync(h, res.p, sizeof(h), hipMemcpyDeviceToHost, s));
       EMS_HIP(hipStreamSynchronize(s));

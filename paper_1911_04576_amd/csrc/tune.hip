@@ -119,7 +119,10 @@ extern "C" emsurf_status emsurf_plan_autotune(emsurf_plan plan, int32_t nrhs, do
     // reciprocal plans have one kernel, the paired product, timed as variant 0
     const bool recip = plan->d.recip != 0;
     auto run = [&](int v) {
-      if (recip)
+      if (recip && structured)
+        launch_block_product_pair_lk(Cx::C64, plan->that32.p, plan->pairs.p, plan->w32.p, plan->winv32.p, w.X.p,
+                                     w.Y.p, n / 2, nrhs, plan->Ps, plan->d.coef, s);
+      else if (recip)
         launch_block_product_pair(Cx::C64, plan->that32.p, plan->pairs.p, plan->w32.p, plan->winv32.p, w.X.p, w.Y.p,
                                   n, nrhs, plan->Ps, s);
       else if (structured)

@@ -76,9 +76,15 @@ def test_reciprocal_plan_bytes_and_desc_checks():
     half = E.emsurf_plan_bytes(128, 128, 192, 16, 4, store=E.EMSURF_STORE_FP32, recip=1)
     store = 256 * 256 * 192 * 192 * 8
     assert abs((full - half) - (store // 2 - 2 * 192 * 192 * 8 - (256 * 256 // 2 + 2) * 8 - 192 * 24)) <= 0
-    # reciprocal storage is for dense blocks only; recip must be 0 or 1
-    assert E.emsurf_plan_bytes(8, 8, 96, 4, 1, form=E.EMSURF_T_LK, recip=1) == 0
+    # recip must be 0 or 1
     assert E.emsurf_plan_bytes(8, 8, 96, 4, 1, recip=2) == 0
+    # structured form: one [L | K] record (96 x 192) per pair instead of L and K per frequency
+    lk_full = E.emsurf_plan_bytes(128, 128, 192, 16, 4, store=E.EMSURF_STORE_FP32, form=E.EMSURF_T_LK)
+    lk_half = E.emsurf_plan_bytes(128, 128, 192, 16, 4, store=E.EMSURF_STORE_FP32, form=E.EMSURF_T_LK, recip=1)
+    lk_store = 256 * 256 * 2 * 96 * 96 * 8
+    assert lk_full - lk_half == lk_store - 32770 * 96 * 192 * 8 - 32770 * 8 - 192 * 24
+    assert E.emsurf_plan_bytes(8, 8, 416, 4, 1, form=E.EMSURF_T_LK, recip=1) > 0
+    assert E.emsurf_plan_bytes(8, 8, 418, 4, 1, form=E.EMSURF_T_LK, recip=1) == 0
 
 
 def test_split_bf16_store_bytes_and_desc_checks():

@@ -199,13 +199,9 @@ def test_recip_argument_errors():
     with pytest.raises(e.EmsurfError) as ex:
         e.emsurf_plan_create_reciprocal(nx, ny, n, 1, 1, Br, w0, S, tm)
     assert ex.value.status == e.EMSURF_ERR_ARG
-    # the entry point needs desc.recip = 1; LK plans have no reciprocal storage
+    # the entry point needs desc.recip = 1
     with pytest.raises(e.EmsurfError) as ex:
         e.emsurf_plan_create_reciprocal(nx, ny, n, 1, 1, Br, w, S, tm, recip=0)
-    assert ex.value.status == e.EMSURF_ERR_ARG
-    L = np.zeros((2 * ny - 1, 2 * nx - 1, 2, n // 2, n // 2), np.complex128)
-    with pytest.raises(e.EmsurfError) as ex:
-        e.emsurf_plan_create(nx, ny, n, 1, 1, L, S, tm, form=e.EMSURF_T_LK, coef=W.OUTER_COEF, recip=1)
     assert ex.value.status == e.EMSURF_ERR_ARG
     # a reciprocal plan has only the paired kernel: MFMA variants are refused and
     # the autotuner times variant 0 alone

@@ -274,6 +274,14 @@ def random_reciprocal_blocks(nx: int, ny: int, n_eq: int, w: np.ndarray, seed: i
     return t
 
 
+def random_reciprocal_lk_blocks(nx: int, ny: int, n_h: int, w: np.ndarray, seed: int) -> np.ndarray:
+    """Random structured blocks [2ny-1][2nx-1][2][n_h][n_h] (L then K), each
+    reciprocal under the n_h weights w: X(-d) = W^-1 X(d)^T W, X(0) = 0."""
+    L = random_reciprocal_blocks(nx, ny, n_h, w, seed)
+    K = random_reciprocal_blocks(nx, ny, n_h, w, seed + 1000)
+    return np.stack([L, K], axis=2)
+
+
 def random_vectors(nrhs: int, nx: int, ny: int, n_eq: int, seed: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_ROOT, 78, seed])))
     shape = (nrhs, ny, nx, n_eq)
