@@ -343,13 +343,14 @@ def macromodel_section(E, W, torch, np):
     return out
 
 
-def serving_section(E, W, np, n_requests, budget_gb, n_surfaces=12, load=0.7, structured=False):
+def serving_section(E, W, np, n_requests, budget_gb, n_surfaces=12, load=0.7, structured=False, recip=1):
     """Poisson stream of solve requests over a catalogue of surfaces (lattices
     8..96, n_eq 96/192/288, 1..32 RHS each), FP32 inner / FP64 refinement to
     1e-6.  A closed-loop pass (every request queued at once) measures capacity;
     the open-loop pass then offers `load` x that rate and reports latency.
     `structured`: every surface uses the structured outer operator (plans hold
-    L and K only)."""
+    L and K only).  `recip`: plans keep one Fourier-domain block (or [L | K]
+    record) per frequency pair; the point-sampled fill is reciprocal."""
     form = E.EMSURF_T_LK if structured else E.EMSURF_T_DENSE
     coef = W.OUTER_COEF if structured else None
     tol = 1e-6
@@ -401,7 +402,7 @@ def serving_section(E, W, np, n_requests, budget_gb, n_surfaces=12, load=0.7, st
                 pending.pop(0)
                 sf = cat[r.surface]
                 geom, S, tm, g = inputs[r.surface]
-                rid = E.emsurf_server_submit(srv, sf.key, sf.n, sf.n, sf.n_types, geom, S, tm, b, form, coef)
+                rid = E.emsurf_server_submit(srv, sf.key, sf.n, sf.n, sf.n_types, geom, S, tm, b, form, coef, recip)
                 arrive[rid] = (0.0 if closed else r.arrival_s, r.nrhs * sf.n * sf.n * sf.n_eq)
                 nxt += 1
             st = E.emsurf_server_query(srv)
@@ -434,7 +435,8 @@ def serving_section(E, W, np, n_requests, budget_gb, n_surfaces=12, load=0.7, st
         f"{unk_c / wall_c:.3e} unknowns*RHS/s), stats {st_c}")
     lat, wall, unk, bad, st = run(rate, closed=False)
     sec = {"workload": f"{n_surfaces} surfaces (n x n lattices, n in 8..96; n_eq 96/192/288; 16 types each"
-                       f"{'; structured outer operator, L and K stored' if structured else ''}), "
+                       f"{'; structured outer operator, L and K stored' if structured else ''}"
+                       f"{'; reciprocal stores (one block per frequency pair)' if recip else ''}), "
                        f"{n_requests} requests of 1..32 RHS, Poisson arrivals at {rate:.2f} req/s "
                        f"(= {load} x closed-loop capacity {cap_rps:.2f} req/s), FP32 inner + FP64 refinement "
                        f"to {tol}, HBM budget {budget_gb} GB, 32 slots per surface",
