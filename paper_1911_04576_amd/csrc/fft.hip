@@ -18,6 +18,7 @@
 
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 
 namespace emsurf {
 namespace {
@@ -111,10 +112,12 @@ struct PassArgs {
 // per column, BT columns per workgroup of NT threads).  Power-of-two lengths
 // run radix-16 stages while possible, then one radix-2/4/8 stage; lengths with
 // a factor 3 run radix-8 stages, one radix-2/4 stage if needed, then radix 3.
-template <int L> struct Shape {
+// WD = 2 doubles the threads and so the columns per workgroup (256-byte runs
+// per point in FP32; 64 KB of LDS at L = 256).
+template <int L, int WD = 1> struct Shape {
   static constexpr bool R3 = L % 3 == 0;
   static constexpr int VPT = R3 ? 24 : (L >= 16 ? 16 : L);
-  static constexpr int NT = R3 ? 128 : 256;
+  static constexpr int NT = (R3 ? 128 : 256) * WD;
   static constexpr int G = L / VPT;
   static constexpr int BT = NT / G;
   static constexpr int nst() {
@@ -144,11 +147,11 @@ template <int L> struct Shape {
   static constexpr int NST = nst();
 };
 
-template <int L, int S, int P, typename VI, typename VC, typename VO>
+template <int L, int WD, int S, int P, typename VI, typename VC, typename VO>
 __device__ __forceinline__ void run_stage(const PassArgs& a, VC* lds, const VI* __restrict__ in,
                                           VO* __restrict__ out, const VC* __restrict__ tw, bool valid, int b,
                                           int g) {
-  using SH = Shape<L>;
+  using SH = Shape<L, WD>;
   constexpr int R = SH::radix(S);
   constexpr int NB = SH::VPT / R;
   constexpr int LR = L / R;
@@ -222,13 +225,13 @@ __device__ __forceinline__ void run_stage(const PassArgs& a, VC* lds, const VI* 
       }
     }
   }
-  if constexpr (!LAST) run_stage<L, S + 1, P * R, VI, VC, VO>(a, lds, in, out, tw, valid, b, g);
+  if constexpr (!LAST) run_stage<L, WD, S + 1, P * R, VI, VC, VO>(a, lds, in, out, tw, valid, b, g);
 }
 
-template <int L, typename VI, typename VC, typename VO>
-__global__ void __launch_bounds__(Shape<L>::NT) fft_pass_kernel(PassArgs a, const VI* __restrict__ in, VO* __restrict__ out,
-                                                       const VC* __restrict__ tw) {
-  using SH = Shape<L>;
+template <int L, int WD, typename VI, typename VC, typename VO>
+__global__ void __launch_bounds__((Shape<L, WD>::NT))
+    fft_pass_kernel(PassArgs a, const VI* __restrict__ in, VO* __restrict__ out, const VC* __restrict__ tw) {
+  using SH = Shape<L, WD>;
   __shared__ VC lds[SH::NST > 1 ? L * SH::BT : 1];
   const int t = threadIdx.x;
   const int b = t % SH::BT;
@@ -240,24 +243,34 @@ __global__ void __launch_bounds__(Shape<L>::NT) fft_pass_kernel(PassArgs a, cons
   // uniform line bases, per-thread 32-bit offsets
   const VI* inl = in + (l1 * a.in_s1 + l0 * a.in_s0 + (long long)blockIdx.x * SH::BT) + b;
   VO* outl = out + (l1 * a.out_s1 + l0 * a.out_s0 + (long long)blockIdx.x * SH::BT) + b;
-  run_stage<L, 0, 1, VI, VC, VO>(a, lds, inl, outl, tw, valid, b, g);
+  run_stage<L, WD, 0, 1, VI, VC, VO>(a, lds, inl, outl, tw, valid, b, g);
 }
 
-template <int L, typename VI, typename VC, typename VO>
-void launch_L(const PassArgs& a, unsigned tiles, unsigned lines, const void* in, void* out, const void* tw,
-              hipStream_t s) {
-  hipLaunchKernelGGL((fft_pass_kernel<L, VI, VC, VO>), dim3(tiles, lines), dim3(Shape<L>::NT), 0, s, a,
+template <int L, int WD, typename VI, typename VC, typename VO>
+void launch_L(const PassArgs& a, int batch, unsigned lines, const void* in, void* out, const void* tw, hipStream_t s) {
+  const unsigned tiles = (unsigned)((batch + Shape<L, WD>::BT - 1) / Shape<L, WD>::BT);
+  hipLaunchKernelGGL((fft_pass_kernel<L, WD, VI, VC, VO>), dim3(tiles, lines), dim3(Shape<L, WD>::NT), 0, s, a,
                      static_cast<const VI*>(in), static_cast<VO*>(out), static_cast<const VC*>(tw));
 }
 
 template <typename VI, typename VC, typename VO>
 void launch_typed(int L, const PassArgs& a, int batch, unsigned lines, const void* in, void* out, const void* tw,
                   hipStream_t s) {
-#define EMS_FFT_CASE(LL)                                                                  \
-  case LL: {                                                                              \
-    const unsigned tiles = (unsigned)((batch + Shape<LL>::BT - 1) / Shape<LL>::BT);      \
-    launch_L<LL, VI, VC, VO>(a, tiles, lines, in, out, tw, s);                             \
-    break;                                                                                \
+  // FP32 arithmetic at power-of-two lengths 64..256 with at least 64 columns
+  // takes the doubled workgroup (measured 5-7% faster at L = 256 with 192 and
+  // 768 columns); FP64 keeps 256 threads, whose LDS would double to 128 KB
+  constexpr bool f32 = std::is_same<VC, float2>::value;
+  const bool wide = f32 && (L == 64 || L == 128 || L == 256) && batch >= 64;
+#define EMS_FFT_CASE(LL)                                                           \
+  case LL: {                                                                       \
+    if constexpr (f32 && (LL == 64 || LL == 128 || LL == 256)) {                   \
+      if (wide) {                                                                  \
+        launch_L<LL, 2, VI, VC, VO>(a, batch, lines, in, out, tw, s);              \
+        break;                                                                     \
+      }                                                                            \
+    }                                                                              \
+    launch_L<LL, 1, VI, VC, VO>(a, batch, lines, in, out, tw, s);                  \
+    break;                                                                         \
   }
   switch (L) {
     EMS_FFT_CASE(2)

@@ -88,7 +88,13 @@ def test_apply_T_nonzero_self_block():
     assert rel_per_rhs(y.cpu().numpy(), yr).max() <= FP64_TOL
 
 
-@pytest.mark.parametrize("nx,ny,n,nrhs", [(9, 6, 24, 3), (65, 17, 8, 2)])
+@pytest.mark.parametrize("nx,ny,n,nrhs", [
+    (9, 6, 24, 3), (65, 17, 8, 2),
+    # FP32 passes of 64, 128 and 256 points over >= 64 columns run 512-thread
+    # workgroups: y passes at L = 64 (72 columns) and L = 256 (80, ragged),
+    # x passes at L = 128 (70, ragged) and L = 256 (64)
+    (32, 28, 24, 3), (50, 3, 70, 1), (100, 1, 64, 1), (2, 100, 40, 2),
+])
 def test_apply_T_fp32_error_reported(nx, ny, n, nrhs):
     e = E()
     plan, B, S, tm = random_plan(nx, ny, n, nrhs, seed=3)
