@@ -311,6 +311,14 @@ def structured_section(E, W, torch, np, steps):
     return sec
 
 
+def device_record(torch, dev):
+    """hipDeviceProp facts of the measured device."""
+    p = torch.cuda.get_device_properties(dev)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
+            "memory_GB": round(p.total_memory / 1e9, 1), "l2_MB": round(getattr(p, "L2_cache_size", 0) / 2**20, 1),
+            "hbm_peak_GBs_datasheet": HBM_PEAK_GBS}
+
+
 def macromodel_section(E, W, torch, np):
     """Macromodel generation (Schur complement of every cell type's interior,
     then S = -(Z~ + Z_self)^-1) at the 64x64 and 128x128 workloads' cell
@@ -458,7 +466,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES solve timing")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--copy-cal", action="store_true", help="also time a plain 2 GiB device copy")
+    ap.add_argument("--copy-cal", action="store_true",
+                    help="time the 2 GiB device copy and 8 GiB read references (the default; kept for old commands)")
+    ap.add_argument("--no-copy-cal", action="store_true", help="skip the copy and read references")
     ap.add_argument("--no-multi", action="store_true", help="skip the 64x64, 16-RHS MFMA section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--no-macromodels", action="store_true", help="skip the macromodel-generation timing")
@@ -619,7 +629,7 @@ def main():
 
     # plain device copy of a known size (bandwidth reference and counter calibration)
     copy = None
-    if args.copy_cal:
+    if not args.no_copy_cal:
         nbytes = 1 << 31
         a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
         c = torch.empty_like(a)
@@ -727,7 +737,10 @@ def main():
                      "bound": "hbm",
                      "achieved": round(bp_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(bp_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(bool(recip)),
-                     "bytes_per_launch": bp_bytes, "avg_launch_ms": round(bp_avg, 4)},
+                     "bytes_per_launch": bp_bytes, "avg_launch_ms": round(bp_avg, 4),
+                     # the same rate against what this device measured for a plain read and a copy
+                     "frac_of_measured_read": round(bp_gbs / copy["read_GBs"], 4) if copy else None,
+                     "frac_of_measured_copy": round(bp_gbs / copy["GBs"], 4) if copy else None},
         "full_store_apply": full,
         "apply_T": {"algorithmic_bytes": apply_bytes,
                     "effective_GBs": round(apply_bytes / (ms_step / 1e3) / 1e9, 1),
@@ -735,6 +748,7 @@ def main():
                     "phase_avg_ms": phase_avg, "fp64_ms": round(ms64, 4)},
         "plan_create_s": round(plan_s, 3),
         "copy_reference": copy,
+        "device": device_record(torch, dev),
         "multi_rhs_64x64": multi,
         "structured_lk_128x128": structured,
         "macromodel_generation": macromodels,
