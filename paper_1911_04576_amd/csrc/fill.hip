@@ -28,7 +28,7 @@ __device__ __forceinline__ int slot_to_offset(int s, int L, int N, bool* ok) {
 // columns are those of the stacked (parts * nb) x nb matrix, column-major:
 // c = v * (parts * nb) + part * nb + u.
 __global__ void pad_blocks_kernel(const double2* __restrict__ Tb, int nx, int ny, int nb, int parts, int Lx, int Ly,
-                                  long long c0, long long nc, double2* __restrict__ K) {
+                                  long long c0, long long nc, int vperm, double2* __restrict__ K) {
   const long long total = (long long)Ly * Lx * nc;
   const long long nbb = (long long)nb * nb;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
@@ -43,9 +43,10 @@ __global__ void pad_blocks_kernel(const double2* __restrict__ Tb, int nx, int ny
     if (okx && oky) {
       const long long c = c0 + j;
       const int rows = parts * nb;
-      const int v = (int)(c / rows);
-      const int w = (int)(c - (long long)v * rows);
+      const int vp = (int)(c / rows);
+      const int w = (int)(c - (long long)vp * rows);
       const int part = w / nb, u = w - part * nb;
+      const int v = vperm ? pair_fill_v(vp, nb) : vp;
       const long long blk = (long long)(dy + ny - 1) * (2 * nx - 1) + (dx + nx - 1);
       val = Tb[(blk * parts + part) * nbb + (long long)u * nb + v];
     }
@@ -122,7 +123,8 @@ __device__ __forceinline__ double2 lk_entry(const double* __restrict__ rho, cons
 
 __global__ void green_padded_kernel(const double* __restrict__ rho, const double* __restrict__ area,
                                     const double* __restrict__ tan, int P, double pitch, double k, int nx, int ny,
-                                    int Lx, int Ly, long long c0, long long nc, double2* __restrict__ K) {
+                                    int Lx, int Ly, long long c0, long long nc, int vperm,
+                                    double2* __restrict__ K) {
   const int n = 4 * P;
   const long long total = (long long)Ly * Lx * nc;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
@@ -136,7 +138,8 @@ __global__ void green_padded_kernel(const double* __restrict__ rho, const double
     double2 val{0.0, 0.0};
     if (okx && oky) {
       const long long c = c0 + j;
-      const int v = (int)(c / n), u = (int)(c - (long long)v * n);
+      const int vp = (int)(c / n), u = (int)(c - (long long)vp * n);
+      const int v = vperm ? pair_fill_v(vp, n) : vp;
       val = green_entry(rho, area, tan, P, pitch, k, dx, dy, u, v);
     }
     K[i] = val;
@@ -205,7 +208,7 @@ __global__ void lk_blocks_kernel(const double* __restrict__ rho, const double* _
 }
 
 __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, long long nn, long long c0,
-                                   long long nc, const int* __restrict__ slot_of, int n, int nh,
+                                   long long nc, const int* __restrict__ slot_of, int n, int nh, int vperm,
                                    double2* __restrict__ t64, float2* __restrict__ t32, __bf16* __restrict__ t16) {
   const long long total = P * nc;
   const long long blk = nh > 0 ? lkpair_block_entries(nh) : pair_block_entries(n);
@@ -247,6 +250,7 @@ __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, 
     } else {
       cv = (int)(col / n);
       u = (int)(col - (long long)cv * n);
+      if (vperm) cv = pair_fill_v(cv, n);
     }
     if (t64) {
       double* d = reinterpret_cast<double*>(t64) + slot * blk * 2;
@@ -325,20 +329,21 @@ unsigned grid_for(long long total, int threads) {
 }  // namespace
 
 void launch_pad_blocks(const void* T_blocks_dev, int nx, int ny, int nb, int parts, int Lx, int Ly, int64_t c0,
-                       int64_t nc, void* K, hipStream_t s) {
+                       int64_t nc, int vperm, void* K, hipStream_t s) {
+  EMS_CHECK_ARG(!vperm || parts == 1, "internal: the pair column order is for dense blocks");
   const long long total = (long long)Ly * Lx * nc;
   hipLaunchKernelGGL(pad_blocks_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s,
                      static_cast<const double2*>(T_blocks_dev), nx, ny, nb, parts, Lx, Ly, (long long)c0,
-                     (long long)nc, static_cast<double2*>(K));
+                     (long long)nc, vperm, static_cast<double2*>(K));
   EMS_LAUNCH_CHECK();
 }
 
-void launch_green_padded(const GreenGeomDev& g, int nx, int ny, int Lx, int Ly, int64_t c0, int64_t nc, void* K,
-                         hipStream_t s) {
+void launch_green_padded(const GreenGeomDev& g, int nx, int ny, int Lx, int Ly, int64_t c0, int64_t nc, int vperm,
+                         void* K, hipStream_t s) {
   const long long total = (long long)Ly * Lx * nc;
   hipLaunchKernelGGL(green_padded_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, g.rho.as<const double>(),
                      g.area.as<const double>(), g.tan.as<const double>(), g.n_patch, g.pitch, g.k, nx, ny, Lx, Ly,
-                     (long long)c0, (long long)nc, static_cast<double2*>(K));
+                     (long long)c0, (long long)nc, vperm, static_cast<double2*>(K));
   EMS_LAUNCH_CHECK();
 }
 
@@ -370,11 +375,12 @@ void launch_green_blocks(const GreenGeomDev& g, int nx, int ny, void* T_blocks, 
 }
 
 void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, const int* slot_of, int n,
-                        int nh, void* that64, void* that32, void* that16, hipStream_t s) {
+                        int nh, int vperm, void* that64, void* that32, void* that16, hipStream_t s) {
   EMS_CHECK_ARG(!(that16 && slot_of), "internal: the split-BF16 store has no reciprocal layout");
+  EMS_CHECK_ARG(!vperm || (slot_of && nh == 0), "internal: the pair column order is for dense reciprocal stores");
   hipLaunchKernelGGL(store_chunk_kernel, dim3(grid_for((long long)P * nc, 256)), dim3(256), 0, s,
                      static_cast<const double2*>(Kc), (long long)P, (long long)nn, (long long)c0, (long long)nc,
-                     slot_of, n, nh, static_cast<double2*>(that64), static_cast<float2*>(that32),
+                     slot_of, n, nh, vperm, static_cast<double2*>(that64), static_cast<float2*>(that32),
                      static_cast<__bf16*>(that16));
   EMS_LAUNCH_CHECK();
 }

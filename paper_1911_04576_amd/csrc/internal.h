@@ -285,14 +285,15 @@ struct GreenGeomDev {
 // validate a box geometry (finite pitch > 0, areas > 0) and copy it to the device
 void upload_geom(const emsurf_geom* g, GreenGeomDev& d);
 // caller blocks: `parts` row-major nb x nb matrices per offset (1 x n_eq dense; 2 x n_h for L, K)
+// vperm: columns in the pair_fill_v order (dense blocks only)
 void launch_pad_blocks(const void* T_blocks_dev, int nx, int ny, int nb, int parts, int Lx, int Ly, int64_t c0,
-                       int64_t nc, void* K, hipStream_t s);
+                       int64_t nc, int vperm, void* K, hipStream_t s);
 // structured (L, K) fill into the padded layout / into [2ny-1][2nx-1][2][n_h][n_h]
 void launch_lk_padded(const GreenGeomDev& g, int nx, int ny, int Lx, int Ly, int64_t c0, int64_t nc, void* K,
                       hipStream_t s);
 void launch_lk_blocks(const GreenGeomDev& g, int nx, int ny, void* LK_blocks, hipStream_t s);
-void launch_green_padded(const GreenGeomDev& g, int nx, int ny, int Lx, int Ly, int64_t c0, int64_t nc, void* K,
-                         hipStream_t s);
+void launch_green_padded(const GreenGeomDev& g, int nx, int ny, int Lx, int Ly, int64_t c0, int64_t nc, int vperm,
+                         void* K, hipStream_t s);
 void launch_green_blocks(const GreenGeomDev& g, int nx, int ny, void* T_blocks, hipStream_t s);
 // Scatter a [P][nc] chunk into the [P][n*n] store at column offset c0 (FP64 and/or FP32 rounded).
 // slot_of (device int [P], or NULL for the identity) maps a frequency to its
@@ -304,7 +305,7 @@ void launch_green_blocks(const GreenGeomDev& g, int nx, int ny, void* T_blocks, 
 // nh > 0: the columns are those of a structured record (v (2 n_h) + half n_h
 // + u) and a reciprocal store takes the [L | K] pair layout.
 void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, const int* slot_of, int n,
-                        int nh, void* that64, void* that32, void* that16, hipStream_t s);
+                        int nh, int vperm, void* that64, void* that32, void* that16, hipStream_t s);
 // max |T(-d)[u][v] - T(d)[v][u] w[v] / w[u]| and max |T(d)| over dense caller
 // blocks [2ny-1][2nx-1][n][n] (device), written to out (device double [2]).
 // parts = 2 for structured blocks [..][2][n][n] (L and K, each checked with w).
@@ -383,6 +384,18 @@ ApplyPrec apply_prec(emsurf_prec prec);
 inline size_t cx_bytes(Cx t) { return t == Cx::C128 ? 16 : 8; }
 // kernel columns (complex entries) of one frequency's Fourier-domain record:
 // n_eq^2 for dense blocks, 2 (n_eq/2)^2 for the L and K operators
+// Column order of the chunked kernel fill of a dense reciprocal plan: column
+// c holds entry (u, v) with u = c % n_eq and v = pair_fill_v(c / n_eq); in each
+// group of 8 consecutive v the even ones come first.  Then v, v + 2, v + 4,
+// v + 6 (the values of one 16-byte chunk of the paired tile layout, in FP32;
+// v, v + 2 in FP64) are 4 consecutive column groups, and a chunk of whole
+// multiples of 4 n_eq columns writes whole 16-byte pieces of the store.
+__host__ __device__ inline int pair_fill_v(int vp, int n) {
+  const int g = vp & ~7, w = vp & 7;
+  const int m = n - g < 8 ? n - g : 8;   // members of this group
+  const int e = (m + 1) >> 1;            // of which even
+  return g + (w < e ? 2 * w : 2 * (w - e) + 1);
+}
 inline int64_t kernel_cols(const emsurf_plan_desc& d) {
   const int64_t n = d.n_eq;
   return d.form == EMSURF_T_LK ? 2 * (n / 2) * (n / 2) : n * n;

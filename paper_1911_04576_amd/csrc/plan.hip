@@ -334,8 +334,14 @@ void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill) {
     EMS_HIP(hipMemcpyAsync(p->pairs.p, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, s));
     EMS_HIP(hipMemcpyAsync(slot_dev.p, slot_of.data(), slot_of.size() * sizeof(int), hipMemcpyHostToDevice, s));
   }
-  // two chunk buffers of at most ~512 MB each
+  // two chunk buffers of at most ~512 MB each.  A dense reciprocal store fills
+  // its columns in the pair_fill_v order, in chunks of whole multiples of
+  // 4 n_eq columns (buffers of up to 1 GiB), so that each chunk writes whole
+  // 16-byte pieces of the paired tiles instead of scattered values
   int64_t nc = (int64_t)((512ull << 20) / ((size_t)P * 16));
+  const int64_t grp = 4 * (int64_t)n;
+  const int vperm = p->d.recip && p->d.form != EMSURF_T_LK && (size_t)P * grp * 16 <= (1ull << 30) ? 1 : 0;
+  if (vperm) nc = std::max<int64_t>(1, nc / grp) * grp;
   nc = std::max<int64_t>(1, std::min<int64_t>(nc, nn));
   nc = std::min<int64_t>(nc, 0x7fffffff);
   DevBuf K((size_t)(P * nc) * 16), tmp((size_t)(P * nc) * 16);
@@ -343,7 +349,7 @@ void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill) {
   const void* twy = twiddle_table(p->Ly, Cx::C128);
   for (int64_t c0 = 0; c0 < nn; c0 += nc) {
     const int64_t cnt = std::min(nc, nn - c0);
-    fill(c0, cnt, K.p);
+    fill(c0, cnt, K.p, vperm);
     FftPass fx;
     fx.L = p->Lx; fx.n_in = p->Lx; fx.n_out = p->Lx; fx.batch = (int)cnt;
     fx.n_lines = p->Ly; fx.nl0 = p->Ly;
@@ -358,7 +364,7 @@ void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill) {
     fy.out_s0 = cnt; fy.out_pt = (int64_t)p->Lx * cnt;
     fy.sign = -1;
     launch_fft_pass(fy, Cx::C128, Cx::C128, Cx::C128, tmp.p, K.p, twy, s);
-    launch_store_chunk(K.p, P, nn, c0, cnt, slot_dev.as<const int>(), n, p->d.form == EMSURF_T_LK ? n / 2 : 0,
+    launch_store_chunk(K.p, P, nn, c0, cnt, slot_dev.as<const int>(), n, p->d.form == EMSURF_T_LK ? n / 2 : 0, vperm,
                        p->that64.p, p->that32.p, p->that16.p, s);
   }
   EMS_HIP(hipStreamSynchronize(s));
@@ -494,8 +500,8 @@ emsurf_status create_from_blocks(const emsurf_plan_desc* desc, const void* T_blo
         throw Err{EMSURF_ERR_ARG};
       }
     }
-    build_that(p, s, [&](int64_t c0, int64_t cnt, void* K) {
-      launch_pad_blocks(Tb, nx, ny, nb, parts, p->Lx, p->Ly, c0, cnt, K, s);
+    build_that(p, s, [&](int64_t c0, int64_t cnt, void* K, int vperm) {
+      launch_pad_blocks(Tb, nx, ny, nb, parts, p->Lx, p->Ly, c0, cnt, vperm, K, s);
     });
     upload_S(p, S_types, s);
     build_tiles(p, elem_type, s);
@@ -562,11 +568,11 @@ emsurf_status emsurf_plan_create_green(const emsurf_plan_desc* desc, const emsur
       for (int u = 0; u < desc->n_eq; ++u) w[u] = geom->area[(u % P2) / 2];
       set_weights(p, w, s);
     }
-    build_that(p, s, [&](int64_t c0, int64_t cnt, void* K) {
+    build_that(p, s, [&](int64_t c0, int64_t cnt, void* K, int vperm) {
       if (desc->form == EMSURF_T_LK)
         launch_lk_padded(g, desc->nx, desc->ny, p->Lx, p->Ly, c0, cnt, K, s);
       else
-        launch_green_padded(g, desc->nx, desc->ny, p->Lx, p->Ly, c0, cnt, K, s);
+        launch_green_padded(g, desc->nx, desc->ny, p->Lx, p->Ly, c0, cnt, vperm, K, s);
     });
     upload_S(p, S_types, s);
     build_tiles(p, elem_type, s);
