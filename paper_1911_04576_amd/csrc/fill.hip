@@ -265,6 +265,70 @@ __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, 
   }
 }
 
+// Dense reciprocal store of one chunk filled in the pair_fill_v order (c0 and
+// the chunk width are multiples of 4 n_eq columns, or the chunk ends the
+// block).  Work item (frequency, quad of 4 column positions, u): the 4
+// positions of a quad of a full group of 8 are v, v + 2, v + 4, v + 6, whose
+// values of one part are one 16-byte piece of an FP32 tile (two of an FP64
+// tile), written whole; consecutive u write consecutive pieces.  Quads at a
+// ragged edge write their values one by one.
+__global__ void store_pair_chunk_kernel(const double2* __restrict__ Kc, int P, int c0, int nc, int nq,
+                                        const int* __restrict__ slot_of, int n, double* __restrict__ t64,
+                                        float* __restrict__ t32) {
+  const int total = P * nq * n;   // host: fits 31 bits
+  const long long blk2 = 2LL * pair_block_entries(n);   // reals per stored block
+  const int pos0 = c0 / n, pend = (c0 + nc) / n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int u = i % n, rest = i / n;
+    const int qd = rest % nq, kf = rest / nq;
+    const int slot = slot_of[kf];
+    if (slot < 0) continue;
+    const int vp0 = pos0 + 4 * qd;
+    const int cnt = pend - vp0 < 4 ? pend - vp0 : 4;
+    int v[4];
+    double2 x[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      v[j] = j < cnt ? pair_fill_v(vp0 + j, n) : 0;
+      x[j] = j < cnt ? Kc[(long long)kf * nc + (long long)(vp0 + j - pos0) * n + u] : double2{0.0, 0.0};
+    }
+    const bool whole = cnt == 4 && (v[0] & 6) == 0 && v[1] == v[0] + 2 && v[2] == v[0] + 4 && v[3] == v[0] + 6;
+    if (t64) {
+      double* d = t64 + slot * blk2;
+      if (whole) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const double2 a = p == 0 ? double2{x[0].x, x[1].x} : double2{x[0].y, x[1].y};
+          const double2 b = p == 0 ? double2{x[2].x, x[3].x} : double2{x[2].y, x[3].y};
+          *reinterpret_cast<double2*>(d + pair_value_offset(n, u, v[0], p, 2)) = a;
+          *reinterpret_cast<double2*>(d + pair_value_offset(n, u, v[2], p, 2)) = b;
+        }
+      } else {
+        for (int j = 0; j < cnt; ++j) {
+          d[pair_value_offset(n, u, v[j], 0, 2)] = x[j].x;
+          d[pair_value_offset(n, u, v[j], 1, 2)] = x[j].y;
+        }
+      }
+    }
+    if (t32) {
+      float* f = t32 + slot * blk2;
+      if (whole) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const float4 a = p == 0 ? float4{(float)x[0].x, (float)x[1].x, (float)x[2].x, (float)x[3].x}
+                                  : float4{(float)x[0].y, (float)x[1].y, (float)x[2].y, (float)x[3].y};
+          *reinterpret_cast<float4*>(f + pair_value_offset(n, u, v[0], p, 4)) = a;
+        }
+      } else {
+        for (int j = 0; j < cnt; ++j) {
+          f[pair_value_offset(n, u, v[j], 0, 4)] = (float)x[j].x;
+          f[pair_value_offset(n, u, v[j], 1, 4)] = (float)x[j].y;
+        }
+      }
+    }
+  }
+}
+
 // Reciprocity check of caller blocks (parts n x n matrices per offset):
 // out[0] = max |X(-d)[u][v] - X(d)[v][u] w[v] / w[u]| over every part X,
 // out[1] = max |X(d)[u][v]| (non-negative doubles combined as their bit
@@ -378,6 +442,18 @@ void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64
                         int nh, int vperm, void* that64, void* that32, void* that16, hipStream_t s) {
   EMS_CHECK_ARG(!(that16 && slot_of), "internal: the split-BF16 store has no reciprocal layout");
   EMS_CHECK_ARG(!vperm || (slot_of && nh == 0), "internal: the pair column order is for dense reciprocal stores");
+  if (vperm) {
+    EMS_CHECK_ARG(c0 % (4 * n) == 0 && nc % n == 0 && (nc % (4 * n) == 0 || c0 + nc == nn),
+                  "internal: pair-order chunks must be whole multiples of 4 n_eq columns");
+    const int64_t nq = (nc / n + 3) / 4;
+    const int64_t total = P * nq * n;
+    EMS_CHECK_ARG(total < (1LL << 31) && c0 + nc < (1LL << 31), "internal: pair-order chunk too large");
+    hipLaunchKernelGGL(store_pair_chunk_kernel, dim3(grid_for((long long)total, 256)), dim3(256), 0, s,
+                       static_cast<const double2*>(Kc), (int)P, (int)c0, (int)nc, (int)nq, slot_of, n,
+                       static_cast<double*>(that64), static_cast<float*>(that32));
+    EMS_LAUNCH_CHECK();
+    return;
+  }
   hipLaunchKernelGGL(store_chunk_kernel, dim3(grid_for((long long)P * nc, 256)), dim3(256), 0, s,
                      static_cast<const double2*>(Kc), (long long)P, (long long)nn, (long long)c0, (long long)nc,
                      slot_of, n, nh, vperm, static_cast<double2*>(that64), static_cast<float2*>(that32),
