@@ -31,20 +31,20 @@ __global__ void pad_blocks_kernel(const double2* __restrict__ Tb, int nx, int ny
                                   long long c0, long long nc, int vperm, double2* __restrict__ K) {
   const long long total = (long long)Ly * Lx * nc;
   const long long nbb = (long long)nb * nb;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
-    const long long j = i % nc;
-    const long long sxy = i / nc;
-    const int sx = (int)(sxy % Lx), sy = (int)(sxy / Lx);
+  // 32-bit index arithmetic: a chunk holds fewer than 2^31 entries (host check)
+  const int ncc = (int)nc;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < (int)total; i += gridDim.x * blockDim.x) {
+    const int sxy = i / ncc, j = i - sxy * ncc;
+    const int sy = sxy / Lx, sx = sxy - sy * Lx;
     bool okx, oky;
     const int dx = slot_to_offset(sx, Lx, nx, &okx);
     const int dy = slot_to_offset(sy, Ly, ny, &oky);
     double2 val{0.0, 0.0};
     if (okx && oky) {
-      const long long c = c0 + j;
+      const int c = (int)c0 + j;
       const int rows = parts * nb;
-      const int vp = (int)(c / rows);
-      const int w = (int)(c - (long long)vp * rows);
+      const int vp = c / rows;
+      const int w = c - vp * rows;
       const int part = w / nb, u = w - part * nb;
       const int v = vperm ? pair_fill_v(vp, nb) : vp;
       const long long blk = (long long)(dy + ny - 1) * (2 * nx - 1) + (dx + nx - 1);
@@ -127,18 +127,18 @@ __global__ void green_padded_kernel(const double* __restrict__ rho, const double
                                     double2* __restrict__ K) {
   const int n = 4 * P;
   const long long total = (long long)Ly * Lx * nc;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
-    const long long j = i % nc;
-    const long long sxy = i / nc;
-    const int sx = (int)(sxy % Lx), sy = (int)(sxy / Lx);
+  // 32-bit index arithmetic: a chunk holds fewer than 2^31 entries (host check)
+  const int ncc = (int)nc;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < (int)total; i += gridDim.x * blockDim.x) {
+    const int sxy = i / ncc, j = i - sxy * ncc;
+    const int sy = sxy / Lx, sx = sxy - sy * Lx;
     bool okx, oky;
     const int dx = slot_to_offset(sx, Lx, nx, &okx);
     const int dy = slot_to_offset(sy, Ly, ny, &oky);
     double2 val{0.0, 0.0};
     if (okx && oky) {
-      const long long c = c0 + j;
-      const int vp = (int)(c / n), u = (int)(c - (long long)vp * n);
+      const int c = (int)c0 + j;
+      const int vp = c / n, u = c - vp * n;
       const int v = vperm ? pair_fill_v(vp, n) : vp;
       val = green_entry(rho, area, tan, P, pitch, k, dx, dy, u, v);
     }
@@ -168,19 +168,19 @@ __global__ void lk_padded_kernel(const double* __restrict__ rho, const double* _
                                  int Lx, int Ly, long long c0, long long nc, double2* __restrict__ K) {
   const int nh = 2 * P;
   const long long total = (long long)Ly * Lx * nc;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
-    const long long j = i % nc;
-    const long long sxy = i / nc;
-    const int sx = (int)(sxy % Lx), sy = (int)(sxy / Lx);
+  // 32-bit index arithmetic: a chunk holds fewer than 2^31 entries (host check)
+  const int ncc = (int)nc;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < (int)total; i += gridDim.x * blockDim.x) {
+    const int sxy = i / ncc, j = i - sxy * ncc;
+    const int sy = sxy / Lx, sx = sxy - sy * Lx;
     bool okx, oky;
     const int dx = slot_to_offset(sx, Lx, nx, &okx);
     const int dy = slot_to_offset(sy, Ly, ny, &oky);
     double2 val{0.0, 0.0};
     if (okx && oky) {
-      const long long c = c0 + j;
-      const int v = (int)(c / (2 * nh));
-      const int w = (int)(c - (long long)v * 2 * nh);
+      const int c = (int)c0 + j;
+      const int v = c / (2 * nh);
+      const int w = c - v * 2 * nh;
       const int part = w / nh, u = w - part * nh;
       val = lk_entry(rho, area, tan, pitch, k, dx, dy, part, u, v);
     }
@@ -396,6 +396,7 @@ void launch_pad_blocks(const void* T_blocks_dev, int nx, int ny, int nb, int par
                        int64_t nc, int vperm, void* K, hipStream_t s) {
   EMS_CHECK_ARG(!vperm || parts == 1, "internal: the pair column order is for dense blocks");
   const long long total = (long long)Ly * Lx * nc;
+  EMS_CHECK_ARG(total < (1LL << 31) && c0 + nc < (1LL << 31), "internal: fill chunk exceeds 32-bit indices");
   hipLaunchKernelGGL(pad_blocks_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s,
                      static_cast<const double2*>(T_blocks_dev), nx, ny, nb, parts, Lx, Ly, (long long)c0,
                      (long long)nc, vperm, static_cast<double2*>(K));
@@ -405,6 +406,7 @@ void launch_pad_blocks(const void* T_blocks_dev, int nx, int ny, int nb, int par
 void launch_green_padded(const GreenGeomDev& g, int nx, int ny, int Lx, int Ly, int64_t c0, int64_t nc, int vperm,
                          void* K, hipStream_t s) {
   const long long total = (long long)Ly * Lx * nc;
+  EMS_CHECK_ARG(total < (1LL << 31) && c0 + nc < (1LL << 31), "internal: fill chunk exceeds 32-bit indices");
   hipLaunchKernelGGL(green_padded_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, g.rho.as<const double>(),
                      g.area.as<const double>(), g.tan.as<const double>(), g.n_patch, g.pitch, g.k, nx, ny, Lx, Ly,
                      (long long)c0, (long long)nc, vperm, static_cast<double2*>(K));
@@ -414,6 +416,7 @@ void launch_green_padded(const GreenGeomDev& g, int nx, int ny, int Lx, int Ly, 
 void launch_lk_padded(const GreenGeomDev& g, int nx, int ny, int Lx, int Ly, int64_t c0, int64_t nc, void* K,
                       hipStream_t s) {
   const long long total = (long long)Ly * Lx * nc;
+  EMS_CHECK_ARG(total < (1LL << 31) && c0 + nc < (1LL << 31), "internal: fill chunk exceeds 32-bit indices");
   hipLaunchKernelGGL(lk_padded_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, g.rho.as<const double>(),
                      g.area.as<const double>(), g.tan.as<const double>(), g.n_patch, g.pitch, g.k, nx, ny, Lx, Ly,
                      (long long)c0, (long long)nc, static_cast<double2*>(K));
