@@ -121,28 +121,65 @@ __device__ __forceinline__ double2 lk_entry(const double* __restrict__ rho, cons
   return double2{Aq * (isor * tt + radr * pr), Aq * (isoi * tt + radi * pr)};
 }
 
+// Green fill of one chunk of kernel columns [c0, c0 + nc).  Work item
+// (lattice slot, column, patch p): the entries of rows u = 2 p + a (J) and
+// 2 P + 2 p + a (M), a = 0, 1, share R and exp(-jkR) (only the half with the
+// column's own current type is nonzero), so a thread evaluates the Green's
+// function once and writes its 4 entries, two adjacent pairs, coalesced over
+// p.  The value of each entry is green_entry's.
 __global__ void green_padded_kernel(const double* __restrict__ rho, const double* __restrict__ area,
                                     const double* __restrict__ tan, int P, double pitch, double k, int nx, int ny,
                                     int Lx, int Ly, long long c0, long long nc, int vperm,
                                     double2* __restrict__ K) {
   const int n = 4 * P;
-  const long long total = (long long)Ly * Lx * nc;
-  // 32-bit index arithmetic: a chunk holds fewer than 2^31 entries (host check)
-  const int ncc = (int)nc;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < (int)total; i += gridDim.x * blockDim.x) {
-    const int sxy = i / ncc, j = i - sxy * ncc;
+  const int cb = (int)c0, ce = (int)(c0 + nc);   // host: fits 31 bits
+  const int vpa = cb / n, ncol = (ce - 1) / n - vpa + 1;
+  const int total = Lx * Ly * ncol * P;        // host: fits 31 bits
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int p = i % P, rest = i / P;
+    const int cl = rest % ncol, sxy = rest / ncol;
     const int sy = sxy / Lx, sx = sxy - sy * Lx;
+    const int vp = vpa + cl;
+    const int v = vperm ? pair_fill_v(vp, n) : vp;
     bool okx, oky;
     const int dx = slot_to_offset(sx, Lx, nx, &okx);
     const int dy = slot_to_offset(sy, Ly, ny, &oky);
-    double2 val{0.0, 0.0};
-    if (okx && oky) {
-      const int c = (int)c0 + j;
-      const int vp = c / n, u = c - vp * n;
-      const int v = vperm ? pair_fill_v(vp, n) : vp;
-      val = green_entry(rho, area, tan, P, pitch, k, dx, dy, u, v);
+    double2 e[2][2] = {{{0.0, 0.0}, {0.0, 0.0}}, {{0.0, 0.0}, {0.0, 0.0}}};   // [current type][a]
+    const int hv = v / (2 * P), lv = v - hv * 2 * P;
+    const int q = lv >> 1, b = lv & 1;
+    if (okx && oky && !(dx == 0 && dy == 0)) {
+      const double* tq = tan + (q * 2 + b) * 3;
+      double dots[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const double* tp = tan + (p * 2 + a) * 3;
+        dots[a] = tp[0] * tq[0] + tp[1] * tq[1] + tp[2] * tq[2];
+      }
+      if (dots[0] != 0.0 || dots[1] != 0.0) {
+        const double ex = rho[3 * p + 0] - rho[3 * q + 0] + pitch * dx;
+        const double ey = rho[3 * p + 1] - rho[3 * q + 1] + pitch * dy;
+        const double ez = rho[3 * p + 2] - rho[3 * q + 2];
+        const double R = sqrt(ex * ex + ey * ey + ez * ez);
+        double sn, cs;
+        sincos(k * R, &sn, &cs);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          if (dots[a] != 0.0) {
+            const double w = dots[a] * area[q] / (4.0 * 3.14159265358979323846 * R);
+            e[hv][a] = double2{w * cs, -w * sn};
+          }
+        }
+      }
     }
-    K[i] = val;
+    const long long kb = (long long)sxy * nc - c0;   // K index of column index c: kb + c
+    const int c_u0 = vp * n;                          // column index of (u = 0, this v)
+#pragma unroll
+    for (int hu = 0; hu < 2; ++hu)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int c = c_u0 + hu * 2 * P + 2 * p + a;
+        if (c >= cb && c < ce) K[kb + c] = e[hu][a];
+      }
   }
 }
 
@@ -405,8 +442,10 @@ void launch_pad_blocks(const void* T_blocks_dev, int nx, int ny, int nb, int par
 
 void launch_green_padded(const GreenGeomDev& g, int nx, int ny, int Lx, int Ly, int64_t c0, int64_t nc, int vperm,
                          void* K, hipStream_t s) {
-  const long long total = (long long)Ly * Lx * nc;
-  EMS_CHECK_ARG(total < (1LL << 31) && c0 + nc < (1LL << 31), "internal: fill chunk exceeds 32-bit indices");
+  const int64_t n = 4LL * g.n_patch;
+  const int64_t ncol = (c0 + nc - 1) / n - c0 / n + 1;
+  const long long total = (long long)Ly * Lx * ncol * g.n_patch;
+  EMS_CHECK_ARG(nc >= 1 && total < (1LL << 31) && c0 + nc < (1LL << 31), "internal: fill chunk exceeds 32-bit indices");
   hipLaunchKernelGGL(green_padded_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, g.rho.as<const double>(),
                      g.area.as<const double>(), g.tan.as<const double>(), g.n_patch, g.pitch, g.k, nx, ny, Lx, Ly,
                      (long long)c0, (long long)nc, vperm, static_cast<double2*>(K));
