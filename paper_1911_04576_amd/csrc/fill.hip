@@ -304,22 +304,22 @@ __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, 
 
 // Dense reciprocal store of one chunk filled in the pair_fill_v order (c0 and
 // the chunk width are multiples of 4 n_eq columns, or the chunk ends the
-// block).  Work item (frequency, quad of 4 column positions, u): the 4
+// block).  Work item (stored pair slot, quad of 4 column positions, u), the
+// slot's frequency from the pair list (k, -k): the 4
 // positions of a quad of a full group of 8 are v, v + 2, v + 4, v + 6, whose
 // values of one part are one 16-byte piece of an FP32 tile (two of an FP64
 // tile), written whole; consecutive u write consecutive pieces.  Quads at a
 // ragged edge write their values one by one.
-__global__ void store_pair_chunk_kernel(const double2* __restrict__ Kc, int P, int c0, int nc, int nq,
-                                        const int* __restrict__ slot_of, int n, double* __restrict__ t64,
+__global__ void store_pair_chunk_kernel(const double2* __restrict__ Kc, int Ps, int c0, int nc, int nq,
+                                        const int* __restrict__ pairs, int n, double* __restrict__ t64,
                                         float* __restrict__ t32) {
-  const int total = P * nq * n;   // host: fits 31 bits
+  const int total = Ps * nq * n;   // host: fits 31 bits
   const long long blk2 = 2LL * pair_block_entries(n);   // reals per stored block
   const int pos0 = c0 / n, pend = (c0 + nc) / n;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
     const int u = i % n, rest = i / n;
-    const int qd = rest % nq, kf = rest / nq;
-    const int slot = slot_of[kf];
-    if (slot < 0) continue;
+    const int qd = rest % nq, slot = rest / nq;
+    const int kf = pairs[2 * slot];
     const int vp0 = pos0 + 4 * qd;
     const int cnt = pend - vp0 < 4 ? pend - vp0 : 4;
     int v[4];
@@ -480,18 +480,20 @@ void launch_green_blocks(const GreenGeomDev& g, int nx, int ny, void* T_blocks, 
   EMS_LAUNCH_CHECK();
 }
 
-void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, const int* slot_of, int n,
-                        int nh, int vperm, void* that64, void* that32, void* that16, hipStream_t s) {
+void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, const int* slot_of,
+                        const int* pairs, int64_t Ps, int n, int nh, int vperm, void* that64, void* that32,
+                        void* that16, hipStream_t s) {
   EMS_CHECK_ARG(!(that16 && slot_of), "internal: the split-BF16 store has no reciprocal layout");
-  EMS_CHECK_ARG(!vperm || (slot_of && nh == 0), "internal: the pair column order is for dense reciprocal stores");
+  EMS_CHECK_ARG(!vperm || (slot_of && pairs && nh == 0), "internal: the pair column order is for dense reciprocal stores");
   if (vperm) {
     EMS_CHECK_ARG(c0 % (4 * n) == 0 && nc % n == 0 && (nc % (4 * n) == 0 || c0 + nc == nn),
                   "internal: pair-order chunks must be whole multiples of 4 n_eq columns");
     const int64_t nq = (nc / n + 3) / 4;
-    const int64_t total = P * nq * n;
-    EMS_CHECK_ARG(total < (1LL << 31) && c0 + nc < (1LL << 31), "internal: pair-order chunk too large");
+    const int64_t total = Ps * nq * n;
+    EMS_CHECK_ARG(Ps >= 1 && Ps <= P && total < (1LL << 31) && c0 + nc < (1LL << 31),
+                  "internal: pair-order chunk too large");
     hipLaunchKernelGGL(store_pair_chunk_kernel, dim3(grid_for((long long)total, 256)), dim3(256), 0, s,
-                       static_cast<const double2*>(Kc), (int)P, (int)c0, (int)nc, (int)nq, slot_of, n,
+                       static_cast<const double2*>(Kc), (int)Ps, (int)c0, (int)nc, (int)nq, pairs, n,
                        static_cast<double*>(that64), static_cast<float*>(that32));
     EMS_LAUNCH_CHECK();
     return;

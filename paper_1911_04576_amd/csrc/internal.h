@@ -304,8 +304,10 @@ void launch_green_blocks(const GreenGeomDev& g, int nx, int ny, void* T_blocks, 
 // split from the FP32-rounded entry.
 // nh > 0: the columns are those of a structured record (v (2 n_h) + half n_h
 // + u) and a reciprocal store takes the [L | K] pair layout.
-void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, const int* slot_of, int n,
-                        int nh, int vperm, void* that64, void* that32, void* that16, hipStream_t s);
+// pairs / Ps: the pair list (k, -k) per stored slot, used by the pair-order store
+void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, const int* slot_of,
+                        const int* pairs, int64_t Ps, int n, int nh, int vperm, void* that64, void* that32,
+                        void* that16, hipStream_t s);
 // max |T(-d)[u][v] - T(d)[v][u] w[v] / w[u]| and max |T(d)| over dense caller
 // blocks [2ny-1][2nx-1][n][n] (device), written to out (device double [2]).
 // parts = 2 for structured blocks [..][2][n][n] (L and K, each checked with w).

@@ -364,7 +364,8 @@ void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill) {
     fy.out_s0 = cnt; fy.out_pt = (int64_t)p->Lx * cnt;
     fy.sign = -1;
     launch_fft_pass(fy, Cx::C128, Cx::C128, Cx::C128, tmp.p, K.p, twy, s);
-    launch_store_chunk(K.p, P, nn, c0, cnt, slot_dev.as<const int>(), n, p->d.form == EMSURF_T_LK ? n / 2 : 0, vperm,
+    launch_store_chunk(K.p, P, nn, c0, cnt, slot_dev.as<const int>(), p->pairs.as<const int>(), p->Ps, n,
+                       p->d.form == EMSURF_T_LK ? n / 2 : 0, vperm,
                        p->that64.p, p->that32.p, p->that16.p, s);
   }
   EMS_HIP(hipStreamSynchronize(s));
