@@ -15,6 +15,7 @@
 // differ from the input and output types (FP64 <-> FP32 converting loads and
 // stores for the mixed-precision solve).
 #include "internal.h"
+#include "green.h"
 
 #include <cmath>
 #include <mutex>
@@ -99,6 +100,18 @@ __device__ __forceinline__ void dft(V (&a)[R], int sign) {
   }
 }
 
+// Inputs generated in the first stage instead of loaded: the point-sampled
+// coupling entries of kernel columns c0 + col (column c = vp n + u, v from vp
+// in the pair_fill_v order when vperm) at lattice slot (point, line) of the x
+// pass of the kernel transform.
+struct GreenGen {
+  const double* rho = nullptr;
+  const double* area = nullptr;
+  const double* tan = nullptr;
+  int P = 0, nx = 0, ny = 0, Ly = 0, c0 = 0, n = 0, vperm = 0;
+  double pitch = 0, k = 0;
+};
+
 struct PassArgs {
   int n_in, n_out, batch, nl0;
   long long in_s0, in_s1, out_s0, out_s1;
@@ -147,10 +160,10 @@ template <int L, int WD = 1> struct Shape {
   static constexpr int NST = nst();
 };
 
-template <int L, int WD, int S, int P, typename VI, typename VC, typename VO>
+template <int L, int WD, int GEN, int S, int P, typename VI, typename VC, typename VO>
 __device__ __forceinline__ void run_stage(const PassArgs& a, VC* lds, const VI* __restrict__ in,
                                           VO* __restrict__ out, const VC* __restrict__ tw, bool valid, int b,
-                                          int g) {
+                                          int g, const GreenGen& gg, int col, int line) {
   using SH = Shape<L, WD>;
   constexpr int R = SH::radix(S);
   constexpr int NB = SH::VPT / R;
@@ -161,7 +174,28 @@ __device__ __forceinline__ void run_stage(const PassArgs& a, VC* lds, const VI* 
   constexpr bool LAST = S == SH::NST - 1;
   VC v[NB][R];
   // ---- load
-  if constexpr (FIRST) {
+  if constexpr (FIRST && GEN) {
+    // this thread's kernel column (u, v) and the line's lattice offset dy
+    bool oky;
+    const int dy = slot_to_offset(line, gg.Ly, gg.ny, &oky);
+    const int c = gg.c0 + col;
+    const int vp = c / gg.n, u = c - vp * gg.n;
+    const int vv = gg.vperm ? pair_fill_v(vp, gg.n) : vp;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int i = g + G * j;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int pos = i + q * LR;
+        bool okx = false;
+        const int dx = slot_to_offset(pos, L, gg.nx, &okx);
+        if (valid && oky && okx && pos < a.n_in)
+          v[j][q] = cvt<VC>(green_entry(gg.rho, gg.area, gg.tan, gg.P, gg.pitch, gg.k, dx, dy, u, vv));
+        else
+          v[j][q] = VC{0, 0};
+      }
+    }
+  } else if constexpr (FIRST) {
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int i = g + G * j;
@@ -225,12 +259,13 @@ __device__ __forceinline__ void run_stage(const PassArgs& a, VC* lds, const VI* 
       }
     }
   }
-  if constexpr (!LAST) run_stage<L, WD, S + 1, P * R, VI, VC, VO>(a, lds, in, out, tw, valid, b, g);
+  if constexpr (!LAST) run_stage<L, WD, GEN, S + 1, P * R, VI, VC, VO>(a, lds, in, out, tw, valid, b, g, gg, col, line);
 }
 
-template <int L, int WD, typename VI, typename VC, typename VO>
+template <int L, int WD, int GEN, typename VI, typename VC, typename VO>
 __global__ void __launch_bounds__((Shape<L, WD>::NT))
-    fft_pass_kernel(PassArgs a, const VI* __restrict__ in, VO* __restrict__ out, const VC* __restrict__ tw) {
+    fft_pass_kernel(PassArgs a, const VI* __restrict__ in, VO* __restrict__ out, const VC* __restrict__ tw,
+                    GreenGen gg) {
   using SH = Shape<L, WD>;
   __shared__ VC lds[SH::NST > 1 ? L * SH::BT : 1];
   const int t = threadIdx.x;
@@ -243,14 +278,15 @@ __global__ void __launch_bounds__((Shape<L, WD>::NT))
   // uniform line bases, per-thread 32-bit offsets
   const VI* inl = in + (l1 * a.in_s1 + l0 * a.in_s0 + (long long)blockIdx.x * SH::BT) + b;
   VO* outl = out + (l1 * a.out_s1 + l0 * a.out_s0 + (long long)blockIdx.x * SH::BT) + b;
-  run_stage<L, WD, 0, 1, VI, VC, VO>(a, lds, inl, outl, tw, valid, b, g);
+  run_stage<L, WD, GEN, 0, 1, VI, VC, VO>(a, lds, inl, outl, tw, valid, b, g, gg, col, (int)l0);
 }
 
-template <int L, int WD, typename VI, typename VC, typename VO>
-void launch_L(const PassArgs& a, int batch, unsigned lines, const void* in, void* out, const void* tw, hipStream_t s) {
+template <int L, int WD, typename VI, typename VC, typename VO, int GEN = 0>
+void launch_L(const PassArgs& a, int batch, unsigned lines, const void* in, void* out, const void* tw, hipStream_t s,
+              const GreenGen& gg = GreenGen{}) {
   const unsigned tiles = (unsigned)((batch + Shape<L, WD>::BT - 1) / Shape<L, WD>::BT);
-  hipLaunchKernelGGL((fft_pass_kernel<L, WD, VI, VC, VO>), dim3(tiles, lines), dim3(Shape<L, WD>::NT), 0, s, a,
-                     static_cast<const VI*>(in), static_cast<VO*>(out), static_cast<const VC*>(tw));
+  hipLaunchKernelGGL((fft_pass_kernel<L, WD, GEN, VI, VC, VO>), dim3(tiles, lines), dim3(Shape<L, WD>::NT), 0, s, a,
+                     static_cast<const VI*>(in), static_cast<VO*>(out), static_cast<const VC*>(tw), gg);
 }
 
 template <typename VI, typename VC, typename VO>
@@ -344,13 +380,12 @@ int fft_length_at_least(int v) {
   return best;
 }
 
-void launch_fft_pass(const FftPass& p, Cx tin, Cx tcomp, Cx tout, const void* in, void* out,
-                     const void* twiddles, hipStream_t s) {
+namespace {
+PassArgs pass_args(const FftPass& p) {
   EMS_CHECK_ARG(fft_length_supported(p.L), "FFT length must be 2^a in [2, 1024] or 3 * 2^a in [24, 768]");
   EMS_CHECK_ARG(p.n_in >= 1 && p.n_in <= p.L && p.n_out >= 1 && p.n_out <= p.L, "FFT prune/crop sizes out of range");
   EMS_CHECK_ARG(p.batch >= 1 && p.n_lines >= 1 && p.nl0 >= 1, "FFT batch/lines must be positive");
   EMS_CHECK_ARG(p.n_lines <= 65535, "FFT pass has more than 65535 lines");
-  // per-thread offsets within a line are 32-bit: (points * stride + tile) must fit
   const long long span_in = (long long)p.L * p.in_pt + p.batch + 1024;
   const long long span_out = (long long)p.L * p.out_pt + p.batch + 1024;
   EMS_CHECK_ARG(span_in < (1LL << 31) && span_out < (1LL << 31), "FFT line span exceeds 32-bit offsets");
@@ -363,6 +398,62 @@ void launch_fft_pass(const FftPass& p, Cx tin, Cx tcomp, Cx tout, const void* in
   a.in_pt = (int)p.in_pt; a.out_pt = (int)p.out_pt;
   a.sign = p.sign;
   a.scale = p.scale;
+  return a;
+}
+}  // namespace
+
+void launch_fft_pass_green(const FftPass& p, const GreenGeomDev& geo, int nx, int ny, int Ly, int64_t c0, int n,
+                           int vperm, void* out, const void* twiddles, hipStream_t s) {
+  const PassArgs a = pass_args(p);
+  // the twiddle table stands in for the input pointer, which the generating
+  // first stage never reads
+  EMS_CHECK_ARG(p.nl0 == p.n_lines && p.n_lines == Ly && n == 4 * geo.n_patch && c0 >= 0 &&
+                    c0 + p.batch <= (int64_t)n * n,
+                "internal: generating kernel pass shape");
+  GreenGen gg;
+  gg.rho = geo.rho.as<const double>();
+  gg.area = geo.area.as<const double>();
+  gg.tan = geo.tan.as<const double>();
+  gg.P = geo.n_patch;
+  gg.nx = nx;
+  gg.ny = ny;
+  gg.Ly = Ly;
+  gg.c0 = (int)c0;
+  gg.n = n;
+  gg.vperm = vperm;
+  gg.pitch = geo.pitch;
+  gg.k = geo.k;
+  const unsigned lines = (unsigned)p.n_lines;
+#define EMS_FFT_GEN(LL)                                                                           \
+  case LL:                                                                                        \
+    launch_L<LL, 1, double2, double2, double2, 1>(a, p.batch, lines, twiddles, out, twiddles, s, gg); \
+    break;
+  switch (p.L) {
+    EMS_FFT_GEN(2)
+    EMS_FFT_GEN(4)
+    EMS_FFT_GEN(8)
+    EMS_FFT_GEN(16)
+    EMS_FFT_GEN(32)
+    EMS_FFT_GEN(64)
+    EMS_FFT_GEN(128)
+    EMS_FFT_GEN(256)
+    EMS_FFT_GEN(512)
+    EMS_FFT_GEN(1024)
+    EMS_FFT_GEN(24)
+    EMS_FFT_GEN(48)
+    EMS_FFT_GEN(96)
+    EMS_FFT_GEN(192)
+    EMS_FFT_GEN(384)
+    EMS_FFT_GEN(768)
+    default: break;
+  }
+#undef EMS_FFT_GEN
+  EMS_LAUNCH_CHECK();
+}
+
+void launch_fft_pass(const FftPass& p, Cx tin, Cx tcomp, Cx tout, const void* in, void* out,
+                     const void* twiddles, hipStream_t s) {
+  const PassArgs a = pass_args(p);
   const unsigned lines = (unsigned)p.n_lines;
   if (tcomp == Cx::C128) {
     EMS_CHECK_ARG(tin == Cx::C128 && tout == Cx::C128, "FP64 FFT needs FP64 input and output");

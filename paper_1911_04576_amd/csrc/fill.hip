@@ -11,16 +11,10 @@
 // [L; K], part 0 = L, 1 = K), as a dense [Ly][Lx][nc] array, so that after the
 // 2-D transform every frequency's record is stored column-major.
 #include "internal.h"
+#include "green.h"
 
 namespace emsurf {
 namespace {
-
-__device__ __forceinline__ int slot_to_offset(int s, int L, int N, bool* ok) {
-  if (s <= N - 1) { *ok = true; return s; }
-  if (s >= L - (N - 1)) { *ok = true; return s - L; }
-  *ok = false;
-  return 0;
-}
 
 // Caller blocks hold `parts` square nb x nb matrices per offset, row-major
 // (row = test, column = source): parts = 1, nb = n_eq for dense blocks;
@@ -52,30 +46,6 @@ __global__ void pad_blocks_kernel(const double2* __restrict__ Tb, int nx, int ny
     }
     K[i] = val;
   }
-}
-
-// T(d)[(tau,p,a),(tau',q,b)] = delta(tau,tau') (t_pa . t_qb) A_q exp(-jkR)/(4 pi R),
-// R = |rho_p - rho_q + pitch (dx, dy, 0)|, T(0) = 0.
-__device__ __forceinline__ double2 green_entry(const double* __restrict__ rho, const double* __restrict__ area,
-                                               const double* __restrict__ tan, int P, double pitch, double k,
-                                               int dx, int dy, int u, int v) {
-  if (dx == 0 && dy == 0) return double2{0.0, 0.0};
-  const int hu = u / (2 * P), hv = v / (2 * P);
-  if (hu != hv) return double2{0.0, 0.0};
-  const int lu = u - hu * 2 * P, lv = v - hv * 2 * P;
-  const int p = lu >> 1, a = lu & 1, q = lv >> 1, b = lv & 1;
-  const double* tp = tan + (p * 2 + a) * 3;
-  const double* tq = tan + (q * 2 + b) * 3;
-  const double dot = tp[0] * tq[0] + tp[1] * tq[1] + tp[2] * tq[2];
-  if (dot == 0.0) return double2{0.0, 0.0};
-  const double ex = rho[3 * p + 0] - rho[3 * q + 0] + pitch * dx;
-  const double ey = rho[3 * p + 1] - rho[3 * q + 1] + pitch * dy;
-  const double ez = rho[3 * p + 2] - rho[3 * q + 2];
-  const double R = sqrt(ex * ex + ey * ey + ez * ez);
-  double sn, cs;
-  sincos(k * R, &sn, &cs);
-  const double w = dot * area[q] / (4.0 * 3.14159265358979323846 * R);
-  return double2{w * cs, -w * sn};
 }
 
 // Structured fill (outer EFIE/MFIE operators, Sec. III-B), local index 2p + a:

@@ -134,6 +134,12 @@ int fft_length_at_least(int v);
 // Launch a pass. tin/tcomp/tout select element types of input, arithmetic and output.
 void launch_fft_pass(const FftPass& p, Cx tin, Cx tcomp, Cx tout, const void* in, void* out,
                      const void* twiddles, hipStream_t s);
+struct GreenGeomDev;
+// x pass of the kernel transform (FP64) whose inputs are the point-sampled
+// coupling entries of columns [c0, c0 + p.batch), generated in the first stage
+// instead of loaded (lines = the Ly slots along y)
+void launch_fft_pass_green(const FftPass& p, const GreenGeomDev& geo, int nx, int ny, int Ly, int64_t c0, int n,
+                           int vperm, void* out, const void* twiddles, hipStream_t s);
 // Twiddle table exp(-2 pi i j / L), j < L, in FP64 (computed on the host with
 // long-double arithmetic) and FP32 (rounded from it).  Device memory, cached.
 const void* twiddle_table(int L, Cx t);

@@ -310,8 +310,11 @@ void upload_S(emsurf_plan p, const void* S_types, hipStream_t s) {
 }
 
 // Kernel FFT of the padded blocks, in column chunks, into the resident stores.
+// gen: dense point-sampled plans generate the entries inside the first pass of
+// the kernel transform (no fill chunk written and read back); else `fill`
+// writes each chunk
 template <typename FillChunk>
-void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill) {
+void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill, const GreenGeomDev* gen = nullptr) {
   const int64_t nn = kernel_cols(p->d);
   const int64_t P = p->P;
   const int n = p->d.n_eq;
@@ -349,14 +352,18 @@ void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill) {
   const void* twy = twiddle_table(p->Ly, Cx::C128);
   for (int64_t c0 = 0; c0 < nn; c0 += nc) {
     const int64_t cnt = std::min(nc, nn - c0);
-    fill(c0, cnt, K.p, vperm);
     FftPass fx;
     fx.L = p->Lx; fx.n_in = p->Lx; fx.n_out = p->Lx; fx.batch = (int)cnt;
     fx.n_lines = p->Ly; fx.nl0 = p->Ly;
     fx.in_s0 = (int64_t)p->Lx * cnt; fx.in_pt = cnt;
     fx.out_s0 = (int64_t)p->Lx * cnt; fx.out_pt = cnt;
     fx.sign = -1;
-    launch_fft_pass(fx, Cx::C128, Cx::C128, Cx::C128, K.p, tmp.p, twx, s);
+    if (gen) {
+      launch_fft_pass_green(fx, *gen, p->d.nx, p->d.ny, p->Ly, c0, n, vperm, tmp.p, twx, s);
+    } else {
+      fill(c0, cnt, K.p, vperm);
+      launch_fft_pass(fx, Cx::C128, Cx::C128, Cx::C128, K.p, tmp.p, twx, s);
+    }
     FftPass fy;
     fy.L = p->Ly; fy.n_in = p->Ly; fy.n_out = p->Ly; fy.batch = (int)cnt;
     fy.n_lines = p->Lx; fy.nl0 = p->Lx;
@@ -574,7 +581,7 @@ emsurf_status emsurf_plan_create_green(const emsurf_plan_desc* desc, const emsur
         launch_lk_padded(g, desc->nx, desc->ny, p->Lx, p->Ly, c0, cnt, K, s);
       else
         launch_green_padded(g, desc->nx, desc->ny, p->Lx, p->Ly, c0, cnt, vperm, K, s);
-    });
+    }, desc->form == EMSURF_T_LK ? nullptr : &g);
     upload_S(p, S_types, s);
     build_tiles(p, elem_type, s);
     finish_plan(p, s);
