@@ -108,7 +108,7 @@ struct GreenGen {
   const double* rho = nullptr;
   const double* area = nullptr;
   const double* tan = nullptr;
-  int P = 0, nx = 0, ny = 0, Ly = 0, c0 = 0, n = 0, vperm = 0;
+  int P = 0, nx = 0, ny = 0, Ly = 0, c0 = 0, n = 0, vperm = 0;   // rows in the green_fill_u order
   double pitch = 0, k = 0;
 };
 
@@ -179,7 +179,8 @@ __device__ __forceinline__ void run_stage(const PassArgs& a, VC* lds, const VI* 
     bool oky;
     const int dy = slot_to_offset(line, gg.Ly, gg.ny, &oky);
     const int c = gg.c0 + col;
-    const int vp = c / gg.n, u = c - vp * gg.n;
+    const int vp = c / gg.n;
+    const int u = green_fill_u(c - vp * gg.n, gg.P);
     const int vv = gg.vperm ? pair_fill_v(vp, gg.n) : vp;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {

@@ -216,15 +216,25 @@ __global__ void lk_blocks_kernel(const double* __restrict__ rho, const double* _
 
 __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, long long nn, long long c0,
                                    long long nc, const int* __restrict__ slot_of, int n, int nh, int vperm,
-                                   double2* __restrict__ t64, float2* __restrict__ t32, __bf16* __restrict__ t16) {
+                                   int uperm, double2* __restrict__ t64, float2* __restrict__ t32,
+                                   __bf16* __restrict__ t16) {
   const long long total = P * nc;
   const long long blk = nh > 0 ? lkpair_block_entries(nh) : pair_block_entries(n);
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
     const long long kf = i / nc, j = i - kf * nc;
-    const double2 v = Kc[i];
     if (!slot_of) {
+      // output-ordered: column c0 + j of the store; with the Green row order its
+      // value sits at the row's position in the same column of the chunk
       const long long dst = kf * nn + c0 + j;
+      double2 v;
+      if (uperm) {
+        const long long col = c0 + j;
+        const int cv = (int)(col / n), u = (int)(col - (long long)cv * n);
+        v = Kc[kf * nc + (long long)cv * n + green_fill_up(u, n / 4) - c0];
+      } else {
+        v = Kc[i];
+      }
       if (t64) t64[dst] = v;
       if (t32) t32[dst] = float2{(float)v.x, (float)v.y};
       if (t16) {
@@ -244,6 +254,7 @@ __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, 
       }
       continue;
     }
+    const double2 v = Kc[i];
     const long long slot = slot_of[kf];
     if (slot < 0) continue;
     const long long col = c0 + j;
@@ -258,6 +269,7 @@ __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, 
       cv = (int)(col / n);
       u = (int)(col - (long long)cv * n);
       if (vperm) cv = pair_fill_v(cv, n);
+      if (uperm) u = green_fill_u(u, n / 4);
     }
     if (t64) {
       double* d = reinterpret_cast<double*>(t64) + slot * blk * 2;
@@ -281,7 +293,7 @@ __global__ void store_chunk_kernel(const double2* __restrict__ Kc, long long P, 
 // tile), written whole; consecutive u write consecutive pieces.  Quads at a
 // ragged edge write their values one by one.
 __global__ void store_pair_chunk_kernel(const double2* __restrict__ Kc, int Ps, int c0, int nc, int nq,
-                                        const int* __restrict__ pairs, int n, double* __restrict__ t64,
+                                        const int* __restrict__ pairs, int n, int uperm, double* __restrict__ t64,
                                         float* __restrict__ t32) {
   const int total = Ps * nq * n;   // host: fits 31 bits
   const long long blk2 = 2LL * pair_block_entries(n);   // reals per stored block
@@ -294,10 +306,11 @@ __global__ void store_pair_chunk_kernel(const double2* __restrict__ Kc, int Ps, 
     const int cnt = pend - vp0 < 4 ? pend - vp0 : 4;
     int v[4];
     double2 x[4];
+    const int up = uperm ? green_fill_up(u, n / 4) : u;   // position of row u in its column
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       v[j] = j < cnt ? pair_fill_v(vp0 + j, n) : 0;
-      x[j] = j < cnt ? Kc[(long long)kf * nc + (long long)(vp0 + j - pos0) * n + u] : double2{0.0, 0.0};
+      x[j] = j < cnt ? Kc[(long long)kf * nc + (long long)(vp0 + j - pos0) * n + up] : double2{0.0, 0.0};
     }
     const bool whole = cnt == 4 && (v[0] & 6) == 0 && v[1] == v[0] + 2 && v[2] == v[0] + 4 && v[3] == v[0] + 6;
     if (t64) {
@@ -451,8 +464,10 @@ void launch_green_blocks(const GreenGeomDev& g, int nx, int ny, void* T_blocks, 
 }
 
 void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, const int* slot_of,
-                        const int* pairs, int64_t Ps, int n, int nh, int vperm, void* that64, void* that32,
-                        void* that16, hipStream_t s) {
+                        const int* pairs, int64_t Ps, int n, int nh, int vperm, int uperm, void* that64,
+                        void* that32, void* that16, hipStream_t s) {
+  EMS_CHECK_ARG(!uperm || (nh == 0 && n % 4 == 0 && c0 % n == 0 && (nc % n == 0 || c0 + nc == nn)),
+                "internal: the Green row order is for dense point-sampled blocks in whole-column chunks");
   EMS_CHECK_ARG(!(that16 && slot_of), "internal: the split-BF16 store has no reciprocal layout");
   EMS_CHECK_ARG(!vperm || (slot_of && pairs && nh == 0), "internal: the pair column order is for dense reciprocal stores");
   if (vperm) {
@@ -463,14 +478,14 @@ void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64
     EMS_CHECK_ARG(Ps >= 1 && Ps <= P && total < (1LL << 31) && c0 + nc < (1LL << 31),
                   "internal: pair-order chunk too large");
     hipLaunchKernelGGL(store_pair_chunk_kernel, dim3(grid_for((long long)total, 256)), dim3(256), 0, s,
-                       static_cast<const double2*>(Kc), (int)Ps, (int)c0, (int)nc, (int)nq, pairs, n,
+                       static_cast<const double2*>(Kc), (int)Ps, (int)c0, (int)nc, (int)nq, pairs, n, uperm,
                        static_cast<double*>(that64), static_cast<float*>(that32));
     EMS_LAUNCH_CHECK();
     return;
   }
   hipLaunchKernelGGL(store_chunk_kernel, dim3(grid_for((long long)P * nc, 256)), dim3(256), 0, s,
                      static_cast<const double2*>(Kc), (long long)P, (long long)nn, (long long)c0, (long long)nc,
-                     slot_of, n, nh, vperm, static_cast<double2*>(that64), static_cast<float2*>(that32),
+                     slot_of, n, nh, vperm, uperm, static_cast<double2*>(that64), static_cast<float2*>(that32),
                      static_cast<__bf16*>(that16));
   EMS_LAUNCH_CHECK();
 }

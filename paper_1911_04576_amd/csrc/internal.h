@@ -311,9 +311,10 @@ void launch_green_blocks(const GreenGeomDev& g, int nx, int ny, void* T_blocks, 
 // nh > 0: the columns are those of a structured record (v (2 n_h) + half n_h
 // + u) and a reciprocal store takes the [L | K] pair layout.
 // pairs / Ps: the pair list (k, -k) per stored slot, used by the pair-order store
+// uperm: rows in the green_fill_u order (point-sampled dense plans)
 void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64_t nc, const int* slot_of,
-                        const int* pairs, int64_t Ps, int n, int nh, int vperm, void* that64, void* that32,
-                        void* that16, hipStream_t s);
+                        const int* pairs, int64_t Ps, int n, int nh, int vperm, int uperm, void* that64,
+                        void* that32, void* that16, hipStream_t s);
 // max |T(-d)[u][v] - T(d)[v][u] w[v] / w[u]| and max |T(d)| over dense caller
 // blocks [2ny-1][2nx-1][n][n] (device), written to out (device double [2]).
 // parts = 2 for structured blocks [..][2][n][n] (L and K, each checked with w).
@@ -403,6 +404,20 @@ __host__ __device__ inline int pair_fill_v(int vp, int n) {
   const int m = n - g < 8 ? n - g : 8;   // members of this group
   const int e = (m + 1) >> 1;            // of which even
   return g + (w < e ? 2 * w : 2 * (w - e) + 1);
+}
+// Row order of the point-sampled (Green) kernel columns: position up of a
+// column holds row u = green_fill_u(up), ordering each current type's rows
+// by tangent index a before patch p (u = 2 P hu + 2 p + a, up = 2 P hu + P a + p),
+// so that neighbouring lanes of the generating transform share a tangent and
+// with it which entries vanish.  green_fill_up is the inverse.
+__host__ __device__ inline int green_fill_u(int up, int P) {
+  const int hu = up / (2 * P), r = up - hu * 2 * P;
+  const int a = r / P, p = r - a * P;
+  return hu * 2 * P + 2 * p + a;
+}
+__host__ __device__ inline int green_fill_up(int u, int P) {
+  const int hu = u / (2 * P), r = u - hu * 2 * P;
+  return hu * 2 * P + (r & 1) * P + (r >> 1);
 }
 inline int64_t kernel_cols(const emsurf_plan_desc& d) {
   const int64_t n = d.n_eq;

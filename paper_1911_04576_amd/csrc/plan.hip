@@ -342,9 +342,14 @@ void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill, const GreenGeomD
   // 4 n_eq columns (buffers of up to 1 GiB), so that each chunk writes whole
   // 16-byte pieces of the paired tiles instead of scattered values
   int64_t nc = (int64_t)((512ull << 20) / ((size_t)P * 16));
+  // Point-sampled dense plans (gen) generate their entries inside the kernel
+  // transform, with rows in the green_fill_u order, on the same whole-column
+  // chunks; plans too large for such chunks fill chunk by chunk instead.
   const int64_t grp = 4 * (int64_t)n;
-  const int vperm = p->d.recip && p->d.form != EMSURF_T_LK && (size_t)P * grp * 16 <= (1ull << 30) ? 1 : 0;
-  if (vperm) nc = std::max<int64_t>(1, nc / grp) * grp;
+  const bool wide = (size_t)P * grp * 16 <= (1ull << 30);
+  const int vperm = p->d.recip && p->d.form != EMSURF_T_LK && wide ? 1 : 0;
+  if (!wide) gen = nullptr;
+  if (vperm || gen) nc = std::max<int64_t>(1, nc / grp) * grp;
   nc = std::max<int64_t>(1, std::min<int64_t>(nc, nn));
   nc = std::min<int64_t>(nc, 0x7fffffff);
   DevBuf K((size_t)(P * nc) * 16), tmp((size_t)(P * nc) * 16);
@@ -372,7 +377,7 @@ void build_that(emsurf_plan p, hipStream_t s, FillChunk&& fill, const GreenGeomD
     fy.sign = -1;
     launch_fft_pass(fy, Cx::C128, Cx::C128, Cx::C128, tmp.p, K.p, twy, s);
     launch_store_chunk(K.p, P, nn, c0, cnt, slot_dev.as<const int>(), p->pairs.as<const int>(), p->Ps, n,
-                       p->d.form == EMSURF_T_LK ? n / 2 : 0, vperm,
+                       p->d.form == EMSURF_T_LK ? n / 2 : 0, vperm, gen ? 1 : 0,
                        p->that64.p, p->that32.p, p->that16.p, s);
   }
   EMS_HIP(hipStreamSynchronize(s));
