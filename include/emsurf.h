@@ -388,10 +388,15 @@ void emsurf_graph_destroy(emsurf_graph graph);
  * result is bitwise the same alone and in a mix.  Finished slots keep their
  * solution until emsurf_session_collect copies it out and frees the slot.
  * Calls on one session must not overlap; different sessions may run
- * concurrently (each on its own stream). */
+ * concurrently (each on its own stream).  The bitwise statement holds for every
+ * plan form: dense and structured, full and reciprocal stores. */
 typedef struct emsurf_session_s* emsurf_session;
-/* device bytes a session with these parameters allocates (slot vectors,
- * Krylov bases, reduction buffers, its stream's apply workspace) */
+/* device bytes a session with these parameters allocates with every slot in
+ * use (slot vectors and Krylov bases, batch staging, reduction buffers) plus
+ * an apply workspace for its stream (none is added when the session shares a
+ * stream that already has one in the plan).  A slot's vectors and Krylov basis,
+ * (restart + 4) unknown vectors, are allocated when the slot is first used and
+ * kept for reuse. */
 size_t emsurf_session_bytes(emsurf_plan plan, int32_t max_slots, const emsurf_solve_opts* opts);
 /* stream NULL: the session creates (and later destroys) its own non-blocking stream. */
 emsurf_status emsurf_session_create(emsurf_plan plan, int32_t max_slots, const emsurf_solve_opts* opts, void* stream,
@@ -415,9 +420,11 @@ void emsurf_session_destroy(emsurf_session session);
  * same surface (lattice, geometry, macromodels, type map).  Each resident
  * surface has a plan (synthetic point-sampled coupling, FP64 and/or FP32
  * stores per desc.store) and a session with max_slots slots on its own stream.
- * emsurf_server_step admits queued requests whose plan fits budget_bytes
- * (evicting idle plans least-recently-used first) and whose session has
- * nrhs free slots, then runs one batched iteration on every busy session
+ * emsurf_server_step admits queued requests whose plan and busy slots fit
+ * budget_bytes and whose session has nrhs free slots.  To make room it first
+ * releases the vectors of free slots, then evicts idle plans (no active or
+ * queued request) least-recently-used first.  Then it runs one batched
+ * iteration on every busy session
  * (launching all sessions before waiting for any, so they overlap on the
  * device), and moves finished requests to the completion queue.  All host
  * inputs are copied at submit. */
@@ -452,9 +459,14 @@ emsurf_status emsurf_server_next_completed(emsurf_server server, int64_t* req_id
 emsurf_status emsurf_server_fetch(emsurf_server server, int64_t req_id, void* x_host, emsurf_solve_info* info,
                                   double* times_ms);
 emsurf_status emsurf_server_query(emsurf_server server, emsurf_server_stats* out);
-/* device bytes a resident surface with this desc (nx, ny, n_eq, n_types) takes on this
- * server (plan + session + staging), as used for admission; 0 if invalid */
+/* device bytes a resident surface with this desc (nx, ny, n_eq, n_types) holds on
+ * this server with no busy right-hand side (plan with its stream's apply
+ * workspace, which its session shares, the session's batch staging and
+ * reductions, one staging vector), as used for admission; 0 if invalid */
 size_t emsurf_server_entry_bytes(emsurf_server server, const emsurf_plan_desc* desc);
+/* device bytes each busy right-hand side adds on that surface (its slot's
+ * vectors and Krylov basis); 0 if invalid */
+size_t emsurf_server_slot_bytes(emsurf_server server, const emsurf_plan_desc* desc);
 void emsurf_server_destroy(emsurf_server server);
 
 void emsurf_plan_destroy(emsurf_plan plan);

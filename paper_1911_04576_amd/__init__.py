@@ -158,6 +158,7 @@ _SIGS = {
     "emsurf_server_query": (ctypes.c_int, [_P, ctypes.POINTER(emsurf_server_stats)]),
     "emsurf_server_destroy": (None, [_P]),
     "emsurf_server_entry_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(emsurf_plan_desc)]),
+    "emsurf_server_slot_bytes": (ctypes.c_size_t, [_P, ctypes.POINTER(emsurf_plan_desc)]),
     "emsurf_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "emsurf_last_error": (ctypes.c_char_p, []),
 }
@@ -594,3 +595,8 @@ def emsurf_server_destroy(srv: Server):
 def emsurf_server_entry_bytes(srv: Server, nx, ny, n_eq, n_types) -> int:
     d = _desc(nx, ny, n_eq, n_types, 1, EMSURF_STORE_FP64)
     return int(lib().emsurf_server_entry_bytes(srv.h, ctypes.byref(d)))
+
+
+def emsurf_server_slot_bytes(srv: Server, nx, ny, n_eq, n_types) -> int:
+    d = _desc(nx, ny, n_eq, n_types, 1, EMSURF_STORE_FP64)
+    return int(lib().emsurf_server_slot_bytes(srv.h, ctypes.byref(d)))

@@ -27,7 +27,12 @@
 // with rows u, read straight from HBM in the lane order of the store) into
 // the tile's row accumulator, and 8 of the transposed product (A = the tile
 // transposed, staged through LDS) into the v tile's column sums, which are
-// added into LDS once per v tile.  Up to 8 right-hand sides per pass
+// added into LDS once per v tile.  Wavefronts 0 and 1 add into one column-sum
+// buffer and wavefronts 2 and 3 into another: with two addends per entry the
+// LDS float addition gives the same bits in either order (0 + a = a, and
+// a + b = b + a), and the two buffers are added in a fixed order at the end,
+// so every output has one rounding sequence whatever the wavefront timing.
+// Up to 8 right-hand sides per pass
 // (2 NR <= 16 MFMA columns).  The two instructions share their A and B
 // layouts (lane l: A[l % 16][l / 16], B[l / 16][l % 16]); the result rows
 // differ: lane l, register e holds row 4 (l / 16) + e in FP32 and row
@@ -101,8 +106,11 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
   const int nt = pair_tiles(n), np = nt * PAIR_TILE;
   T* xs = reinterpret_cast<T*>(smem_raw);  // [np][NRW][2]: xh[k]; row sums at the end
   T* xt = xs + np * NRW * 2;               // [np][NRW][2]: W xh[-k]
-  T* zs = xt + np * NRW * 2;               // [np][2 NRW]: column sums
-  T* tiles = zs + np * 2 * NRW;            // [4 waves][stages][512]
+  T* zs = xt + np * NRW * 2;               // [np][2 NRW]: column sums of wavefronts 0, 1
+  // column sums of wavefronts 2, 3: over xt once the B operands it holds are
+  // in registers (B2R), else a region of their own
+  T* zs2 = B2R ? xt : zs + np * 2 * NRW;
+  T* tiles = zs + np * 2 * NRW * (B2R ? 1 : 2);   // [4 waves][stages][512]
   const long long slot = blockIdx.x;
   const int2 pr = pairs[slot];
   const long long k = pr.x, kb = pr.y;
@@ -150,6 +158,8 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
     xt[(v * NRW + r) * 2 + 1] = b.y;
   }
   for (int e = threadIdx.x; e < np * 2 * NRW; e += PNT) zs[e] = T(0);
+  if constexpr (!B2R)
+    for (int e = threadIdx.x; e < np * 2 * NRW; e += PNT) zs2[e] = T(0);
   __syncthreads();
   // lane roles: k-slot kk = l / 16 -> (pair offset off, part); column jj = l % 16
   const int kk = l >> 4, jj = l & 15, off = kk >> 1, part = kk & 1, a16 = l & 15;
@@ -166,6 +176,12 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
   for (int ta = 0; ta < NB2; ++ta)
 #pragma unroll
     for (int s = 0; s < 8; ++s) b2[ta][s] = B2R && ta < ntw ? bval(xt, (wv + 4 * ta) * PAIR_TILE + 2 * s + off) : T(0);
+  if constexpr (B2R) {
+    // xt becomes the second column-sum buffer
+    __syncthreads();
+    for (int e = threadIdx.x; e < np * 2 * NRW; e += PNT) zs2[e] = T(0);
+    __syncthreads();
+  }
   Acc acc[TPW];
 #pragma unroll
   for (int ta = 0; ta < TPW; ++ta) acc[ta] = Acc{};
@@ -226,9 +242,10 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
       }
     }
     if (!self && ntw > 0) {
+      T* zd = wv < 2 ? zs : zs2;
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (jok) atomicAdd(&zs[(q * PAIR_TILE + M::row(l, e)) * 2 * NRW + jj], zq[e]);
+        if (jok) atomicAdd(&zd[(q * PAIR_TILE + M::row(l, e)) * 2 * NRW + jj], zq[e]);
     }
   }
   // outputs: the row sums are staged in LDS over the spectral columns of
@@ -257,7 +274,8 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
       __builtin_nontemporal_store(d2v{ys[c0], ys[c0 + NRW]}, reinterpret_cast<d2v*>(y0 + e));
       if (!self) {
         const double wi = winv[v];
-        __builtin_nontemporal_store(d2v{zs[c0] * wi, zs[c0 + NRW] * wi}, reinterpret_cast<d2v*>(y1 + e));
+        __builtin_nontemporal_store(d2v{(zs[c0] + zs2[c0]) * wi, (zs[c0 + NRW] + zs2[c0 + NRW]) * wi},
+                                    reinterpret_cast<d2v*>(y1 + e));
       }
     }
   } else {
@@ -270,7 +288,8 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
         __builtin_nontemporal_store(a, reinterpret_cast<f4v*>(y0 + e));
         if (!self) {
           const float w0 = winv[v], w1 = winv[v + 1];
-          const f4v b = {zs[c0] * w0, zs[c0 + NRW] * w0, zs[c1] * w1, zs[c1 + NRW] * w1};
+          const f4v b = {(zs[c0] + zs2[c0]) * w0, (zs[c0 + NRW] + zs2[c0 + NRW]) * w0, (zs[c1] + zs2[c1]) * w1,
+                         (zs[c1 + NRW] + zs2[c1 + NRW]) * w1};
           __builtin_nontemporal_store(b, reinterpret_cast<f4v*>(y1 + e));
         }
       }
@@ -279,16 +298,21 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
         const int r = e / n, v = e - r * n;
         const int c0 = v * 2 * NRW + r;
         y0[e] = V2{ys[c0], ys[c0 + NRW]};
-        if (!self) y1[e] = V2{zs[c0] * winv[v], zs[c0 + NRW] * winv[v]};
+        if (!self) y1[e] = V2{(zs[c0] + zs2[c0]) * winv[v], (zs[c0 + NRW] + zs2[c0 + NRW]) * winv[v]};
       }
     }
   }
 }
 
+// FP64 B operands of the transposed product stay in registers for at most 2 u
+// tiles per wavefront; beyond that they are rebuilt from LDS per tile
+template <typename T> constexpr bool pair_b2r(int tpw) { return sizeof(T) == 4 || tpw <= 2; }
+
 template <typename T>
 size_t pair_lds_bytes(int n, int nrw) {
   const int np = pair_tiles(n) * PAIR_TILE;
-  return (size_t)(np * nrw * 2 * 3 + 4 * pair_stages<T>() * 512) * sizeof(T);
+  const bool b2r = pair_b2r<T>((pair_tiles(n) + 3) / 4);
+  return (size_t)(np * nrw * 2 * (b2r ? 3 : 4) + 4 * pair_stages<T>() * 512) * sizeof(T);
 }
 
 template <typename T, int TPW, int NRW>
@@ -296,7 +320,7 @@ void launch_mfma_pair(const void* That, const void* pairs, const void* w, const 
                       int n, int nrhs, int r0, int nr, int64_t Ps, hipStream_t s) {
   using V2 = typename Mf<T>::V2;
   // FP64 B operands of many u tiles would not fit the registers
-  constexpr bool B2R = sizeof(T) == 4 || TPW <= 2;
+  constexpr bool B2R = pair_b2r<T>(TPW);
   const size_t shm = pair_lds_bytes<T>(n, NRW);
   hipLaunchKernelGGL((pair_mfma_kernel<T, TPW, NRW, B2R>), dim3((unsigned)Ps), dim3(PNT), shm, s,
                      static_cast<const T*>(That), static_cast<const int2*>(pairs), static_cast<const T*>(w),

@@ -37,6 +37,14 @@ void validate_desc(const emsurf_plan_desc* d) {
                   "the split-BF16 store needs a dense plan that stores every frequency (recip 0)");
     EMS_CHECK_ARG(block_bf16_supported(d->n_eq), "the split-BF16 store needs n_eq a multiple of 32 in [32, 480]");
   }
+  // The pass along y of a full-width apply spans Lx Ly max_rhs n_eq complex
+  // values, addressed with 32-bit offsets inside the FFT kernels: refuse such
+  // plans here rather than at their first apply.
+  const int64_t Lx = fft_length_at_least(2 * d->nx - 1), Ly = fft_length_at_least(2 * d->ny - 1);
+  const int64_t B = (int64_t)d->max_rhs * d->n_eq;
+  EMS_CHECK_ARG(Lx * Ly * B + B + 1024 < (1LL << 31),
+                "padded lattice x max_rhs x n_eq exceeds the 2^31 values one FFT pass addresses; "
+                "lower max_rhs (or n_eq)");
 }
 
 // complex entries of one stored block of a reciprocal plan (tile padding included)

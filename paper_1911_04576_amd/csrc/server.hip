@@ -46,7 +46,9 @@ struct PlanEntry {
   emsurf_plan plan = nullptr;
   emsurf_session session = nullptr;
   hipStream_t stream = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;        // plan, session staging and reductions, host staging vector
+  size_t slot_bytes = 0;   // vectors and Krylov basis of one slot
+  size_t held = 0;         // slot buffers the session holds now
   double last_used = 0;
   int active = 0;
   DevBuf staging;   // one right-hand side, for host -> slot copies
@@ -83,48 +85,84 @@ void destroy_entry(emsurf_server sv, std::map<uint64_t, std::unique_ptr<PlanEntr
   if (e.session) emsurf_session_destroy(e.session);
   if (e.plan) emsurf_plan_destroy(e.plan);
   if (e.stream) (void)hipStreamDestroy(e.stream);
-  sv->used -= e.bytes;
+  sv->used -= e.bytes + e.held;
   sv->plans.erase(it);
 }
 
-// Device bytes a resident surface takes: plan, session, staging vector.
-size_t entry_bytes(emsurf_server sv, emsurf_plan_desc pd) {
+emsurf_plan_desc server_desc(emsurf_server sv, emsurf_plan_desc pd) {
   pd.max_rhs = sv->d.max_slots;
   pd.store = sv->d.store;
-  const size_t pb = emsurf_plan_bytes(&pd);
-  if (pb == 0) return 0;
-  return pb + session_bytes(pd, sv->d.max_slots, sv->d.opts.restart) + (size_t)pd.nx * pd.ny * pd.n_eq * 16;
+  return pd;
 }
 
-// Make the plan of request rq resident (building it if needed), evicting
-// least-recently-used plans that have neither active nor queued requests.
-// Returns null when it does not fit the budget even then.
-PlanEntry* resident(emsurf_server sv, Request& rq, const std::map<uint64_t, int>& queued_keys) {
-  auto it = sv->plans.find(rq.key);
-  if (it != sv->plans.end()) return it->second.get();
-  emsurf_plan_desc pd = rq.desc;
-  pd.max_rhs = sv->d.max_slots;
-  pd.store = sv->d.store;
-  const size_t need = entry_bytes(sv, pd);
-  if (need == 0 || need > sv->d.budget_bytes) {   // invalid, or can never be admitted
-    rq.bad = true;
-    return nullptr;
+// Device bytes a resident surface holds with no busy right-hand side: the plan
+// (its stores and the apply workspace of its stream, which the session on the
+// same stream shares), the session's batch staging and reductions, and one
+// staging vector.  Each busy slot adds entry_slot_bytes.
+size_t entry_bytes(emsurf_server sv, emsurf_plan_desc pd) {
+  pd = server_desc(sv, pd);
+  const size_t pb = emsurf_plan_bytes(&pd);
+  if (pb == 0) return 0;
+  return pb + session_fixed_bytes(pd, sv->d.max_slots, sv->d.opts.restart) + (size_t)pd.nx * pd.ny * pd.n_eq * 16;
+}
+
+size_t entry_slot_bytes(emsurf_server sv, emsurf_plan_desc pd) {
+  return session_slot_bytes(server_desc(sv, pd), sv->d.opts.restart);
+}
+
+// Account for the slot buffers the entry's session holds now.
+void refresh_held(emsurf_server sv, PlanEntry& e) {
+  const size_t h = session_held_bytes(e.session);
+  sv->used = sv->used - e.held + h;
+  e.held = h;
+}
+
+// Make room for `need` more bytes: first release the buffers of free slots
+// (cheap to allocate again), then evict idle plans (neither active nor queued,
+// least recently used first).  Nothing is released unless the need can be met.
+bool make_room(emsurf_server sv, size_t need, const std::map<uint64_t, int>& protect) {
+  const size_t budget = sv->d.budget_bytes;
+  if (sv->used + need <= budget) return true;
+  auto idle = [&](const PlanEntry& e, uint64_t key) { return e.active == 0 && protect.count(key) == 0; };
+  size_t releasable = 0;
+  for (auto& kv : sv->plans) {
+    PlanEntry& e = *kv.second;
+    releasable += idle(e, kv.first) ? e.bytes + e.held
+                                    : (size_t)session_free_held(e.session) * e.slot_bytes;
   }
-  auto idle = [&](const PlanEntry& e, uint64_t key) { return e.active == 0 && queued_keys.count(key) == 0; };
-  size_t freeable = 0;
-  for (auto& kv : sv->plans)
-    if (idle(*kv.second, kv.first)) freeable += kv.second->bytes;
-  if (sv->used - freeable + need > sv->d.budget_bytes) return nullptr;   // wait; evict nothing
-  while (sv->used + need > sv->d.budget_bytes) {
+  if (sv->used - releasable + need > budget) return false;   // wait; release nothing
+  for (auto& kv : sv->plans) {
+    if (sv->used + need <= budget) return true;
+    (void)session_trim(kv.second->session);
+    refresh_held(sv, *kv.second);
+  }
+  while (sv->used + need > budget) {
     auto victim = sv->plans.end();
     for (auto p = sv->plans.begin(); p != sv->plans.end(); ++p)
       if (idle(*p->second, p->first) &&
           (victim == sv->plans.end() || p->second->last_used < victim->second->last_used))
         victim = p;
-    if (victim == sv->plans.end()) return nullptr;
+    if (victim == sv->plans.end()) return false;
     destroy_entry(sv, victim);
     ++sv->evictions;
   }
+  return true;
+}
+
+// Make the plan of request rq resident (building it if needed) with room for
+// the request's slots.  Returns null when it does not fit the budget yet.
+PlanEntry* resident(emsurf_server sv, Request& rq, const std::map<uint64_t, int>& queued_keys) {
+  auto it = sv->plans.find(rq.key);
+  if (it != sv->plans.end()) return it->second.get();
+  const emsurf_plan_desc pd = server_desc(sv, rq.desc);
+  const size_t fixed = entry_bytes(sv, pd);
+  const size_t slot = entry_slot_bytes(sv, pd);
+  const size_t need = fixed + (size_t)rq.nrhs * slot;
+  if (fixed == 0 || need > sv->d.budget_bytes) {   // invalid, or can never be admitted
+    rq.bad = true;
+    return nullptr;
+  }
+  if (!make_room(sv, need, queued_keys)) return nullptr;
   auto e = std::make_unique<PlanEntry>();
   EMS_HIP(hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking));
   emsurf_geom g{(int32_t)rq.area.size(), rq.rho.data(), rq.area.data(), rq.tan.data(), rq.pitch, rq.k};
@@ -140,9 +178,10 @@ PlanEntry* resident(emsurf_server sv, Request& rq, const std::map<uint64_t, int>
     throw Err{st};
   }
   e->staging.alloc((size_t)pd.nx * pd.ny * pd.n_eq * 16);
-  e->bytes = need;
+  e->bytes = fixed;
+  e->slot_bytes = slot;
   e->last_used = now_ms();
-  sv->used += need;
+  sv->used += fixed;
   ++sv->plans_built;
   PlanEntry* raw = e.get();
   sv->plans[rq.key] = std::move(e);
@@ -166,6 +205,7 @@ void place(emsurf_server sv, Request& rq, PlanEntry* e) {
     rq.slots[r] = slot;
   }
   EMS_HIP(hipStreamSynchronize(e->stream));
+  refresh_held(sv, *e);
   e->active += 1;
   e->last_used = now_ms();
   rq.state = Request::ACTIVE;
@@ -183,18 +223,27 @@ void admit(emsurf_server sv) {
     sv->active[id] = std::move(*it);
     return sv->queue.erase(it);
   };
+  std::map<uint64_t, int> queued_keys;
+  for (auto& q : sv->queue) queued_keys[q->key] += 1;
   for (auto it = sv->queue.begin(); it != sv->queue.end();) {
     Request& rq = **it;
     auto pe = sv->plans.find(rq.key);
+    bool placed = false;
     if (pe != sv->plans.end() && free_slots(pe->second->session) >= rq.nrhs) {
-      place(sv, rq, pe->second.get());
+      PlanEntry& e = *pe->second;
+      const int fresh = std::max(0, rq.nrhs - session_free_held(e.session));
+      if (make_room(sv, (size_t)fresh * e.slot_bytes, queued_keys)) {
+        place(sv, rq, &e);
+        placed = true;
+      }
+    }
+    if (placed) {
+      if (--queued_keys[rq.key] == 0) queued_keys.erase(rq.key);
       it = take(it);
     } else {
       ++it;
     }
   }
-  std::map<uint64_t, int> queued_keys;
-  for (auto& q : sv->queue) queued_keys[q->key] += 1;
   for (auto it = sv->queue.begin(); it != sv->queue.end();) {
     Request& rq = **it;
     if (sv->plans.count(rq.key)) { ++it; continue; }
@@ -215,6 +264,7 @@ void admit(emsurf_server sv) {
     }
     if (e && free_slots(e->session) >= rq.nrhs) {
       place(sv, rq, e);
+      if (--queued_keys[rq.key] == 0) queued_keys.erase(rq.key);
       it = take(it);
       continue;
     }
@@ -380,6 +430,15 @@ size_t emsurf_server_entry_bytes(emsurf_server sv, const emsurf_plan_desc* desc)
   if (!sv || !desc) return 0;
   try {
     return entry_bytes(sv, *desc);
+  } catch (...) {
+    return 0;
+  }
+}
+
+size_t emsurf_server_slot_bytes(emsurf_server sv, const emsurf_plan_desc* desc) {
+  if (!sv || !desc) return 0;
+  try {
+    return entry_bytes(sv, *desc) ? entry_slot_bytes(sv, *desc) : 0;
   } catch (...) {
     return 0;
   }

@@ -19,9 +19,21 @@ struct SessionSlot {
   std::vector<double> cs;
 };
 
+// Device bytes of a session: the part held for its lifetime (batch staging,
+// reductions, item lists), the vectors of one slot ([b | x | r | V_0..V_m],
+// allocated when a slot is first used), and the total with every slot
+// allocated plus the apply workspace of its stream.
+size_t session_fixed_bytes(const emsurf_plan_desc& d, int max_slots, int restart);
+size_t session_slot_bytes(const emsurf_plan_desc& d, int restart);
 size_t session_bytes(const emsurf_plan_desc& d, int max_slots, int restart);
 void session_launch(emsurf_session ss);
 int session_finish(emsurf_session ss);
+// bytes of the slot buffers the session holds, and the number of free slots
+// that hold one
+size_t session_held_bytes(emsurf_session ss);
+int session_free_held(emsurf_session ss);
+// release the buffers of free slots; returns the bytes released
+size_t session_trim(emsurf_session ss);
 
 }  // namespace emsurf
 
@@ -33,7 +45,8 @@ struct emsurf_session_s {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipEvent_t ev = nullptr;
-  emsurf::DevBuf b, x, r, V, xin, wout, partial, red, coef, items;
+  emsurf::DevBuf xin, wout, partial, red, coef, items;
+  std::vector<emsurf::DevBuf> mem;   // per slot: [b | x | r | V_0 .. V_m] (N values each), or empty
   emsurf::PinnedBuf h_red, h_coef, h_items;
   int nblk = 0, ns = 0, rstride = 0, variant32 = 0;
   bool launched = false;

@@ -59,18 +59,50 @@ emsurf_session_s::~emsurf_session_s() {
 
 namespace emsurf {
 
-size_t session_bytes(const emsurf_plan_desc& d, int max_slots, int restart) {
+size_t session_fixed_bytes(const emsurf_plan_desc& d, int max_slots, int restart) {
   const size_t N = (size_t)d.nx * d.ny * d.n_eq;
-  const size_t per_slot = (size_t)(restart + 1 + 5) * N * 16;
+  const size_t staging = 2 * (size_t)max_slots * N * 16;   // gathered operands, apply outputs
   const int nblk = dot_blocks((long long)N);
   const size_t red = (size_t)max_slots * (2 * (restart + 2) + 8) * 16 * 2;
   const size_t partial = (size_t)max_slots * nblk * (restart + 2) * 16;
-  // the session's own stream gets its own apply workspace in the plan
+  const size_t coef = (size_t)max_slots * restart * 16;
+  return staging + red + partial + coef + (size_t)16 * max_slots * sizeof(VecItem);
+}
+
+size_t session_slot_bytes(const emsurf_plan_desc& d, int restart) {
+  const size_t N = (size_t)d.nx * d.ny * d.n_eq;
+  return (size_t)(restart + 4) * N * 16;
+}
+
+size_t session_bytes(const emsurf_plan_desc& d, int max_slots, int restart) {
+  // a stream without an apply workspace in the plan gets one
   const int64_t Lx = fft_length_at_least(2 * d.nx - 1);
   const int64_t Ly = fft_length_at_least(2 * d.ny - 1);
   const int64_t B = (int64_t)d.max_rhs * d.n_eq;
   const size_t ws = (size_t)(d.ny * Lx * B) * 16 + 2 * (size_t)(Lx * Ly * B) * 16 + (size_t)(B * d.nx * d.ny) * 16;
-  return per_slot * max_slots + red + partial + ws + (size_t)16 * max_slots * 64 * sizeof(VecItem);
+  return session_fixed_bytes(d, max_slots, restart) + (size_t)max_slots * session_slot_bytes(d, restart) + ws;
+}
+
+size_t session_held_bytes(emsurf_session ss) {
+  size_t b = 0;
+  for (auto& m : ss->mem) b += m.bytes;
+  return b;
+}
+
+int session_free_held(emsurf_session ss) {
+  int c = 0;
+  for (int s = 0; s < ss->S; ++s) c += ss->slot[s].ph == SessionSlot::FREE && ss->mem[s].p != nullptr;
+  return c;
+}
+
+size_t session_trim(emsurf_session ss) {
+  size_t freed = 0;
+  for (int s = 0; s < ss->S; ++s)
+    if (ss->slot[s].ph == SessionSlot::FREE && ss->mem[s].p) {
+      freed += ss->mem[s].bytes;
+      ss->mem[s].release();
+    }
+  return freed;
 }
 
 void session_init(emsurf_session ss, emsurf_plan plan, int max_slots, const emsurf_solve_opts& o, hipStream_t s,
@@ -83,10 +115,9 @@ void session_init(emsurf_session ss, emsurf_plan plan, int max_slots, const emsu
   ss->stream = s;
   ss->own_stream = own;
   const size_t vb = (size_t)ss->N * 16;
-  ss->b.alloc(vb * ss->S);
-  ss->x.alloc(vb * ss->S);
-  ss->r.alloc(vb * ss->S);
-  ss->V.alloc(vb * ss->S * (ss->m + 1));
+  // slot vectors and Krylov bases are allocated per slot at its first submit
+  ss->mem.clear();
+  ss->mem.resize(ss->S);
   ss->xin.alloc(vb * ss->S);
   ss->wout.alloc(vb * ss->S);
   ss->nblk = dot_blocks(ss->N);
@@ -104,7 +135,6 @@ void session_init(emsurf_session ss, emsurf_plan plan, int max_slots, const emsu
   // the FP32 product variant is fixed for the session's lifetime
   ss->variant32 = choose_variant(plan, std::min(ss->S, plan->d.max_rhs));
   (void)workspace(plan, s);
-  EMS_HIP(hipMemsetAsync(ss->x.p, 0, ss->x.bytes, s));
   EMS_HIP(hipStreamSynchronize(s));
 }
 
@@ -121,9 +151,11 @@ void push_items(emsurf_session ss, int list, int count) {
 }
 
 double2* vec(const DevBuf& buf, long long N, int s) { return buf.as<double2>() + (size_t)s * N; }
-double2* basis(emsurf_session ss, int s, int l) {
-  return ss->V.as<double2>() + ((size_t)s * (ss->m + 1) + l) * ss->N;
-}
+// vectors of slot s: right-hand side, iterate, residual, Krylov basis
+double2* sb(emsurf_session ss, int s) { return ss->mem[s].as<double2>(); }
+double2* sx(emsurf_session ss, int s) { return ss->mem[s].as<double2>() + ss->N; }
+double2* sr(emsurf_session ss, int s) { return ss->mem[s].as<double2>() + 2 * ss->N; }
+double2* basis(emsurf_session ss, int s, int l) { return ss->mem[s].as<double2>() + (size_t)(3 + l) * ss->N; }
 
 Cx arnoldi_type(const emsurf_solve_opts& o) { return o.prec == EMSURF_FP64 ? Cx::C128 : Cx::C64; }
 Cx resid_type(const emsurf_solve_opts& o) { return o.prec == EMSURF_FP32 ? Cx::C64 : Cx::C128; }
@@ -139,9 +171,9 @@ void batched_apply(emsurf_session ss, const std::vector<std::pair<int, int>>& gr
   for (int q = 0; q < nq; ++q) {
     const int s = group[q].first;
     const bool res = group[q].second == 0;
-    g[q] = VecItem{res ? (const void*)vec(ss->x, N, s) : (const void*)basis(ss, s, ss->slot[s].j), nullptr,
+    g[q] = VecItem{res ? (const void*)sx(ss, s) : (const void*)basis(ss, s, ss->slot[s].j), nullptr,
                    vec(ss->xin, N, q), 1.0, 0, 0};
-    sc[q] = res ? VecItem{vec(ss->wout, N, q), vec(ss->b, N, s), vec(ss->r, N, s), 1.0, 0, 0}
+    sc[q] = res ? VecItem{vec(ss->wout, N, q), sb(ss, s), sr(ss, s), 1.0, 0, 0}
                 : VecItem{vec(ss->wout, N, q), nullptr, basis(ss, s, ss->slot[s].j + 1), 1.0, 0, 0};
   }
   push_items(ss, list_g, nq);
@@ -177,7 +209,7 @@ void session_launch(emsurf_session ss) {
   if (!init.empty()) {
     VecItem* it = hitem(ss, 0);
     for (size_t i = 0; i < init.size(); ++i)
-      it[i] = VecItem{vec(ss->b, N, init[i]), nullptr, vec(ss->r, N, init[i]), 1.0, 0, 0};
+      it[i] = VecItem{sb(ss, init[i]), nullptr, sr(ss, init[i]), 1.0, 0, 0};
     push_items(ss, 0, (int)init.size());
     launch_copy_list(ditem(ss, 0), (int)init.size(), N, ss->stream);
   }
@@ -193,7 +225,7 @@ void session_launch(emsurf_session ss) {
   double2* red = ss->red.as<double2>();
   if (nn > 0) {
     VecItem* it = hitem(ss, 5);
-    for (int i = 0; i < nn; ++i) it[i] = VecItem{nullptr, nullptr, vec(ss->r, N, ss->q_norm[i]), 1.0, 0, 0};
+    for (int i = 0; i < nn; ++i) it[i] = VecItem{nullptr, nullptr, sr(ss, ss->q_norm[i]), 1.0, 0, 0};
     push_items(ss, 5, nn);
     launch_dot_list(ditem(ss, 5), nn, 1, N, ss->partial.p, ss->nblk, red, ss->rstride, 0, ss->stream);
   }
@@ -250,7 +282,7 @@ int session_finish(emsurf_session ss) {
       y[i] = acc / q.H[(size_t)i * (m + 1) + i];
     }
     axp[naxp++] = VecItem{basis(ss, s, 0), reinterpret_cast<const double2*>(ss->coef.p) + (size_t)s * m,
-                          vec(ss->x, N, s), 1.0, k, 0};
+                          sx(ss, s), 1.0, k, 0};
     q.cycles += 1;
     q.ph = SessionSlot::RESID;
   };
@@ -290,7 +322,7 @@ int session_finish(emsurf_session ss) {
     q.sn.assign(m, cd(0));
     q.g.assign(m + 1, cd(0));
     q.g[0] = beta;
-    scl[nscl++] = VecItem{vec(ss->r, N, s), nullptr, basis(ss, s, 0), 1.0 / beta, 0, 0};
+    scl[nscl++] = VecItem{sr(ss, s), nullptr, basis(ss, s, 0), 1.0 / beta, 0, 0};
   }
   // Arnoldi results
   const double2* ha = hr + (size_t)nn * ss->rstride;
@@ -401,15 +433,19 @@ emsurf_status emsurf_session_create(emsurf_plan plan, int32_t max_slots, const e
 emsurf_status emsurf_session_submit(emsurf_session ss, const void* b_dev, int64_t tag, int32_t* slot) {
   return sguard([&] {
     EMS_CHECK_ARG(ss != nullptr && b_dev != nullptr, "session and b must be non-NULL");
+    // a free slot that already holds its vectors first, else any free slot
     int s = -1;
-    for (int i = 0; i < ss->S; ++i)
-      if (ss->slot[i].ph == SessionSlot::FREE) { s = i; break; }
+    for (int i = 0; i < ss->S && s < 0; ++i)
+      if (ss->slot[i].ph == SessionSlot::FREE && ss->mem[i].p) s = i;
+    for (int i = 0; i < ss->S && s < 0; ++i)
+      if (ss->slot[i].ph == SessionSlot::FREE) s = i;
     if (s < 0) {
       set_error("no free slot");
       throw Err{EMSURF_ERR_BUSY};
     }
-    EMS_HIP(hipMemcpyAsync(vec(ss->b, ss->N, s), b_dev, (size_t)ss->N * 16, hipMemcpyDeviceToDevice, ss->stream));
-    EMS_HIP(hipMemsetAsync(vec(ss->x, ss->N, s), 0, (size_t)ss->N * 16, ss->stream));
+    if (!ss->mem[s].p) ss->mem[s].alloc((size_t)(ss->m + 4) * ss->N * 16);
+    EMS_HIP(hipMemcpyAsync(sb(ss, s), b_dev, (size_t)ss->N * 16, hipMemcpyDeviceToDevice, ss->stream));
+    EMS_HIP(hipMemsetAsync(sx(ss, s), 0, (size_t)ss->N * 16, ss->stream));
     SessionSlot q;
     q.ph = SessionSlot::INIT;
     q.tag = tag;
@@ -461,7 +497,7 @@ emsurf_status emsurf_session_collect(emsurf_session ss, int32_t slot, void* x_de
     SessionSlot& q = ss->slot[slot];
     EMS_CHECK_ARG(q.ph == SessionSlot::DONE, "slot has not finished");
     if (x_dev) {
-      EMS_HIP(hipMemcpyAsync(x_dev, vec(ss->x, ss->N, slot), (size_t)ss->N * 16, hipMemcpyDeviceToDevice, ss->stream));
+      EMS_HIP(hipMemcpyAsync(x_dev, sx(ss, slot), (size_t)ss->N * 16, hipMemcpyDeviceToDevice, ss->stream));
       EMS_HIP(hipStreamSynchronize(ss->stream));
     }
     if (info) {

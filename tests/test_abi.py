@@ -48,6 +48,19 @@ def test_host_only_calls():
     assert E.emsurf_plan_bytes(4, 4, 96, 4, 65) == 0
 
 
+def test_plan_bytes_refuses_fft_spans_beyond_32_bits():
+    # a full-width apply's pass along y spans Lx Ly max_rhs n_eq values (32-bit
+    # offsets in the FFT kernels): such plans are refused at creation
+    import paper_1911_04576_amd as E
+    if not os.path.exists(E.LIB_PATH):
+        pytest.skip("library not built")
+    assert E.emsurf_plan_bytes(128, 128, 512, 16, 64) == 0            # 256^2 x 64 x 512 = 2^31
+    assert E.emsurf_plan_bytes(128, 128, 512, 16, 63) > 0
+    assert E.emsurf_plan_bytes(512, 512, 96, 4, 32) == 0              # 1024^2 x 32 x 96 > 2^31
+    assert E.emsurf_plan_bytes(512, 512, 96, 4, 21) > 0
+    assert E.emsurf_plan_bytes(128, 128, 192, 16, 32) > 0             # the 128 x 128 serving shape
+
+
 @pytest.mark.parametrize("Lx,Ly", [(1, 1), (2, 1), (3, 1), (1, 4), (3, 3), (4, 6), (12, 8), (6, 3), (256, 256)])
 def test_spectrum_pairs_cover_every_frequency_once(Lx, Ly):
     import paper_1911_04576_amd as E

@@ -115,3 +115,61 @@ def test_fullsize_128x128_fp32_ir_solve_sampled_residual():
         say(f"  element ({iy},{ix}): oracle residual {r:.2e}")
         assert r <= 50 * c.tol
     plan.destroy()
+
+
+@pytest.mark.timeout(600)
+def test_fullsize_32x32_solves_against_oracle_gmres():
+    """The 32 x 32, n_eq 192, theta = 30 deg TE workload: FP64 GMRES to 1e-8
+    matches the oracle's GMRES (same algorithm on the direct, FFT-free FP64
+    operator) in iteration count and solution; FP32 + FP64 refinement reaches
+    1e-6 with the oracle's full operator."""
+    from oracle import krylov as K
+    from oracle import macromodel as MM
+    e, c, g, S, tm, plan = build(2)
+    say(f"full-size solves: {c.nx}x{c.ny}, n_eq {c.n_eq}, {c.nrhs} RHS, tol {c.tol}")
+    b = W.plane_wave_rhs(c, g)
+    b64 = torch.from_numpy(b).to("cuda")
+    x64 = torch.zeros_like(b64)
+    st, info64 = e.emsurf_solve(plan, e.solve_opts(e.EMSURF_FP64, tol=c.tol), 1, b64, x64)
+    xir = torch.zeros_like(b64)
+    st2, info_ir = e.emsurf_solve(plan, e.solve_opts(e.EMSURF_FP32_IR, tol=1e-6), 1, b64, xir)
+    torch.cuda.synchronize()
+    say(f"  GPU FP64 {e.emsurf_status_str(st)} {info64}; FP32+IR {e.emsurf_status_str(st2)} {info_ir}")
+    assert st == e.EMSURF_OK and st2 == e.EMSURF_OK
+    plan.destroy()
+    B = C.coupling_blocks(g.rho, g.area, g.tan, c.nx, c.ny, W.PITCH, W.K0)
+    Tf = lambda v: C.apply_T_direct(lambda dy, dx: B[dy + c.ny - 1, dx + c.nx - 1], v)
+    Af = lambda v: MM.apply_A(Tf, S, tm, v.reshape(b.shape)).ravel()
+    x_or, info_or = K.gmres(Af, b.ravel(), c.tol)
+    say(f"  oracle GMRES: {info_or.iters} iterations, true residual {info_or.rel_res_true:.2e}")
+    assert info_or.converged and info64[0]["iters"] == info_or.iters
+    d = rel(x64.cpu().numpy().ravel(), x_or)
+    say(f"  FP64 GPU solution vs oracle GMRES: {d:.2e}")
+    assert d <= 1e-10
+    xs = xir.cpu().numpy()
+    r = rel(Af(xs.ravel()), b.ravel())
+    say(f"  FP32+IR: oracle residual {r:.2e} (library reports {info_ir[0]['rel_res_true']:.2e})")
+    assert r <= 1e-6 and info_ir[0]["converged"]
+
+
+def test_fullsize_64x64_fp64_gmres_reference_sampled():
+    """The 64 x 64, n_eq 288, 16-RHS workload solved by FP64 GMRES (the
+    reference of its reduced-precision products): converged per right-hand
+    side, with the oracle's residual at sampled elements within the bar."""
+    e, c, g, S, tm, plan = build(3)
+    b = W.plane_wave_rhs(c, g)
+    b64 = torch.from_numpy(b).to("cuda")
+    x = torch.zeros_like(b64)
+    st, info = e.emsurf_solve(plan, e.solve_opts(e.EMSURF_FP64, tol=c.tol), c.nrhs, b64, x)
+    torch.cuda.synchronize()
+    say(f"  64x64 FP64 GMRES: {e.emsurf_status_str(st)}, iterations {[i['iters'] for i in info]}")
+    assert st == e.EMSURF_OK and all(i["converged"] and i["rel_res_true"] <= c.tol for i in info)
+    xs = x.cpu().numpy()
+    elems = [(0, 63), (40, 17)]
+    tx = sampled_rows(c, g, xs, elems)
+    for i, (iy, ix) in enumerate(elems):
+        Ax = xs[:, iy, ix] - tx[i] @ S[tm[iy, ix]].T
+        r = rel(Ax, b[:, iy, ix])
+        say(f"  element ({iy},{ix}): oracle residual {r:.2e}")
+        assert r <= 50 * c.tol
+    plan.destroy()

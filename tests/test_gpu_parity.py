@@ -59,6 +59,8 @@ def random_plan(nx, ny, n, nrhs, seed, n_types=3, zero_self=True, store=3):
     (3, 4, 257, 1), (8, 8, 40, 9), (5, 5, 33, 17),
     # padded lengths with a factor 3: 24, 48, 96, 192, 384, 768
     (10, 3, 5, 1), (20, 12, 6, 2), (33, 1, 4, 1), (65, 2, 3, 1), (130, 2, 2, 1), (300, 1, 2, 1), (24, 24, 4, 3),
+    # padded lengths 512 and 1024 along either axis
+    (200, 1, 3, 1), (3, 200, 2, 2), (400, 1, 2, 1), (2, 450, 2, 1), (257, 3, 2, 1),
 ])
 def test_apply_T_fp64_random_blocks(nx, ny, n, nrhs):
     say(f"apply_T fp64 random {nx}x{ny} n={n} nrhs={nrhs}")
@@ -94,6 +96,8 @@ def test_apply_T_nonzero_self_block():
     # workgroups: y passes at L = 64 (72 columns) and L = 256 (80, ragged),
     # x passes at L = 128 (70, ragged) and L = 256 (64)
     (32, 28, 24, 3), (50, 3, 70, 1), (100, 1, 64, 1), (2, 100, 40, 2),
+    # padded lengths 512 and 1024
+    (200, 2, 4, 1), (1, 400, 3, 2),
 ])
 def test_apply_T_fp32_error_reported(nx, ny, n, nrhs):
     e = E()

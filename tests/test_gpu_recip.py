@@ -72,6 +72,8 @@ def apply(e, plan, prec, x):
     (9, 7, 10, 1), (17, 5, 12, 2), (2, 33, 8, 1), (6, 6, 97, 2), (4, 3, 130, 1), (3, 3, 193, 4),
     (3, 2, 200, 2), (2, 2, 385, 1), (2, 2, 512, 1), (8, 8, 40, 9), (5, 5, 33, 17), (10, 3, 5, 5),
     (20, 12, 6, 2), (24, 24, 4, 3), (65, 2, 3, 1),
+    # padded lengths 512 and 1024 (pairs k, -k across the long axis)
+    (200, 1, 3, 1), (1, 400, 2, 2),
 ])
 def test_recip_apply_T_fp64_random_blocks(nx, ny, n, nrhs):
     say(f"reciprocal apply_T fp64 {nx}x{ny} n={n} nrhs={nrhs}")

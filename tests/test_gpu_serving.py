@@ -67,13 +67,16 @@ def run_session(e, sess, plan_shape, schedule, max_steps=500):
     return out
 
 
+@pytest.mark.parametrize("recip", [0, 1])
 @pytest.mark.parametrize("prec", [0, 2])
-def test_session_alone_equals_mix(prec):
+def test_session_alone_equals_mix(prec, recip):
+    # recip = 1: the paired block product on the reciprocal store, the store
+    # the serving benchmark uses (its column sums have a fixed rounding order)
     e = E()
     nx, ny, npch = 5, 4, 24
     g, S, tm = surface(nx, ny, npch, 3, seed=1)
     geom = e.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)
-    plan = e.emsurf_plan_create_green(nx, ny, 3, 6, geom, S, tm)
+    plan = e.emsurf_plan_create_green(nx, ny, 3, 6, geom, S, tm, recip=recip)
     bs = rhs_set(nx, ny, npch, 5, seed=2)
     bs[3] *= 1e3
     opts = e.solve_opts(prec, tol=1e-8 if prec == 0 else 1e-6, restart=4)
@@ -84,7 +87,7 @@ def test_session_alone_equals_mix(prec):
     mix = run_session(e, sess, shape, {0: [(1, bs[1]), (2, bs[2])], 2: [(0, bs[0]), (3, bs[3])], 3: [(4, bs[4])]})
     xa, ia = alone[0]
     xm, im = mix[0]
-    say(f"prec {prec}: alone iters {ia['iters']} cycles {ia['outer_iters']}; mix iters {im['iters']}")
+    say(f"prec {prec} recip {recip}: alone iters {ia['iters']} cycles {ia['outer_iters']}; mix iters {im['iters']}")
     assert ia["iters"] == im["iters"] and ia["converged"]
     assert np.array_equal(xa, xm)
     A = dense_A(g, S, tm, nx, ny)
@@ -149,12 +152,17 @@ def test_server_many_surfaces_with_eviction():
     for i, (nx, ny, npch, nt) in enumerate(shapes):
         g, S, tm = surface(nx, ny, npch, nt, seed=20 + i)
         surf.append((nx, ny, npch, nt, g, S, tm, e.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)))
-    # the largest surface cannot share the budget with any other: forces evictions
+    # the largest surface with all 4 slots busy cannot share the budget with
+    # any other resident surface: forces evictions
     probe = e.emsurf_server_create(1 << 40, 4, opts)
-    needs = [e.emsurf_server_entry_bytes(probe, nx, ny, 4 * npch, nt) for nx, ny, npch, nt, *_ in surf]
+    fixed = [e.emsurf_server_entry_bytes(probe, nx, ny, 4 * npch, nt) for nx, ny, npch, nt, *_ in surf]
+    slot = [e.emsurf_server_slot_bytes(probe, nx, ny, 4 * npch, nt) for nx, ny, npch, nt, *_ in surf]
     probe.destroy()
-    assert min(needs) > 0
-    srv = e.emsurf_server_create(max(needs) + min(needs) - 1, 4, opts)
+    assert min(fixed) > 0 and min(slot) > 0
+    # slots hold (restart + 4) unknown vectors each
+    assert slot[0] == (8 + 4) * 4 * 4 * 96 * 16
+    needs = [f + 4 * s for f, s in zip(fixed, slot)]
+    srv = e.emsurf_server_create(max(needs) + min(fixed) - 1, 4, opts)
     reqs = {}
     rng = np.random.default_rng(0)
     for r in range(9):
@@ -190,3 +198,83 @@ def test_server_many_surfaces_with_eviction():
             res = np.linalg.norm(dense[k] @ x[r] - b[r].ravel()) / np.linalg.norm(b[r])
             assert infos[r]["converged"] and res <= 1e-6, (rid, r, res)
     srv.destroy()
+
+
+@pytest.mark.parametrize("n_rhs_mix", [3, 9])
+def test_session_reciprocal_wide_batches_alone_equals_mix(n_rhs_mix):
+    """A right-hand side alone (a 4-wide pass of the paired product) and in a
+    batch of 9 (8-wide passes over two launches), on a 192-row block (12 row
+    tiles: every wavefront adds column sums), FP32 inner with FP64 refinement."""
+    e = E()
+    nx, ny, npch = 4, 3, 48
+    g, S, tm = surface(nx, ny, npch, 2, seed=8)
+    geom = e.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)
+    plan = e.emsurf_plan_create_green(nx, ny, 2, 10, geom, S, tm, recip=1)
+    bs = rhs_set(nx, ny, npch, n_rhs_mix, seed=9)
+    opts = e.solve_opts(2, tol=1e-7, restart=5)
+    shape = (ny, nx, g.n_eq)
+    sess = e.emsurf_session_create(plan, 10, opts)
+    alone = run_session(e, sess, shape, {0: [(0, bs[0])]})
+    mix = run_session(e, sess, shape, {0: [(t, bs[t]) for t in range(1, n_rhs_mix)], 1: [(0, bs[0])]})
+    assert np.array_equal(alone[0][0], mix[0][0]) and alone[0][1]["iters"] == mix[0][1]["iters"]
+    A = dense_A(g, S, tm, nx, ny)
+    for tag in range(n_rhs_mix):
+        x, info = mix[tag]
+        res = np.linalg.norm(A @ x.ravel() - bs[tag].ravel()) / np.linalg.norm(bs[tag])
+        assert info["converged"] and res <= 1e-7, (tag, res)
+    sess.destroy()
+    plan.destroy()
+
+
+def test_server_reciprocal_plans_match_sessions_alone():
+    """Server on reciprocal plans (the bench's serving configuration): each
+    right-hand side's result is bitwise the one it gets solved alone in a
+    session of the same plan shape, slots and options, and meets the tolerance
+    with the oracle's FP64 operator."""
+    e = E()
+    opts = e.solve_opts(2, tol=1e-6, restart=8)
+    slots = 4
+    shapes = [(4, 4, 24, 2), (6, 3, 48, 3)]
+    surf = []
+    for i, (nx, ny, npch, nt) in enumerate(shapes):
+        g, S, tm = surface(nx, ny, npch, nt, seed=40 + i)
+        surf.append((nx, ny, npch, nt, g, S, tm, e.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)))
+    srv = e.emsurf_server_create(1 << 36, slots, opts)
+    reqs = {}
+    rng = np.random.default_rng(3)
+    for r in range(6):
+        k = r % 2
+        nx, ny, npch, nt, g, S, tm, geom = surf[k]
+        nrhs = int(rng.integers(1, 4))
+        b = rhs_set(nx, ny, npch, nrhs, seed=300 + r)
+        rid = e.emsurf_server_submit(srv, k, nx, ny, nt, geom, S, tm, b, recip=1)
+        reqs[rid] = (k, b)
+    got = {}
+    for _ in range(2000):
+        e.emsurf_server_step(srv)
+        while True:
+            c = e.emsurf_server_next_completed(srv)
+            if c is None:
+                break
+            rid, nrhs, nu = c
+            got[rid] = e.emsurf_server_fetch(srv, rid, nrhs, nu)
+        if len(got) == len(reqs):
+            break
+    srv.destroy()
+    assert len(got) == len(reqs)
+    for k, (nx, ny, npch, nt, g, S, tm, geom) in enumerate(surf):
+        plan = e.emsurf_plan_create_green(nx, ny, nt, slots, geom, S, tm, recip=1)
+        sess = e.emsurf_session_create(plan, slots, opts)
+        A = dense_A(g, S, tm, nx, ny)
+        for rid, (kk, b) in reqs.items():
+            if kk != k:
+                continue
+            x, infos, _ = got[rid]
+            for r in range(b.shape[0]):
+                xa, ia = run_session(e, sess, b.shape[1:], {0: [(r, b[r])]})[r]
+                assert np.array_equal(xa.ravel(), x[r]), (rid, r)
+                assert ia["iters"] == infos[r]["iters"]
+                res = np.linalg.norm(A @ x[r] - b[r].ravel()) / np.linalg.norm(b[r])
+                assert infos[r]["converged"] and res <= 1e-6, (rid, r, res)
+        sess.destroy()
+        plan.destroy()

@@ -183,3 +183,21 @@ def test_givens_zeroes_second_component():
         assert abs(bot) <= 1e-15 * max(1.0, abs(top))
         assert abs(abs(top) - np.hypot(abs(a), abs(b))) <= 1e-15 * abs(top)
         assert abs(c * c + abs(s) ** 2 - 1) <= 1e-15
+
+
+def test_gmres_multi_columns_against_lu():
+    # independent instances per right-hand side: each column of the [nrhs][...]
+    # input is solved to the dense LU solution, with the iteration count the
+    # one-column solve reports, and the output keeps the input's shape
+    B, S, tm, n = _lattice(2, 2, seed=11)
+    _, Afun = _ops(B, S, tm)
+    A = np.eye(4 * n) - MM.dense_S(S, tm) @ C.dense_T(B, 2, 2)
+    b = W.random_vectors(3, 2, 2, n, seed=12)
+    b[1] *= 1e-3                                    # scale must not matter per column
+    xs, infos = K.gmres_multi(Afun, b, 1e-12)
+    assert xs.shape == b.shape and len(infos) == 3
+    for r in range(3):
+        x_lu = K.solve_dense(A, b[r].ravel())
+        assert np.linalg.norm(xs[r].ravel() - x_lu) <= 1e-11 * np.linalg.norm(x_lu)
+        x1, i1 = K.gmres(lambda v: Afun(v.reshape((1,) + b.shape[1:])).ravel(), b[r].ravel(), 1e-12)
+        assert infos[r].iters == i1.iters and np.array_equal(x1, xs[r].ravel())
