@@ -104,13 +104,16 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
   constexpr int TILE_BYTES = 2 * PAIR_TILE * PAIR_TILE * (int)sizeof(T);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nt = pair_tiles(n), np = nt * PAIR_TILE;
-  T* xs = reinterpret_cast<T*>(smem_raw);  // [np][NRW][2]: xh[k]; row sums at the end
-  T* xt = xs + np * NRW * 2;               // [np][NRW][2]: W xh[-k]
-  T* zs = xt + np * NRW * 2;               // [np][2 NRW]: column sums of wavefronts 0, 1
-  // column sums of wavefronts 2, 3: over xt once the B operands it holds are
-  // in registers (B2R), else a region of their own
-  T* zs2 = B2R ? xt : zs + np * 2 * NRW;
-  T* tiles = zs + np * 2 * NRW * (B2R ? 1 : 2);   // [4 waves][stages][512]
+  // LDS: one spectral input (xh[k] when the transposed product's B operands
+  // stay in registers, B2R; else W xh[-k], whose operands are rebuilt per
+  // tile while xh[k] is read from memory a v tile ahead), the column sums of
+  // wavefronts 0, 1 and of wavefronts 2, 3, the transposed staging.  The
+  // spectral input's region stages the row sums at the end.
+  T* xs = reinterpret_cast<T*>(smem_raw);        // [np][NRW][2]: xh[k] (B2R)
+  T* xt = xs;                                    // [np][NRW][2]: W xh[-k] (!B2R)
+  T* zs = xs + np * NRW * 2;                     // [np][2 NRW]
+  T* zs2 = zs + np * 2 * NRW;                    // [np][2 NRW]
+  T* tiles = zs2 + np * 2 * NRW;                 // [4 waves][stages][512]
   const long long slot = blockIdx.x;
   const int2 pr = pairs[slot];
   const long long k = pr.x, kb = pr.y;
@@ -144,44 +147,51 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
   }
   const V2* x0 = xh + k * (long long)nrhs * n + (long long)r0 * n;
   const V2* x1 = xh + kb * (long long)nrhs * n + (long long)r0 * n;
-  for (int e = threadIdx.x; e < np * NRW; e += PNT) {
-    const int r = e / np, v = e - r * np;
-    V2 a{0, 0}, b{0, 0};
-    if (r < nr && v < n) {
-      a = x0[(long long)r * n + v];
-      const V2 c = x1[(long long)r * n + v];
-      b = V2{w[v] * c.x, w[v] * c.y};
-    }
-    xs[(v * NRW + r) * 2] = a.x;
-    xs[(v * NRW + r) * 2 + 1] = a.y;
-    xt[(v * NRW + r) * 2] = b.x;
-    xt[(v * NRW + r) * 2 + 1] = b.y;
-  }
-  for (int e = threadIdx.x; e < np * 2 * NRW; e += PNT) zs[e] = T(0);
-  if constexpr (!B2R)
-    for (int e = threadIdx.x; e < np * 2 * NRW; e += PNT) zs2[e] = T(0);
-  __syncthreads();
   // lane roles: k-slot kk = l / 16 -> (pair offset off, part); column jj = l % 16
   const int kk = l >> 4, jj = l & 15, off = kk >> 1, part = kk & 1, a16 = l & 15;
   const bool jre = jj < NRW, jok = jj < 2 * NRW;
   const int rj = jre ? jj : (jok ? jj - NRW : 0);
-  auto bval = [&](const T* x, int idx) {
-    const T xr = x[(idx * NRW + rj) * 2], xi = x[(idx * NRW + rj) * 2 + 1];
+  // embedding column of a complex input value (xr, xi) for this lane
+  auto embed = [&](T xr, T xi) {
     const T val = part == 0 ? (jre ? xr : xi) : (jre ? -xi : xr);
     return jok ? val : T(0);
   };
+  auto bval = [&](const T* x, int idx) { return embed(x[(idx * NRW + rj) * 2], x[(idx * NRW + rj) * 2 + 1]); };
+  // B operands of the transposed product held in registers (B2R): W xh[-k]
+  // read straight from memory
   constexpr int NB2 = B2R ? TPW : 1;
   T b2[NB2][8];
 #pragma unroll
   for (int ta = 0; ta < NB2; ++ta)
 #pragma unroll
-    for (int s = 0; s < 8; ++s) b2[ta][s] = B2R && ta < ntw ? bval(xt, (wv + 4 * ta) * PAIR_TILE + 2 * s + off) : T(0);
-  if constexpr (B2R) {
-    // xt becomes the second column-sum buffer
-    __syncthreads();
-    for (int e = threadIdx.x; e < np * 2 * NRW; e += PNT) zs2[e] = T(0);
-    __syncthreads();
+    for (int s = 0; s < 8; ++s) {
+      const int v = (wv + 4 * ta) * PAIR_TILE + 2 * s + off;
+      T val = T(0);
+      if (B2R && ta < ntw && jok && rj < nr && v < n) {
+        const V2 c = x1[(long long)rj * n + v];
+        val = embed(w[v] * c.x, w[v] * c.y);
+      }
+      b2[ta][s] = val;
+    }
+  for (int e = threadIdx.x; e < np * NRW; e += PNT) {
+    const int r = e / np, v = e - r * np;
+    V2 a{0, 0};
+    if constexpr (B2R) {
+      if (r < nr && v < n) a = x0[(long long)r * n + v];
+    } else {
+      if (r < nr && v < n) {
+        const V2 c = x1[(long long)r * n + v];
+        a = V2{w[v] * c.x, w[v] * c.y};
+      }
+    }
+    xs[(v * NRW + r) * 2] = a.x;
+    xs[(v * NRW + r) * 2 + 1] = a.y;
   }
+  for (int e = threadIdx.x; e < np * 2 * NRW; e += PNT) {
+    zs[e] = T(0);
+    zs2[e] = T(0);
+  }
+  __syncthreads();
   Acc acc[TPW];
 #pragma unroll
   for (int ta = 0; ta < TPW; ++ta) acc[ta] = Acc{};
@@ -194,16 +204,29 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
   T* tw = tiles + wv * NSTG * 512;
   int stage = 0;
   // B operands of the first product for v tile q, built one v tile ahead
+  // (from LDS, or from memory when LDS holds W xh[-k])
+  auto b1val = [&](int v) {
+    if constexpr (B2R) {
+      return bval(xs, v);
+    } else {
+      T val = T(0);
+      if (jok && rj < nr && v < n) {
+        const V2 c = x0[(long long)rj * n + v];
+        val = embed(c.x, c.y);
+      }
+      return val;
+    }
+  };
   T b1n[8];
 #pragma unroll
-  for (int s = 0; s < 8; ++s) b1n[s] = bval(xs, 2 * s + off);
+  for (int s = 0; s < 8; ++s) b1n[s] = b1val(2 * s + off);
   for (int q = 0; q < nt; ++q) {
     T b1[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) b1[s] = b1n[s];
     const int qn = q + 1 < nt ? q + 1 : q;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) b1n[s] = bval(xs, qn * PAIR_TILE + 2 * s + off);
+    for (int s = 0; s < 8; ++s) b1n[s] = b1val(qn * PAIR_TILE + 2 * s + off);
     Acc zq{};
 #pragma unroll
     for (int ta = 0; ta < TPW; ++ta) {
@@ -248,10 +271,10 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
         if (jok) atomicAdd(&zd[(q * PAIR_TILE + M::row(l, e)) * 2 * NRW + jj], zq[e]);
     }
   }
-  // outputs: the row sums are staged in LDS over the spectral columns of
-  // xh[k] (no longer read once every wavefront is past its loop), in the
-  // layout of the column sums, and both products leave as coalesced
-  // non-temporal stores of 16 bytes per lane
+  // outputs: the row sums are staged in LDS over the spectral input (no
+  // longer read once every wavefront is past its loop), in the layout of the
+  // column sums, and both products leave as coalesced non-temporal stores of
+  // 16 bytes per lane
   __syncthreads();
   T* ys = xs;  // [np][2 NRW]: row sums (yh[k])
 #pragma unroll
@@ -311,8 +334,7 @@ template <typename T> constexpr bool pair_b2r(int tpw) { return sizeof(T) == 4 |
 template <typename T>
 size_t pair_lds_bytes(int n, int nrw) {
   const int np = pair_tiles(n) * PAIR_TILE;
-  const bool b2r = pair_b2r<T>((pair_tiles(n) + 3) / 4);
-  return (size_t)(np * nrw * 2 * (b2r ? 3 : 4) + 4 * pair_stages<T>() * 512) * sizeof(T);
+  return (size_t)(np * nrw * 2 * 3 + 4 * pair_stages<T>() * 512) * sizeof(T);
 }
 
 template <typename T, int TPW, int NRW>

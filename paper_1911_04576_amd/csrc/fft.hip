@@ -337,6 +337,14 @@ std::map<std::pair<int, int>, DevBuf*> g_tw;
 
 }  // namespace
 
+const void* twiddle_lookup(int L, Cx t) {
+  int dev = 0;
+  EMS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_tw_mu);
+  auto it = g_tw.find({L, (t == Cx::C128 ? 1 : 0) + 2 * dev});
+  return it == g_tw.end() ? nullptr : it->second->p;
+}
+
 const void* twiddle_table(int L, Cx t) {
   int dev = 0;
   EMS_HIP(hipGetDevice(&dev));

@@ -380,6 +380,22 @@ int choose_variant(emsurf_plan p, int nrhs);
 // be C64) with one or three matrix-core products per entry.
 void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* x, void* y, hipStream_t s,
                    int variant = -1, int split = 0);
+// The same apply on caller-supplied intermediates: W (half-transformed, Ny Lx
+// nrhs n_eq values), X and Y (spectra, Lx Ly nrhs n_eq values each) in the
+// compute type, and the twiddle tables of Lx and Ly.  timed: record the
+// plan's phase events when kernel timing is on.
+struct ApplyBufs {
+  void* W;
+  void* X;
+  void* Y;
+  const void* twx;
+  const void* twy;
+};
+void apply_T_bufs(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* x, void* y, const ApplyBufs& b,
+                  hipStream_t s, int variant, int split, bool timed);
+// values (complex, compute type) of W and of each of X, Y for nrhs right-hand sides
+inline int64_t apply_W_values(emsurf_plan p, int nrhs);
+inline int64_t apply_X_values(emsurf_plan p, int nrhs);
 // apply_A with explicit types: x (tx) -> y (ty) = x - S T x, arithmetic in tc.
 void apply_A_typed(emsurf_plan p, Cx tx, Cx tc, Cx ty, int nrhs, const void* x, void* y, hipStream_t s,
                    int variant = -1, int split = 0);
@@ -390,6 +406,10 @@ struct ApplyPrec {
   int split;
 };
 ApplyPrec apply_prec(emsurf_prec prec);
+inline int64_t apply_W_values(emsurf_plan p, int nrhs) { return (int64_t)p->d.ny * p->Lx * nrhs * p->d.n_eq; }
+inline int64_t apply_X_values(emsurf_plan p, int nrhs) { return p->P * nrhs * p->d.n_eq; }
+// twiddle table if it exists already (no allocation), else NULL
+const void* twiddle_lookup(int L, Cx t);
 inline size_t cx_bytes(Cx t) { return t == Cx::C128 ? 16 : 8; }
 // kernel columns (complex entries) of one frequency's Fourier-domain record:
 // n_eq^2 for dense blocks, 2 (n_eq/2)^2 for the L and K operators

@@ -128,8 +128,6 @@ Workspace& workspace(emsurf_plan p, hipStream_t s) {
   return *raw;
 }
 
-namespace {
-
 void timer_begin(emsurf_plan p, int phase, hipStream_t s, hipEvent_t* end_out) {
   *end_out = nullptr;
   if (!p->timer.enabled) return;
@@ -149,10 +147,15 @@ void timer_end(hipEvent_t e, hipStream_t s) {
   if (e) EMS_HIP(hipEventRecord(e, s));
 }
 
-}  // namespace
-
 void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* x, void* y, hipStream_t s,
                    int variant, int split) {
+  Workspace& w = workspace(p, s);
+  const ApplyBufs b{w.W.p, w.X.p, w.Y.p, twiddle_table(p->Lx, tc), twiddle_table(p->Ly, tc)};
+  apply_T_bufs(p, tin, tc, tout, nrhs, x, y, b, s, variant, split, true);
+}
+
+void apply_T_bufs(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* x, void* y, const ApplyBufs& bufs,
+                  hipStream_t s, int variant, int split, bool timed) {
   EMS_CHECK_ARG(split == 0 || (tc == Cx::C64 && (split == 1 || split == 3)), "internal: bad split-BF16 request");
   const void* That = split ? p->that16.p : (tc == Cx::C128) ? p->that64.p : p->that32.p;
   if (!That) {
@@ -160,13 +163,20 @@ void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* 
               : tc == Cx::C128 ? "plan has no FP64 Fourier-domain store" : "plan has no FP32 Fourier-domain store");
     throw Err{EMSURF_ERR_UNSUPPORTED};
   }
-  Workspace& w = workspace(p, s);
+  struct Bufs {
+    void *W, *X, *Y;
+  } w{bufs.W, bufs.X, bufs.Y};
   const int n = p->d.n_eq, Nx = p->d.nx, Ny = p->d.ny, Lx = p->Lx, Ly = p->Ly;
   const int64_t M = p->M;
   const int64_t B = (int64_t)nrhs * n;
-  const void* twx = twiddle_table(Lx, tc);
-  const void* twy = twiddle_table(Ly, tc);
+  const void* twx = bufs.twx;
+  const void* twy = bufs.twy;
   hipEvent_t e;
+  // phase events only on timed applies
+  auto timer_begin = [&](emsurf_plan pp, int phase, hipStream_t ss, hipEvent_t* end_out) {
+    *end_out = nullptr;
+    if (timed) ::emsurf::timer_begin(pp, phase, ss, end_out);
+  };
 
   // forward along x: lines (r, iy); x[r][iy][ix][u] -> W[iy][kx][r][u]
   FftPass fx;
@@ -176,7 +186,7 @@ void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* 
   fx.out_s1 = n; fx.out_s0 = (int64_t)Lx * B; fx.out_pt = B;
   fx.sign = -1;
   timer_begin(p, 0, s, &e);
-  launch_fft_pass(fx, tin, tc, tc, x, w.W.p, twx, s);
+  launch_fft_pass(fx, tin, tc, tc, x, w.W, twx, s);
   timer_end(e, s);
 
   // forward along y: lines kx; W[iy][kx][b] -> X[ky][kx][b]
@@ -187,7 +197,7 @@ void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* 
   fy.out_s0 = B; fy.out_pt = (int64_t)Lx * B;
   fy.sign = -1;
   timer_begin(p, 1, s, &e);
-  launch_fft_pass(fy, tc, tc, tc, w.W.p, w.X.p, twy, s);
+  launch_fft_pass(fy, tc, tc, tc, w.W, w.X, twy, s);
   timer_end(e, s);
 
   // Fourier-domain block products
@@ -195,25 +205,25 @@ void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* 
   const int v = tc == Cx::C64 && !p->d.recip && !split ? (variant >= 0 ? variant : choose_variant(p, nrhs))
                                                        : BP_GEMV;
   if (split)
-    launch_block_bf16(split, That, w.X.p, w.Y.p, n, nrhs, p->P, s);
+    launch_block_bf16(split, That, w.X, w.Y, n, nrhs, p->P, s);
   else if (p->d.recip && p->d.form == EMSURF_T_LK)
     launch_block_product_pair_lk(tc, That, p->pairs.p, tc == Cx::C128 ? p->w64.p : p->w32.p,
-                                 tc == Cx::C128 ? p->winv64.p : p->winv32.p, w.X.p, w.Y.p, n / 2, nrhs, p->Ps,
+                                 tc == Cx::C128 ? p->winv64.p : p->winv32.p, w.X, w.Y, n / 2, nrhs, p->Ps,
                                  p->d.coef, s);
   else if (p->d.recip)
     launch_block_product_pair(tc, That, p->pairs.p, tc == Cx::C128 ? p->w64.p : p->w32.p,
-                              tc == Cx::C128 ? p->winv64.p : p->winv32.p, w.X.p, w.Y.p, n, nrhs, p->Ps, s);
+                              tc == Cx::C128 ? p->winv64.p : p->winv32.p, w.X, w.Y, n, nrhs, p->Ps, s);
   else if (p->d.form == EMSURF_T_LK)
-    launch_block_product_lk(tc, v, That, w.X.p, w.Y.p, n / 2, nrhs, p->P, p->d.coef, s);
+    launch_block_product_lk(tc, v, That, w.X, w.Y, n / 2, nrhs, p->P, p->d.coef, s);
   else
-    launch_block_product_variant(tc, v, That, w.X.p, w.Y.p, n, nrhs, p->P, s);
+    launch_block_product_variant(tc, v, That, w.X, w.Y, n, nrhs, p->P, s);
   timer_end(e, s);
 
   // inverse along y, keep rows iy < Ny
   FftPass iy = fy;
   iy.n_in = Ly; iy.n_out = Ny; iy.sign = +1;
   timer_begin(p, 3, s, &e);
-  launch_fft_pass(iy, tc, tc, tc, w.Y.p, w.W.p, twy, s);
+  launch_fft_pass(iy, tc, tc, tc, w.Y, w.W, twy, s);
   timer_end(e, s);
 
   // inverse along x, keep ix < Nx, scale 1/(Lx Ly)
@@ -225,7 +235,7 @@ void apply_T_typed(emsurf_plan p, Cx tin, Cx tc, Cx tout, int nrhs, const void* 
   ix.sign = +1;
   ix.scale = 1.0 / ((double)Lx * (double)Ly);
   timer_begin(p, 4, s, &e);
-  launch_fft_pass(ix, tc, tc, tout, w.W.p, y, twx, s);
+  launch_fft_pass(ix, tc, tc, tout, w.W, y, twx, s);
   timer_end(e, s);
 }
 
