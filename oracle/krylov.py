@@ -12,7 +12,10 @@ not state its variant.  The reading used here (and by the GPU solver):
   then confirm with the true residual ||b - A x|| / ||b||; if it is not yet
   below tol, restart from that x;
 * lucky breakdown when h_{j+1,j} <= 1e-14 * ||A v_j||;
-* x0 = 0 unless given; each right-hand side is an independent solve.
+* x0 = 0 unless given; each right-hand side is an independent solve;
+* optional right preconditioning (Sec. IV-A, eq. (final_precond)): the
+  Arnoldi process runs on A M^-1, the cycle ends with x += M^-1 (V y), and
+  every residual is the unpreconditioned b - A x.
 
 Parity: pinned by dense LU (library zgesv), by scipy's GMRES iteration counts,
 by finite termination on tiny systems and by the closed-form solves in
@@ -45,8 +48,9 @@ def givens(a: complex, b: complex):
 
 
 def gmres(apply_A, b: np.ndarray, tol: float, restart: int = 30, max_iter: int = 500,
-          x0: np.ndarray | None = None, breakdown: float = 1e-14):
-    """Solve A x = b for one right-hand side (flat complex vector)."""
+          x0: np.ndarray | None = None, breakdown: float = 1e-14, M_inv=None):
+    """Solve A x = b for one right-hand side (flat complex vector); M_inv, if
+    given, is the right preconditioner's solve v -> M^-1 v."""
     b = np.asarray(b, dtype=np.complex128).ravel()
     bnorm = np.linalg.norm(b)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.complex128).ravel()
@@ -72,7 +76,7 @@ def gmres(apply_A, b: np.ndarray, tol: float, restart: int = 30, max_iter: int =
         V[0] = r / beta
         j_end = None
         for j in range(m):
-            w = apply_A(V[j])
+            w = apply_A(V[j] if M_inv is None else M_inv(V[j]))
             total += 1
             wnorm0 = np.linalg.norm(w)
             h = np.zeros(j + 1, dtype=np.complex128)
@@ -101,7 +105,7 @@ def gmres(apply_A, b: np.ndarray, tol: float, restart: int = 30, max_iter: int =
             V[j + 1] = w / hn
         k = j_end + 1
         y = _back_substitute(H[:k, :k], g[:k])
-        x = x + y @ V[:k]
+        x = x + (y @ V[:k] if M_inv is None else M_inv(y @ V[:k]))
         restarts += 1
 
 
