@@ -291,6 +291,20 @@ emsurf_status emsurf_apply_S(emsurf_plan plan, emsurf_prec prec, int32_t nrhs, c
 emsurf_status emsurf_apply_A(emsurf_plan plan, emsurf_prec prec, int32_t nrhs, const void* x_dev,
                              void* y_dev, void* stream);
 
+/* y = T x exactly as emsurf_apply_T (same kernels, same results), for callers
+ * that cannot allocate device memory: code under HIP-graph capture, serving
+ * loops, harnesses that forbid hipMalloc.  The call allocates nothing; its
+ * intermediates (Ny Lx + 2 Lx Ly values of nrhs n_eq complex numbers in the
+ * precision's type, each part rounded up to 256 bytes) live in one static
+ * device workspace of emsurf_apply_T_noalloc_limit() bytes (64 MiB) per GPU,
+ * held until the process ends.  Larger requests return EMSURF_ERR_ARG.  Every
+ * call on one GPU shares that workspace: calls that overlap on a GPU race
+ * (serialise them on one stream).  Arguments, layouts and the other errors as
+ * for emsurf_apply_T; the plan's own workspaces are not touched. */
+emsurf_status emsurf_apply_T_noalloc(emsurf_plan plan, emsurf_prec prec, int32_t nrhs, const void* x_dev,
+                                     void* y_dev, void* stream);
+size_t emsurf_apply_T_noalloc_limit(void);
+
 /* Solve A x = b for nrhs independent right-hand sides with restarted GMRES
  * (Sec. IV-A).  b_dev, x_dev: c128 [nrhs][ny][nx][n_eq] device.  With use_x0
  * the solve starts from x_dev's content.  info_host: nrhs entries (may be

@@ -123,6 +123,8 @@ _SIGS = {
     "emsurf_apply_T": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
     "emsurf_apply_S": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
     "emsurf_apply_A": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
+    "emsurf_apply_T_noalloc": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
+    "emsurf_apply_T_noalloc_limit": (ctypes.c_size_t, []),
     "emsurf_solve": (ctypes.c_int, [_P, ctypes.POINTER(emsurf_solve_opts), ctypes.c_int32, _P, _P,
                                     ctypes.POINTER(emsurf_solve_info), _P]),
     "emsurf_plan_query": (ctypes.c_int, [_P, ctypes.POINTER(emsurf_plan_stats)]),
@@ -351,6 +353,14 @@ def emsurf_far_field(geom: Geometry, nx, ny, nrhs, Lu, Lv, x_dev, E_dev, stream=
 
 def emsurf_apply_T(plan: Plan, prec, nrhs, x_dev, y_dev, stream=None):
     _check(lib().emsurf_apply_T(plan.h, int(prec), int(nrhs), _dptr(x_dev), _dptr(y_dev), _stream(stream)))
+
+
+def emsurf_apply_T_noalloc(plan: Plan, prec, nrhs, x_dev, y_dev, stream=None):
+    _check(lib().emsurf_apply_T_noalloc(plan.h, int(prec), int(nrhs), _dptr(x_dev), _dptr(y_dev), _stream(stream)))
+
+
+def emsurf_apply_T_noalloc_limit() -> int:
+    return int(lib().emsurf_apply_T_noalloc_limit())
 
 
 def emsurf_apply_S(plan: Plan, prec, nrhs, x_dev, y_dev, stream=None):
