@@ -32,6 +32,9 @@
 // LDS float addition gives the same bits in either order (0 + a = a, and
 // a + b = b + a), and the two buffers are added in a fixed order at the end,
 // so every output has one rounding sequence whatever the wavefront timing.
+// The second buffer has a region of its own, or (OVL, where that region would
+// cost a workgroup per CU) takes the place of W xh[-k] once its values are in
+// registers, which costs two more barriers per workgroup.
 // Up to 8 right-hand sides per pass
 // (2 NR <= 16 MFMA columns).  The two instructions share their A and B
 // layouts (lane l: A[l % 16][l / 16], B[l / 16][l % 16]); the result rows
@@ -89,8 +92,9 @@ __device__ __forceinline__ C ld_chunk(__amdgpu_buffer_rsrc_t rs, unsigned voff, 
 // T = float or double; TPW u tiles per wavefront; NRW right-hand sides per
 // pass (4 or 8: the MFMA columns used, 2 NRW of 16).  B2R keeps the B
 // operands of the transposed product in registers for the whole block (else
-// they are rebuilt from LDS for every tile).
-template <typename T, int TPW, int NRW, bool B2R>
+// they are rebuilt from LDS for every tile).  OVL (needs B2R): the second
+// column-sum buffer overlays W xh[-k].
+template <typename T, int TPW, int NRW, bool B2R, bool OVL>
 __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__ That, const int2* __restrict__ pairs,
                                                            const T* __restrict__ w, const T* __restrict__ winv,
                                                            const typename Mf<T>::V2* __restrict__ xh,
@@ -104,16 +108,12 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
   constexpr int TILE_BYTES = 2 * PAIR_TILE * PAIR_TILE * (int)sizeof(T);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nt = pair_tiles(n), np = nt * PAIR_TILE;
-  // LDS: one spectral input (xh[k] when the transposed product's B operands
-  // stay in registers, B2R; else W xh[-k], whose operands are rebuilt per
-  // tile while xh[k] is read from memory a v tile ahead), the column sums of
-  // wavefronts 0, 1 and of wavefronts 2, 3, the transposed staging.  The
-  // spectral input's region stages the row sums at the end.
-  T* xs = reinterpret_cast<T*>(smem_raw);        // [np][NRW][2]: xh[k] (B2R)
-  T* xt = xs;                                    // [np][NRW][2]: W xh[-k] (!B2R)
-  T* zs = xs + np * NRW * 2;                     // [np][2 NRW]
-  T* zs2 = zs + np * 2 * NRW;                    // [np][2 NRW]
-  T* tiles = zs2 + np * 2 * NRW;                 // [4 waves][stages][512]
+  T* xs = reinterpret_cast<T*>(smem_raw);  // [np][NRW][2]: xh[k]; row sums at the end
+  T* xt = xs + np * NRW * 2;               // [np][NRW][2]: W xh[-k]
+  T* zs = xt + np * NRW * 2;               // [np][2 NRW]: column sums of wavefronts 0, 1
+  // column sums of wavefronts 2, 3
+  T* zs2 = OVL ? xt : zs + np * 2 * NRW;
+  T* tiles = zs + np * 2 * NRW * (OVL ? 1 : 2);   // [4 waves][stages][512]
   const long long slot = blockIdx.x;
   const int2 pr = pairs[slot];
   const long long k = pr.x, kb = pr.y;
@@ -147,51 +147,44 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
   }
   const V2* x0 = xh + k * (long long)nrhs * n + (long long)r0 * n;
   const V2* x1 = xh + kb * (long long)nrhs * n + (long long)r0 * n;
+  for (int e = threadIdx.x; e < np * NRW; e += PNT) {
+    const int r = e / np, v = e - r * np;
+    V2 a{0, 0}, b{0, 0};
+    if (r < nr && v < n) {
+      a = x0[(long long)r * n + v];
+      const V2 c = x1[(long long)r * n + v];
+      b = V2{w[v] * c.x, w[v] * c.y};
+    }
+    xs[(v * NRW + r) * 2] = a.x;
+    xs[(v * NRW + r) * 2 + 1] = a.y;
+    xt[(v * NRW + r) * 2] = b.x;
+    xt[(v * NRW + r) * 2 + 1] = b.y;
+  }
+  for (int e = threadIdx.x; e < np * 2 * NRW; e += PNT) zs[e] = T(0);
+  if constexpr (!OVL)
+    for (int e = threadIdx.x; e < np * 2 * NRW; e += PNT) zs2[e] = T(0);
+  __syncthreads();
   // lane roles: k-slot kk = l / 16 -> (pair offset off, part); column jj = l % 16
   const int kk = l >> 4, jj = l & 15, off = kk >> 1, part = kk & 1, a16 = l & 15;
   const bool jre = jj < NRW, jok = jj < 2 * NRW;
   const int rj = jre ? jj : (jok ? jj - NRW : 0);
-  // embedding column of a complex input value (xr, xi) for this lane
-  auto embed = [&](T xr, T xi) {
+  auto bval = [&](const T* x, int idx) {
+    const T xr = x[(idx * NRW + rj) * 2], xi = x[(idx * NRW + rj) * 2 + 1];
     const T val = part == 0 ? (jre ? xr : xi) : (jre ? -xi : xr);
     return jok ? val : T(0);
   };
-  auto bval = [&](const T* x, int idx) { return embed(x[(idx * NRW + rj) * 2], x[(idx * NRW + rj) * 2 + 1]); };
-  // B operands of the transposed product held in registers (B2R): W xh[-k]
-  // read straight from memory
   constexpr int NB2 = B2R ? TPW : 1;
   T b2[NB2][8];
 #pragma unroll
   for (int ta = 0; ta < NB2; ++ta)
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int v = (wv + 4 * ta) * PAIR_TILE + 2 * s + off;
-      T val = T(0);
-      if (B2R && ta < ntw && jok && rj < nr && v < n) {
-        const V2 c = x1[(long long)rj * n + v];
-        val = embed(w[v] * c.x, w[v] * c.y);
-      }
-      b2[ta][s] = val;
-    }
-  for (int e = threadIdx.x; e < np * NRW; e += PNT) {
-    const int r = e / np, v = e - r * np;
-    V2 a{0, 0};
-    if constexpr (B2R) {
-      if (r < nr && v < n) a = x0[(long long)r * n + v];
-    } else {
-      if (r < nr && v < n) {
-        const V2 c = x1[(long long)r * n + v];
-        a = V2{w[v] * c.x, w[v] * c.y};
-      }
-    }
-    xs[(v * NRW + r) * 2] = a.x;
-    xs[(v * NRW + r) * 2 + 1] = a.y;
+    for (int s = 0; s < 8; ++s) b2[ta][s] = B2R && ta < ntw ? bval(xt, (wv + 4 * ta) * PAIR_TILE + 2 * s + off) : T(0);
+  if constexpr (OVL) {
+    // xt becomes the second column-sum buffer
+    __syncthreads();
+    for (int e = threadIdx.x; e < np * 2 * NRW; e += PNT) zs2[e] = T(0);
+    __syncthreads();
   }
-  for (int e = threadIdx.x; e < np * 2 * NRW; e += PNT) {
-    zs[e] = T(0);
-    zs2[e] = T(0);
-  }
-  __syncthreads();
   Acc acc[TPW];
 #pragma unroll
   for (int ta = 0; ta < TPW; ++ta) acc[ta] = Acc{};
@@ -204,29 +197,16 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
   T* tw = tiles + wv * NSTG * 512;
   int stage = 0;
   // B operands of the first product for v tile q, built one v tile ahead
-  // (from LDS, or from memory when LDS holds W xh[-k])
-  auto b1val = [&](int v) {
-    if constexpr (B2R) {
-      return bval(xs, v);
-    } else {
-      T val = T(0);
-      if (jok && rj < nr && v < n) {
-        const V2 c = x0[(long long)rj * n + v];
-        val = embed(c.x, c.y);
-      }
-      return val;
-    }
-  };
   T b1n[8];
 #pragma unroll
-  for (int s = 0; s < 8; ++s) b1n[s] = b1val(2 * s + off);
+  for (int s = 0; s < 8; ++s) b1n[s] = bval(xs, 2 * s + off);
   for (int q = 0; q < nt; ++q) {
     T b1[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) b1[s] = b1n[s];
     const int qn = q + 1 < nt ? q + 1 : q;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) b1n[s] = b1val(qn * PAIR_TILE + 2 * s + off);
+    for (int s = 0; s < 8; ++s) b1n[s] = bval(xs, qn * PAIR_TILE + 2 * s + off);
     Acc zq{};
 #pragma unroll
     for (int ta = 0; ta < TPW; ++ta) {
@@ -271,10 +251,10 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
         if (jok) atomicAdd(&zd[(q * PAIR_TILE + M::row(l, e)) * 2 * NRW + jj], zq[e]);
     }
   }
-  // outputs: the row sums are staged in LDS over the spectral input (no
-  // longer read once every wavefront is past its loop), in the layout of the
-  // column sums, and both products leave as coalesced non-temporal stores of
-  // 16 bytes per lane
+  // outputs: the row sums are staged in LDS over the spectral columns of
+  // xh[k] (no longer read once every wavefront is past its loop), in the
+  // layout of the column sums, and both products leave as coalesced
+  // non-temporal stores of 16 bytes per lane
   __syncthreads();
   T* ys = xs;  // [np][2 NRW]: row sums (yh[k])
 #pragma unroll
@@ -331,10 +311,24 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
 // tiles per wavefront; beyond that they are rebuilt from LDS per tile
 template <typename T> constexpr bool pair_b2r(int tpw) { return sizeof(T) == 4 || tpw <= 2; }
 
+// LDS of a workgroup: spectral inputs xh[k] and W xh[-k], two column-sum
+// buffers (one of them over W xh[-k] when ovl), the transposed staging
 template <typename T>
-size_t pair_lds_bytes(int n, int nrw) {
+size_t pair_lds_bytes(int n, int nrw, bool ovl) {
   const int np = pair_tiles(n) * PAIR_TILE;
-  return (size_t)(np * nrw * 2 * 3 + 4 * pair_stages<T>() * 512) * sizeof(T);
+  return (size_t)(np * nrw * 2 * (ovl ? 3 : 4) + 4 * pair_stages<T>() * 512) * sizeof(T);
+}
+
+constexpr size_t CU_LDS = 160 * 1024;
+
+// Overlay the second column-sum buffer only where its own region would leave
+// fewer workgroups per CU (by LDS; a workgroup has one wavefront per SIMD,
+// and at most 4 per CU fit the registers of the matrix-core forms here).
+template <typename T>
+bool pair_overlay(int n, int nrw) {
+  if (!pair_b2r<T>((pair_tiles(n) + 3) / 4)) return false;
+  auto wgs = [](size_t b) { const size_t w = CU_LDS / b; return w < 4 ? w : (size_t)4; };
+  return wgs(pair_lds_bytes<T>(n, nrw, false)) < wgs(pair_lds_bytes<T>(n, nrw, true));
 }
 
 template <typename T, int TPW, int NRW>
@@ -343,10 +337,19 @@ void launch_mfma_pair(const void* That, const void* pairs, const void* w, const 
   using V2 = typename Mf<T>::V2;
   // FP64 B operands of many u tiles would not fit the registers
   constexpr bool B2R = pair_b2r<T>(TPW);
-  const size_t shm = pair_lds_bytes<T>(n, NRW);
-  hipLaunchKernelGGL((pair_mfma_kernel<T, TPW, NRW, B2R>), dim3((unsigned)Ps), dim3(PNT), shm, s,
-                     static_cast<const T*>(That), static_cast<const int2*>(pairs), static_cast<const T*>(w),
-                     static_cast<const T*>(winv), static_cast<const V2*>(xh), static_cast<V2*>(yh), n, nrhs, r0, nr);
+  const bool ovl = pair_overlay<T>(n, NRW);
+  const size_t shm = pair_lds_bytes<T>(n, NRW, ovl);
+  if (ovl) {
+    if constexpr (B2R)
+      hipLaunchKernelGGL((pair_mfma_kernel<T, TPW, NRW, B2R, true>), dim3((unsigned)Ps), dim3(PNT), shm, s,
+                         static_cast<const T*>(That), static_cast<const int2*>(pairs), static_cast<const T*>(w),
+                         static_cast<const T*>(winv), static_cast<const V2*>(xh), static_cast<V2*>(yh), n, nrhs, r0,
+                         nr);
+  } else {
+    hipLaunchKernelGGL((pair_mfma_kernel<T, TPW, NRW, B2R, false>), dim3((unsigned)Ps), dim3(PNT), shm, s,
+                       static_cast<const T*>(That), static_cast<const int2*>(pairs), static_cast<const T*>(w),
+                       static_cast<const T*>(winv), static_cast<const V2*>(xh), static_cast<V2*>(yh), n, nrhs, r0, nr);
+  }
 }
 
 template <typename T, int TPW>
@@ -367,8 +370,9 @@ void launch_pair_typed(const void* That, const void* pairs, const void* w, const
   const int tpw = (pair_tiles(n) + 3) / 4;
   // 4-wide passes for at most 4 right-hand sides (less LDS, more workgroups
   // per CU), and wherever 8-wide ones would not fit the LDS
-  const int nrw = nrhs <= 4 || pair_lds_bytes<T>(n, 8) > PAIR_LDS_MAX ? 4 : 8;
-  EMS_CHECK_ARG(pair_lds_bytes<T>(n, nrw) <= PAIR_LDS_MAX, "internal: paired product LDS too large");
+  const int nrw = nrhs <= 4 || pair_lds_bytes<T>(n, 8, pair_overlay<T>(n, 8)) > PAIR_LDS_MAX ? 4 : 8;
+  EMS_CHECK_ARG(pair_lds_bytes<T>(n, nrw, pair_overlay<T>(n, nrw)) <= PAIR_LDS_MAX,
+                "internal: paired product LDS too large");
   for (int r0 = 0; r0 < nrhs; r0 += nrw) {
     const int nr = nrhs - r0 < nrw ? nrhs - r0 : nrw;
     switch (tpw) {
