@@ -348,6 +348,25 @@ def multi_rhs_section(E, W, torch, np):
                                   **{name: d["_out"][:, e[0], e[1]] for name, d in split.items()}}}
     for d in split.values():
         d.pop("_out")
+    # FP64 GMRES outer loop as the reference solve, and the FP32 + FP64 refinement solve against it
+    ref_solve = {}
+    xs = {}
+    for name, prec in (("fp64", E.EMSURF_FP64), ("fp32_ir", E.EMSURF_FP32_IR)):
+        x = torch.zeros_like(b64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stt, info = E.emsurf_solve(plan, E.solve_opts(prec, tol=cfg.tol), nrhs, b64, x)
+        torch.cuda.synchronize()
+        ref_solve[name] = {"ms": round(1e3 * (time.perf_counter() - t0), 3), "status": E.emsurf_status_str(stt),
+                           "iters": [i["iters"] for i in info],
+                           "max_rel_res_true": float(f"{max(i['rel_res_true'] for i in info):.3e}")}
+        xs[name] = x.cpu().numpy()
+    ref_solve["fp32_ir_vs_fp64_max_rel_diff"] = float(np.max(
+        np.linalg.norm((xs["fp32_ir"] - xs["fp64"]).reshape(nrhs, -1), axis=1) /
+        np.linalg.norm(xs["fp64"].reshape(nrhs, -1), axis=1)))
+    ref_solve["tol"] = cfg.tol
+    sec["gmres_reference"] = ref_solve
+    log(f"64x64 GMRES reference: {ref_solve}")
     plan.destroy()
     # the same lattice with the structured outer operator (L and K stored)
     plan = E.emsurf_plan_create_green(cfg.nx, cfg.ny, cfg.n_types, nrhs, geom, S, tm, form=E.EMSURF_T_LK,
@@ -471,6 +490,96 @@ def structured_section(E, W, torch, np, steps):
     rsec["rel_diff_vs_full_store"] = {"fp32": rdiff(r32, f32), "fp64": rdiff(r64, f64)}
     sec["reciprocal"] = rsec
     log(f"structured L/K 128x128: {sec}")
+    return sec
+
+
+def _timed(torch, fn, reps):
+    """Average wall time (ms) of fn() over reps calls, device synchronised."""
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / reps
+
+
+def config2_section(E, W, torch, np):
+    """32 x 32 lattice, n_eq 192, one oblique RHS (theta 30 deg TE), 16 types:
+    FP64 against FP32 coupling applies, GMRES to 1e-8 in FP64 and FP32 inner
+    solves with FP64 refinement to 1e-6."""
+    cfg = W.config(2)
+    g = W.box_geometry(cfg.n_patch)
+    S, tm = W.s_types(cfg), W.type_map(cfg)
+    b = W.plane_wave_rhs(cfg, g)
+    geom = E.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)
+    t0 = time.perf_counter()
+    plan = E.emsurf_plan_create_green(cfg.nx, cfg.ny, cfg.n_types, 1, geom, S, tm, recip=1)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    b64 = torch.from_numpy(b).to("cuda")
+    x32 = b64.to(torch.complex64)
+    y64, y32 = torch.empty_like(b64), torch.empty_like(x32)
+    ms64 = _timed(torch, lambda: E.emsurf_apply_T(plan, E.EMSURF_FP64, 1, b64, y64), 20)
+    ms32 = _timed(torch, lambda: E.emsurf_apply_T(plan, E.EMSURF_FP32, 1, x32, y32), 20)
+    ref = y64.cpu().numpy()
+    err32 = float(np.linalg.norm(y32.cpu().numpy().astype(np.complex128) - ref) / np.linalg.norm(ref))
+    solve = {}
+    x = torch.zeros_like(b64)
+    for name, prec, tol in (("fp64_1e-8", E.EMSURF_FP64, 1e-8), ("fp32_ir_1e-6", E.EMSURF_FP32_IR, 1e-6)):
+        E.emsurf_solve(plan, E.solve_opts(prec, tol=tol), 1, b64, x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stt, info = E.emsurf_solve(plan, E.solve_opts(prec, tol=tol), 1, b64, x)
+        torch.cuda.synchronize()
+        solve[name] = {"ms": round(1e3 * (time.perf_counter() - t0), 3), "status": E.emsurf_status_str(stt),
+                       "iters": info[0]["iters"], "outer": info[0]["outer_iters"],
+                       "rel_res_true": float(f"{info[0]['rel_res_true']:.3e}")}
+    sec = {"workload": "32x32 lattice, n_eq 192 (48 patches/box), 196608 unknowns, 1 RHS (theta 30 deg TE), "
+                       "16 cell types, 64x64 padded FFT, reciprocal store",
+           "plan_create_s": round(plan_s, 3),
+           "apply_T_fp64_ms": round(ms64, 4), "apply_T_fp32_ms": round(ms32, 4),
+           "unknowns_rhs_per_s_fp64": cfg.n_unknowns / (ms64 / 1e3),
+           "unknowns_rhs_per_s_fp32": cfg.n_unknowns / (ms32 / 1e3),
+           "fp32_rel_err_vs_fp64": err32, "solve": solve}
+    log(f"32x32: {sec}")
+    plan.destroy()
+    return sec
+
+
+def precond_section(E, W, torch, np, plan, geom, cfg, b64, stream, plain):
+    """Near-field right preconditioner (Delta_NF = lambda/10, 2 x 2 tiles) on
+    the headline plan: build, one apply, and both solves against the plain ones."""
+    delta = 0.1 * W.WAVELENGTH
+    t0 = time.perf_counter()
+    pc = E.emsurf_precond_create(plan, geom, delta, 2, 2, stream=stream)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    st = pc.stats()
+    y = torch.empty_like(b64)
+    ms_apply = _timed(torch, lambda: E.emsurf_precond_apply(pc, cfg.nrhs, b64, y, stream), 10)
+    nq, ntiles = st["nq_max"], st["n_tiles"]
+    g_bytes = ntiles * nq * nq * 16
+    solve = {}
+    x = torch.zeros_like(b64)
+    for name, prec in (("fp32_ir", E.EMSURF_FP32_IR), ("fp64", E.EMSURF_FP64)):
+        E.emsurf_solve_precond(plan, pc, E.solve_opts(prec, tol=cfg.tol), cfg.nrhs, b64, x, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stt, info = E.emsurf_solve_precond(plan, pc, E.solve_opts(prec, tol=cfg.tol), cfg.nrhs, b64, x, stream)
+        torch.cuda.synchronize()
+        solve[name] = {"ms": round(1e3 * (time.perf_counter() - t0), 3), "status": E.emsurf_status_str(stt),
+                       "iters": [i["iters"] for i in info],
+                       "iters_without": plain[name]["iters"] if plain else None,
+                       "ms_without": plain[name]["ms"] if plain else None,
+                       "rel_res_true": [float(f"{i['rel_res_true']:.3e}") for i in info]}
+    sec = {"delta_nf": delta, "tiles": [2, 2], "n_tiles": ntiles, "nq_max": nq,
+           "near_entries": st["near_entries"], "device_bytes": st["bytes"], "build_s": round(build_s, 3),
+           "apply_ms": round(ms_apply, 4),
+           "apply_G_GBs": round(g_bytes / (ms_apply / 1e3) / 1e9, 1),
+           "solve": solve}
+    log(f"near-field preconditioner: {sec}")
+    pc.destroy()
     return sec
 
 
@@ -650,6 +759,8 @@ def main():
                     help="time the 2 GiB device copy and 8 GiB read references (the default; kept for old commands)")
     ap.add_argument("--no-copy-cal", action="store_true", help="skip the copy and read references")
     ap.add_argument("--no-multi", action="store_true", help="skip the 64x64, 16-RHS MFMA section")
+    ap.add_argument("--no-cfg2", action="store_true", help="skip the 32x32 apply and solve section")
+    ap.add_argument("--no-precond", action="store_true", help="skip the near-field preconditioner section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--no-macromodels", action="store_true", help="skip the macromodel-generation timing")
     ap.add_argument("--serving-structured", action="store_true",
@@ -797,6 +908,10 @@ def main():
         solve["speedup_fp32_ir_vs_fp64"] = round(solve["fp64"]["ms"] / solve["fp32_ir"]["ms"], 3)
         solve["tol"] = cfg.tol
 
+    precond = None
+    if not args.no_solve and not args.no_precond:
+        precond = precond_section(E, W, torch, np, plan, geom, cfg, b64, stream, solve)
+
     # far field of the solved currents (the last FP64 solve's x) at the bins of a 256 x 256 lattice DFT
     far = None
     if solve is not None:
@@ -846,6 +961,10 @@ def main():
         copy["read_GBs"] = round((8 << 30) / (rms / 1e3) / 1e9, 1)
         log(f"read 8 GiB (sum): {rms:.3f} ms, {copy['read_GBs']} GB/s")
         del big
+
+    cfg2 = None
+    if not args.no_cfg2:
+        cfg2 = config2_section(E, W, torch, np)
 
     multi = None
     if not args.no_multi:
@@ -927,6 +1046,8 @@ def main():
         "plan_create_s": round(plan_s, 3),
         "copy_reference": copy,
         "device": device_record(torch, dev),
+        "config_32x32": cfg2,
+        "near_field_precond_128x128": precond,
         "multi_rhs_64x64": multi,
         "structured_lk_128x128": structured,
         "macromodel_generation": macromodels,

@@ -319,6 +319,48 @@ size_t emsurf_apply_T_noalloc_limit(void);
 emsurf_status emsurf_solve(emsurf_plan plan, const emsurf_solve_opts* opts, int32_t nrhs,
                            const void* b_dev, void* x_dev, emsurf_solve_info* info_host, void* stream);
 
+/* ---- Near-field right preconditioner (Sec. IV-A, eq. (final_precond)) ----
+ * The paper preconditions on the right with P, the entries of the system
+ * matrix that couple basis functions closer than Delta_NF (lambda/10 to
+ * lambda/6), and applies P^-1 through an LU factorisation.  In the form solved
+ * here, A = I - S T, this is
+ *     P = I - S T_NF,  T_NF(d)[u][v] = T(d)[u][v] where |r_u - r_v + pitch (dx, dy, 0)| < delta_nf, else 0,
+ * r_u the centre of the patch of unknown u (geom->rho; u = tau 2 n_patch +
+ * 2 p + alpha).  Each element's own block stays whole in S (the exact inverse
+ * of its self block).  delta_nf may reach adjacent elements only (ERR_ARG
+ * otherwise).  P is factored on the device per tile of tile_x x tile_y
+ * elements (1 <= tile_x tile_y <= 64; tiles from element (0, 0), ragged at
+ * the far edges): couplings between tiles are dropped, and a tile that covers
+ * the lattice gives the paper's P exactly.
+ * T_near: host c128 [3][3][n_eq][n_eq], block [dy + 1][dx + 1] = T(d) row-major
+ * [test u][source v] (the plan's own blocks at the 8 neighbour offsets; the
+ * centre block is ignored), or NULL to take the point-sampled fill of geom
+ * (as emsurf_plan_create_green).  Dense-form plans with an FP64 macromodel
+ * copy only.  The preconditioner keeps a pointer to the plan (destroy it
+ * first) and owns its device memory (per tile a |Q|^2 c128 matrix, |Q| the
+ * tile's unknowns with a near partner in another element of the tile, and a
+ * max_rhs vector workspace).  ERR_ARG if a tile's block is singular.  Calls
+ * on one preconditioner must not overlap. */
+typedef struct emsurf_precond_s* emsurf_precond;
+typedef struct {
+  int32_t n_tiles, nq_max;    /* tiles, largest near-field unknown set of a tile */
+  int64_t near_entries;       /* (u, v, d) triples within delta_nf over the 8 offsets */
+  size_t bytes;               /* device bytes held */
+  double build_ms;            /* host time of emsurf_precond_create */
+} emsurf_precond_stats;
+emsurf_status emsurf_precond_create(emsurf_plan plan, const emsurf_geom* geom, double delta_nf, int32_t tile_x,
+                                    int32_t tile_y, const void* T_near, void* stream, emsurf_precond* out);
+/* x = P^-1 y, c128 [nrhs][ny][nx][n_eq] device, distinct buffers; async on stream. */
+emsurf_status emsurf_precond_apply(emsurf_precond pc, int32_t nrhs, const void* y_dev, void* x_dev, void* stream);
+emsurf_status emsurf_precond_query(emsurf_precond pc, emsurf_precond_stats* out);
+void emsurf_precond_destroy(emsurf_precond pc);
+/* emsurf_solve on the right-preconditioned system A P^-1 y = b, x = P^-1 y
+ * (the Arnoldi process runs on A P^-1, every cycle ends with x += P^-1 V y,
+ * residuals and tol are those of A x = b).  pc must belong to plan.  With
+ * EMSURF_FP32_IR the inner solves are preconditioned (P^-1 in FP64). */
+emsurf_status emsurf_solve_precond(emsurf_plan plan, emsurf_precond pc, const emsurf_solve_opts* opts, int32_t nrhs,
+                                   const void* b_dev, void* x_dev, emsurf_solve_info* info_host, void* stream);
+
 /* Plan facts (padded sizes and memory). */
 emsurf_status emsurf_plan_query(emsurf_plan plan, emsurf_plan_stats* out);
 

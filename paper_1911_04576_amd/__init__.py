@@ -98,6 +98,11 @@ class emsurf_server_stats(ctypes.Structure):
                 ("admit_ms", ctypes.c_double), ("step_ms", ctypes.c_double)]
 
 
+class emsurf_precond_stats(ctypes.Structure):
+    _fields_ = [("n_tiles", ctypes.c_int32), ("nq_max", ctypes.c_int32), ("near_entries", ctypes.c_int64),
+                ("bytes", ctypes.c_size_t), ("build_ms", ctypes.c_double)]
+
+
 class emsurf_plan_stats(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("n_freq", ctypes.c_int64),
                 ("bytes_that64", ctypes.c_size_t), ("bytes_that32", ctypes.c_size_t),
@@ -128,6 +133,13 @@ _SIGS = {
     "emsurf_solve": (ctypes.c_int, [_P, ctypes.POINTER(emsurf_solve_opts), ctypes.c_int32, _P, _P,
                                     ctypes.POINTER(emsurf_solve_info), _P]),
     "emsurf_plan_query": (ctypes.c_int, [_P, ctypes.POINTER(emsurf_plan_stats)]),
+    "emsurf_precond_create": (ctypes.c_int, [_P, ctypes.POINTER(emsurf_geom), ctypes.c_double, ctypes.c_int32,
+                                             ctypes.c_int32, _P, _P, ctypes.POINTER(_P)]),
+    "emsurf_precond_apply": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
+    "emsurf_precond_query": (ctypes.c_int, [_P, ctypes.POINTER(emsurf_precond_stats)]),
+    "emsurf_precond_destroy": (None, [_P]),
+    "emsurf_solve_precond": (ctypes.c_int, [_P, _P, ctypes.POINTER(emsurf_solve_opts), ctypes.c_int32, _P, _P,
+                                            ctypes.POINTER(emsurf_solve_info), _P]),
     "emsurf_kernel_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "emsurf_kernel_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "emsurf_plan_destroy": (None, [_P]),
@@ -381,6 +393,68 @@ def emsurf_solve(plan: Plan, opts: emsurf_solve_opts, nrhs, b_dev, x_dev, stream
     infos = (emsurf_solve_info * int(nrhs))()
     st = lib().emsurf_solve(plan.h, ctypes.byref(opts), int(nrhs), _dptr(b_dev), _dptr(x_dev), infos,
                             _stream(stream))
+    if st != EMSURF_OK and (st != EMSURF_ERR_NOT_CONVERGED or raise_not_converged):
+        _check(st)
+    out = [dict(iters=i.iters, outer_iters=i.outer_iters, converged=bool(i.converged),
+                rel_res_true=i.rel_res_true, ms=i.ms) for i in infos]
+    return st, out
+
+
+class Precond:
+    """Handle of a near-field right preconditioner (destroyed with destroy()
+    or when garbage collected, before its plan)."""
+
+    def __init__(self, handle, plan: Plan):
+        self.h = handle
+        self.plan = plan
+
+    def destroy(self):
+        if self.h:
+            lib().emsurf_precond_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def stats(self):
+        return emsurf_precond_query(self)
+
+
+def emsurf_precond_create(plan: Plan, geom: Geometry, delta_nf, tile_x, tile_y, T_near=None, stream=None) -> Precond:
+    """T_near: numpy complex128 [3][3][n_eq][n_eq] (host) or None for the point-sampled fill of geom."""
+    if T_near is not None:
+        tn, ptn = _host(T_near, np.complex128)
+    else:
+        tn, ptn = None, None
+    out = ctypes.c_void_p()
+    _check(lib().emsurf_precond_create(plan.h, ctypes.byref(geom.c), float(delta_nf), int(tile_x), int(tile_y), ptn,
+                                       _stream(stream), ctypes.byref(out)))
+    return Precond(out.value, plan)
+
+
+def emsurf_precond_apply(pc: Precond, nrhs, y_dev, x_dev, stream=None):
+    _check(lib().emsurf_precond_apply(pc.h, int(nrhs), _dptr(y_dev), _dptr(x_dev), _stream(stream)))
+
+
+def emsurf_precond_query(pc: Precond):
+    s = emsurf_precond_stats()
+    _check(lib().emsurf_precond_query(pc.h, ctypes.byref(s)))
+    return dict(n_tiles=s.n_tiles, nq_max=s.nq_max, near_entries=s.near_entries, bytes=s.bytes, build_ms=s.build_ms)
+
+
+def emsurf_precond_destroy(pc: Precond):
+    pc.destroy()
+
+
+def emsurf_solve_precond(plan: Plan, pc: Precond, opts: emsurf_solve_opts, nrhs, b_dev, x_dev, stream=None,
+                         raise_not_converged=False):
+    """emsurf_solve on the right-preconditioned system; returns (status, [info per RHS])."""
+    infos = (emsurf_solve_info * int(nrhs))()
+    st = lib().emsurf_solve_precond(plan.h, pc.h, ctypes.byref(opts), int(nrhs), _dptr(b_dev), _dptr(x_dev), infos,
+                                    _stream(stream))
     if st != EMSURF_OK and (st != EMSURF_ERR_NOT_CONVERGED or raise_not_converged):
         _check(st)
     out = [dict(iters=i.iters, outer_iters=i.outer_iters, converged=bool(i.converged),

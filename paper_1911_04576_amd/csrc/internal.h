@@ -321,6 +321,14 @@ void launch_store_chunk(const void* Kc, int64_t P, int64_t nn, int64_t c0, int64
 void launch_recip_check(const void* T_blocks_dev, int nx, int ny, int n, int parts, const double* w_dev, double* out,
                         hipStream_t s);
 
+// ----------------------------------------------------------------------------- dense elimination
+// Partial elimination of the leading K x K block of T row-major N x N FP64
+// complex matrices (A + b N^2), partial pivoting among the leading rows: the
+// trailing block becomes A22 - A21 A11^-1 A12.  piv: int [T][K] work space;
+// info[b] (zeroed by the caller) receives 1 + the first column whose pivot
+// candidates are all zero.
+void schur_eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t s);
+
 // ----------------------------------------------------------------------------- vector ops (GMRES)
 void launch_convert(Cx tin, Cx tout, const void* in, void* out, int64_t n, hipStream_t s);
 
@@ -370,6 +378,10 @@ struct emsurf_plan_s {
 };
 
 namespace emsurf {
+// x = P^-1 y with a near-field preconditioner (precond.hip); FP64 c128
+// [nrhs][M][n_eq], x != y
+void precond_apply(emsurf_precond pc, int nrhs, const void* y, void* x, hipStream_t s);
+emsurf_plan precond_plan(emsurf_precond pc);
 Workspace& workspace(emsurf_plan p, hipStream_t s);
 // FP32 block-product variant for this plan and nrhs: explicit choice, else the
 // persisted autotuning cache, else a heuristic.

@@ -273,6 +273,11 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
 }
 
 }  // namespace
+
+void schur_eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t s) {
+  eliminate(A, N, K, T, piv, info, s);
+}
+
 }  // namespace emsurf
 
 using namespace emsurf;

@@ -44,6 +44,7 @@ struct SolveWork {
   DevBuf ycoef;    // nrhs x m complex
   DevBuf mask;     // nrhs ints
   DevBuf ir_r, ir_d, ir_t;  // refinement residual, correction, operator output: nrhs x N each
+  DevBuf pz, pz2;           // right preconditioning: P^-1 v and P^-1 V y, nrhs x N each
   PinnedBuf h_red, h_scale, h_y, h_mask;
   void init(int nrhs_, int m_, long long N_) {
     nrhs = nrhs_;
@@ -70,9 +71,13 @@ struct SolveWork {
     ir_d.reserve((size_t)nrhs * N * 16);
     ir_t.reserve((size_t)nrhs * N * 16);
   }
+  void init_precond() {
+    pz.reserve((size_t)nrhs * N * 16);
+    pz2.reserve((size_t)nrhs * N * 16);
+  }
   size_t bytes() const {
     return V.bytes + r.bytes + t.bytes + partial.bytes + red.bytes + scale.bytes + ycoef.bytes + mask.bytes +
-           ir_r.bytes + ir_d.bytes + ir_t.bytes;
+           ir_r.bytes + ir_d.bytes + ir_t.bytes + pz.bytes + pz2.bytes;
   }
 };
 
@@ -123,7 +128,9 @@ struct RhsState {
 
 // Batched GMRES on op(x) = b.  x holds the start (zeros or x0).  `confirm`
 // selects the true-residual check after a converged cycle (top-level solve).
-void gmres(emsurf_plan p, OpFn op, SolveWork& w, int nrhs, const double2* b, double2* x,
+// pc (or NULL): right preconditioner, the Arnoldi process runs on op P^-1 and
+// a cycle ends with x += P^-1 V y.
+void gmres(emsurf_plan p, OpFn op, emsurf_precond pc, SolveWork& w, int nrhs, const double2* b, double2* x,
            const std::vector<double>& tol, int max_iter, bool confirm, bool start_zero, std::vector<RhsState>& st,
            hipStream_t s) {
   const int m = w.m;
@@ -174,7 +181,12 @@ void gmres(emsurf_plan p, OpFn op, SolveWork& w, int nrhs, const double2* b, dou
     launch_scale(w.r.p, w.scale.p, w.Vp(0), N, nrhs, s);
     for (int j = 0; j < m; ++j) {
       double2* wv = w.Vp(j + 1);
-      op(p, nrhs, w.Vp(j), wv, s);
+      if (pc) {
+        precond_apply(pc, nrhs, w.Vp(j), w.pz.p, s);
+        op(p, nrhs, w.pz.p, wv, s);
+      } else {
+        op(p, nrhs, w.Vp(j), wv, s);
+      }
       // CGS2: red layout per RHS: [c1 (j+1)][|w0|^2][c2 (j+1)][|w1|^2][|w2|^2]
       const int nv = j + 1;
       const int o1 = 0, o2 = nv + 1, o3 = 2 * nv + 2;
@@ -240,7 +252,14 @@ void gmres(emsurf_plan p, OpFn op, SolveWork& w, int nrhs, const double2* b, dou
       if (!q.done) q.cycles += 1;
     }
     EMS_HIP(hipMemcpyAsync(w.ycoef.p, hy, (size_t)nrhs * m * 16, hipMemcpyHostToDevice, s));
-    launch_axpy_basis(w.V.p, vstride, kmax, w.ycoef.p, m, x, N, nrhs, s);
+    if (pc) {
+      EMS_HIP(hipMemsetAsync(w.pz.p, 0, (size_t)nrhs * N * 16, s));
+      launch_axpy_basis(w.V.p, vstride, kmax, w.ycoef.p, m, w.pz.p, N, nrhs, s);
+      precond_apply(pc, nrhs, w.pz.p, w.pz2.p, s);
+      launch_add(x, w.pz2.p, (long long)nrhs * N, s);
+    } else {
+      launch_axpy_basis(w.V.p, vstride, kmax, w.ycoef.p, m, x, N, nrhs, s);
+    }
     if (!confirm) {
       // inner solve: accept the estimate
       for (int r = 0; r < nrhs; ++r) {
@@ -278,14 +297,17 @@ void check_opts(emsurf_plan plan, const emsurf_solve_opts* o, int32_t nrhs) {
 
 using namespace emsurf;
 
-extern "C" emsurf_status emsurf_solve(emsurf_plan plan, const emsurf_solve_opts* opts, int32_t nrhs,
-                                      const void* b_dev, void* x_dev, emsurf_solve_info* info_host, void* stream) {
+namespace {
+
+emsurf_status solve_impl(emsurf_plan plan, emsurf_precond pc, const emsurf_solve_opts* opts, int32_t nrhs,
+                         const void* b_dev, void* x_dev, emsurf_solve_info* info_host, void* stream) {
   const auto t0 = std::chrono::steady_clock::now();
   bool all_conv = true;
   std::vector<RhsState> st;
   int outer = 0;
   try {
     check_opts(plan, opts, nrhs);
+    EMS_CHECK_ARG(pc == nullptr || precond_plan(pc) == plan, "the preconditioner belongs to another plan");
     EMS_CHECK_ARG(b_dev != nullptr && x_dev != nullptr, "b and x must be non-NULL device pointers");
     EMS_CHECK_ARG(b_dev != x_dev, "b and x must be distinct buffers");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -299,6 +321,7 @@ extern "C" emsurf_status emsurf_solve(emsurf_plan plan, const emsurf_solve_opts*
     }
     SolveWork& w = *wp;
     w.init(nrhs, opts->restart, N);
+    if (pc) w.init_precond();
     // finiteness and norms of b
     int* hm = w.h_mask.as<int>();
     for (int r = 0; r < nrhs; ++r) hm[r] = 1;
@@ -322,7 +345,7 @@ extern "C" emsurf_status emsurf_solve(emsurf_plan plan, const emsurf_solve_opts*
     }
     if (opts->prec != EMSURF_FP32_IR) {
       OpFn op = opts->prec == EMSURF_FP64 ? op_fp64 : op_fp32;
-      gmres(plan, op, w, nrhs, static_cast<const double2*>(b_dev), static_cast<double2*>(x_dev),
+      gmres(plan, op, pc, w, nrhs, static_cast<const double2*>(b_dev), static_cast<double2*>(x_dev),
             std::vector<double>(nrhs, opts->tol), opts->max_iter, true, !opts->use_x0, st, s);
       for (int r = 0; r < nrhs; ++r) outer = std::max(outer, st[r].cycles);
     } else {
@@ -369,7 +392,7 @@ extern "C" emsurf_status emsurf_solve(emsurf_plan plan, const emsurf_solve_opts*
         int budget = 0;
         for (int r = 0; r < nrhs; ++r)
           if (!st[r].done) budget = std::max(budget, opts->max_iter - st[r].iters);
-        gmres(plan, op_fp32, w, nrhs, rr.as<double2>(), d.as<double2>(), itol, std::max(1, budget), false, true,
+        gmres(plan, op_fp32, pc, w, nrhs, rr.as<double2>(), d.as<double2>(), itol, std::max(1, budget), false, true,
               inner, s);
         for (int r = 0; r < nrhs; ++r) st[r].iters += inner[r].iters;
         launch_add(x_dev, d.p, (long long)nrhs * N, s);
@@ -395,4 +418,21 @@ extern "C" emsurf_status emsurf_solve(emsurf_plan plan, const emsurf_solve_opts*
     return EMSURF_ERR_NOT_CONVERGED;
   }
   return EMSURF_OK;
+}
+
+}  // namespace
+
+extern "C" emsurf_status emsurf_solve(emsurf_plan plan, const emsurf_solve_opts* opts, int32_t nrhs,
+                                      const void* b_dev, void* x_dev, emsurf_solve_info* info_host, void* stream) {
+  return solve_impl(plan, nullptr, opts, nrhs, b_dev, x_dev, info_host, stream);
+}
+
+extern "C" emsurf_status emsurf_solve_precond(emsurf_plan plan, emsurf_precond pc, const emsurf_solve_opts* opts,
+                                              int32_t nrhs, const void* b_dev, void* x_dev,
+                                              emsurf_solve_info* info_host, void* stream) {
+  if (pc == nullptr) {
+    set_error("pc is NULL");
+    return EMSURF_ERR_ARG;
+  }
+  return solve_impl(plan, pc, opts, nrhs, b_dev, x_dev, info_host, stream);
 }
