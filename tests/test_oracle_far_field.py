@@ -110,3 +110,39 @@ def test_z_electric_element_closed_form():
     th = np.arcsin(np.sqrt(u * u + v * v))
     assert np.allclose(E[0, :, 0], -0.25 * np.sin(th), atol=1e-14)
     assert np.allclose(E[0, :, 1], 0.0, atol=1e-14)
+
+
+def _bin_at(Lu, Lv, u0, v0):
+    u, v = FF.fft_bin_directions(Lu, Lv, W.PITCH, W.K0)
+    q, p = np.unravel_index(np.argmin((u - u0) ** 2 + (v - v0) ** 2), u.shape)
+    return q, p
+
+
+def test_directivity_of_an_electric_element_and_a_huygens_source():
+    # Directivity 3/2 of an elementary electric current at broadside, and 3 of
+    # a Huygens source (J = x with M = y, pattern (1 + cos theta)^2) at
+    # broadside with a null behind it; the bin quadrature of P_rad converges
+    # to the closed-form sphere integrals (8 pi / 3 and 16 pi / 3) as the grid refines
+    rho, area, tan = _single_patch_geometry()
+    for Lu, tol in ((256, 2e-2), (1024, 6e-3)):
+        x = np.zeros((2, 1, 1, 4), complex)
+        x[0, 0, 0, 0] = 1.0                      # J = x
+        x[1, 0, 0, 0] = 1.0                      # J = x ...
+        x[1, 0, 0, 3] = 1.0                      # ... with M = y
+        D, P = FF.directivity(rho, area, tan, W.PITCH, W.K0, x, Lu, Lu)
+        q, p = _bin_at(Lu, Lu, 0.0, 0.0)
+        assert abs(D[0, 0, q, p] - 1.5) <= tol * 1.5, (Lu, D[0, 0, q, p])
+        assert abs(D[1, 0, q, p] - 3.0) <= tol * 3.0, (Lu, D[1, 0, q, p])
+        assert D[1, 1, q, p] <= 1e-20
+        assert abs(P[0] / (area[0] ** 2) - 8 * np.pi / 3) <= tol * 8 * np.pi / 3
+        assert abs(P[1] / (area[0] ** 2) - 16 * np.pi / 3) <= tol * 16 * np.pi / 3
+
+
+def test_directivity_lower_half_space_mirrors_the_upper():
+    # sources in the z = 0 plane radiate symmetric patterns up and down for a
+    # current pair whose fields mirror: an electric current alone
+    rho, area, tan = _single_patch_geometry()
+    x = np.zeros((1, 1, 1, 4), complex)
+    x[0, 0, 0, 1] = 2.0 - 1.0j
+    D, _ = FF.directivity(rho, area, tan, W.PITCH, W.K0, x, 64, 48)
+    assert np.allclose(D[0, 0], D[0, 1], rtol=1e-13, atol=0)
