@@ -272,6 +272,21 @@ emsurf_status emsurf_macromodels(int32_t n_types, int32_t n_eq, int32_t n_int, c
 emsurf_status emsurf_far_field(const emsurf_geom* geom, int32_t nx, int32_t ny, int32_t nrhs, int32_t Lu,
                                int32_t Lv, const void* x_dev, void* E_dev, void* stream);
 
+/* Directivity of the same currents (Sec. V shows it in the phi = 0, 45 and 90
+ * degree cuts): D = 4 pi U / P_rad with U = |E_theta|^2 + |E_phi|^2 (the
+ * dropped common factor cancels).  The paper does not state how it integrates
+ * the radiated power; here P_rad is the midpoint rule in direction cosines
+ * over the lattice-DFT bins of both half spaces, dOmega = du dv / |w|, with
+ * du = 2 pi / (Lu k pitch), dv = 2 pi / (Lv k pitch): finer bins (larger Lu,
+ * Lv) integrate more accurately.
+ *   D_dev      double [nrhs][2][Lv][Lu]: half space 0 (w >= 0) then 1 (w < 0);
+ *              zero at bins outside the visible region.
+ *   prad_host  double [nrhs] (may be NULL): P_rad in units of U.
+ * Other arguments as for emsurf_far_field.  EMSURF_ERR_ARG if a right-hand
+ * side radiates no power.  Synchronises `stream`. */
+emsurf_status emsurf_directivity(const emsurf_geom* geom, int32_t nx, int32_t ny, int32_t nrhs, int32_t Lu,
+                                 int32_t Lv, const void* x_dev, void* D_dev, double* prad_host, void* stream);
+
 /* y = T x over nrhs right-hand sides (1 <= nrhs <= max_rhs).  x_dev and y_dev
  * are c128 for EMSURF_FP64 and c64 for EMSURF_FP32, EMSURF_BF16X3 and
  * EMSURF_BF16, [nrhs][ny][nx][n_eq]; they must not overlap.  Requires the

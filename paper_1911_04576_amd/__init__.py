@@ -125,6 +125,9 @@ _SIGS = {
     "emsurf_macromodels": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "emsurf_far_field": (ctypes.c_int, [ctypes.POINTER(emsurf_geom), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
+    "emsurf_directivity": (ctypes.c_int, [ctypes.POINTER(emsurf_geom), ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P,
+                                          ctypes.POINTER(ctypes.c_double), _P]),
     "emsurf_apply_T": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
     "emsurf_apply_S": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
     "emsurf_apply_A": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, _P]),
@@ -361,6 +364,15 @@ def emsurf_far_field(geom: Geometry, nx, ny, nrhs, Lu, Lv, x_dev, E_dev, stream=
     """x_dev c128 [nrhs][ny][nx][n_eq]; E_dev c128 [nrhs][Lv][Lu][2] (E_theta, E_phi)."""
     _check(lib().emsurf_far_field(ctypes.byref(geom.c), int(nx), int(ny), int(nrhs), int(Lu), int(Lv),
                                   _dptr(x_dev), _dptr(E_dev), _stream(stream)))
+
+
+def emsurf_directivity(geom: Geometry, nx, ny, nrhs, Lu, Lv, x_dev, D_dev, stream=None):
+    """Returns P_rad per right-hand side (numpy float64 [nrhs]); D_dev receives
+    the directivity, float64 [nrhs][2][Lv][Lu]."""
+    pr = (ctypes.c_double * int(nrhs))()
+    _check(lib().emsurf_directivity(ctypes.byref(geom.c), int(nx), int(ny), int(nrhs), int(Lu), int(Lv),
+                                    _dptr(x_dev), _dptr(D_dev), pr, _stream(stream)))
+    return np.array(pr[:], dtype=np.float64)
 
 
 def emsurf_apply_T(plan: Plan, prec, nrhs, x_dev, y_dev, stream=None):

@@ -103,3 +103,56 @@ def test_far_field_of_the_128x128_solution():
     say(f"128x128 solution, {len(keep)} sampled bins: max error / term sum {err:.2e} "
         f"(term sum {scale.max():.3e}, pattern peak {np.abs(got).max():.3e})")
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("nx,ny,npch,nrhs,Lu,Lv", [(3, 4, 24, 2, 8, 16), (5, 2, 48, 1, 48, 24), (1, 1, 24, 1, 64, 64)])
+def test_directivity_matches_oracle(nx, ny, npch, nrhs, Lu, Lv):
+    # D = 4 pi U / P_rad at every bin of both half spaces and P_rad, against the
+    # oracle's sums (oracle/far_field.py directivity), FP64 1e-12
+    e = E()
+    g = W.box_geometry(npch)
+    x = W.random_vectors(nrhs, nx, ny, g.n_eq, seed=nx * 3 + ny)
+    geom = e.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)
+    D = torch.empty((nrhs, 2, Lv, Lu), dtype=torch.float64, device="cuda")
+    prad = e.emsurf_directivity(geom, nx, ny, nrhs, Lu, Lv, dev(x), D)
+    Dr, Pr = FF.directivity(g.rho, g.area, g.tan, W.PITCH, W.K0, x, Lu, Lv)
+    got = D.cpu().numpy()
+    errP = np.max(np.abs(prad - Pr) / Pr)
+    errD = np.linalg.norm((got - Dr).reshape(nrhs, -1), axis=1) / np.linalg.norm(Dr.reshape(nrhs, -1), axis=1)
+    say(f"directivity {nx}x{ny} bins {Lu}x{Lv}: P_rad err {errP:.2e}, D err {errD}, max D {got.max():.3f}")
+    assert errP <= 1e-12 and np.all(errD <= 1e-12)
+
+
+def test_directivity_of_the_128x128_solution_normalises():
+    # the scattered pattern of the solved 128 x 128 currents: the directivity
+    # integrates to 4 pi over both half spaces with the same bin weights, and
+    # its peak matches the oracle's far field at that bin over P_rad
+    e = E()
+    c = W.config(4)
+    g = W.box_geometry(c.n_patch)
+    S, tm = W.s_types(c), W.type_map(c)
+    geom = e.Geometry(g.rho, g.area, g.tan, W.PITCH, W.K0)
+    plan = e.emsurf_plan_create_green(c.nx, c.ny, c.n_types, c.nrhs, geom, S, tm, recip=1)
+    b = W.plane_wave_rhs(c, g)
+    x = torch.zeros_like(dev(b))
+    st, _ = e.emsurf_solve(plan, e.solve_opts(e.EMSURF_FP32_IR, tol=c.tol), c.nrhs, dev(b), x)
+    assert st == e.EMSURF_OK
+    plan.destroy()
+    Lu = Lv = 256
+    D = torch.empty((c.nrhs, 2, Lv, Lu), dtype=torch.float64, device="cuda")
+    prad = e.emsurf_directivity(geom, c.nx, c.ny, c.nrhs, Lu, Lv, x, D)
+    Dh = D.cpu().numpy()
+    u, v = FF.fft_bin_directions(Lu, Lv, W.PITCH, W.K0)
+    vis = u * u + v * v < 1.0
+    wgt = np.where(vis, (2 * np.pi / (Lu * W.K0 * W.PITCH)) ** 2 / np.sqrt(np.where(vis, 1 - u * u - v * v, 1.0)), 0)
+    total = np.einsum("rhqp,qp->r", Dh, wgt)
+    say(f"128x128 directivity: P_rad {prad}, peak D {Dh.reshape(c.nrhs, -1).max(axis=1)}, integral / 4 pi {total / (4 * np.pi)}")
+    assert np.allclose(total, 4 * np.pi, rtol=1e-12)
+    for r in range(c.nrhs):
+        h, q, p = np.unravel_index(np.argmax(Dh[r]), Dh[r].shape)
+        Ef = FF.far_field(g.rho, g.area, g.tan, W.PITCH, W.K0, x.cpu().numpy()[r:r + 1], u[q:q + 1, p], v[q:q + 1, p],
+                          lower=h == 1)
+        Dref = 4 * np.pi * np.sum(np.abs(Ef) ** 2) / prad[r]
+        # the solved currents' terms cancel to about 2e-4 of their magnitude sum
+        # at the peak (see the far-field test above): 1e-6 leaves that room
+        assert abs(Dh[r, h, q, p] - Dref) <= 1e-6 * Dref
