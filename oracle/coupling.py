@@ -18,7 +18,12 @@ integrals, which need its meshes; this build uses a point-sampled stand-in):
 
 tested at the centre of patch p on the test box, one-point quadrature over
 source patch q; J couples to J and M to M only; T(0) = 0 (the self term of a
-box belongs to its macromodel).
+box belongs to its macromodel).  When boxes touch (Sec. III-D: pitch equal
+to the box edge), patches of a shared face coincide (R = 0); there A_q g(R)
+is replaced by its average over a square source patch of the same area,
+    (4 a ln(1 + sqrt 2) - j k a^2) / (4 pi),   a = sqrt(A_q),
+the integral of 1/(4 pi R) over the square about its centre plus the first
+term of (exp(-jkR) - 1) / (4 pi R).
 
 Parity: pinned by closed-form entries (facing patches across the 0.05 gap,
 patch pairs at exactly one pitch), reciprocity of the Green's function, the
@@ -35,6 +40,13 @@ import numpy as np
 def green(R: np.ndarray, k: float) -> np.ndarray:
     """Scalar free-space Green's function exp(-jkR)/(4 pi R) (e^{+jwt} convention)."""
     return np.exp(-1j * k * R) / (4.0 * np.pi * R)
+
+
+def coincident_patch_term(A, k: float):
+    """A g(R) for a test point at the centre of its own (square) source patch of
+    area A: (4 a ln(1 + sqrt 2) - j k a^2) / (4 pi), a = sqrt(A)."""
+    a = np.sqrt(A)
+    return (4.0 * a * np.log(1.0 + np.sqrt(2.0)) - 1j * k * a * a) / (4.0 * np.pi)
 
 
 def tangent_products(tan: np.ndarray) -> np.ndarray:
@@ -59,7 +71,9 @@ def coupling_blocks_at(rho, area, tan, offsets, pitch: float, k: float) -> np.nd
     R = np.sqrt(np.sum(disp * disp, axis=-1))
     self_mask = (offsets[:, 0] == 0) & (offsets[:, 1] == 0)
     R[self_mask] = 1.0                      # value discarded below
-    G = green(R, k) * area[None, None, :]   # [o][p][q], weighted by the source area
+    touch = R <= 1e-9 * np.sqrt(area)[None, None, :]
+    G = green(np.where(touch, 1.0, R), k) * area[None, None, :]   # [o][p][q], weighted by the source area
+    G = np.where(touch, coincident_patch_term(area, k)[None, None, :], G)
     G[self_mask] = 0.0
     tt = tangent_products(tan)              # [2P][2P]
     half = G[:, :, None, :, None] * tt.reshape(P, 2, P, 2)[None]   # [o][p][a][q][b]
