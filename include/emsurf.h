@@ -446,6 +446,40 @@ emsurf_status emsurf_graph_create(emsurf_plan plan, int32_t op, emsurf_prec prec
 emsurf_status emsurf_graph_launch(emsurf_graph graph, void* stream);
 void emsurf_graph_destroy(emsurf_graph graph);
 
+/* ---- Touching fictitious surfaces (Sec. III-D, eqs. (connections_IUI), (final)) ----
+ * When the lattice pitch equals the box edge, adjacent boxes share faces and
+ * the shared faces' currents are expanded twice.  The paper keeps one set of
+ * unknowns through the sparse incidence U_o (Y = U_o Y~) and solves
+ * U_o^T [Z_eq + Z_o] U_o Y~ = U_o^T V.  Readings for the point-sampled
+ * patches: a patch of element (ix + 1, iy) or (ix, iy + 1) whose centre
+ * coincides with a patch of (ix, iy) is a duplicate, with currents
+ * x' = -sum_a (t'_b . t_a) x_a for both J and M (continuous tangential fields,
+ * opposite outward normals), the face staying with the lower-index element;
+ * with ground_plane = 1 the bottom face of every box (the patches with the
+ * lowest centres and horizontal tangents) lies on PEC and its M unknowns
+ * leave the system.  U_o's columns are the remaining unknowns in increasing
+ * full index m n_eq + u.  The coupling fill of such plans evaluates
+ * coincident test and source points with the square-patch average of the
+ * Green's function (emsurf_plan_create_green).  Z_eq + Z_o is D + T with
+ * D = -S^-1 per cell type (the block-Jacobi form), so the reduced operator is
+ *     y~ = U_o^T (T U_o x~ - S^-1 U_o x~).
+ * The handle keeps a pointer to the plan (destroy the handle first), S^-1 of
+ * every type (ERR_ARG if a macromodel is singular) and three max_rhs
+ * full-length vectors.  FP64 c128 throughout; calls on one handle must not
+ * overlap. */
+typedef struct emsurf_overlap_s* emsurf_overlap;
+emsurf_status emsurf_overlap_create(emsurf_plan plan, const emsurf_geom* geom, int32_t ground_plane, void* stream,
+                                    emsurf_overlap* out);
+/* sizes: full unknowns M n_eq, unique unknowns N~, device bytes (each may be NULL) */
+emsurf_status emsurf_overlap_query(emsurf_overlap ov, int64_t* n_full, int64_t* n_unique, size_t* bytes);
+/* x = U_o x~: x~ c128 [nrhs][N~] -> x c128 [nrhs][M n_eq] (async on stream) */
+emsurf_status emsurf_overlap_expand(emsurf_overlap ov, int32_t nrhs, const void* xt_dev, void* x_dev, void* stream);
+/* y~ = U_o^T y: y c128 [nrhs][M n_eq] -> y~ c128 [nrhs][N~] (async on stream) */
+emsurf_status emsurf_overlap_reduce(emsurf_overlap ov, int32_t nrhs, const void* y_dev, void* yt_dev, void* stream);
+/* y~ = U_o^T (D + T) U_o x~, nrhs <= the plan's max_rhs (async on stream) */
+emsurf_status emsurf_apply_reduced(emsurf_overlap ov, int32_t nrhs, const void* xt_dev, void* yt_dev, void* stream);
+void emsurf_overlap_destroy(emsurf_overlap ov);
+
 /* ---- Continuous-batching sessions (serving) ----
  * A session holds max_slots right-hand-side slots on one plan and its own
  * stream.  emsurf_session_submit places one right-hand side (c128

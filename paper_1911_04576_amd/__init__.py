@@ -136,6 +136,14 @@ _SIGS = {
     "emsurf_solve": (ctypes.c_int, [_P, ctypes.POINTER(emsurf_solve_opts), ctypes.c_int32, _P, _P,
                                     ctypes.POINTER(emsurf_solve_info), _P]),
     "emsurf_plan_query": (ctypes.c_int, [_P, ctypes.POINTER(emsurf_plan_stats)]),
+    "emsurf_overlap_create": (ctypes.c_int, [_P, ctypes.POINTER(emsurf_geom), ctypes.c_int32, _P,
+                                             ctypes.POINTER(_P)]),
+    "emsurf_overlap_query": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.POINTER(ctypes.c_size_t)]),
+    "emsurf_overlap_expand": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
+    "emsurf_overlap_reduce": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
+    "emsurf_apply_reduced": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
+    "emsurf_overlap_destroy": (None, [_P]),
     "emsurf_precond_create": (ctypes.c_int, [_P, ctypes.POINTER(emsurf_geom), ctypes.c_double, ctypes.c_int32,
                                              ctypes.c_int32, _P, _P, ctypes.POINTER(_P)]),
     "emsurf_precond_apply": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
@@ -410,6 +418,57 @@ def emsurf_solve(plan: Plan, opts: emsurf_solve_opts, nrhs, b_dev, x_dev, stream
     out = [dict(iters=i.iters, outer_iters=i.outer_iters, converged=bool(i.converged),
                 rel_res_true=i.rel_res_true, ms=i.ms) for i in infos]
     return st, out
+
+
+class Overlap:
+    """Handle of a touching-box incidence U_o (destroyed before its plan)."""
+
+    def __init__(self, handle, plan: Plan):
+        self.h = handle
+        self.plan = plan
+
+    def destroy(self):
+        if self.h:
+            lib().emsurf_overlap_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def sizes(self):
+        return emsurf_overlap_query(self)
+
+
+def emsurf_overlap_create(plan: Plan, geom: Geometry, ground_plane=0, stream=None) -> Overlap:
+    out = ctypes.c_void_p()
+    _check(lib().emsurf_overlap_create(plan.h, ctypes.byref(geom.c), int(ground_plane), _stream(stream),
+                                       ctypes.byref(out)))
+    return Overlap(out.value, plan)
+
+
+def emsurf_overlap_query(ov: Overlap):
+    nf, nu, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+    _check(lib().emsurf_overlap_query(ov.h, ctypes.byref(nf), ctypes.byref(nu), ctypes.byref(nb)))
+    return dict(n_full=nf.value, n_unique=nu.value, bytes=nb.value)
+
+
+def emsurf_overlap_expand(ov: Overlap, nrhs, xt_dev, x_dev, stream=None):
+    _check(lib().emsurf_overlap_expand(ov.h, int(nrhs), _dptr(xt_dev), _dptr(x_dev), _stream(stream)))
+
+
+def emsurf_overlap_reduce(ov: Overlap, nrhs, y_dev, yt_dev, stream=None):
+    _check(lib().emsurf_overlap_reduce(ov.h, int(nrhs), _dptr(y_dev), _dptr(yt_dev), _stream(stream)))
+
+
+def emsurf_apply_reduced(ov: Overlap, nrhs, xt_dev, yt_dev, stream=None):
+    _check(lib().emsurf_apply_reduced(ov.h, int(nrhs), _dptr(xt_dev), _dptr(yt_dev), _stream(stream)))
+
+
+def emsurf_overlap_destroy(ov: Overlap):
+    ov.destroy()
 
 
 class Precond:

@@ -130,14 +130,10 @@ __global__ void green_padded_kernel(const double* __restrict__ rho, const double
         const double ey = rho[3 * p + 1] - rho[3 * q + 1] + pitch * dy;
         const double ez = rho[3 * p + 2] - rho[3 * q + 2];
         const double R = sqrt(ex * ex + ey * ey + ez * ez);
-        double sn, cs;
-        sincos(k * R, &sn, &cs);
+        const double2 gq = area_green(R, area[q], k);
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-          if (dots[a] != 0.0) {
-            const double w = dots[a] * area[q] / (4.0 * 3.14159265358979323846 * R);
-            e[hv][a] = double2{w * cs, -w * sn};
-          }
+          if (dots[a] != 0.0) e[hv][a] = double2{dots[a] * gq.x, dots[a] * gq.y};
         }
       }
     }

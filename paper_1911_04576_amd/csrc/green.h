@@ -16,6 +16,21 @@ __device__ __forceinline__ int slot_to_offset(int s, int L, int N, bool* ok) {
   return 0;
 }
 
+// A exp(-jkR) / (4 pi R), the Green's function weighted by the source patch
+// area.  A test point on the centre of the source patch (touching boxes share
+// a face, Sec. III-D) takes the average over a square source patch of that
+// area instead: (4 a ln(1 + sqrt 2) - j k a^2) / (4 pi), a = sqrt(A) (the
+// static part integrated over the square, plus the first term of
+// (exp(-jkR) - 1) / (4 pi R)).
+__device__ __forceinline__ double2 area_green(double R, double A, double k) {
+  const double inv4pi = 0.25 / 3.14159265358979323846;
+  if (R * R <= 1e-18 * A) return double2{4.0 * sqrt(A) * 0.88137358701954302523 * inv4pi, -k * A * inv4pi};
+  double sn, cs;
+  sincos(k * R, &sn, &cs);
+  const double w = A * inv4pi / R;
+  return double2{w * cs, -w * sn};
+}
+
 // T(d)[(tau,p,a),(tau',q,b)] = delta(tau,tau') (t_pa . t_qb) A_q exp(-jkR)/(4 pi R),
 // R = |rho_p - rho_q + pitch (dx, dy, 0)|, T(0) = 0.
 __device__ __forceinline__ double2 green_entry(const double* __restrict__ rho, const double* __restrict__ area,
@@ -34,10 +49,8 @@ __device__ __forceinline__ double2 green_entry(const double* __restrict__ rho, c
   const double ey = rho[3 * p + 1] - rho[3 * q + 1] + pitch * dy;
   const double ez = rho[3 * p + 2] - rho[3 * q + 2];
   const double R = sqrt(ex * ex + ey * ey + ez * ez);
-  double sn, cs;
-  sincos(k * R, &sn, &cs);
-  const double w = dot * area[q] / (4.0 * 3.14159265358979323846 * R);
-  return double2{w * cs, -w * sn};
+  const double2 g = area_green(R, area[q], k);
+  return double2{dot * g.x, dot * g.y};
 }
 
 }  // namespace emsurf

@@ -290,6 +290,8 @@ struct GreenGeomDev {
 };
 // validate a box geometry (finite pitch > 0, areas > 0) and copy it to the device
 void upload_geom(const emsurf_geom* g, GreenGeomDev& d);
+// a patch centre of one box coincides with one of an adjacent box (touching boxes)
+bool boxes_touch(const emsurf_geom* g);
 // caller blocks: `parts` row-major nb x nb matrices per offset (1 x n_eq dense; 2 x n_h for L, K)
 // vperm: columns in the pair_fill_v order (dense blocks only)
 void launch_pad_blocks(const void* T_blocks_dev, int nx, int ny, int nb, int parts, int Lx, int Ly, int64_t c0,

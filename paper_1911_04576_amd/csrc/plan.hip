@@ -247,6 +247,22 @@ void apply_A_typed(emsurf_plan p, Cx tx, Cx tc, Cx ty, int nrhs, const void* x, 
   launch_apply_S(tc, tc, ty, S, p->tiles, p->d.n_eq, p->M, nrhs, w.t.p, x, y, s);
 }
 
+bool boxes_touch(const emsurf_geom* g) {
+  const int P = g->n_patch;
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) {
+      if (dx == 0 && dy == 0) continue;
+      for (int p = 0; p < P; ++p)
+        for (int q = 0; q < P; ++q) {
+          const double ex = g->rho[3 * p] - g->rho[3 * q] + g->pitch * dx;
+          const double ey = g->rho[3 * p + 1] - g->rho[3 * q + 1] + g->pitch * dy;
+          const double ez = g->rho[3 * p + 2] - g->rho[3 * q + 2];
+          if (ex * ex + ey * ey + ez * ez <= 1e-18 * g->area[q]) return true;
+        }
+    }
+  return false;
+}
+
 void upload_geom(const emsurf_geom* g, GreenGeomDev& d) {
   EMS_CHECK_ARG(g != nullptr && g->rho && g->area && g->tan, "geometry pointers must be non-NULL");
   EMS_CHECK_ARG(g->n_patch >= 1, "n_patch must be >= 1");
@@ -591,6 +607,8 @@ emsurf_status emsurf_plan_create_green(const emsurf_plan_desc* desc, const emsur
     EMS_CHECK_ARG(desc->form != EMSURF_T_LK || geom->k > 0, "the structured fill needs a wavenumber k > 0");
     GreenGeomDev g;
     upload_geom(geom, g);
+    EMS_CHECK_ARG(desc->form != EMSURF_T_LK || !boxes_touch(geom),
+                  "the structured fill needs boxes that do not touch (its gradient terms are singular there)");
     p = new_plan(desc);
     if (desc->recip) {
       // the fill weights each source by its patch area: W = that area per unknown
@@ -640,6 +658,8 @@ emsurf_status emsurf_fill_LK_point_green(const emsurf_geom* geom, int32_t nx, in
     hipStream_t s = static_cast<hipStream_t>(stream);
     GreenGeomDev g;
     upload_geom(geom, g);
+    EMS_CHECK_ARG(!boxes_touch(geom),
+                  "the structured fill needs boxes that do not touch (its gradient terms are singular there)");
     launch_lk_blocks(g, nx, ny, LK_blocks_dev, s);
     EMS_HIP(hipStreamSynchronize(s));
   });
