@@ -299,6 +299,37 @@ def multi_rhs_section(E, W, torch, np):
                             np.linalg.norm(ref.reshape(nrhs, -1), axis=1)))
 
     err32 = err_vs(out)
+    # the reciprocal store (one block per pair {k, -k}, Sec. IV-A symmetry):
+    # both products of a pair from one read of its block, 16 RHS per pass
+    rplan = E.emsurf_plan_create_green(cfg.nx, cfg.ny, cfg.n_types, nrhs, geom, S, tm, recip=1,
+                                       store=E.EMSURF_STORE_FP32)
+    r_stored = rplan.stats().n_stored
+    yr32 = torch.empty_like(x32)
+    for _ in range(2):
+        E.emsurf_apply_T(rplan, E.EMSURF_FP32, nrhs, x32, yr32)
+    torch.cuda.synchronize()
+    E.emsurf_kernel_timing(rplan, True)
+    E.emsurf_kernel_times(rplan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        E.emsurf_apply_T(rplan, E.EMSURF_FP32, nrhs, x32, yr32)
+    torch.cuda.synchronize()
+    r_apply = 1e3 * (time.perf_counter() - t0) / reps
+    ph = E.emsurf_kernel_times(rplan)
+    E.emsurf_kernel_timing(rplan, False)
+    r_bms = ph["block_product"][0] / max(1, ph["block_product"][1])
+    r_bytes = r_stored * n * n * 8 + 2 * P * nrhs * n * 8
+    recip_sec = {
+        "kernel": "pair_mfma_kernel<float, 5, 16, true, true> (16 RHS per pass in two B tiles)",
+        "stored_blocks": r_stored,
+        "block_product_ms": round(r_bms, 4), "block_product_TFs": round(flops / (r_bms / 1e3) / 1e12, 2),
+        "frac_fp32_mfma_peak": round(flops / (r_bms / 1e3) / 1e12 / MFMA_FP32_PEAK_TFS, 4),
+        "algorithmic_bytes": r_bytes, "block_product_GBs": round(r_bytes / (r_bms / 1e3) / 1e9, 1),
+        "apply_T_ms": round(r_apply, 4), "unknowns_rhs_per_s": cfg.n_unknowns * nrhs / (r_apply / 1e3),
+        "fp32_rel_err_vs_fp64": err_vs(yr32.cpu().numpy().astype(np.complex128))}
+    log(f"64x64 reciprocal store: {recip_sec}")
+    rplan.destroy()
     # split-bfloat16 products (three or one matrix-core products per entry) on
     # the split store: same FP32 FFTs, timed the same way
     split = {}
@@ -341,6 +372,7 @@ def multi_rhs_section(E, W, torch, np):
            "apply_T_ms": round(apply_ms, 4),
            "unknowns_rhs_per_s": cfg.n_unknowns * nrhs / (apply_ms / 1e3),
            "fp32_rel_err_vs_fp64": err32,
+           "reciprocal_store": recip_sec,
            "split_bf16": split}
     e = (cfg.ny // 3, cfg.nx // 2)
     sec["_sample"] = {"element": e, "b": b, "geom": g,
@@ -1029,7 +1061,7 @@ def main():
                    "lattice": [cfg.nx, cfg.ny], "n_eq": n, "nrhs": nrhs,
                    "unknowns": cfg.n_unknowns, "padded_fft": [Lx, Ly], "stored_blocks": Ps,
                    "parallelism": "1 GPU"},
-        "roofline": {"kernel": ("pair_mfma_kernel<float, 3, 4, true> (paired Fourier-domain block product, matrix cores)" if recip
+        "roofline": {"kernel": ("pair_mfma_kernel<float, 3, 4, true, false> (paired Fourier-domain block product, matrix cores)" if recip
                                 else "block_gemv_kernel<float2,4,8> (Fourier-domain block product)"),
                      "bound": "hbm",
                      "achieved": round(bp_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

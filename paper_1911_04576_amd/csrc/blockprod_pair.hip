@@ -20,43 +20,60 @@
 // v_mfma_f64_16x16x4f64) on the real embedding of the complex products: for
 // an A operand of 16 rows x 4 k-slots the slots are (source index pair,
 // real / imaginary part), and the B operand columns are the real parts
-// (columns r < NR) and imaginary parts (NR <= column < 2 NR) of the outputs:
+// (columns r < NRT) and imaginary parts (NRT <= column < 2 NRT) of NRT
+// outputs:
 //     part 0 (re M): B = [ xr | xi ],   part 1 (im M): B = [ -xi | xr ].
-// Wavefront w owns u tiles w, w + 4, ... (TPW of them) and visits every v
-// tile; for tile (t, q) it runs 8 MFMAs of the first product (A = the tile
-// with rows u, read straight from HBM in the lane order of the store) into
-// the tile's row accumulator, and 8 of the transposed product (A = the tile
-// transposed, staged through LDS) into the v tile's column sums, which are
-// added into LDS once per v tile.  Wavefronts 0 and 1 add into one column-sum
-// buffer and wavefronts 2 and 3 into another: with two addends per entry the
-// LDS float addition gives the same bits in either order (0 + a = a, and
-// a + b = b + a), and the two buffers are added in a fixed order at the end,
-// so every output has one rounding sequence whatever the wavefront timing.
-// The second buffer has a region of its own, or (OVL, where that region would
-// cost a workgroup per CU) takes the place of W xh[-k] once its values are in
-// registers, which costs two more barriers per workgroup.
-// Up to 8 right-hand sides per pass
-// (2 NR <= 16 MFMA columns).  The two instructions share their A and B
-// layouts (lane l: A[l % 16][l / 16], B[l / 16][l % 16]); the result rows
-// differ: lane l, register e holds row 4 (l / 16) + e in FP32 and row
-// l / 16 + 4 e in FP64.
+// A pass takes NRW = 4, 8 or 16 right-hand sides, in NCT = 1 or 2 such
+// B tiles of NRT = min(NRW, 8) right-hand sides.  The two instructions share
+// their A and B layouts (lane l: A[l % 16][l / 16], B[l / 16][l % 16]); the
+// result rows differ: lane l, register e holds row 4 (l / 16) + e in FP32 and
+// row l / 16 + 4 e in FP64.
 //
-// The blocks are read non-temporally with buffer loads; two tiles are in
-// flight per wavefront and the next request is unconditional (a visit index
-// past the end re-reads the last tile) so that every wait covers only the
-// older stage.  The row sums are staged in LDS at the end and both products
-// leave as coalesced non-temporal stores.
+// Wavefront w owns u tiles w, w + 4, ... (ntw <= TPW of them) and visits the
+// v tiles in nt steps, v tile (q + w) mod nt at step q, so that the four
+// wavefronts are on four different v tiles at every step.  For tile (t, v) it
+// runs 8 MFMAs per B tile of the first product (A = the tile with rows u,
+// read straight from HBM in the lane order of the store) into the tile's row
+// accumulator, and 8 of the transposed product (A = the tile transposed,
+// staged through LDS) into the v tile's column sums, which the wavefront adds
+// into one LDS buffer at the end of the step (plain loads and stores: no other
+// wavefront touches that v tile during the step); a barrier closes each step.  So
+// every column sum receives its four addends in a fixed order (that of the
+// steps), every row sum its v tiles in a fixed order, and the bits of every
+// output are the same whatever the wavefront timing and whichever columns
+// share the pass.  The column sums take the place of W xh[-k] once its values
+// are in registers (OVL), where the LDS would otherwise cost a workgroup per
+// CU.
+//
+// The blocks are read non-temporally with buffer loads; each wavefront keeps
+// one tile in flight per u tile it owns, and the next request is
+// unconditional (a visit index past the end re-reads the last tile) so that
+// every wait covers only the oldest tile.  The row sums are staged in LDS at
+// the end and both products leave as coalesced non-temporal stores.
 #include "internal.h"
 
 namespace emsurf {
 namespace {
 
 constexpr int PNT = 256;  // threads per workgroup
-// LDS stages of the transposed staging per wavefront: two in FP32; one in
-// FP64, which brings a workgroup at n_eq 192 and 4 RHS under 54 KB, so that
-// three fit a CU (a wavefront's LDS operations complete in order, so the next
-// tile's writes cannot overtake the reads of the current one)
-template <typename T> constexpr int pair_stages() { return sizeof(T) == 8 ? 1 : 2; }
+// Transposed staging of one wavefront: one tile of 16 rows of 32 values (a
+// wavefront's LDS operations complete in order, so the next tile's writes
+// cannot overtake the reads of the current one, and one stage suffices).
+// The rows carry 16 bytes of padding, or (SWZ) their 16-byte chunks are
+// permuted by a key of the row instead, where the LDS has no room for the
+// padding; either way the 16-byte reads of one instruction (rows 0..15 at
+// the same place) start on distinct banks.
+template <typename T, bool SWZ> constexpr int pair_row_vals() { return SWZ ? 32 : 32 + 16 / (int)sizeof(T); }
+template <typename T, bool SWZ> constexpr int pair_stage_vals() { return 16 * pair_row_vals<T, SWZ>(); }
+// 16 right-hand sides per pass: the staging without padding
+constexpr bool pair_swz(int nrw) { return nrw > 8; }
+
+// Wavefronts per SIMD that the LDS of a workgroup leaves room for at the
+// sizes each instance serves (FP32 up to 3 u tiles and 8 right-hand sides:
+// four workgroups per CU; FP64 beyond 3 u tiles: one), as the register budget
+template <typename T> constexpr int pair_min_waves(int tpw, int nrw) {
+  return sizeof(T) == 4 ? (tpw <= 3 && nrw <= 8 ? 4 : 2) : (tpw <= 3 ? 2 : 1);
+}
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d2v __attribute__((ext_vector_type(2)));
@@ -89,65 +106,75 @@ __device__ __forceinline__ C ld_chunk(__amdgpu_buffer_rsrc_t rs, unsigned voff, 
   return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 2));
 }
 
-// T = float or double; TPW u tiles per wavefront; NRW right-hand sides per
-// pass (4 or 8: the MFMA columns used, 2 NRW of 16).  B2R keeps the B
-// operands of the transposed product in registers for the whole block (else
-// they are rebuilt from LDS for every tile).  OVL (needs B2R): the second
-// column-sum buffer overlays W xh[-k].
+// Column sums and row sums in LDS: [np][2 NRW], right-hand side r, part p at
+// column (r / NRT) 2 NRT + p NRT + r % NRT; the columns of row v are permuted
+// by XOR with v, so that the output loop (consecutive v per lane, one column)
+// does not hit one bank
+template <int NRW> __device__ __forceinline__ int sum_idx(int v, int col) {
+  return v * 2 * NRW + (col ^ (v & (2 * NRW - 1)));
+}
+template <int NRW> __device__ __forceinline__ int sum_col(int r, int p) {
+  constexpr int NRT = NRW > 8 ? 8 : NRW;
+  return (r / NRT) * 2 * NRT + p * NRT + r % NRT;
+}
+
+// T = float or double; TPW u tiles per wavefront at most; NRW right-hand
+// sides per pass (4, 8, or 16 in FP32).  B2R keeps the B operands of the
+// transposed product in registers for the whole block (else they are rebuilt
+// from LDS for every tile).  OVL (needs B2R): the column sums overlay
+// W xh[-k].
 template <typename T, int TPW, int NRW, bool B2R, bool OVL>
-__global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__ That, const int2* __restrict__ pairs,
-                                                           const T* __restrict__ w, const T* __restrict__ winv,
-                                                           const typename Mf<T>::V2* __restrict__ xh,
-                                                           typename Mf<T>::V2* __restrict__ yh, int n, int nrhs, int r0,
-                                                           int nr) {
+__global__ void __launch_bounds__(PNT, pair_min_waves<T>(TPW, NRW)) pair_mfma_kernel(
+    const T* __restrict__ That, const int2* __restrict__ pairs, const T* __restrict__ w, const T* __restrict__ winv,
+    const typename Mf<T>::V2* __restrict__ xh, typename Mf<T>::V2* __restrict__ yh, int n, int nrhs, int r0, int nr) {
   using M = Mf<T>;
   using C = typename M::C;
   using Acc = typename M::Acc;
   using V2 = typename M::V2;
   constexpr int CH = M::CH, NCH = 8 / CH;   // chunks per lane per tile
+  constexpr int NCT = NRW > 8 ? 2 : 1;      // B tiles
+  constexpr int NRT = NRW / NCT;            // right-hand sides per B tile
+  constexpr bool SWZ = pair_swz(NRW);
+  constexpr int TROW = pair_row_vals<T, SWZ>();
   constexpr int TILE_BYTES = 2 * PAIR_TILE * PAIR_TILE * (int)sizeof(T);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nt = pair_tiles(n), np = nt * PAIR_TILE;
+  const int tid = (int)threadIdx.x;
   T* xs = reinterpret_cast<T*>(smem_raw);  // [np][NRW][2]: xh[k]; row sums at the end
   T* xt = xs + np * NRW * 2;               // [np][NRW][2]: W xh[-k]
-  T* zs = xt + np * NRW * 2;               // [np][2 NRW]: column sums of wavefronts 0, 1
-  // column sums of wavefronts 2, 3
-  T* zs2 = OVL ? xt : zs + np * 2 * NRW;
-  T* tiles = zs + np * 2 * NRW * (OVL ? 1 : 2);   // [4 waves][stages][512]
+  T* zs = OVL ? xt : xt + np * NRW * 2;    // column sums
+  T* tiles = xt + np * NRW * 2 * (OVL ? 1 : 2);   // [4 waves][16 rows][TROW]
   const long long slot = blockIdx.x;
   const int2 pr = pairs[slot];
   const long long k = pr.x, kb = pr.y;
   const bool self = k == kb;
-  const int l = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int ntw = (nt - wv + 3) / 4;  // u tiles of this wavefront (<= TPW)
   const long long blk = (long long)nt * nt * 2 * PAIR_TILE * PAIR_TILE;  // reals
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(That + slot * blk), (short)0, (int)(blk * (long long)sizeof(T)), 0x00020000);
   const unsigned voff = (unsigned)(l * 16);   // chunk m of this lane sits 1024 m bytes on
   // this wavefront's tiles are stored contiguously in visiting order
-  // it = q * ntw + ta (u tile wv + 4 ta, v tile q)
+  // it = q * ntw + ta (u tile wv + 4 ta, step q)
   const int nvisit = ntw * nt, wbase_tile = pair_wave_base(nt, wv);
+  // visit it, clamped to the wavefront's tiles (a wavefront without tiles
+  // reads the block's first tile and uses none of it)
   auto visit_off = [&](int it) {
     if (it > nvisit - 1) it = nvisit - 1;
-    return (wbase_tile + it) * TILE_BYTES;
+    if (it < 0) it = 0;
+    return nvisit > 0 ? (wbase_tile + it) * TILE_BYTES : 0;
   };
-  // two tiles in flight: p (current) and nx (next)
-  C p[NCH], nx[NCH];
+  // one tile in flight per u tile of the wavefront: while tile (q, ta) is
+  // used, the tiles of the rest of step q and of step q + 1 up to ta - 1 are
+  // on their way (every slot is requested, whatever ntw: see the sweep)
+  C buf[TPW][NCH];
 #pragma unroll
-  for (int m = 0; m < NCH; ++m) {
-    p[m] = C{};
-    nx[m] = C{};
-  }
-  if (ntw > 0) {
+  for (int ta = 0; ta < TPW; ++ta)
 #pragma unroll
-    for (int m = 0; m < NCH; ++m) {
-      p[m] = ld_chunk<C>(rs, voff + 1024 * m, visit_off(0));
-      nx[m] = ld_chunk<C>(rs, voff + 1024 * m, visit_off(1));
-    }
-  }
+    for (int m = 0; m < NCH; ++m) buf[ta][m] = ld_chunk<C>(rs, voff + 1024 * m, visit_off(ta));
   const V2* x0 = xh + k * (long long)nrhs * n + (long long)r0 * n;
   const V2* x1 = xh + kb * (long long)nrhs * n + (long long)r0 * n;
-  for (int e = threadIdx.x; e < np * NRW; e += PNT) {
+  for (int e = tid; e < np * NRW; e += PNT) {
     const int r = e / np, v = e - r * np;
     V2 a{0, 0}, b{0, 0};
     if (r < nr && v < n) {
@@ -160,148 +187,198 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
     xt[(v * NRW + r) * 2] = b.x;
     xt[(v * NRW + r) * 2 + 1] = b.y;
   }
-  for (int e = threadIdx.x; e < np * 2 * NRW; e += PNT) zs[e] = T(0);
   if constexpr (!OVL)
-    for (int e = threadIdx.x; e < np * 2 * NRW; e += PNT) zs2[e] = T(0);
+    for (int e = tid; e < np * 2 * NRW; e += PNT) zs[e] = T(0);
   __syncthreads();
   // lane roles: k-slot kk = l / 16 -> (pair offset off, part); column jj = l % 16
   const int kk = l >> 4, jj = l & 15, off = kk >> 1, part = kk & 1, a16 = l & 15;
-  const bool jre = jj < NRW, jok = jj < 2 * NRW;
-  const int rj = jre ? jj : (jok ? jj - NRW : 0);
-  auto bval = [&](const T* x, int idx) {
+  const bool jre = jj < NRT, jok = jj < 2 * NRT;
+  const int rjt = jre ? jj : (jok ? jj - NRT : 0);
+  // B operand value of B tile c at source index idx
+  auto bval = [&](const T* x, int idx, int c) {
+    const int rj = c * NRT + rjt;
     const T xr = x[(idx * NRW + rj) * 2], xi = x[(idx * NRW + rj) * 2 + 1];
     const T val = part == 0 ? (jre ? xr : xi) : (jre ? -xi : xr);
     return jok ? val : T(0);
   };
   constexpr int NB2 = B2R ? TPW : 1;
-  T b2[NB2][8];
+  T b2[NB2][NCT][8];
 #pragma unroll
   for (int ta = 0; ta < NB2; ++ta)
 #pragma unroll
-    for (int s = 0; s < 8; ++s) b2[ta][s] = B2R && ta < ntw ? bval(xt, (wv + 4 * ta) * PAIR_TILE + 2 * s + off) : T(0);
+    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+        b2[ta][c][s] = B2R && ta < ntw ? bval(xt, (wv + 4 * ta) * PAIR_TILE + 2 * s + off, c) : T(0);
   if constexpr (OVL) {
-    // xt becomes the second column-sum buffer
+    // xt becomes the column-sum buffer
     __syncthreads();
-    for (int e = threadIdx.x; e < np * 2 * NRW; e += PNT) zs2[e] = T(0);
+    for (int e = tid; e < np * 2 * NRW; e += PNT) zs[e] = T(0);
     __syncthreads();
   }
-  Acc acc[TPW];
+  Acc acc[TPW][NCT];
 #pragma unroll
-  for (int ta = 0; ta < TPW; ++ta) acc[ta] = Acc{};
+  for (int ta = 0; ta < TPW; ++ta)
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) acc[ta][c] = Acc{};
   // transposed staging: value s of this lane, entry (u = a16, v = 2 s + off, part), goes to
-  // ((v * 2 + part) * 2 + u % 2) * 8 + u / 2; lane l then reads its 8 transposed operands
-  // (u = 2 s + off, v = a16, part) as 8 consecutive values
-  const int wbase = (part * 2 + (a16 & 1)) * 8 + (a16 >> 1);
-  const int rbase = ((a16 * 2 + part) * 2 + off) * 8;
-  constexpr int NSTG = pair_stages<T>();
-  T* tw = tiles + wv * NSTG * 512;
-  int stage = 0;
-  // B operands of the first product for v tile q, built one v tile ahead
-  T b1n[8];
+  // row v, place (part * 2 + u % 2) * 8 + u / 2; lane l then reads its 8 transposed operands
+  // (u = 2 s + off, v = a16, part) as 8 consecutive values of row a16 (with SWZ, the 16-byte
+  // chunks of row v permuted by XOR with (v % 8) ^ (v / 8 % 2))
+  T* Tw = tiles + wv * pair_stage_vals<T, SWZ>();
+  const int wplace = (part * 2 + (a16 & 1)) * 8 + (a16 >> 1);
+  const int wbase = off * TROW + wplace;
+  auto wpos = [&](int s) {
+    if constexpr (SWZ) {
+      const int v = 2 * s + off, key = (v & 7) ^ ((v >> 3) & 1);
+      return v * TROW + ((wplace / CH) ^ key) * CH + wplace % CH;
+    } else {
+      return 2 * s * TROW + wbase;
+    }
+  };
+  const int rplace = (part * 2 + off) * 8;
+  const int rkey = (a16 & 7) ^ ((a16 >> 3) & 1);
+  auto rpos = [&](int m) {
+    if constexpr (SWZ)
+      return a16 * TROW + ((rplace / CH + m) ^ rkey) * CH;
+    else
+      return a16 * TROW + rplace + m * CH;
+  };
+  // v tile of step q for this wavefront
+  auto vtile = [&](int q) { return (q + wv) % nt; };
+  // B operands of the first product for the v tile of step q, built one step ahead
+  T b1n[NCT][8];
 #pragma unroll
-  for (int s = 0; s < 8; ++s) b1n[s] = bval(xs, 2 * s + off);
+  for (int c = 0; c < NCT; ++c)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) b1n[c][s] = bval(xs, vtile(0) * PAIR_TILE + 2 * s + off, c);
   for (int q = 0; q < nt; ++q) {
-    T b1[8];
+    const int vq = vtile(q);
+    T b1[NCT][8];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) b1[s] = b1n[s];
-    const int qn = q + 1 < nt ? q + 1 : q;
+    for (int c = 0; c < NCT; ++c)
 #pragma unroll
-    for (int s = 0; s < 8; ++s) b1n[s] = bval(xs, qn * PAIR_TILE + 2 * s + off);
-    Acc zq{};
+      for (int s = 0; s < 8; ++s) b1[c][s] = b1n[c][s];
+    const int vn = vtile(q + 1 < nt ? q + 1 : q);
+#pragma unroll
+    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) b1n[c][s] = bval(xs, vn * PAIR_TILE + 2 * s + off, c);
+    Acc zq[NCT];
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) zq[c] = Acc{};
 #pragma unroll
     for (int ta = 0; ta < TPW; ++ta) {
-      if (ta < ntw) {
-        T a1[8];
+      const bool live = ta < ntw;
+      C cr[NCH];
+      if (live) {
 #pragma unroll
-        for (int m = 0; m < NCH; ++m)
-#pragma unroll
-          for (int c = 0; c < CH; ++c) a1[m * CH + c] = p[m][c];
-        T* Tw = tw + stage * 512;
-#pragma unroll
-        for (int s = 0; s < 8; ++s) Tw[(2 * s + off) * 32 + wbase] = a1[s];
+        for (int s = 0; s < 8; ++s) Tw[wpos(s)] = buf[ta][s / CH][s % CH];
         __builtin_amdgcn_wave_barrier();
-        C cr[NCH];
 #pragma unroll
-        for (int m = 0; m < NCH; ++m) cr[m] = *reinterpret_cast<const C*>(Tw + rbase + m * CH);
-        const int noff = visit_off(q * ntw + ta + 2);
-#pragma unroll
-        for (int m = 0; m < NCH; ++m) {
-          p[m] = nx[m];
-          nx[m] = ld_chunk<C>(rs, voff + 1024 * m, noff);
-        }
+        for (int m = 0; m < NCH; ++m) cr[m] = *reinterpret_cast<const C*>(Tw + rpos(m));
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int s = 0; s < 8; ++s) acc[ta] = M::mfma(a1[s], b1[s], acc[ta]);
-        __builtin_amdgcn_sched_barrier(0);
-        T bt[8];
 #pragma unroll
         for (int s = 0; s < 8; ++s)
-          bt[s] = B2R ? b2[B2R ? ta : 0][s] : bval(xt, (wv + 4 * ta) * PAIR_TILE + 2 * s + off);
 #pragma unroll
-        for (int m = 0; m < NCH; ++m)
+          for (int c = 0; c < NCT; ++c) acc[ta][c] = M::mfma(buf[ta][s / CH][s % CH], b1[c][s], acc[ta][c]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // the slot's registers are free: request its tile of step q + 1 (every
+      // slot requests one, whatever ntw, so that each wait covers exactly
+      // the oldest tile; a slot past ntw repeats the request before it)
+      const int noff = visit_off((q + 1) * ntw + (live ? ta : ntw - 1));
 #pragma unroll
-          for (int c = 0; c < CH; ++c) zq = M::mfma(cr[m][c], bt[m * CH + c], zq);
-        stage = NSTG == 2 ? stage ^ 1 : 0;
+      for (int m = 0; m < NCH; ++m) buf[ta][m] = ld_chunk<C>(rs, voff + 1024 * m, noff);
+      if (live) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+#pragma unroll
+          for (int c = 0; c < NCT; ++c) {
+            const T bt = B2R ? b2[B2R ? ta : 0][c][s] : bval(xt, (wv + 4 * ta) * PAIR_TILE + 2 * s + off, c);
+            zq[c] = M::mfma(cr[s / CH][s % CH], bt, zq[c]);
+          }
       }
     }
     if (!self && ntw > 0) {
-      T* zd = wv < 2 ? zs : zs2;
+      // the v tile is this wavefront's alone during the step: a plain
+      // read, add and write (LDS float atomics are far slower).  FP32 rows
+      // 4 (l / 16) + e: the four lane groups start at register (e + l / 16)
+      // % 4, so that one access touches four rows that are not a multiple
+      // of the bank count apart
+      int zi[NCT][4];
+      T zo[NCT][4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (jok) atomicAdd(&zd[(q * PAIR_TILE + M::row(l, e)) * 2 * NRW + jj], zq[e]);
+      for (int c = 0; c < NCT; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int er = sizeof(T) == 4 ? (e + kk) & 3 : e;
+          zi[c][e] = sum_idx<NRW>(vq * PAIR_TILE + M::row(l, er), c * 2 * NRT + jj);
+          zo[c][e] = jok ? zs[zi[c][e]] : T(0);
+        }
+#pragma unroll
+      for (int c = 0; c < NCT; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int er = sizeof(T) == 4 ? (e + kk) & 3 : e;
+          const T val = er == 0 ? zq[c][0] : er == 1 ? zq[c][1] : er == 2 ? zq[c][2] : zq[c][3];
+          if (jok) zs[zi[c][e]] = zo[c][e] + val;
+        }
     }
+    // the next step's adds to this v tile come from another wavefront
+    __syncthreads();
   }
   // outputs: the row sums are staged in LDS over the spectral columns of
   // xh[k] (no longer read once every wavefront is past its loop), in the
   // layout of the column sums, and both products leave as coalesced
   // non-temporal stores of 16 bytes per lane
-  __syncthreads();
   T* ys = xs;  // [np][2 NRW]: row sums (yh[k])
 #pragma unroll
   for (int ta = 0; ta < TPW; ++ta) {
     if (ta < ntw) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int u = (wv + 4 * ta) * PAIR_TILE + M::row(l, e);
-        if (jok) ys[u * 2 * NRW + jj] = acc[ta][e];
-      }
+      for (int c = 0; c < NCT; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int u = (wv + 4 * ta) * PAIR_TILE + M::row(l, e);
+          if (jok) ys[sum_idx<NRW>(u, c * 2 * NRT + jj)] = acc[ta][c][e];
+        }
     }
   }
   __syncthreads();
   V2* y0 = yh + k * (long long)nrhs * n + (long long)r0 * n;
   V2* y1 = yh + kb * (long long)nrhs * n + (long long)r0 * n;
   if constexpr (sizeof(T) == 8) {
-    for (int e = threadIdx.x; e < nr * n; e += PNT) {
+    for (int e = tid; e < nr * n; e += PNT) {
       const int r = e / n, v = e - r * n;
-      const int c0 = v * 2 * NRW + r;
-      __builtin_nontemporal_store(d2v{ys[c0], ys[c0 + NRW]}, reinterpret_cast<d2v*>(y0 + e));
+      const int cr0 = sum_idx<NRW>(v, sum_col<NRW>(r, 0)), ci0 = sum_idx<NRW>(v, sum_col<NRW>(r, 1));
+      __builtin_nontemporal_store(d2v{ys[cr0], ys[ci0]}, reinterpret_cast<d2v*>(y0 + e));
       if (!self) {
         const double wi = winv[v];
-        __builtin_nontemporal_store(d2v{(zs[c0] + zs2[c0]) * wi, (zs[c0 + NRW] + zs2[c0 + NRW]) * wi},
-                                    reinterpret_cast<d2v*>(y1 + e));
+        __builtin_nontemporal_store(d2v{zs[cr0] * wi, zs[ci0] * wi}, reinterpret_cast<d2v*>(y1 + e));
       }
     }
   } else {
     if ((n & 1) == 0) {
       // two complex values per 16-byte store
-      for (int e2 = threadIdx.x; e2 < nr * n / 2; e2 += PNT) {
+      for (int e2 = tid; e2 < nr * n / 2; e2 += PNT) {
         const int e = 2 * e2, r = e / n, v = e - r * n;   // v + 1 < n in the same row r
-        const int c0 = v * 2 * NRW + r, c1 = c0 + 2 * NRW;
-        const f4v a = {ys[c0], ys[c0 + NRW], ys[c1], ys[c1 + NRW]};
-        __builtin_nontemporal_store(a, reinterpret_cast<f4v*>(y0 + e));
+        const int colr = sum_col<NRW>(r, 0), coli = sum_col<NRW>(r, 1);
+        const int a0 = sum_idx<NRW>(v, colr), a1 = sum_idx<NRW>(v, coli);
+        const int b0 = sum_idx<NRW>(v + 1, colr), b1 = sum_idx<NRW>(v + 1, coli);
+        __builtin_nontemporal_store(f4v{ys[a0], ys[a1], ys[b0], ys[b1]}, reinterpret_cast<f4v*>(y0 + e));
         if (!self) {
           const float w0 = winv[v], w1 = winv[v + 1];
-          const f4v b = {(zs[c0] + zs2[c0]) * w0, (zs[c0 + NRW] + zs2[c0 + NRW]) * w0, (zs[c1] + zs2[c1]) * w1,
-                         (zs[c1 + NRW] + zs2[c1 + NRW]) * w1};
-          __builtin_nontemporal_store(b, reinterpret_cast<f4v*>(y1 + e));
+          __builtin_nontemporal_store(f4v{zs[a0] * w0, zs[a1] * w0, zs[b0] * w1, zs[b1] * w1},
+                                      reinterpret_cast<f4v*>(y1 + e));
         }
       }
     } else {
-      for (int e = threadIdx.x; e < nr * n; e += PNT) {
+      for (int e = tid; e < nr * n; e += PNT) {
         const int r = e / n, v = e - r * n;
-        const int c0 = v * 2 * NRW + r;
-        y0[e] = V2{ys[c0], ys[c0 + NRW]};
-        if (!self) y1[e] = V2{(zs[c0] + zs2[c0]) * winv[v], (zs[c0 + NRW] + zs2[c0 + NRW]) * winv[v]};
+        const int cr0 = sum_idx<NRW>(v, sum_col<NRW>(r, 0)), ci0 = sum_idx<NRW>(v, sum_col<NRW>(r, 1));
+        y0[e] = V2{ys[cr0], ys[ci0]};
+        if (!self) y1[e] = V2{zs[cr0] * winv[v], zs[ci0] * winv[v]};
       }
     }
   }
@@ -311,19 +388,24 @@ __global__ void __launch_bounds__(PNT, 2) pair_mfma_kernel(const T* __restrict__
 // tiles per wavefront; beyond that they are rebuilt from LDS per tile
 template <typename T> constexpr bool pair_b2r(int tpw) { return sizeof(T) == 4 || tpw <= 2; }
 
-// LDS of a workgroup: spectral inputs xh[k] and W xh[-k], two column-sum
-// buffers (one of them over W xh[-k] when ovl), the transposed staging
+// LDS of a workgroup: spectral inputs xh[k] and W xh[-k], the column sums
+// (over W xh[-k] when ovl), the transposed staging
 template <typename T>
 size_t pair_lds_bytes(int n, int nrw, bool ovl) {
   const int np = pair_tiles(n) * PAIR_TILE;
-  return (size_t)(np * nrw * 2 * (ovl ? 3 : 4) + 4 * pair_stages<T>() * 512) * sizeof(T);
+  const int stage = pair_swz(nrw) ? pair_stage_vals<T, true>() : pair_stage_vals<T, false>();
+  return (size_t)(np * nrw * 2 * (ovl ? 2 : 3) + 4 * stage) * sizeof(T);
 }
 
 constexpr size_t CU_LDS = 160 * 1024;
+constexpr int PAIR16_TPW_MAX = 5;
+// LDS of one workgroup at most 160 KB
+constexpr size_t PAIR_LDS_MAX = CU_LDS;
 
-// Overlay the second column-sum buffer only where its own region would leave
-// fewer workgroups per CU (by LDS; a workgroup has one wavefront per SIMD,
-// and at most 4 per CU fit the registers of the matrix-core forms here).
+// Overlay the column sums where their own region would leave fewer
+// workgroups per CU (by LDS; a workgroup has one wavefront per SIMD, and at
+// most 4 per CU fit the registers of the matrix-core forms here), or where
+// the workgroup would not fit otherwise
 template <typename T>
 bool pair_overlay(int n, int nrw) {
   if (!pair_b2r<T>((pair_tiles(n) + 3) / 4)) return false;
@@ -345,6 +427,8 @@ void launch_mfma_pair(const void* That, const void* pairs, const void* w, const 
                          static_cast<const T*>(That), static_cast<const int2*>(pairs), static_cast<const T*>(w),
                          static_cast<const T*>(winv), static_cast<const V2*>(xh), static_cast<V2*>(yh), n, nrhs, r0,
                          nr);
+    else
+      EMS_CHECK_ARG(false, "internal: column-sum overlay without register B operands");
   } else {
     hipLaunchKernelGGL((pair_mfma_kernel<T, TPW, NRW, B2R, false>), dim3((unsigned)Ps), dim3(PNT), shm, s,
                        static_cast<const T*>(That), static_cast<const int2*>(pairs), static_cast<const T*>(w),
@@ -355,22 +439,35 @@ void launch_mfma_pair(const void* That, const void* pairs, const void* w, const 
 template <typename T, int TPW>
 void launch_mfma_pair_tpw(int nrw, const void* That, const void* pairs, const void* w, const void* winv,
                           const void* xh, void* yh, int n, int nrhs, int r0, int nr, int64_t Ps, hipStream_t s) {
-  if (nrw == 4)
+  if (nrw == 4) {
     launch_mfma_pair<T, TPW, 4>(That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s);
-  else
+  } else if (nrw == 8) {
     launch_mfma_pair<T, TPW, 8>(That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s);
+  } else {
+    if constexpr (sizeof(T) == 4 && TPW <= PAIR16_TPW_MAX)
+      launch_mfma_pair<T, TPW, 16>(That, pairs, w, winv, xh, yh, n, nrhs, r0, nr, Ps, s);
+    else
+      EMS_CHECK_ARG(false, "internal: 16 right-hand sides per pass are FP32 only, n_eq <= 320");
+  }
 }
 
-// LDS of one workgroup at most 160 KB
-constexpr size_t PAIR_LDS_MAX = 160 * 1024;
+// Right-hand sides per pass: 4 for at most 4 (less LDS, more workgroups per
+// CU); else 8, or 16 in FP32 above 8 (up to 5 u tiles per wavefront, n_eq <=
+// 320, whose registers fit two wavefronts per SIMD), wherever the workgroup
+// fits the LDS
+template <typename T>
+int pair_nrw(int n, int nrhs) {
+  auto fits = [&](int nrw) { return pair_lds_bytes<T>(n, nrw, pair_overlay<T>(n, nrw)) <= PAIR_LDS_MAX; };
+  if (nrhs <= 4 || !fits(8)) return 4;
+  if (sizeof(T) == 4 && nrhs > 8 && (pair_tiles(n) + 3) / 4 <= PAIR16_TPW_MAX && fits(16)) return 16;
+  return 8;
+}
 
 template <typename T>
 void launch_pair_typed(const void* That, const void* pairs, const void* w, const void* winv, const void* xh, void* yh,
                        int n, int nrhs, int64_t Ps, hipStream_t s) {
   const int tpw = (pair_tiles(n) + 3) / 4;
-  // 4-wide passes for at most 4 right-hand sides (less LDS, more workgroups
-  // per CU), and wherever 8-wide ones would not fit the LDS
-  const int nrw = nrhs <= 4 || pair_lds_bytes<T>(n, 8, pair_overlay<T>(n, 8)) > PAIR_LDS_MAX ? 4 : 8;
+  const int nrw = pair_nrw<T>(n, nrhs);
   EMS_CHECK_ARG(pair_lds_bytes<T>(n, nrw, pair_overlay<T>(n, nrw)) <= PAIR_LDS_MAX,
                 "internal: paired product LDS too large");
   for (int r0 = 0; r0 < nrhs; r0 += nrw) {

@@ -165,9 +165,10 @@ void launch_block_product_variant(Cx t, int variant, const void* That, const voi
 // Block layout of the reciprocal store (FP64 and FP32 alike, padding zero):
 // 16 x 16 tiles (nt = ceil(n / 16) per side), 256 complex entries per tile,
 // in the order the four wavefronts of the paired product visit them: u tile t
-// belongs to wavefront t % 4, which walks v tiles q outer and its own u tiles
-// inner, so tile (t, q) sits at base(t % 4) + q ntw(t % 4) + t / 4, with
-// ntw(w) = (nt - w + 3) / 4 and base(w) = nt sum_{w' < w} ntw(w').  Within a
+// belongs to wavefront w = t % 4, which walks v tiles outer (v tile q at step
+// (q - w) mod nt) and its own u tiles inner, so tile (t, q) sits at
+// base(w) + ((q - w) mod nt) ntw(w) + t / 4, with ntw(w) = (nt - w + 3) / 4
+// and base(w) = nt sum_{w' < w} ntw(w').  Within a
 // tile, real and imaginary parts apart: the first product's A operand on the
 // matrix cores holds part p of tile entry (a, b) in lane L = a + 16 p +
 // 32 (b % 2), register r = b / 2.  With ch = 16 / (bytes of a real) values per
@@ -189,8 +190,8 @@ __host__ __device__ inline int pair_wave_base(int nt, int w) {
 }
 // tile position of (u tile t, v tile q) within a block
 __host__ __device__ inline int pair_tile_pos(int nt, int t, int q) {
-  const int w = t % 4;
-  return pair_wave_base(nt, w) + q * pair_wave_tiles(nt, w) + t / 4;
+  const int w = t % 4;   // < nt, as t < nt
+  return pair_wave_base(nt, w) + ((q - w + nt) % nt) * pair_wave_tiles(nt, w) + t / 4;
 }
 // in-tile real-value offset of part p of tile entry (a, b) (row a, column b
 // of a 16 x 16 tile): lane a + 16 p + 32 (b % 2), register b / 2 of the

@@ -93,7 +93,10 @@ def test_recip_apply_T_fp64_random_blocks(nx, ny, n, nrhs):
 
 
 @pytest.mark.parametrize("nx,ny,n,nrhs", [(9, 6, 24, 3), (65, 17, 8, 2), (4, 4, 192, 4), (3, 3, 300, 2),
-                                          (7, 5, 96, 8), (2, 2, 512, 1)])
+                                          (7, 5, 96, 8), (2, 2, 512, 1),
+                                          # 16 right-hand sides per pass (two B tiles), and 8 beyond 5 u tiles
+                                          (5, 4, 288, 16), (4, 3, 192, 12), (3, 4, 40, 9), (6, 5, 288, 21),
+                                          (2, 3, 336, 16)])
 def test_recip_apply_T_fp32(nx, ny, n, nrhs):
     e = E()
     plan, B, w, S, tm = recip_plan(nx, ny, n, nrhs, seed=3 + n)
@@ -103,6 +106,24 @@ def test_recip_apply_T_fp32(nx, ny, n, nrhs):
     err = rel_per_rhs(y, yr)
     say(f"reciprocal apply_T fp32 {nx}x{ny} n={n} nrhs={nrhs}: rel err per rhs {err}")
     assert np.all(err <= FP32_TOL)
+
+
+@pytest.mark.parametrize("prec,n,nrhs", [("fp32", 288, 16), ("fp32", 192, 11), ("fp32", 40, 9), ("fp64", 192, 8),
+                                         ("fp64", 40, 13)])
+def test_recip_columns_bitwise_alone_and_batched(prec, n, nrhs):
+    # every right-hand side gets the same bits alone (a pass of 4) and in a
+    # batch of passes of 8 or 16 (one or two B tiles)
+    e = E()
+    nx, ny = 4, 3
+    plan, B, w, S, tm = recip_plan(nx, ny, n, nrhs, seed=n + nrhs)
+    p = e.EMSURF_FP32 if prec == "fp32" else e.EMSURF_FP64
+    x = W.random_vectors(nrhs, nx, ny, n, seed=31)
+    yb = apply(e, plan, p, x)
+    for r in range(nrhs):
+        ya = apply(e, plan, p, x[r:r + 1])
+        assert np.array_equal(ya[0], yb[r]), r
+    say(f"reciprocal {prec} n={n}: {nrhs} columns alone == batched")
+    plan.destroy()
 
 
 @pytest.mark.parametrize("signed,zero_self", [(False, True), (True, False)])
