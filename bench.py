@@ -243,6 +243,7 @@ def measured_traffic(recip=True):
 
 
 MFMA_FP32_PEAK_TFS = 157.3
+MFMA_FP64_PEAK_TFS = 78.6
 
 
 def multi_rhs_section(E, W, torch, np):
@@ -885,6 +886,27 @@ def main():
     ms64 = 1e3 * (time.perf_counter() - t0) / k64
     log(f"T-apply fp64: {ms64:.3f} ms/step")
 
+    # macromodel apply y = S t (Sec. III-A, eq. (Zmacromodel_Array)): grouped
+    # complex GEMMs per cell type on the matrix cores
+    s_flops = 8 * M * n * n * nrhs
+    sapply = {"kernel": "apply_S_mfma_kernel<float|double, ...> (packed macromodels, LDS-staged vectors)",
+              "flop": s_flops}
+    for sname, sprec, xin, peak in (("fp32", E.EMSURF_FP32, x32, MFMA_FP32_PEAK_TFS),
+                                    ("fp64", E.EMSURF_FP64, b64, MFMA_FP64_PEAK_TFS)):
+        ys_ = torch.empty_like(xin)
+        for _ in range(3):
+            E.emsurf_apply_S(plan, sprec, nrhs, xin, ys_, stream)
+        torch.cuda.synchronize()
+        ks = 20
+        t0 = time.perf_counter()
+        for _ in range(ks):
+            E.emsurf_apply_S(plan, sprec, nrhs, xin, ys_, stream)
+        torch.cuda.synchronize()
+        sms = 1e3 * (time.perf_counter() - t0) / ks
+        sapply[sname] = {"ms": round(sms, 4), "TFs": round(s_flops / (sms / 1e3) / 1e12, 2),
+                         "frac_mfma_peak": round(s_flops / (sms / 1e3) / 1e12 / peak, 4)}
+    log(f"S-apply: {sapply}")
+
     # the same operator on a plan that stores every frequency (reference)
     full = None
     if recip:
@@ -1071,6 +1093,7 @@ def main():
                      "frac_of_measured_read": round(bp_gbs / copy["read_GBs"], 4) if copy else None,
                      "frac_of_measured_copy": round(bp_gbs / copy["GBs"], 4) if copy else None},
         "full_store_apply": full,
+        "macromodel_apply_128x128": sapply,
         "apply_T": {"algorithmic_bytes": apply_bytes,
                     "effective_GBs": round(apply_bytes / (ms_step / 1e3) / 1e9, 1),
                     "frac_of_hbm_peak": round(apply_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),

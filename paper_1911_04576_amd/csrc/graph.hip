@@ -48,8 +48,7 @@ extern "C" emsurf_status emsurf_graph_create(emsurf_plan plan, int32_t op, emsur
     } else if (op == EMSURF_OP_A) {
       apply_A_typed(plan, t, t, t, nrhs, x_dev, y_dev, s, -1, ap.split);
     } else {
-      const void* S = (t == Cx::C128) ? plan->S64.p : plan->S32.p;
-      launch_apply_S(t, t, t, S, plan->tiles, plan->d.n_eq, plan->M, nrhs, x_dev, nullptr, y_dev, s);
+      apply_S_plan(plan, t, t, nrhs, x_dev, nullptr, y_dev, s);
     }
     capturing = false;
     EMS_HIP(hipStreamEndCapture(s, &g->graph));

@@ -280,6 +280,13 @@ struct TypeTiles {
 // types: S store type; t type; x_axpy and y types (FP64 or FP32 per ty/tx).
 void launch_apply_S(Cx ts, Cx tt, Cx txy, const void* S, const TypeTiles& tiles, int n, int M, int nrhs,
                     const void* t, const void* x_axpy, void* y, hipStream_t s);
+// The same on the matrix cores, from macromodels packed by launch_pack_S
+// (FP64 or FP32 reals, packed_S_reals of them, from the FP64 [type][n][n]
+// macromodels); compute type tc for S and t, x_axpy and y of type txy.
+size_t packed_S_reals(int n, int n_types);
+void launch_pack_S(Cx t, const void* S64, void* out, int n, int n_types, hipStream_t s);
+void launch_apply_S_packed(Cx tc, Cx txy, const void* Sp, const TypeTiles& tiles, int n, int M, int nrhs,
+                           const void* t, const void* x_axpy, void* y, hipStream_t s);
 
 // ----------------------------------------------------------------------------- fill
 // Write padded kernel K[sy][sx][v][u] (columns cols [c0, c0+nc) of the n*n batch
@@ -369,6 +376,7 @@ struct emsurf_plan_s {
   emsurf::DevBuf pairs;           // reciprocal plans: int [Ps][2]
   emsurf::DevBuf w64, winv64, w32, winv32;  // reciprocal weights and inverses [n]
   emsurf::DevBuf S64, S32;        // [n_types][n][n] row-major
+  emsurf::DevBuf SP64, SP32;      // the same packed for the matrix-core apply
   emsurf::TypeTiles tiles;
   std::mutex mu;
   std::map<hipStream_t, emsurf::Workspace*> ws;
@@ -414,6 +422,9 @@ inline int64_t apply_X_values(emsurf_plan p, int nrhs);
 // apply_A with explicit types: x (tx) -> y (ty) = x - S T x, arithmetic in tc.
 void apply_A_typed(emsurf_plan p, Cx tx, Cx tc, Cx ty, int nrhs, const void* x, void* y, hipStream_t s,
                    int variant = -1, int split = 0);
+// y = (x_axpy ? x_axpy - : ) S t with the plan's macromodels (matrix cores),
+// compute type tc for t, type ty for x_axpy and y
+void apply_S_plan(emsurf_plan p, Cx tc, Cx ty, int nrhs, const void* t, const void* x_axpy, void* y, hipStream_t s);
 // element type and split of an apply precision (EMSURF_FP64, EMSURF_FP32,
 // EMSURF_BF16X3, EMSURF_BF16); ERR_ARG for any other
 struct ApplyPrec {

@@ -82,7 +82,7 @@ Sizes sizes_of(const emsurf_plan_desc* d) {
   z.that64 = (d->store & EMSURF_STORE_FP64) ? (size_t)(z.Ps * kc64) * 16 : 0;
   z.that32 = (d->store & EMSURF_STORE_FP32) ? (size_t)(z.Ps * kc32) * 8 : 0;
   z.that16 = (d->store & EMSURF_STORE_BF16) ? (size_t)(z.P * z.nn) * 8 : 0;
-  z.S = (size_t)d->n_types * z.nn * (16 + 8);
+  z.S = (size_t)d->n_types * z.nn * (16 + 8) + packed_S_reals(z.n, d->n_types) * (8 + 4);
   z.tiles = (size_t)z.M * 4 + (size_t)(z.M + d->n_types) * 12;
   if (d->recip) z.tiles += (size_t)z.Ps * 8 + (size_t)z.n * 24;  // pair list and weights
   const int64_t B = (int64_t)d->max_rhs * z.n;
@@ -243,8 +243,12 @@ void apply_A_typed(emsurf_plan p, Cx tx, Cx tc, Cx ty, int nrhs, const void* x, 
                    int variant, int split) {
   Workspace& w = workspace(p, s);
   apply_T_typed(p, tx, tc, tc, nrhs, x, w.t.p, s, variant, split);
-  const void* S = (tc == Cx::C128) ? p->S64.p : p->S32.p;
-  launch_apply_S(tc, tc, ty, S, p->tiles, p->d.n_eq, p->M, nrhs, w.t.p, x, y, s);
+  apply_S_plan(p, tc, ty, nrhs, w.t.p, x, y, s);
+}
+
+void apply_S_plan(emsurf_plan p, Cx tc, Cx ty, int nrhs, const void* t, const void* x_axpy, void* y, hipStream_t s) {
+  const void* Sp = (tc == Cx::C128) ? p->SP64.p : p->SP32.p;
+  launch_apply_S_packed(tc, ty, Sp, p->tiles, p->d.n_eq, p->M, nrhs, t, x_axpy, y, s);
 }
 
 bool boxes_touch(const emsurf_geom* g) {
@@ -340,6 +344,11 @@ void upload_S(emsurf_plan p, const void* S_types, hipStream_t s) {
   p->S32.alloc(cnt * 8);
   EMS_HIP(hipMemcpyAsync(p->S64.p, S_types, cnt * 16, hipMemcpyHostToDevice, s));
   launch_convert(Cx::C128, Cx::C64, p->S64.p, p->S32.p, (int64_t)cnt, s);
+  const size_t pk = packed_S_reals(p->d.n_eq, p->d.n_types);
+  p->SP64.alloc(pk * 8);
+  p->SP32.alloc(pk * 4);
+  launch_pack_S(Cx::C128, p->S64.p, p->SP64.p, p->d.n_eq, p->d.n_types, s);
+  launch_pack_S(Cx::C64, p->S64.p, p->SP32.p, p->d.n_eq, p->d.n_types, s);
   EMS_HIP(hipStreamSynchronize(s));
 }
 
@@ -681,7 +690,6 @@ emsurf_status emsurf_apply_S(emsurf_plan plan, emsurf_prec prec, int32_t nrhs, c
     check_apply(plan, nrhs, x_dev, y_dev);
     const Cx t = apply_prec(prec).t;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const void* S = (t == Cx::C128) ? plan->S64.p : plan->S32.p;
     const void* src = x_dev;
     if (x_dev == y_dev) {
       Workspace& w = workspace(plan, s);
@@ -689,7 +697,7 @@ emsurf_status emsurf_apply_S(emsurf_plan plan, emsurf_prec prec, int32_t nrhs, c
       EMS_HIP(hipMemcpyAsync(w.t.p, x_dev, bytes, hipMemcpyDeviceToDevice, s));
       src = w.t.p;
     }
-    launch_apply_S(t, t, t, S, plan->tiles, plan->d.n_eq, plan->M, nrhs, src, nullptr, y_dev, s);
+    apply_S_plan(plan, t, t, nrhs, src, nullptr, y_dev, s);
   });
 }
 
@@ -714,6 +722,7 @@ emsurf_status emsurf_plan_query(emsurf_plan plan, emsurf_plan_stats* out) {
     out->n_stored = plan->Ps;
     out->bytes_that16 = plan->that16.bytes;
     size_t tot = plan->that64.bytes + plan->that32.bytes + plan->that16.bytes + plan->S64.bytes + plan->S32.bytes +
+                 plan->SP64.bytes + plan->SP32.bytes +
                  plan->tiles.elem_sorted.bytes + plan->tiles.tiles.bytes + plan->pairs.bytes + plan->w64.bytes +
                  plan->winv64.bytes + plan->w32.bytes + plan->winv32.bytes;
     std::lock_guard<std::mutex> lk(plan->mu);

@@ -196,7 +196,7 @@ void precond_apply(emsurf_precond pc, int nrhs, const void* y, void* x, hipStrea
                      pc->qidx.as<const int>(), pc->qpos.as<const int>(), pc->G.as<const double2>(),
                      static_cast<const double2*>(y), pc->t.as<double2>());
   EMS_LAUNCH_CHECK();
-  launch_apply_S(Cx::C128, Cx::C128, Cx::C128, p->S64.p, p->tiles, n, p->M, nrhs, pc->t.p, y, x, s);
+  apply_S_plan(p, Cx::C128, Cx::C128, nrhs, pc->t.p, y, x, s);
 }
 
 emsurf_plan precond_plan(emsurf_precond pc) { return pc->plan; }

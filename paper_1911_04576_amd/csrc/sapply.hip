@@ -5,10 +5,16 @@
 // across up to TC elements: the apply becomes a grouped complex GEMM
 // (rows u, columns = elements of one type) with an optional fused
 // "y = x - S t" epilogue used by the operator A = I - S T.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace emsurf {
 namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 template <typename V> struct Real;
 template <> struct Real<float2> { using T = float; };
@@ -119,9 +125,222 @@ void launch_typed(const void* S, const TypeTiles& tl, int n, int M, int nrhs, co
                      static_cast<const VT*>(t), static_cast<const VX*>(x), static_cast<VX*>(y));
 }
 
+// ----------------------------------------------------------------------------- matrix-core apply
+// The grouped product y[col][u] = sum_v S[u][v] t[col][v] of one type on the
+// matrix cores (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64), in the real
+// embedding of the complex product: A = the t columns (16 columns x 4
+// k-slots, slot kk = (half h = kk / 2, part p = kk % 2) of 8 source indices
+// v = 16 vt + 8 h + s for MFMA s), B = the macromodel with the signs of the
+// complex product folded in (16 output columns = 8 rows u x (re, im)):
+//     out re: p = 0 -> Sr[u][v], p = 1 -> -Si[u][v]
+//     out im: p = 0 -> Si[u][v], p = 1 ->  Sr[u][v]
+// so D[col][(u, q)] is part q of (S t)[col][u].  B comes packed once per plan
+// in the lane order of the instruction (below); A is staged per 16-index
+// k-tile through LDS from the plain [r][m][v] vectors.
+template <typename T> struct SM;
+template <> struct SM<float> {
+  using V2 = float2;
+  using C = f4;
+  using Acc = f4;
+  __device__ static Acc mfma(float a, float b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int l, int e) { return 4 * (l >> 4) + e; }
+};
+template <> struct SM<double> {
+  using V2 = double2;
+  using C = d2;
+  using Acc = d4;
+  __device__ static Acc mfma(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int l, int e) { return (l >> 4) + 4 * e; }
+};
+
+constexpr int SA_THREADS = 256;
+constexpr int SA_COLS = 64;   // columns per workgroup: 4 tiles of 16
+constexpr int SA_UT = 8;      // row tiles of 8 per workgroup (64 rows)
+
+__host__ __device__ inline int s_row_tiles(int n) { return (n + 7) / 8; }
+__host__ __device__ inline int s_k_tiles(int n) { return (n + 15) / 16; }
+
+// Packed layout per type: blocks (ut, vt) of 512 reals, ut = u / 8 outer,
+// vt = v / 16 inner; within a block, value s of lane L = 16 kk + j (k-slot
+// kk, output column j = (u % 8) + 8 q) at (s / CH) 64 CH + L CH + s % CH,
+// CH = 16 / (bytes of a real), so that each 16-byte load instruction of a
+// wavefront reads 1024 contiguous bytes.  Zero beyond n.
+template <typename T>
+__global__ void pack_S_kernel(const double2* __restrict__ S, T* __restrict__ out, int n, int n_types) {
+  constexpr int CH = 16 / (int)sizeof(T);
+  const int nut = s_row_tiles(n), nvt = s_k_tiles(n);
+  const long long total = (long long)n_types * nut * nvt * 512;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long blk = i / 512;
+    const int w = (int)(i - blk * 512);
+    const int sc = w / (64 * CH), rem = w - sc * 64 * CH, L = rem / CH, s = sc * CH + rem % CH;
+    const int type = (int)(blk / ((long long)nut * nvt));
+    const int r2 = (int)(blk - (long long)type * nut * nvt), ut = r2 / nvt, vt = r2 - (r2 / nvt) * nvt;
+    const int kk = L >> 4, j = L & 15, h = kk >> 1, p = kk & 1, q = j >> 3;
+    const int u = ut * 8 + (j & 7), v = vt * 16 + h * 8 + s;
+    double val = 0.0;
+    if (u < n && v < n) {
+      const double2 a = S[((long long)type * n + u) * n + v];
+      val = q == 0 ? (p == 0 ? a.x : -a.y) : (p == 0 ? a.y : a.x);
+    }
+    out[i] = static_cast<T>(val);
+  }
+}
+
+// grid: x = type tile * ncb + column block, y = block of SA_UT row tiles.
+// Wavefront (wc, wu) = (w % 2, w / 2) takes column tiles 2 wc, 2 wc + 1 and
+// row tiles 4 wu .. 4 wu + 3 of the workgroup.
+template <typename T, typename VX>
+__global__ void __launch_bounds__(SA_THREADS, 2) apply_S_mfma_kernel(
+    const T* __restrict__ Sp, const int* __restrict__ elem_sorted, const int* __restrict__ tiles, int n, int M,
+    int nrhs, int ncb, const typename SM<T>::V2* __restrict__ t, const VX* __restrict__ x_axpy, VX* __restrict__ y) {
+  using V2 = typename SM<T>::V2;
+  using C = typename SM<T>::C;
+  using Acc = typename SM<T>::Acc;
+  using R = typename Real<VX>::T;
+  constexpr int CH = 16 / (int)sizeof(T), NCH = 8 / CH;
+  constexpr int NBC = SA_UT * 512 / CH / SA_THREADS;   // B chunks staged per thread
+  __shared__ __align__(16) T As[4 * 512];
+  __shared__ __align__(16) T Bs[SA_UT * 512];
+  const int tile = blockIdx.x / ncb, cb = blockIdx.x - tile * ncb;
+  const int type = tiles[3 * tile], start = tiles[3 * tile + 1], count = tiles[3 * tile + 2];
+  const int ncols = nrhs * count, col0 = cb * SA_COLS;
+  if (col0 >= ncols) return;   // the whole workgroup: no barrier reached
+  const int nut = s_row_tiles(n), nvt = s_k_tiles(n);
+  const int ut0 = blockIdx.y * SA_UT;
+  const T* St = Sp + (long long)type * nut * nvt * 512;
+  const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6, wc = wv & 1, wu = wv >> 1;
+  // A staging: column ac of the block, source indices 4 aq .. 4 aq + 3 of the k-tile
+  const int ac = tid >> 2, aq = tid & 3;
+  const int acol = col0 + ac;
+  const V2* tcol = nullptr;
+  if (acol < ncols) {
+    const int r = acol / count, e = acol - r * count;
+    tcol = t + ((long long)r * M + elem_sorted[start + e]) * n;
+  }
+  V2 an[4];
+  C bn[NBC];
+  auto load_k = [&](int vt) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int v = vt * 16 + 4 * aq + i;
+      an[i] = (tcol != nullptr && v < n) ? tcol[v] : V2{0, 0};
+    }
+#pragma unroll
+    for (int j = 0; j < NBC; ++j) {
+      const int ci = tid + SA_THREADS * j, bu = ci / (512 / CH), wi = ci - bu * (512 / CH);
+      bn[j] = ut0 + bu < nut ? *reinterpret_cast<const C*>(St + ((long long)(ut0 + bu) * nvt + vt) * 512 + wi * CH)
+                             : C{};
+    }
+  };
+  // A-lane position of this thread's values: lane (2 h + p) 16 + ac % 16 of column tile ac / 16
+  const int ah = aq >> 1, as0 = 4 * (aq & 1), act = ac >> 4, a16 = ac & 15;
+  Acc acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = Acc{};
+  load_k(0);
+  for (int vt = 0; vt < nvt; ++vt) {
+    __syncthreads();   // the previous k-tile's reads are done
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int L = (2 * ah + p) * 16 + a16;
+      T* dst = As + act * 512;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int s = as0 + i;
+        dst[(s / CH) * 64 * CH + L * CH + s % CH] = p == 0 ? an[i].x : an[i].y;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NBC; ++j) *reinterpret_cast<C*>(Bs + (tid + SA_THREADS * j) * CH) = bn[j];
+    __syncthreads();
+    load_k(vt + 1 < nvt ? vt + 1 : vt);   // the next k-tile is on its way during the products
+    C a[2][NCH], b[4][NCH];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int m = 0; m < NCH; ++m) a[i][m] = *reinterpret_cast<const C*>(As + (2 * wc + i) * 512 + m * 64 * CH + l * CH);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int m = 0; m < NCH; ++m) b[j][m] = *reinterpret_cast<const C*>(Bs + (4 * wu + j) * 512 + m * 64 * CH + l * CH);
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = SM<T>::mfma(a[i][s / CH][s % CH], b[j][s / CH][s % CH], acc[i][j]);
+  }
+  // lane l, register e: column tile row SM::row(l, e), output column l % 16 = (u % 8) + 8 q
+  const int jj = l & 15, q = jj >> 3;
+  R* yr = reinterpret_cast<R*>(y);
+  const R* xr = reinterpret_cast<const R*>(x_axpy);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int col = col0 + 16 * (2 * wc + i) + SM<T>::row(l, e);
+      if (col >= ncols) continue;
+      const int r = col / count, el = col - r * count;
+      const long long base = ((long long)r * M + elem_sorted[start + el]) * n;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int u = 8 * (ut0 + 4 * wu + j) + (jj & 7);
+        if (u >= n) continue;
+        const long long o = 2 * (base + u) + q;
+        const R val = static_cast<R>(acc[i][j][e]);
+        yr[o] = xr ? xr[o] - val : val;
+      }
+    }
+}
+
+template <typename T, typename VX>
+void launch_mfma_typed(const void* Sp, const TypeTiles& tl, int n, int M, int nrhs, const void* t, const void* x,
+                       void* y, hipStream_t s) {
+  const int ncb = (nrhs * TC + SA_COLS - 1) / SA_COLS;
+  const int nub = (s_row_tiles(n) + SA_UT - 1) / SA_UT;
+  EMS_CHECK_ARG((long long)tl.n_tiles * ncb <= 0x7fffffffLL, "too many macromodel tiles");
+  dim3 grid((unsigned)(tl.n_tiles * ncb), (unsigned)nub);
+  hipLaunchKernelGGL((apply_S_mfma_kernel<T, VX>), grid, dim3(SA_THREADS), 0, s, static_cast<const T*>(Sp),
+                     tl.elem_sorted.as<const int>(), tl.tiles.as<const int>(), n, M, nrhs, ncb,
+                     static_cast<const typename SM<T>::V2*>(t), static_cast<const VX*>(x), static_cast<VX*>(y));
+}
+
 }  // namespace
 
 int apply_S_tile_cols() { return TC; }
+
+size_t packed_S_reals(int n, int n_types) { return (size_t)n_types * s_row_tiles(n) * s_k_tiles(n) * 512; }
+
+void launch_pack_S(Cx t, const void* S64, void* out, int n, int n_types, hipStream_t s) {
+  const long long total = (long long)packed_S_reals(n, n_types);
+  const unsigned blocks = (unsigned)std::min<long long>((total + 255) / 256, 65536);
+  if (t == Cx::C128)
+    hipLaunchKernelGGL(pack_S_kernel<double>, dim3(blocks), dim3(256), 0, s, static_cast<const double2*>(S64),
+                       static_cast<double*>(out), n, n_types);
+  else
+    hipLaunchKernelGGL(pack_S_kernel<float>, dim3(blocks), dim3(256), 0, s, static_cast<const double2*>(S64),
+                       static_cast<float*>(out), n, n_types);
+  EMS_LAUNCH_CHECK();
+}
+
+void launch_apply_S_packed(Cx tc, Cx txy, const void* Sp, const TypeTiles& tiles, int n, int M, int nrhs,
+                           const void* t, const void* x_axpy, void* y, hipStream_t s) {
+  if (tc == Cx::C128) {
+    EMS_CHECK_ARG(txy == Cx::C128, "FP64 macromodel apply needs FP64 vectors");
+    launch_mfma_typed<double, double2>(Sp, tiles, n, M, nrhs, t, x_axpy, y, s);
+  } else if (txy == Cx::C64) {
+    launch_mfma_typed<float, float2>(Sp, tiles, n, M, nrhs, t, x_axpy, y, s);
+  } else {
+    launch_mfma_typed<float, double2>(Sp, tiles, n, M, nrhs, t, x_axpy, y, s);
+  }
+  EMS_LAUNCH_CHECK();
+}
 
 void launch_apply_S(Cx ts, Cx tt, Cx txy, const void* S, const TypeTiles& tiles, int n, int M, int nrhs,
                     const void* t, const void* x_axpy, void* y, hipStream_t s) {

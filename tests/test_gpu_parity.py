@@ -186,7 +186,9 @@ def test_plan_green_config1_fp64():
 
 
 # ----------------------------------------------------------------------------- S and A
-@pytest.mark.parametrize("nx,ny,n,nrhs,nt", [(3, 2, 5, 2, 3), (8, 8, 96, 1, 4), (7, 5, 70, 3, 5), (40, 1, 8, 1, 2)])
+@pytest.mark.parametrize("nx,ny,n,nrhs,nt", [(3, 2, 5, 2, 3), (8, 8, 96, 1, 4), (7, 5, 70, 3, 5), (40, 1, 8, 1, 2),
+                                              # several column blocks and row blocks per type, ragged tiles
+                                              (9, 8, 192, 4, 3), (5, 4, 288, 9, 2), (17, 3, 20, 3, 1)])
 def test_apply_S_and_A_fp64(nx, ny, n, nrhs, nt):
     e = E()
     plan, B, S, tm = random_plan(nx, ny, n, nrhs, seed=nx + ny, n_types=nt)
@@ -208,6 +210,20 @@ def test_apply_S_and_A_fp64(nx, ny, n, nrhs, nt):
     e.emsurf_apply_S(plan, e.EMSURF_FP64, nrhs, xd, xd)
     torch.cuda.synchronize()
     assert rel_per_rhs(xd.cpu().numpy(), ys).max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("nx,ny,n,nrhs,nt", [(3, 2, 5, 2, 3), (9, 8, 192, 4, 3), (5, 4, 288, 16, 2), (17, 3, 20, 3, 1)])
+def test_apply_S_fp32(nx, ny, n, nrhs, nt):
+    # the FP32 matrix-core apply against the FP64 oracle (FP32 bar 1e-5)
+    e = E()
+    plan, B, S, tm = random_plan(nx, ny, n, nrhs, seed=nx * ny + n, n_types=nt)
+    x = W.random_vectors(nrhs, nx, ny, n, seed=12)
+    y = torch.empty(x.shape, dtype=torch.complex64, device="cuda")
+    e.emsurf_apply_S(plan, e.EMSURF_FP32, nrhs, dev(x.astype(np.complex64)), y)
+    torch.cuda.synchronize()
+    err = rel_per_rhs(y.cpu().numpy().astype(np.complex128), MM.apply_S(S, tm, x))
+    say(f"apply_S fp32 {nx}x{ny} n={n} nrhs={nrhs}: {err}")
+    assert err.max() <= 1e-5
 
 
 def test_apply_A_fp32_error_reported():
