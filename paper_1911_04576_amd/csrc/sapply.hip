@@ -6,6 +6,7 @@
 // (rows u, columns = elements of one type) with an optional fused
 // "y = x - S t" epilogue used by the operator A = I - S T.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -156,8 +157,9 @@ template <> struct SM<double> {
 };
 
 constexpr int SA_THREADS = 256;
-constexpr int SA_COLS = 64;   // columns per workgroup: 4 tiles of 16
 constexpr int SA_UT = 8;      // row tiles of 8 per workgroup (64 rows)
+// columns per workgroup: two wavefronts across, CTW column tiles of 16 each
+template <int CTW> constexpr int sa_cols() { return 32 * CTW; }
 
 __host__ __device__ inline int s_row_tiles(int n) { return (n + 7) / 8; }
 __host__ __device__ inline int s_k_tiles(int n) { return (n + 15) / 16; }
@@ -190,45 +192,69 @@ __global__ void pack_S_kernel(const double2* __restrict__ S, T* __restrict__ out
   }
 }
 
-// grid: x = type tile * ncb + column block, y = block of SA_UT row tiles.
-// Wavefront (wc, wu) = (w % 2, w / 2) takes column tiles 2 wc, 2 wc + 1 and
-// row tiles 4 wu .. 4 wu + 3 of the workgroup.
-template <typename T, typename VX>
+// Work items w = (type tile * nub + row block) * ncb + column block, in type
+// order.  Workgroups go to the 8 XCDs in turn (workgroup b to XCD b % 8), so
+// XCD x takes the contiguous items [x per, (x + 1) per): the workgroups an
+// XCD holds at a time share a few macromodel slices in its L2.  Wavefront
+// (wc, wu) = (w % 2, w / 2) takes column tiles CTW wc .. CTW wc + CTW - 1 and
+// row tiles 4 wu .. 4 wu + 3 of the item.
+template <typename T, typename VX, int CTW>
 __global__ void __launch_bounds__(SA_THREADS, 2) apply_S_mfma_kernel(
     const T* __restrict__ Sp, const int* __restrict__ elem_sorted, const int* __restrict__ tiles, int n, int M,
-    int nrhs, int ncb, const typename SM<T>::V2* __restrict__ t, const VX* __restrict__ x_axpy, VX* __restrict__ y) {
+    int nrhs, int ncb, int nub, int items, int per, const typename SM<T>::V2* __restrict__ t,
+    const VX* __restrict__ x_axpy, VX* __restrict__ y) {
   using V2 = typename SM<T>::V2;
   using C = typename SM<T>::C;
   using Acc = typename SM<T>::Acc;
   using R = typename Real<VX>::T;
   constexpr int CH = 16 / (int)sizeof(T), NCH = 8 / CH;
-  constexpr int NBC = SA_UT * 512 / CH / SA_THREADS;   // B chunks staged per thread
-  __shared__ __align__(16) T As[4 * 512];
-  __shared__ __align__(16) T Bs[SA_UT * 512];
-  const int tile = blockIdx.x / ncb, cb = blockIdx.x - tile * ncb;
+  constexpr int NCOL = sa_cols<CTW>(), NAC = (NCOL + 63) / 64;   // columns staged per thread
+  constexpr int NBC = SA_UT * 512 / CH / SA_THREADS;   // macromodel chunks staged per thread
+  // a k-tile of the vectors in A-lane order and of the packed macromodels;
+  // two buffers: the next k-tile is staged while the current one is used.
+  // At the end the same memory holds the output tile, rows of YROW values
+  // (64 rows u x (re, im) and padding: the rows start 16 banks apart)
+  constexpr int AS = 2 * CTW * 512, BS = SA_UT * 512;
+  constexpr int YROW = sizeof(T) == 4 ? 132 : 144;
+  constexpr int LDS_T = 2 * (AS + BS) > NCOL * YROW ? 2 * (AS + BS) : NCOL * YROW;
+  __shared__ __align__(16) T lds[LDS_T];
+  auto As = [&](int bf) { return lds + bf * AS; };
+  auto Bs = [&](int bf) { return lds + 2 * AS + bf * BS; };
+  const int w = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (w >= items) return;   // the whole workgroup: no barrier reached
+  const int cb = w % ncb, tub = w / ncb, tile = tub / nub, ub = tub - tile * nub;
   const int type = tiles[3 * tile], start = tiles[3 * tile + 1], count = tiles[3 * tile + 2];
-  const int ncols = nrhs * count, col0 = cb * SA_COLS;
+  const int ncols = nrhs * count, col0 = cb * NCOL;
   if (col0 >= ncols) return;   // the whole workgroup: no barrier reached
   const int nut = s_row_tiles(n), nvt = s_k_tiles(n);
-  const int ut0 = blockIdx.y * SA_UT;
+  const int ut0 = ub * SA_UT;
   const T* St = Sp + (long long)type * nut * nvt * 512;
   const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6, wc = wv & 1, wu = wv >> 1;
-  // A staging: column ac of the block, source indices 4 aq .. 4 aq + 3 of the k-tile
+  // A staging: columns ac + 64 g of the block, source indices 4 aq .. 4 aq + 3 of the k-tile
   const int ac = tid >> 2, aq = tid & 3;
-  const int acol = col0 + ac;
-  const V2* tcol = nullptr;
-  if (acol < ncols) {
-    const int r = acol / count, e = acol - r * count;
-    tcol = t + ((long long)r * M + elem_sorted[start + e]) * n;
-  }
-  V2 an[4];
-  C bn[NBC];
-  auto load_k = [&](int vt) {
+  const V2* tcol[NAC];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int v = vt * 16 + 4 * aq + i;
-      an[i] = (tcol != nullptr && v < n) ? tcol[v] : V2{0, 0};
+  for (int g = 0; g < NAC; ++g) {
+    const int acol = col0 + ac + 64 * g;
+    tcol[g] = nullptr;
+    if (ac + 64 * g < NCOL && acol < ncols) {
+      const int r = acol / count, e = acol - r * count;
+      tcol[g] = t + ((long long)r * M + elem_sorted[start + e]) * n;
     }
+  }
+  V2 an[NAC][4];
+  auto load_a = [&](int vt) {
+#pragma unroll
+    for (int g = 0; g < NAC; ++g)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int v = vt * 16 + 4 * aq + i;
+        an[g][i] = (tcol[g] != nullptr && v < n) ? tcol[g][v] : V2{0, 0};
+      }
+  };
+  // the workgroup's SA_UT row tiles of the packed macromodels (zero past n)
+  C bn[NBC];
+  auto load_b = [&](int vt) {
 #pragma unroll
     for (int j = 0; j < NBC; ++j) {
       const int ci = tid + SA_THREADS * j, bu = ci / (512 / CH), wi = ci - bu * (512 / CH);
@@ -236,78 +262,147 @@ __global__ void __launch_bounds__(SA_THREADS, 2) apply_S_mfma_kernel(
                              : C{};
     }
   };
-  // A-lane position of this thread's values: lane (2 h + p) 16 + ac % 16 of column tile ac / 16
+  // A-lane position of this thread's values: lane (2 h + p) 16 + ac % 16 of column tile ac / 16 + 4 g
   const int ah = aq >> 1, as0 = 4 * (aq & 1), act = ac >> 4, a16 = ac & 15;
-  Acc acc[2][4];
+  Acc acc[CTW][4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < CTW; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = Acc{};
-  load_k(0);
-  for (int vt = 0; vt < nvt; ++vt) {
-    __syncthreads();   // the previous k-tile's reads are done
+  R* yr = reinterpret_cast<R*>(y);
+  const R* xr = reinterpret_cast<const R*>(x_axpy);
+  // stage the k-tile held in an and bn into LDS buffer bf (whose previous
+  // contents every wavefront has used: a barrier lies between)
+  auto stage = [&](int bf) {
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      const int L = (2 * ah + p) * 16 + a16;
-      T* dst = As + act * 512;
+    for (int g = 0; g < NAC; ++g)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int s = as0 + i;
-        dst[(s / CH) * 64 * CH + L * CH + s % CH] = p == 0 ? an[i].x : an[i].y;
+      for (int p = 0; p < 2; ++p) {
+        if (ac + 64 * g >= NCOL) break;
+        const int L = (2 * ah + p) * 16 + a16;
+        T* dst = As(bf) + (act + 4 * g) * 512;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int s = as0 + i;
+          dst[(s / CH) * 64 * CH + L * CH + s % CH] = p == 0 ? an[g][i].x : an[g][i].y;
+        }
       }
-    }
 #pragma unroll
-    for (int j = 0; j < NBC; ++j) *reinterpret_cast<C*>(Bs + (tid + SA_THREADS * j) * CH) = bn[j];
-    __syncthreads();
-    load_k(vt + 1 < nvt ? vt + 1 : vt);   // the next k-tile is on its way during the products
-    C a[2][NCH], b[4][NCH];
+    for (int j = 0; j < NBC; ++j) *reinterpret_cast<C*>(Bs(bf) + (tid + SA_THREADS * j) * CH) = bn[j];
+  };
+  // the products of the k-tile staged in buffer bf
+  auto products = [&](int bf) {
+    C a[CTW][NCH], b[4][NCH];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < CTW; ++i)
 #pragma unroll
-      for (int m = 0; m < NCH; ++m) a[i][m] = *reinterpret_cast<const C*>(As + (2 * wc + i) * 512 + m * 64 * CH + l * CH);
+      for (int m = 0; m < NCH; ++m)
+        a[i][m] = *reinterpret_cast<const C*>(As(bf) + (CTW * wc + i) * 512 + m * 64 * CH + l * CH);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int m = 0; m < NCH; ++m) b[j][m] = *reinterpret_cast<const C*>(Bs + (4 * wu + j) * 512 + m * 64 * CH + l * CH);
+      for (int m = 0; m < NCH; ++m)
+        b[j][m] = *reinterpret_cast<const C*>(Bs(bf) + (4 * wu + j) * 512 + m * 64 * CH + l * CH);
 #pragma unroll
     for (int s = 0; s < 8; ++s)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < CTW; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = SM<T>::mfma(a[i][s / CH][s % CH], b[j][s / CH][s % CH], acc[i][j]);
-  }
-  // lane l, register e: column tile row SM::row(l, e), output column l % 16 = (u % 8) + 8 q
-  const int jj = l & 15, q = jj >> 3;
-  R* yr = reinterpret_cast<R*>(y);
-  const R* xr = reinterpret_cast<const R*>(x_axpy);
+  };
+  // Output chunks of 16 bytes (XC complex values of x and y): chunk k of
+  // this thread is column c = k-th chunk / (64 / XC), rows 8 ut0 + XC (chunk
+  // % (64 / XC)) + 0 .. XC - 1.  Whole chunks where n allows 16-byte access
+  // (n even for FP32 vectors); value by value otherwise.
+  constexpr int XC = 16 / (2 * (int)sizeof(R)), CPC = 64 / XC, NXC = NCOL * CPC / SA_THREADS;
+  using XV = typename std::conditional<sizeof(R) == 4, f4, d2>::type;
+  const bool whole = XC == 1 || (n & 1) == 0;
+  // twice the vector offset (in reals) of the column of each chunk, -1 past the block's columns
+  long long colbase[NXC];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int col = col0 + 16 * (2 * wc + i) + SM<T>::row(l, e);
-      if (col >= ncols) continue;
+  for (int k = 0; k < NXC; ++k) {
+    const int col = col0 + (tid + SA_THREADS * k) / CPC;
+    colbase[k] = -1;
+    if (col < ncols) {
       const int r = col / count, el = col - r * count;
-      const long long base = ((long long)r * M + elem_sorted[start + el]) * n;
+      colbase[k] = 2 * (((long long)r * M + elem_sorted[start + el]) * n);
+    }
+  }
+  // the vectors of the fused y = x - S t, requested before the last products
+  XV xv[NXC];
+  auto load_x = [&]() {
+    if (!xr) return;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int u = 8 * (ut0 + 4 * wu + j) + (jj & 7);
-        if (u >= n) continue;
-        const long long o = 2 * (base + u) + q;
-        const R val = static_cast<R>(acc[i][j][e]);
-        yr[o] = xr ? xr[o] - val : val;
+    for (int k = 0; k < NXC; ++k) {
+      const int ch = tid + SA_THREADS * k, c = ch / CPC, u = 8 * ut0 + XC * (ch - c * CPC);
+      const long long b = colbase[k];
+      xv[k] = XV{};
+      if (b >= 0 && whole && u + XC <= n) {
+        xv[k] = *reinterpret_cast<const XV*>(xr + b + 2 * u);
+      } else if (b >= 0) {
+#pragma unroll
+        for (int z = 0; z < 2 * XC; ++z)
+          if (u + z / 2 < n) xv[k][z] = xr[b + 2 * u + z];
       }
     }
+  };
+  load_a(0);
+  load_b(0);
+  stage(0);
+  __syncthreads();
+  for (int vt = 0; vt + 1 < nvt; ++vt) {
+    load_a(vt + 1);   // the next k-tile is on its way during the products
+    load_b(vt + 1);
+    products(vt & 1);
+    stage((vt + 1) & 1);
+    __syncthreads();
+  }
+  load_x();
+  products((nvt - 1) & 1);
+  // the output tile through LDS: every wavefront is past its last reads first
+  __syncthreads();
+  {
+    const int jj = l & 15, q = jj >> 3;
+#pragma unroll
+    for (int i = 0; i < CTW; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = 16 * (CTW * wc + i) + SM<T>::row(l, e);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) lds[c * YROW + 2 * (8 * (4 * wu + j) + (jj & 7)) + q] = acc[i][j][e];
+      }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NXC; ++k) {
+    const int ch = tid + SA_THREADS * k, c = ch / CPC, ul = XC * (ch - c * CPC), u = 8 * ut0 + ul;
+    const long long b = colbase[k];
+    if (b < 0 || u >= n) continue;
+    XV v;
+#pragma unroll
+    for (int z = 0; z < 2 * XC; ++z) v[z] = static_cast<R>(lds[c * YROW + 2 * ul + z]);
+    if (xr) v = xv[k] - v;
+    if (whole && u + XC <= n) {
+      *reinterpret_cast<XV*>(yr + b + 2 * u) = v;
+    } else {
+#pragma unroll
+      for (int z = 0; z < 2 * XC; ++z)
+        if (u + z / 2 < n) yr[b + 2 * u + z] = v[z];
+    }
+  }
 }
 
-template <typename T, typename VX>
+template <typename T, typename VX, int CTW = sizeof(T) == 4 ? 2 : 1>
 void launch_mfma_typed(const void* Sp, const TypeTiles& tl, int n, int M, int nrhs, const void* t, const void* x,
                        void* y, hipStream_t s) {
-  const int ncb = (nrhs * TC + SA_COLS - 1) / SA_COLS;
+  const int ncb = (nrhs * TC + sa_cols<CTW>() - 1) / sa_cols<CTW>();
   const int nub = (s_row_tiles(n) + SA_UT - 1) / SA_UT;
-  EMS_CHECK_ARG((long long)tl.n_tiles * ncb <= 0x7fffffffLL, "too many macromodel tiles");
-  dim3 grid((unsigned)(tl.n_tiles * ncb), (unsigned)nub);
-  hipLaunchKernelGGL((apply_S_mfma_kernel<T, VX>), grid, dim3(SA_THREADS), 0, s, static_cast<const T*>(Sp),
-                     tl.elem_sorted.as<const int>(), tl.tiles.as<const int>(), n, M, nrhs, ncb,
+  const long long items = (long long)tl.n_tiles * ncb * nub;
+  EMS_CHECK_ARG(items + 8 <= 0x7fffffffLL, "too many macromodel tiles");
+  const int per = (int)((items + 7) / 8);
+  hipLaunchKernelGGL((apply_S_mfma_kernel<T, VX, CTW>), dim3((unsigned)(8 * per)), dim3(SA_THREADS), 0, s,
+                     static_cast<const T*>(Sp), tl.elem_sorted.as<const int>(), tl.tiles.as<const int>(), n, M, nrhs,
+                     ncb, nub, (int)items, per,
                      static_cast<const typename SM<T>::V2*>(t), static_cast<const VX*>(x), static_cast<VX*>(y));
 }
 
