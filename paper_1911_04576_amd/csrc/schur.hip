@@ -107,6 +107,265 @@ __global__ void __launch_bounds__(512) panel_kernel(double2* __restrict__ A, int
   }
 }
 
+// Lane value moved by DPP within rows of 16 lanes (quad permutes, row
+// rotations); a double moves as its two halves
+template <int CTRL> __device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL> __device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ void argmax_take(double& v, int& idx, double ov, int oi) {
+  if (ov > v || (ov == v && oi < idx)) {
+    v = ov;
+    idx = oi;
+  }
+}
+// (largest v, first index on ties) over the 64 lanes, in every lane: quad
+// exchanges 1 and 2 and row rotations 4 and 8 by DPP, then the two row
+// halves and the two wavefront halves by lane exchange
+__device__ __forceinline__ void wave_argmax(double& v, int& idx) {
+  argmax_take(v, idx, dpp_d<0xB1>(v), dpp_i<0xB1>(idx));   // quad_perm [1,0,3,2]
+  argmax_take(v, idx, dpp_d<0x4E>(v), dpp_i<0x4E>(idx));   // quad_perm [2,3,0,1]
+  argmax_take(v, idx, dpp_d<0x124>(v), dpp_i<0x124>(idx)); // row_ror 4
+  argmax_take(v, idx, dpp_d<0x128>(v), dpp_i<0x128>(idx)); // row_ror 8
+  argmax_take(v, idx, __shfl_xor(v, 16), __shfl_xor(idx, 16));
+  argmax_take(v, idx, __shfl_xor(v, 32), __shfl_xor(idx, 32));
+}
+
+// The same panel with the rows in registers, for N - k0 <= 1024: 256
+// threads, thread t owning rows k0 + t, k0 + t + 256, ... (RPT of them; few
+// wavefronts keep the per-column barriers and reductions short).  The
+// panel's columns go in sub-blocks of PSB: a sub-block is staged through
+// LDS with coalesced loads and stores (rows [c0, N)), held in registers, its
+// columns are
+// factorised there (pivot by a reduction over the thread's rows, a
+// wavefront reduction and one over the 4 wavefronts in LDS, row exchange
+// through LDS), and the panel columns outside it then take the sub-block's
+// row swaps at once, and the columns to its right its U rows (L11^-1 A12 by
+// one wavefront) and one rank-PSB update, so that the panel makes one pass
+// through memory per sub-block instead of one per column.  Same pivots
+// (largest |a|^2 among rows [kk, K), first index on ties), same singular
+// flags.
+constexpr int PSB = 8;
+constexpr int PNT_REG = 256;
+template <int RPT>
+__global__ void __launch_bounds__(PNT_REG) panel_reg_kernel(double2* __restrict__ A, int N, int K, int k0, int kb,
+                                                            int* __restrict__ piv, int* __restrict__ info) {
+  const int b = blockIdx.x;
+  double2* M = A + (long long)b * N * N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double rv[PNT_REG / 64];
+  __shared__ int ri[PNT_REG / 64];
+  __shared__ double2 prow[PSB];            // the pivot row over the sub-block
+  __shared__ double2 krow[PSB];            // the row it displaces
+  __shared__ double2 U[PSB][PANEL];        // the sub-block's U rows over the columns to its right
+  __shared__ int spv[PSB];                 // the sub-block's pivot rows
+  extern __shared__ double2 sub[];         // [N - c0][PSB]: the sub-block, rows c0 ..
+  auto rowof = [&](int q) { return k0 + tid + PNT_REG * q; };
+  int first_singular = -1;   // the same in every thread
+  for (int sb0 = 0; sb0 < kb; sb0 += PSB) {
+    const int sbw = kb - sb0 < PSB ? kb - sb0 : PSB;
+    const int c0 = k0 + sb0, rc0 = sb0 + sbw;   // rc0: first panel column to the right (panel-relative)
+    // rows above c0 keep their values in this sub-block (U rows of the panel)
+    const int nsub = (N - c0) * PSB;
+    for (int e = tid; e < nsub; e += PNT_REG) {
+      const int c = e & (PSB - 1);
+      sub[e] = c < sbw ? M[(long long)(c0 + (e / PSB)) * N + k0 + sb0 + c] : double2{0.0, 0.0};
+    }
+    __syncthreads();
+    double2 r[RPT][PSB];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int rr = rowof(q);
+#pragma unroll
+      for (int c = 0; c < PSB; ++c) r[q][c] = (rr >= c0 && rr < N) ? sub[(rr - c0) * PSB + c] : double2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int kk = 0; kk < PSB; ++kk) {
+      if (kk >= sbw) break;
+      const int col = k0 + sb0 + kk;
+      // pivot: largest |a|^2 among rows [col, K), first index on ties
+      double v = -1.0;
+      int idx = tid;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int rr = rowof(q);
+        const double vq = (rr >= col && rr < K) ? r[q][kk].x * r[q][kk].x + r[q][kk].y * r[q][kk].y : -1.0;
+        argmax_take(v, idx, vq, rr);
+      }
+      wave_argmax(v, idx);
+      if (lane == 0) {
+        rv[wave] = v;
+        ri[wave] = idx;
+      }
+      __syncthreads();
+      double bv = rv[0];
+      int p = ri[0];
+#pragma unroll
+      for (int w = 1; w < PNT_REG / 64; ++w) argmax_take(bv, p, rv[w], ri[w]);
+      const bool singular = !(bv > 0.0);
+      if (singular && first_singular < 0) first_singular = col;
+      if (tid == 0) spv[kk] = p;
+      // exchange rows col and p in this sub-block through LDS from the
+      // owners' registers; the other panel columns take the sub-block's swaps
+      // together after it (no memory operation inside the column loop, whose
+      // barriers would wait for it)
+      const int qp = (p - k0) / PNT_REG, qc = (col - k0) / PNT_REG;
+      if (tid == (p - k0) % PNT_REG) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+          if (q == qp)
+#pragma unroll
+            for (int c = 0; c < PSB; ++c) prow[c] = r[q][c];
+      }
+      if (tid == (col - k0) % PNT_REG) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+          if (q == qc)
+#pragma unroll
+            for (int c = 0; c < PSB; ++c) krow[c] = r[q][c];
+      }
+      __syncthreads();
+      if (p != col) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          if (rowof(q) == col) {
+#pragma unroll
+            for (int c = 0; c < PSB; ++c) r[q][c] = prow[c];
+          } else if (rowof(q) == p) {
+#pragma unroll
+            for (int c = 0; c < PSB; ++c) r[q][c] = krow[c];
+          }
+        }
+      }
+      // multipliers and the rank-1 update inside the sub-block
+      const double2 inv = singular ? double2{0.0, 0.0} : cinv(prow[kk]);
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int rr = rowof(q);
+        if (rr < N && rr > col) {
+          const double2 mlt = cmul(r[q][kk], inv);
+          r[q][kk] = mlt;
+#pragma unroll
+          for (int c = 0; c < PSB; ++c)
+            if (c > kk && c < sbw) r[q][c] = csub_mul(r[q][c], mlt, prow[c]);
+        }
+      }
+    }
+    // the sub-block back to memory through LDS
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int rr = rowof(q);
+      if (rr >= c0 && rr < N)
+#pragma unroll
+        for (int c = 0; c < PSB; ++c) sub[(rr - c0) * PSB + c] = r[q][c];
+    }
+    __syncthreads();
+    for (int e = tid; e < nsub; e += PNT_REG) {
+      const int c = e & (PSB - 1);
+      if (c < sbw) M[(long long)(c0 + (e / PSB)) * N + k0 + sb0 + c] = sub[e];
+    }
+    // the sub-block's swaps on the other panel columns at once: (slot x,
+    // panel column c) writes row X (c0 + x / 2, or the pivot row of column
+    // x / 2) with the value the swap sequence brings to it, the value that
+    // row sigma(X) held before, sigma the swaps applied in reverse order
+    {
+      int Xs[2], srcs[2];
+      double2 mv[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int e = tid + PNT_REG * h, x = e >> 5, c = e & 31;
+        Xs[h] = -1;
+        srcs[h] = -1;
+        mv[h] = double2{0.0, 0.0};
+        if (x < 2 * sbw && c < kb && (c < sb0 || c >= sb0 + sbw)) {
+          const int X = (x & 1) ? spv[x >> 1] : c0 + (x >> 1);
+          int src = X;
+          for (int i = sbw - 1; i >= 0; --i) {
+            const int pi = spv[i];
+            if (src == c0 + i)
+              src = pi;
+            else if (src == pi)
+              src = c0 + i;
+          }
+          if (src != X) {
+            Xs[h] = X;
+            srcs[h] = src;
+            mv[h] = M[(long long)src * N + k0 + c];
+          }
+        }
+      }
+      __syncthreads();   // every value is read before any is written
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = (tid + PNT_REG * h) & 31;
+        if (Xs[h] >= 0) M[(long long)Xs[h] * N + k0 + c] = mv[h];
+      }
+      if (tid < sbw) piv[(long long)b * K + c0 + tid] = spv[tid];
+    }
+    if (rc0 < kb) {
+      // (the sub-block's unit lower factor: rows 0 .. sbw - 1 of sub)
+      __syncthreads();
+      // U rows c0 .. c0 + sbw - 1 over the columns to the right: forward
+      // substitution with the unit lower L11, one lane per column
+      if (wave == 0 && rc0 + lane < kb) {
+        const int c = rc0 + lane;
+        double2 x[PSB];
+#pragma unroll
+        for (int i = 0; i < PSB; ++i) x[i] = i < sbw ? M[(long long)(c0 + i) * N + k0 + c] : double2{0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < PSB; ++i) {
+          if (i >= sbw) break;
+          double2 vv = x[i];
+#pragma unroll
+          for (int j = 0; j < PSB; ++j)
+            if (j < i) vv = csub_mul(vv, sub[i * PSB + j], x[j]);
+          x[i] = vv;
+          U[i][c] = vv;
+          M[(long long)(c0 + i) * N + k0 + c] = vv;
+        }
+      }
+      __syncthreads();
+      // rank-sbw update of the columns to the right for the rows below the
+      // sub-block: consecutive threads on consecutive columns of a row, the
+      // row's multipliers from LDS, four elements' requests in flight at once
+      const int nrc = kb - rc0, nel = (N - c0 - sbw) * nrc;
+      for (int e0 = tid; e0 < nel; e0 += 4 * PNT_REG) {
+        double2 vv[4];
+        long long at[4];
+#pragma unroll
+        for (int z = 0; z < 4; ++z) {
+          const int e = e0 + z * PNT_REG;
+          at[z] = -1;
+          if (e < nel) {
+            const int rr = c0 + sbw + e / nrc, c = rc0 + e % nrc;
+            at[z] = (long long)rr * N + k0 + c;
+            vv[z] = M[at[z]];
+          }
+        }
+#pragma unroll
+        for (int z = 0; z < 4; ++z) {
+          const int e = e0 + z * PNT_REG;
+          if (e < nel) {
+            const int rl = sbw + e / nrc, c = rc0 + e % nrc;
+            double2 w = vv[z];
+#pragma unroll
+            for (int i = 0; i < PSB; ++i)
+              if (i < sbw) w = csub_mul(w, sub[rl * PSB + i], U[i][c]);
+            M[at[z]] = w;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0 && first_singular >= 0 && info[b] == 0) info[b] = first_singular + 1;
+}
+
 // Columns j >= k0 + kb: apply the panel's row swaps, then U12 = L11^-1 A12
 // (unit lower triangular L11 of the panel).  One thread per column.
 __global__ void __launch_bounds__(64) swap_trsm_kernel(double2* __restrict__ A, int N, int K, int k0, int kb,
@@ -260,7 +519,18 @@ unsigned grid1(long long total) {
 void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t s) {
   for (int k0 = 0; k0 < K; k0 += PANEL) {
     const int kb = K - k0 < PANEL ? K - k0 : PANEL;
-    hipLaunchKernelGGL(panel_kernel, dim3((unsigned)T), dim3(512), 0, s, A, N, K, k0, kb, piv, info);
+    const int rpt = (N - k0 + PNT_REG - 1) / PNT_REG;
+    const size_t shm = (size_t)(N - k0) * PSB * sizeof(double2);
+    if (rpt == 1)
+      hipLaunchKernelGGL(panel_reg_kernel<1>, dim3((unsigned)T), dim3(PNT_REG), shm, s, A, N, K, k0, kb, piv, info);
+    else if (rpt == 2)
+      hipLaunchKernelGGL(panel_reg_kernel<2>, dim3((unsigned)T), dim3(PNT_REG), shm, s, A, N, K, k0, kb, piv, info);
+    else if (rpt == 3)
+      hipLaunchKernelGGL(panel_reg_kernel<3>, dim3((unsigned)T), dim3(PNT_REG), shm, s, A, N, K, k0, kb, piv, info);
+    else if (rpt == 4)
+      hipLaunchKernelGGL(panel_reg_kernel<4>, dim3((unsigned)T), dim3(PNT_REG), shm, s, A, N, K, k0, kb, piv, info);
+    else
+      hipLaunchKernelGGL(panel_kernel, dim3((unsigned)T), dim3(512), 0, s, A, N, K, k0, kb, piv, info);
     const int rest = N - k0 - kb;
     if (rest > 0) {
       hipLaunchKernelGGL(swap_trsm_kernel, dim3((unsigned)((rest + 63) / 64), (unsigned)T), dim3(64), 0, s, A, N, K,
