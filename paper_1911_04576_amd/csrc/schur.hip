@@ -407,51 +407,92 @@ __global__ void __launch_bounds__(64) swap_trsm_kernel(double2* __restrict__ A, 
     if (i < kb) M[(long long)(k0 + i) * N + j] = x[i];
 }
 
-// Trailing update A22 -= L21 U12 over rows and columns [k0 + kb, N): 32 x 32
-// output tiles, 256 threads each owning 4 outputs of one row.
-constexpr int TT = 32;
-__global__ void __launch_bounds__(256) update_kernel(double2* __restrict__ A, int N, int k0, int kb) {
+// Trailing update A22 -= L21 U12 over rows and columns [k0 + kb, N) on the
+// matrix cores (v_mfma_f64_16x16x4f64): 64 x 64
+// output tiles, 4 wavefronts of 2 x 2 tiles of 16 x 16.  The complex
+// product in two real ones that share the B operand: k-slot kk = (source
+// pair offset h = kk / 2, part p = kk % 2) of l = 2 s + h for MFMA s,
+//     B = part p of U12[l][col],
+//     A_re = p = 0 ? Re L21[row][l] : -Im L21[row][l]  -> Re (L21 U12)
+//     A_im = p = 0 ? Im L21[row][l] :  Re L21[row][l]  -> Im (L21 U12)
+// L21 and U12 are staged through LDS; the tile of A22 is read before the
+// products and written after them.
+constexpr int UT = 64;
+constexpr int ULP = PANEL + 1;   // L rows padded: the 16 rows of a read start on distinct banks
+__global__ void __launch_bounds__(256, 2) update_mfma_kernel(double2* __restrict__ A, int N, int k0, int kb) {
+  typedef double d4v __attribute__((ext_vector_type(4)));
   const int b = blockIdx.z;
   double2* M = A + (long long)b * N * N;
-  const int r0 = k0 + kb + blockIdx.y * TT;
-  const int c0 = k0 + kb + blockIdx.x * TT;
-  __shared__ double2 Ls[TT][PANEL + 1];
-  __shared__ double2 Us[PANEL][TT + 1];
-  for (int t = threadIdx.x; t < TT * PANEL; t += blockDim.x) {
-    const int i = t / PANEL, l = t - i * PANEL;
+  const int r0 = k0 + kb + blockIdx.y * UT;
+  const int c0 = k0 + kb + blockIdx.x * UT;
+  __shared__ double2 Ls[UT * ULP];     // [row][l]
+  __shared__ double2 Us[PANEL * UT];   // [l][col]
+  const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6, wr = wv & 1, wc = wv >> 1;
+#pragma unroll
+  for (int j = 0; j < UT * PANEL / 256; ++j) {
+    const int e = tid + 256 * j;
+    const int i = e / PANEL, ll = e - i * PANEL;   // L: row i, column ll
     const int gi = r0 + i;
-    Ls[i][l] = (gi < N && l < kb) ? M[(long long)gi * N + k0 + l] : double2{0.0, 0.0};
+    Ls[i * ULP + ll] = (gi < N && ll < kb) ? M[(long long)gi * N + k0 + ll] : double2{0.0, 0.0};
+    const int lu = e / UT, cc = e - lu * UT;       // U: row lu, column cc
+    const int gc = c0 + cc;
+    Us[lu * UT + cc] = (gc < N && lu < kb) ? M[(long long)(k0 + lu) * N + gc] : double2{0.0, 0.0};
   }
-  for (int t = threadIdx.x; t < PANEL * TT; t += blockDim.x) {
-    const int l = t / TT, jj = t - l * TT;
-    const int gj = c0 + jj;
-    Us[l][jj] = (gj < N && l < kb) ? M[(long long)(k0 + l) * N + gj] : double2{0.0, 0.0};
-  }
+  // this lane's outputs: tile (rt, ct), register e -> row (l / 16) + 4 e, column l % 16
+  const int jj = l & 15, qrow = l >> 4;
+  double2 cv[2][2][4];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gi = r0 + 32 * wr + 16 * rt + qrow + 4 * e, gc = c0 + 32 * wc + 16 * ct + jj;
+        cv[rt][ct][e] = (gi < N && gc < N) ? M[(long long)gi * N + gc] : double2{0.0, 0.0};
+      }
   __syncthreads();
-  const int i = threadIdx.x / 8;           // tile row
-  const int jb = (threadIdx.x % 8) * 4;    // first of 4 tile columns
-  const int gi = r0 + i;
-  if (gi >= N) return;
-  double2 acc[4];
+  d4v dre[2][2], dim[2][2];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = double2{0.0, 0.0};
-  for (int l = 0; l < kb; ++l) {
-    const double2 a = Ls[i][l];
+  for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double2 u = Us[l][jb + q];
-      acc[q].x = __builtin_fma(a.x, u.x, __builtin_fma(-a.y, u.y, acc[q].x));
-      acc[q].y = __builtin_fma(a.x, u.y, __builtin_fma(a.y, u.x, acc[q].y));
+    for (int ct = 0; ct < 2; ++ct) {
+      dre[rt][ct] = d4v{0, 0, 0, 0};
+      dim[rt][ct] = d4v{0, 0, 0, 0};
     }
+  const int kk = l >> 4, h = kk >> 1, p = kk & 1, i16 = l & 15;
+  const int ns = (kb + 1) / 2;
+  for (int s = 0; s < ns; ++s) {
+    const int ll = 2 * s + h;
+    double are[2], aim[2], bb[2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const double2 Lv = Ls[(32 * wr + 16 * rt + i16) * ULP + ll];
+      are[rt] = p == 0 ? Lv.x : -Lv.y;
+      aim[rt] = p == 0 ? Lv.y : Lv.x;
+    }
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const double2 Uv = Us[ll * UT + 32 * wc + 16 * ct + jj];
+      bb[ct] = p == 0 ? Uv.x : Uv.y;
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        dre[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[rt], bb[ct], dre[rt][ct], 0, 0, 0);
+        dim[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[rt], bb[ct], dim[rt][ct], 0, 0, 0);
+      }
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int gj = c0 + jb + q;
-    if (gj < N) {
-      double2* c = M + (long long)gi * N + gj;
-      *c = double2{c->x - acc[q].x, c->y - acc[q].y};
-    }
-  }
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gi = r0 + 32 * wr + 16 * rt + qrow + 4 * e, gc = c0 + 32 * wc + 16 * ct + jj;
+        if (gi < N && gc < N)
+          M[(long long)gi * N + gc] = double2{cv[rt][ct][e].x - dre[rt][ct][e], cv[rt][ct][e].y - dim[rt][ct][e]};
+      }
 }
 
 // A1[t] = [[Z_int,int, Z_int,eq], [Z_eq,int, Z_eq,eq]] from Z[t] = [[Z_eq,eq, ...]]
@@ -535,8 +576,8 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
     if (rest > 0) {
       hipLaunchKernelGGL(swap_trsm_kernel, dim3((unsigned)((rest + 63) / 64), (unsigned)T), dim3(64), 0, s, A, N, K,
                          k0, kb, piv);
-      const unsigned tiles = (unsigned)((rest + TT - 1) / TT);
-      hipLaunchKernelGGL(update_kernel, dim3(tiles, tiles, (unsigned)T), dim3(256), 0, s, A, N, k0, kb);
+      const unsigned tiles = (unsigned)((rest + UT - 1) / UT);
+      hipLaunchKernelGGL(update_mfma_kernel, dim3(tiles, tiles, (unsigned)T), dim3(256), 0, s, A, N, k0, kb);
     }
     EMS_LAUNCH_CHECK();
   }
