@@ -158,10 +158,10 @@ __global__ void __launch_bounds__(PNT_REG) panel_reg_kernel(double2* __restrict_
   const int b = blockIdx.x;
   double2* M = A + (long long)b * N * N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ double rv[PNT_REG / 64];
-  __shared__ int ri[PNT_REG / 64];
-  __shared__ double2 prow[PSB];            // the pivot row over the sub-block
-  __shared__ double2 krow[PSB];            // the row it displaces
+  __shared__ double rv[2][PNT_REG / 64];
+  __shared__ int ri[2][PNT_REG / 64];
+  __shared__ double2 cand[2][PNT_REG / 64][PSB];   // each wavefront's best candidate row
+  __shared__ double2 krow[2][PSB];                 // row col, which the pivot row displaces
   __shared__ double2 U[PSB][PANEL];        // the sub-block's U rows over the columns to its right
   __shared__ int spv[PSB];                 // the sub-block's pivot rows
   extern __shared__ double2 sub[];         // [N - c0][PSB]: the sub-block, rows c0 ..
@@ -171,10 +171,21 @@ __global__ void __launch_bounds__(PNT_REG) panel_reg_kernel(double2* __restrict_
     const int sbw = kb - sb0 < PSB ? kb - sb0 : PSB;
     const int c0 = k0 + sb0, rc0 = sb0 + sbw;   // rc0: first panel column to the right (panel-relative)
     // rows above c0 keep their values in this sub-block (U rows of the panel)
+    // (every load of the sub-block is issued before the first is used:
+    // nsub <= RPT * PNT_REG * PSB)
     const int nsub = (N - c0) * PSB;
-    for (int e = tid; e < nsub; e += PNT_REG) {
-      const int c = e & (PSB - 1);
-      sub[e] = c < sbw ? M[(long long)(c0 + (e / PSB)) * N + k0 + sb0 + c] : double2{0.0, 0.0};
+    {
+      double2 st[RPT * PSB];
+#pragma unroll
+      for (int j = 0; j < RPT * PSB; ++j) {
+        const int e = tid + PNT_REG * j, c = e & (PSB - 1);
+        st[j] = (e < nsub && c < sbw) ? M[(long long)(c0 + (e / PSB)) * N + k0 + sb0 + c] : double2{0.0, 0.0};
+      }
+#pragma unroll
+      for (int j = 0; j < RPT * PSB; ++j) {
+        const int e = tid + PNT_REG * j;
+        if (e < nsub) sub[e] = st[j];
+      }
     }
     __syncthreads();
     double2 r[RPT][PSB];
@@ -198,38 +209,42 @@ __global__ void __launch_bounds__(PNT_REG) panel_reg_kernel(double2* __restrict_
         argmax_take(v, idx, vq, rr);
       }
       wave_argmax(v, idx);
+      // one barrier per column: before it each wavefront publishes its best
+      // candidate (value, row, and the row's sub-block values), and the owner
+      // of row col publishes that row; the slots alternate with the column's
+      // parity, so the next column's writes cannot meet this column's reads
+      const int par = kk & 1;
       if (lane == 0) {
-        rv[wave] = v;
-        ri[wave] = idx;
+        rv[par][wave] = v;
+        ri[par][wave] = idx;
+      }
+      const int qc = (col - k0) / PNT_REG;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        if (rowof(q) == idx && v >= 0.0)
+#pragma unroll
+          for (int c = 0; c < PSB; ++c) cand[par][wave][c] = r[q][c];
+        if (q == qc && tid == (col - k0) % PNT_REG)
+#pragma unroll
+          for (int c = 0; c < PSB; ++c) krow[par][c] = r[q][c];
       }
       __syncthreads();
-      double bv = rv[0];
-      int p = ri[0];
+      double bv = rv[par][0];
+      int p = ri[par][0], pw = 0;
 #pragma unroll
-      for (int w = 1; w < PNT_REG / 64; ++w) argmax_take(bv, p, rv[w], ri[w]);
+      for (int w = 1; w < PNT_REG / 64; ++w)
+        if (rv[par][w] > bv || (rv[par][w] == bv && ri[par][w] < p)) {
+          bv = rv[par][w];
+          p = ri[par][w];
+          pw = w;
+        }
+      const double2* prow = cand[par][pw];   // the pivot row over the sub-block
       const bool singular = !(bv > 0.0);
       if (singular && first_singular < 0) first_singular = col;
       if (tid == 0) spv[kk] = p;
-      // exchange rows col and p in this sub-block through LDS from the
-      // owners' registers; the other panel columns take the sub-block's swaps
-      // together after it (no memory operation inside the column loop, whose
-      // barriers would wait for it)
-      const int qp = (p - k0) / PNT_REG, qc = (col - k0) / PNT_REG;
-      if (tid == (p - k0) % PNT_REG) {
-#pragma unroll
-        for (int q = 0; q < RPT; ++q)
-          if (q == qp)
-#pragma unroll
-            for (int c = 0; c < PSB; ++c) prow[c] = r[q][c];
-      }
-      if (tid == (col - k0) % PNT_REG) {
-#pragma unroll
-        for (int q = 0; q < RPT; ++q)
-          if (q == qc)
-#pragma unroll
-            for (int c = 0; c < PSB; ++c) krow[c] = r[q][c];
-      }
-      __syncthreads();
+      // exchange rows col and p in this sub-block (the other panel columns
+      // take the sub-block's swaps together after it: no memory operation
+      // inside the column loop, whose barrier would wait for it)
       if (p != col) {
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
@@ -238,7 +253,7 @@ __global__ void __launch_bounds__(PNT_REG) panel_reg_kernel(double2* __restrict_
             for (int c = 0; c < PSB; ++c) r[q][c] = prow[c];
           } else if (rowof(q) == p) {
 #pragma unroll
-            for (int c = 0; c < PSB; ++c) r[q][c] = krow[c];
+            for (int c = 0; c < PSB; ++c) r[q][c] = krow[par][c];
           }
         }
       }
@@ -265,9 +280,10 @@ __global__ void __launch_bounds__(PNT_REG) panel_reg_kernel(double2* __restrict_
         for (int c = 0; c < PSB; ++c) sub[(rr - c0) * PSB + c] = r[q][c];
     }
     __syncthreads();
-    for (int e = tid; e < nsub; e += PNT_REG) {
-      const int c = e & (PSB - 1);
-      if (c < sbw) M[(long long)(c0 + (e / PSB)) * N + k0 + sb0 + c] = sub[e];
+#pragma unroll
+    for (int j = 0; j < RPT * PSB; ++j) {
+      const int e = tid + PNT_REG * j, c = e & (PSB - 1);
+      if (e < nsub && c < sbw) M[(long long)(c0 + (e / PSB)) * N + k0 + sb0 + c] = sub[e];
     }
     // the sub-block's swaps on the other panel columns at once: (slot x,
     // panel column c) writes row X (c0 + x / 2, or the pivot row of column
@@ -331,32 +347,34 @@ __global__ void __launch_bounds__(PNT_REG) panel_reg_kernel(double2* __restrict_
       }
       __syncthreads();
       // rank-sbw update of the columns to the right for the rows below the
-      // sub-block: consecutive threads on consecutive columns of a row, the
-      // row's multipliers from LDS, four elements' requests in flight at once
-      const int nrc = kb - rc0, nel = (N - c0 - sbw) * nrc;
-      for (int e0 = tid; e0 < nel; e0 += 4 * PNT_REG) {
-        double2 vv[4];
-        long long at[4];
+      // sub-block: a thread keeps one column's U values in registers and
+      // walks rows rofs, rofs + rstep, ... (consecutive threads on
+      // consecutive columns of a row, the row's multipliers from LDS), with
+      // UB rows' requests in flight at once
+      constexpr int UB = 16;
+      const int nrc = kb - rc0, rstep = PNT_REG / nrc, nrow = N - c0 - sbw;
+      const int rofs = tid / nrc, c = rc0 + tid % nrc;
+      if (rofs < rstep) {
+        double2 u[PSB];
 #pragma unroll
-        for (int z = 0; z < 4; ++z) {
-          const int e = e0 + z * PNT_REG;
-          at[z] = -1;
-          if (e < nel) {
-            const int rr = c0 + sbw + e / nrc, c = rc0 + e % nrc;
-            at[z] = (long long)rr * N + k0 + c;
-            vv[z] = M[at[z]];
+        for (int i = 0; i < PSB; ++i) u[i] = i < sbw ? U[i][c] : double2{0.0, 0.0};
+        for (int rb = rofs; rb < nrow; rb += UB * rstep) {
+          double2 vv[UB];
+#pragma unroll
+          for (int z = 0; z < UB; ++z) {
+            const int rl = rb + z * rstep;
+            vv[z] = rl < nrow ? M[(long long)(c0 + sbw + rl) * N + k0 + c] : double2{0.0, 0.0};
           }
-        }
 #pragma unroll
-        for (int z = 0; z < 4; ++z) {
-          const int e = e0 + z * PNT_REG;
-          if (e < nel) {
-            const int rl = sbw + e / nrc, c = rc0 + e % nrc;
-            double2 w = vv[z];
+          for (int z = 0; z < UB; ++z) {
+            const int rl = rb + z * rstep;
+            if (rl < nrow) {
+              double2 w = vv[z];
 #pragma unroll
-            for (int i = 0; i < PSB; ++i)
-              if (i < sbw) w = csub_mul(w, sub[rl * PSB + i], U[i][c]);
-            M[at[z]] = w;
+              for (int i = 0; i < PSB; ++i)
+                if (i < sbw) w = csub_mul(w, sub[(sbw + rl) * PSB + i], u[i]);
+              M[(long long)(c0 + sbw + rl) * N + k0 + c] = w;
+            }
           }
         }
       }
@@ -366,32 +384,67 @@ __global__ void __launch_bounds__(PNT_REG) panel_reg_kernel(double2* __restrict_
   if (tid == 0 && first_singular >= 0 && info[b] == 0) info[b] = first_singular + 1;
 }
 
-// Columns j >= k0 + kb: apply the panel's row swaps, then U12 = L11^-1 A12
-// (unit lower triangular L11 of the panel).  One thread per column.
-__global__ void __launch_bounds__(64) swap_trsm_kernel(double2* __restrict__ A, int N, int K, int k0, int kb,
-                                                       const int* __restrict__ piv) {
+// Columns [cb, ce) right of the panel (cb >= k0 + kb): the panel's row swaps,
+// then U12 = L11^-1 A12 (unit lower triangular L11 of the panel).  One thread
+// per column.  The swaps are composed before any memory is touched: only the
+// panel rows and the pivot rows move, and after the swap sequence row X holds
+// what row sigma(X) held before, sigma the swaps applied in reverse order.  A
+// column is then read once for those rows and written once, instead of one
+// dependent read-write pair per swap.
+__global__ void __launch_bounds__(64) swap_trsm_kernel(double2* __restrict__ A, int N, int K, int k0, int kb, int cb,
+                                                       int ce, const int* __restrict__ piv) {
   const int b = blockIdx.y;
   double2* M = A + (long long)b * N * N;
   __shared__ double2 L[PANEL][PANEL + 1];
-  for (int t = threadIdx.x; t < kb * kb; t += blockDim.x) {
-    const int i = t / kb, l = t - i * kb;
-    L[i][l] = M[(long long)(k0 + i) * N + k0 + l];
-  }
-  __syncthreads();
-  const int j = k0 + kb + blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
-  for (int kk = k0; kk < k0 + kb; ++kk) {
-    const int p = piv[(long long)b * K + kk];
-    if (p != kk) {
-      const double2 t = M[(long long)p * N + j];
-      M[(long long)p * N + j] = M[(long long)kk * N + j];
-      M[(long long)kk * N + j] = t;
+  __shared__ int pv[PANEL], Xs[2 * PANEL], Ss[2 * PANEL];
+  {
+    // every load of L11 is issued before the first is used (kb^2 <= 16 * 64)
+    double2 lv[PANEL * PANEL / 64];
+#pragma unroll
+    for (int q = 0; q < PANEL * PANEL / 64; ++q) {
+      const int t = threadIdx.x + 64 * q, i = t / kb, l = t - i * kb;
+      lv[q] = t < kb * kb ? M[(long long)(k0 + i) * N + k0 + l] : double2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int q = 0; q < PANEL * PANEL / 64; ++q) {
+      const int t = threadIdx.x + 64 * q, i = t / kb, l = t - i * kb;
+      if (t < kb * kb) L[i][l] = lv[q];
     }
   }
-  double2 x[PANEL];
+  if (threadIdx.x < kb) pv[threadIdx.x] = piv[(long long)b * K + k0 + threadIdx.x];
+  __syncthreads();
+  // slot t < kb: panel row k0 + t; slot kb + i: the pivot row of column k0 + i
+  if (threadIdx.x < 2 * kb) {
+    const int t = threadIdx.x;
+    const int X = t < kb ? k0 + t : pv[t - kb];
+    int src = X;
+    for (int i = kb - 1; i >= 0; --i) {
+      if (src == k0 + i)
+        src = pv[i];
+      else if (src == pv[i])
+        src = k0 + i;
+    }
+    Xs[t] = X;
+    Ss[t] = src;
+  }
+  __syncthreads();
+  const int j = cb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ce) return;
+  double2 x[PANEL], y[PANEL];
+#pragma unroll
+  for (int i = 0; i < PANEL; ++i) {
+    x[i] = double2{0.0, 0.0};
+    y[i] = double2{0.0, 0.0};
+    if (i < kb) {
+      x[i] = M[(long long)Ss[i] * N + j];
+      if (Xs[kb + i] >= k0 + kb) y[i] = M[(long long)Ss[kb + i] * N + j];
+    }
+  }
+  // every read of the column precedes its writes (a pivot row named by
+  // several columns gets the same value from each slot)
 #pragma unroll
   for (int i = 0; i < PANEL; ++i)
-    if (i < kb) x[i] = M[(long long)(k0 + i) * N + j];
+    if (i < kb && Xs[kb + i] >= k0 + kb && Ss[kb + i] != Xs[kb + i]) M[(long long)Xs[kb + i] * N + j] = y[i];
 #pragma unroll
   for (int i = 1; i < PANEL; ++i) {
     if (i < kb) {
@@ -403,11 +456,11 @@ __global__ void __launch_bounds__(64) swap_trsm_kernel(double2* __restrict__ A, 
     }
   }
 #pragma unroll
-  for (int i = 1; i < PANEL; ++i)
+  for (int i = 0; i < PANEL; ++i)
     if (i < kb) M[(long long)(k0 + i) * N + j] = x[i];
 }
 
-// Trailing update A22 -= L21 U12 over rows and columns [k0 + kb, N) on the
+// Trailing update A22 -= L21 U12 over rows [k0 + kb, N) and columns [cb, ce) on the
 // matrix cores (v_mfma_f64_16x16x4f64): 64 x 64
 // output tiles, 4 wavefronts of 2 x 2 tiles of 16 x 16.  The complex
 // product in two real ones that share the B operand: k-slot kk = (source
@@ -419,12 +472,13 @@ __global__ void __launch_bounds__(64) swap_trsm_kernel(double2* __restrict__ A, 
 // products and written after them.
 constexpr int UT = 64;
 constexpr int ULP = PANEL + 1;   // L rows padded: the 16 rows of a read start on distinct banks
-__global__ void __launch_bounds__(256, 2) update_mfma_kernel(double2* __restrict__ A, int N, int k0, int kb) {
+__global__ void __launch_bounds__(256, 2) update_mfma_kernel(double2* __restrict__ A, int N, int k0, int kb, int cb,
+                                                               int ce) {
   typedef double d4v __attribute__((ext_vector_type(4)));
   const int b = blockIdx.z;
   double2* M = A + (long long)b * N * N;
   const int r0 = k0 + kb + blockIdx.y * UT;
-  const int c0 = k0 + kb + blockIdx.x * UT;
+  const int c0 = cb + blockIdx.x * UT;
   __shared__ double2 Ls[UT * ULP];     // [row][l]
   __shared__ double2 Us[PANEL * UT];   // [l][col]
   const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6, wr = wv & 1, wc = wv >> 1;
@@ -436,7 +490,7 @@ __global__ void __launch_bounds__(256, 2) update_mfma_kernel(double2* __restrict
     Ls[i * ULP + ll] = (gi < N && ll < kb) ? M[(long long)gi * N + k0 + ll] : double2{0.0, 0.0};
     const int lu = e / UT, cc = e - lu * UT;       // U: row lu, column cc
     const int gc = c0 + cc;
-    Us[lu * UT + cc] = (gc < N && lu < kb) ? M[(long long)(k0 + lu) * N + gc] : double2{0.0, 0.0};
+    Us[lu * UT + cc] = (gc < ce && lu < kb) ? M[(long long)(k0 + lu) * N + gc] : double2{0.0, 0.0};
   }
   // this lane's outputs: tile (rt, ct), register e -> row (l / 16) + 4 e, column l % 16
   const int jj = l & 15, qrow = l >> 4;
@@ -448,7 +502,7 @@ __global__ void __launch_bounds__(256, 2) update_mfma_kernel(double2* __restrict
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int gi = r0 + 32 * wr + 16 * rt + qrow + 4 * e, gc = c0 + 32 * wc + 16 * ct + jj;
-        cv[rt][ct][e] = (gi < N && gc < N) ? M[(long long)gi * N + gc] : double2{0.0, 0.0};
+        cv[rt][ct][e] = (gi < N && gc < ce) ? M[(long long)gi * N + gc] : double2{0.0, 0.0};
       }
   __syncthreads();
   d4v dre[2][2], dim[2][2];
@@ -490,7 +544,7 @@ __global__ void __launch_bounds__(256, 2) update_mfma_kernel(double2* __restrict
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int gi = r0 + 32 * wr + 16 * rt + qrow + 4 * e, gc = c0 + 32 * wc + 16 * ct + jj;
-        if (gi < N && gc < N)
+        if (gi < N && gc < ce)
           M[(long long)gi * N + gc] = double2{cv[rt][ct][e].x - dre[rt][ct][e], cv[rt][ct][e].y - dim[rt][ct][e]};
       }
 }
@@ -556,8 +610,56 @@ unsigned grid1(long long total) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
-// Leading K x K elimination of T matrices N x N at A (see the file header).
+// A second stream per device for the lookahead of the elimination below,
+// created once (default priority, non-blocking) and kept until the process
+// ends; calls that share it only queue behind each other on it, each with
+// events of its own.
+hipStream_t lookahead_stream() {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  EMS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(dev);
+  if (it != streams.end()) return it->second;
+  hipStream_t a = nullptr;
+  EMS_HIP(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+  streams[dev] = a;
+  return a;
+}
+
+struct EventPair {
+  hipEvent_t panel = nullptr, rest = nullptr;
+  EventPair() {
+    EMS_HIP(hipEventCreateWithFlags(&panel, hipEventDisableTiming));
+    EMS_HIP(hipEventCreateWithFlags(&rest, hipEventDisableTiming));
+  }
+  ~EventPair() {
+    if (panel) (void)hipEventDestroy(panel);
+    if (rest) (void)hipEventDestroy(rest);
+  }
+  EventPair(const EventPair&) = delete;
+  EventPair& operator=(const EventPair&) = delete;
+};
+
+// Leading K x K elimination of T matrices N x N at A (see the file header),
+// with a lookahead of one panel: after panel k the columns of panel k + 1
+// take its swaps, U12 and update on the caller's stream, and panel k + 1
+// starts at once, while the columns beyond take theirs on the second stream
+// (their update, the largest kernel of the step, runs beside the next panel,
+// which holds one workgroup per matrix).  Before it touches those columns the
+// caller's stream waits for the second one.  On return all work is on the
+// caller's stream.
 void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t s) {
+  hipStream_t aux = lookahead_stream();
+  EventPair ev;
+  bool rest_pending = false;
+  auto swap_update = [&](hipStream_t st, int k0, int kb, int cb, int ce) {
+    hipLaunchKernelGGL(swap_trsm_kernel, dim3((unsigned)((ce - cb + 63) / 64), (unsigned)T), dim3(64), 0, st, A, N, K,
+                       k0, kb, cb, ce, piv);
+    const unsigned rt = (unsigned)((N - k0 - kb + UT - 1) / UT), ct = (unsigned)((ce - cb + UT - 1) / UT);
+    hipLaunchKernelGGL(update_mfma_kernel, dim3(ct, rt, (unsigned)T), dim3(256), 0, st, A, N, k0, kb, cb, ce);
+  };
   for (int k0 = 0; k0 < K; k0 += PANEL) {
     const int kb = K - k0 < PANEL ? K - k0 : PANEL;
     const int rpt = (N - k0 + PNT_REG - 1) / PNT_REG;
@@ -572,15 +674,26 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
       hipLaunchKernelGGL(panel_reg_kernel<4>, dim3((unsigned)T), dim3(PNT_REG), shm, s, A, N, K, k0, kb, piv, info);
     else
       hipLaunchKernelGGL(panel_kernel, dim3((unsigned)T), dim3(512), 0, s, A, N, K, k0, kb, piv, info);
-    const int rest = N - k0 - kb;
-    if (rest > 0) {
-      hipLaunchKernelGGL(swap_trsm_kernel, dim3((unsigned)((rest + 63) / 64), (unsigned)T), dim3(64), 0, s, A, N, K,
-                         k0, kb, piv);
-      const unsigned tiles = (unsigned)((rest + UT - 1) / UT);
-      hipLaunchKernelGGL(update_mfma_kernel, dim3(tiles, tiles, (unsigned)T), dim3(256), 0, s, A, N, k0, kb);
+    EMS_LAUNCH_CHECK();
+    // the previous step's far columns, [k0 + kb, N), are final on the second stream
+    if (rest_pending) EMS_HIP(hipStreamWaitEvent(s, ev.rest, 0));
+    rest_pending = false;
+    const int c1 = k0 + kb;
+    if (c1 >= N) continue;
+    const int nk = K - c1 < PANEL ? K - c1 : PANEL;   // width of the next panel (0 after the last)
+    const int c2 = nk > 0 ? c1 + nk : N;
+    if (c2 < N) {
+      EMS_HIP(hipEventRecord(ev.panel, s));
+      EMS_HIP(hipStreamWaitEvent(aux, ev.panel, 0));
+      swap_update(aux, k0, kb, c2, N);
+      EMS_LAUNCH_CHECK();
+      EMS_HIP(hipEventRecord(ev.rest, aux));
+      rest_pending = true;
     }
+    swap_update(s, k0, kb, c1, c2);
     EMS_LAUNCH_CHECK();
   }
+  if (rest_pending) EMS_HIP(hipStreamWaitEvent(s, ev.rest, 0));
 }
 
 }  // namespace
