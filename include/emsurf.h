@@ -244,7 +244,9 @@ emsurf_status emsurf_fill_LK_point_green(const emsurf_geom* geom, int32_t nx, in
  *   Zt_dev     c128 [n_types][n_eq][n_eq] output of Z~, or NULL.
  * 1 <= n_types <= 4096, 1 <= n_eq <= 512, 0 <= n_int <= 4096.  Workspaces of
  * n_types ((n_eq + n_int)^2 + 4 n_eq^2) complex values are allocated for the
- * call.  Blocks on `stream`; a singular Z_int,int or Z~ + Z_self (a zero
+ * call.  Part of the elimination runs on a second stream that the library
+ * creates once per device (default priority) and joins back into `stream`;
+ * the call blocks until `stream` is done.  A singular Z_int,int or Z~ + Z_self (a zero
  * pivot column) returns EMSURF_ERR_ARG naming the cell type, with the outputs
  * unspecified. */
 emsurf_status emsurf_macromodels(int32_t n_types, int32_t n_eq, int32_t n_int, const void* Z_dev,

@@ -34,8 +34,8 @@ __device__ __forceinline__ double2 csub_mul(double2 c, double2 a, double2 b) {
                  __builtin_fma(-a.x, b.y, __builtin_fma(-a.y, b.x, c.y))};
 }
 __device__ __forceinline__ double2 cinv(double2 a) {
-  const double d = a.x * a.x + a.y * a.y;
-  return double2{a.x / d, -a.y / d};
+  const double rd = 1.0 / (a.x * a.x + a.y * a.y);
+  return double2{a.x * rd, -a.y * rd};
 }
 
 // Panel columns [k0, k0 + kb) over rows [k0, N): pivot, swap (panel columns
@@ -119,31 +119,43 @@ template <int CTRL> __device__ __forceinline__ int dpp_i(int v) {
   return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
 }
 __device__ __forceinline__ void argmax_take(double& v, int& idx, double ov, int oi) {
-  if (ov > v || (ov == v && oi < idx)) {
-    v = ov;
-    idx = oi;
-  }
+  // (bitwise operators: no short-circuit branches)
+  const bool take = (ov > v) | ((ov == v) & (oi < idx));
+  v = take ? ov : v;
+  idx = take ? oi : idx;
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 // (largest v, first index on ties) over the 64 lanes, in every lane: quad
-// exchanges 1 and 2 and row rotations 4 and 8 by DPP, then the two row
-// halves and the two wavefront halves by lane exchange
+// exchanges 1 and 2 and row rotations 4 and 8 by DPP leave each row of 16
+// lanes with its own result, and the four rows' results are then combined
+// as wavefront-uniform values read from lanes 0, 16, 32 and 48 (the order
+// does not matter: the rule is a maximum over (v, -index))
 __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
   argmax_take(v, idx, dpp_d<0xB1>(v), dpp_i<0xB1>(idx));   // quad_perm [1,0,3,2]
   argmax_take(v, idx, dpp_d<0x4E>(v), dpp_i<0x4E>(idx));   // quad_perm [2,3,0,1]
   argmax_take(v, idx, dpp_d<0x124>(v), dpp_i<0x124>(idx)); // row_ror 4
   argmax_take(v, idx, dpp_d<0x128>(v), dpp_i<0x128>(idx)); // row_ror 8
-  argmax_take(v, idx, __shfl_xor(v, 16), __shfl_xor(idx, 16));
-  argmax_take(v, idx, __shfl_xor(v, 32), __shfl_xor(idx, 32));
+  double w = readlane_d(v, 0);
+  int wi = __builtin_amdgcn_readlane(idx, 0);
+#pragma unroll
+  for (int r = 1; r < 4; ++r) argmax_take(w, wi, readlane_d(v, 16 * r), __builtin_amdgcn_readlane(idx, 16 * r));
+  v = w;
+  idx = wi;
 }
 
-// The same panel with the rows in registers, for N - k0 <= 1024: 256
-// threads, thread t owning rows k0 + t, k0 + t + 256, ... (RPT of them; few
+// The same panel with the rows in registers, for N - k0 <= NT * RPT: NT
+// threads, thread t owning rows k0 + t, k0 + t + NT, ... (RPT of them; few
 // wavefronts keep the per-column barriers and reductions short).  The
 // panel's columns go in sub-blocks of PSB: a sub-block is staged through
 // LDS with coalesced loads and stores (rows [c0, N)), held in registers, its
 // columns are
 // factorised there (pivot by a reduction over the thread's rows, a
-// wavefront reduction and one over the 4 wavefronts in LDS, row exchange
+// wavefront reduction and one over the NT / 64 wavefronts in LDS, row exchange
 // through LDS), and the panel columns outside it then take the sub-block's
 // row swaps at once, and the columns to its right its U rows (L11^-1 A12 by
 // one wavefront) and one rank-PSB update, so that the panel makes one pass
@@ -151,39 +163,38 @@ __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
 // (largest |a|^2 among rows [kk, K), first index on ties), same singular
 // flags.
 constexpr int PSB = 8;
-constexpr int PNT_REG = 256;
-template <int RPT>
-__global__ void __launch_bounds__(PNT_REG) panel_reg_kernel(double2* __restrict__ A, int N, int K, int k0, int kb,
+template <int NT, int RPT>
+__global__ void __launch_bounds__(NT) panel_reg_kernel(double2* __restrict__ A, int N, int K, int k0, int kb,
                                                             int* __restrict__ piv, int* __restrict__ info) {
   const int b = blockIdx.x;
   double2* M = A + (long long)b * N * N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ double rv[2][PNT_REG / 64];
-  __shared__ int ri[2][PNT_REG / 64];
-  __shared__ double2 cand[2][PNT_REG / 64][PSB];   // each wavefront's best candidate row
+  __shared__ double rv[2][NT / 64];
+  __shared__ int ri[2][NT / 64];
+  __shared__ double2 cand[2][NT / 64][PSB];   // each wavefront's best candidate row
   __shared__ double2 krow[2][PSB];                 // row col, which the pivot row displaces
   __shared__ double2 U[PSB][PANEL];        // the sub-block's U rows over the columns to its right
   __shared__ int spv[PSB];                 // the sub-block's pivot rows
   extern __shared__ double2 sub[];         // [N - c0][PSB]: the sub-block, rows c0 ..
-  auto rowof = [&](int q) { return k0 + tid + PNT_REG * q; };
+  auto rowof = [&](int q) { return k0 + tid + NT * q; };
   int first_singular = -1;   // the same in every thread
   for (int sb0 = 0; sb0 < kb; sb0 += PSB) {
     const int sbw = kb - sb0 < PSB ? kb - sb0 : PSB;
     const int c0 = k0 + sb0, rc0 = sb0 + sbw;   // rc0: first panel column to the right (panel-relative)
     // rows above c0 keep their values in this sub-block (U rows of the panel)
     // (every load of the sub-block is issued before the first is used:
-    // nsub <= RPT * PNT_REG * PSB)
+    // nsub <= RPT * NT * PSB)
     const int nsub = (N - c0) * PSB;
     {
       double2 st[RPT * PSB];
 #pragma unroll
       for (int j = 0; j < RPT * PSB; ++j) {
-        const int e = tid + PNT_REG * j, c = e & (PSB - 1);
+        const int e = tid + NT * j, c = e & (PSB - 1);
         st[j] = (e < nsub && c < sbw) ? M[(long long)(c0 + (e / PSB)) * N + k0 + sb0 + c] : double2{0.0, 0.0};
       }
 #pragma unroll
       for (int j = 0; j < RPT * PSB; ++j) {
-        const int e = tid + PNT_REG * j;
+        const int e = tid + NT * j;
         if (e < nsub) sub[e] = st[j];
       }
     }
@@ -218,13 +229,13 @@ __global__ void __launch_bounds__(PNT_REG) panel_reg_kernel(double2* __restrict_
         rv[par][wave] = v;
         ri[par][wave] = idx;
       }
-      const int qc = (col - k0) / PNT_REG;
+      const int qc = (col - k0) / NT;
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         if (rowof(q) == idx && v >= 0.0)
 #pragma unroll
           for (int c = 0; c < PSB; ++c) cand[par][wave][c] = r[q][c];
-        if (q == qc && tid == (col - k0) % PNT_REG)
+        if (q == qc && tid == (col - k0) % NT)
 #pragma unroll
           for (int c = 0; c < PSB; ++c) krow[par][c] = r[q][c];
       }
@@ -232,12 +243,14 @@ __global__ void __launch_bounds__(PNT_REG) panel_reg_kernel(double2* __restrict_
       double bv = rv[par][0];
       int p = ri[par][0], pw = 0;
 #pragma unroll
-      for (int w = 1; w < PNT_REG / 64; ++w)
-        if (rv[par][w] > bv || (rv[par][w] == bv && ri[par][w] < p)) {
-          bv = rv[par][w];
-          p = ri[par][w];
-          pw = w;
-        }
+      for (int w = 1; w < NT / 64; ++w) {
+        const double ov = rv[par][w];
+        const int oi = ri[par][w];
+        const bool take = (ov > bv) | ((ov == bv) & (oi < p));
+        bv = take ? ov : bv;
+        p = take ? oi : p;
+        pw = take ? w : pw;
+      }
       const double2* prow = cand[par][pw];   // the pivot row over the sub-block
       const bool singular = !(bv > 0.0);
       if (singular && first_singular < 0) first_singular = col;
@@ -282,7 +295,7 @@ __global__ void __launch_bounds__(PNT_REG) panel_reg_kernel(double2* __restrict_
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < RPT * PSB; ++j) {
-      const int e = tid + PNT_REG * j, c = e & (PSB - 1);
+      const int e = tid + NT * j, c = e & (PSB - 1);
       if (e < nsub && c < sbw) M[(long long)(c0 + (e / PSB)) * N + k0 + sb0 + c] = sub[e];
     }
     // the sub-block's swaps on the other panel columns at once: (slot x,
@@ -294,7 +307,7 @@ __global__ void __launch_bounds__(PNT_REG) panel_reg_kernel(double2* __restrict_
       double2 mv[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int e = tid + PNT_REG * h, x = e >> 5, c = e & 31;
+        const int e = tid + NT * h, x = e >> 5, c = e & 31;
         Xs[h] = -1;
         srcs[h] = -1;
         mv[h] = double2{0.0, 0.0};
@@ -318,7 +331,7 @@ __global__ void __launch_bounds__(PNT_REG) panel_reg_kernel(double2* __restrict_
       __syncthreads();   // every value is read before any is written
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int c = (tid + PNT_REG * h) & 31;
+        const int c = (tid + NT * h) & 31;
         if (Xs[h] >= 0) M[(long long)Xs[h] * N + k0 + c] = mv[h];
       }
       if (tid < sbw) piv[(long long)b * K + c0 + tid] = spv[tid];
@@ -351,8 +364,8 @@ __global__ void __launch_bounds__(PNT_REG) panel_reg_kernel(double2* __restrict_
       // walks rows rofs, rofs + rstep, ... (consecutive threads on
       // consecutive columns of a row, the row's multipliers from LDS), with
       // UB rows' requests in flight at once
-      constexpr int UB = 16;
-      const int nrc = kb - rc0, rstep = PNT_REG / nrc, nrow = N - c0 - sbw;
+      constexpr int UB = NT >= 1024 ? 8 : 16;
+      const int nrc = kb - rc0, rstep = NT / nrc, nrow = N - c0 - sbw;
       const int rofs = tid / nrc, c = rc0 + tid % nrc;
       if (rofs < rstep) {
         double2 u[PSB];
@@ -385,79 +398,106 @@ __global__ void __launch_bounds__(PNT_REG) panel_reg_kernel(double2* __restrict_
 }
 
 // Columns [cb, ce) right of the panel (cb >= k0 + kb): the panel's row swaps,
-// then U12 = L11^-1 A12 (unit lower triangular L11 of the panel).  One thread
-// per column.  The swaps are composed before any memory is touched: only the
-// panel rows and the pivot rows move, and after the swap sequence row X holds
-// what row sigma(X) held before, sigma the swaps applied in reverse order.  A
-// column is then read once for those rows and written once, instead of one
-// dependent read-write pair per swap.
-__global__ void __launch_bounds__(64) swap_trsm_kernel(double2* __restrict__ A, int N, int K, int k0, int kb, int cb,
-                                                       int ce, const int* __restrict__ piv) {
+// then U12 = L11^-1 A12 (unit lower triangular L11 of the panel).  Four
+// threads per column (one quad of lanes), thread g holding rows g, g + 4, ...
+// of the column.  The swaps are composed before any memory is touched: only
+// the panel rows and the pivot rows move, and after the swap sequence row X
+// holds what row sigma(X) held before, sigma the swaps applied in reverse
+// order; a column is read once for those rows and written once.  The
+// substitution goes by columns of L11: the owner of x[l] passes it to its
+// quad by DPP and each thread updates its own rows below l.
+template <int CTRL> __device__ __forceinline__ double2 dpp_d2(double2 v) {
+  return double2{dpp_d<CTRL>(v.x), dpp_d<CTRL>(v.y)};
+}
+__device__ __forceinline__ double2 quad_bcast(double2 v, int src) {
+  switch (src) {
+    case 0: return dpp_d2<0x00>(v);   // quad_perm [0,0,0,0]
+    case 1: return dpp_d2<0x55>(v);   // quad_perm [1,1,1,1]
+    case 2: return dpp_d2<0xAA>(v);   // quad_perm [2,2,2,2]
+    default: return dpp_d2<0xFF>(v);  // quad_perm [3,3,3,3]
+  }
+}
+constexpr int STC = 64;                 // columns per workgroup
+constexpr int STR = PANEL / 4;          // rows per thread
+__global__ void __launch_bounds__(4 * STC) swap_trsm_kernel(double2* __restrict__ A, int N, int K, int k0, int kb,
+                                                            int cb, int ce, const int* __restrict__ piv) {
   const int b = blockIdx.y;
   double2* M = A + (long long)b * N * N;
   __shared__ double2 L[PANEL][PANEL + 1];
   __shared__ int pv[PANEL], Xs[2 * PANEL], Ss[2 * PANEL];
+  const int tid = threadIdx.x, g = tid & 3;
   {
-    // every load of L11 is issued before the first is used (kb^2 <= 16 * 64)
-    double2 lv[PANEL * PANEL / 64];
+    // every load of L11 is issued before the first is used (kb^2 <= 4 * 256)
+    double2 lv[PANEL * PANEL / (4 * STC)];
 #pragma unroll
-    for (int q = 0; q < PANEL * PANEL / 64; ++q) {
-      const int t = threadIdx.x + 64 * q, i = t / kb, l = t - i * kb;
+    for (int q = 0; q < PANEL * PANEL / (4 * STC); ++q) {
+      const int t = tid + 4 * STC * q, i = t / kb, l = t - i * kb;
       lv[q] = t < kb * kb ? M[(long long)(k0 + i) * N + k0 + l] : double2{0.0, 0.0};
     }
 #pragma unroll
-    for (int q = 0; q < PANEL * PANEL / 64; ++q) {
-      const int t = threadIdx.x + 64 * q, i = t / kb, l = t - i * kb;
+    for (int q = 0; q < PANEL * PANEL / (4 * STC); ++q) {
+      const int t = tid + 4 * STC * q, i = t / kb, l = t - i * kb;
       if (t < kb * kb) L[i][l] = lv[q];
     }
   }
-  if (threadIdx.x < kb) pv[threadIdx.x] = piv[(long long)b * K + k0 + threadIdx.x];
+  if (tid < kb) pv[tid] = piv[(long long)b * K + k0 + tid];
   __syncthreads();
   // slot t < kb: panel row k0 + t; slot kb + i: the pivot row of column k0 + i
-  if (threadIdx.x < 2 * kb) {
-    const int t = threadIdx.x;
-    const int X = t < kb ? k0 + t : pv[t - kb];
+  if (tid < 2 * kb) {
+    const int X = tid < kb ? k0 + tid : pv[tid - kb];
     int src = X;
-    for (int i = kb - 1; i >= 0; --i) {
-      if (src == k0 + i)
-        src = pv[i];
-      else if (src == pv[i])
-        src = k0 + i;
+#pragma unroll
+    for (int i = PANEL - 1; i >= 0; --i) {
+      if (i < kb) {
+        const int pi = pv[i];
+        src = src == k0 + i ? pi : (src == pi ? k0 + i : src);
+      }
     }
-    Xs[t] = X;
-    Ss[t] = src;
+    Xs[tid] = X;
+    Ss[tid] = src;
   }
   __syncthreads();
-  const int j = cb + blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= ce) return;
-  double2 x[PANEL], y[PANEL];
+  const int j = cb + blockIdx.x * STC + (tid >> 2);
+  const bool live = j < ce;
+  const int jc = live ? j : cb;   // (a column in range for the idle threads' addresses)
+  double2 x[STR], y[STR];
 #pragma unroll
-  for (int i = 0; i < PANEL; ++i) {
-    x[i] = double2{0.0, 0.0};
-    y[i] = double2{0.0, 0.0};
-    if (i < kb) {
-      x[i] = M[(long long)Ss[i] * N + j];
-      if (Xs[kb + i] >= k0 + kb) y[i] = M[(long long)Ss[kb + i] * N + j];
+  for (int m = 0; m < STR; ++m) {
+    const int i = g + 4 * m;
+    x[m] = double2{0.0, 0.0};
+    y[m] = double2{0.0, 0.0};
+    if (live && i < kb) {
+      x[m] = M[(long long)Ss[i] * N + jc];
+      if (Xs[kb + i] >= k0 + kb) y[m] = M[(long long)Ss[kb + i] * N + jc];
     }
   }
-  // every read of the column precedes its writes (a pivot row named by
-  // several columns gets the same value from each slot)
+  // every read of the column (by its four threads) completes before its
+  // writes; a pivot row named by several columns gets the same value from
+  // each slot
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 #pragma unroll
-  for (int i = 0; i < PANEL; ++i)
-    if (i < kb && Xs[kb + i] >= k0 + kb && Ss[kb + i] != Xs[kb + i]) M[(long long)Xs[kb + i] * N + j] = y[i];
+  for (int m = 0; m < STR; ++m) {
+    const int i = g + 4 * m;
+    if (live && i < kb && Xs[kb + i] >= k0 + kb && Ss[kb + i] != Xs[kb + i])
+      M[(long long)Xs[kb + i] * N + jc] = y[m];
+  }
 #pragma unroll
-  for (int i = 1; i < PANEL; ++i) {
-    if (i < kb) {
-      double2 v = x[i];
+  for (int l = 0; l < PANEL - 1; ++l) {
+    if (l < kb) {
+      const double2 xl = quad_bcast(x[l >> 2], l & 3);
 #pragma unroll
-      for (int l = 0; l < PANEL; ++l)
-        if (l < i) v = csub_mul(v, L[i][l], x[l]);
-      x[i] = v;
+      for (int m = 0; m < STR; ++m) {
+        const int i = g + 4 * m;
+        if (i > l && i < kb) x[m] = csub_mul(x[m], L[i][l], xl);
+      }
     }
   }
 #pragma unroll
-  for (int i = 0; i < PANEL; ++i)
-    if (i < kb) M[(long long)(k0 + i) * N + j] = x[i];
+  for (int m = 0; m < STR; ++m) {
+    const int i = g + 4 * m;
+    if (live && i < kb) M[(long long)(k0 + i) * N + jc] = x[m];
+  }
 }
 
 // Trailing update A22 -= L21 U12 over rows [k0 + kb, N) and columns [cb, ce) on the
@@ -472,25 +512,21 @@ __global__ void __launch_bounds__(64) swap_trsm_kernel(double2* __restrict__ A, 
 // products and written after them.
 constexpr int UT = 64;
 constexpr int ULP = PANEL + 1;   // L rows padded: the 16 rows of a read start on distinct banks
-__global__ void __launch_bounds__(256, 2) update_mfma_kernel(double2* __restrict__ A, int N, int k0, int kb, int cb,
-                                                               int ce) {
+// One 64 x 64 tile of the update by 256 threads (Ls, Us: this tile's LDS);
+// every thread of the workgroup calls it, live or not (it holds barriers).
+__device__ __forceinline__ void update_tile(double2* __restrict__ M, int N, int k0, int kb, int ce, int r0, int c0,
+                                            bool live, double2* __restrict__ Ls, double2* __restrict__ Us, int tid) {
   typedef double d4v __attribute__((ext_vector_type(4)));
-  const int b = blockIdx.z;
-  double2* M = A + (long long)b * N * N;
-  const int r0 = k0 + kb + blockIdx.y * UT;
-  const int c0 = cb + blockIdx.x * UT;
-  __shared__ double2 Ls[UT * ULP];     // [row][l]
-  __shared__ double2 Us[PANEL * UT];   // [l][col]
-  const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6, wr = wv & 1, wc = wv >> 1;
+  const int l = tid & 63, wv = tid >> 6, wr = wv & 1, wc = wv >> 1;
 #pragma unroll
   for (int j = 0; j < UT * PANEL / 256; ++j) {
     const int e = tid + 256 * j;
     const int i = e / PANEL, ll = e - i * PANEL;   // L: row i, column ll
     const int gi = r0 + i;
-    Ls[i * ULP + ll] = (gi < N && ll < kb) ? M[(long long)gi * N + k0 + ll] : double2{0.0, 0.0};
+    Ls[i * ULP + ll] = (live && gi < N && ll < kb) ? M[(long long)gi * N + k0 + ll] : double2{0.0, 0.0};
     const int lu = e / UT, cc = e - lu * UT;       // U: row lu, column cc
     const int gc = c0 + cc;
-    Us[lu * UT + cc] = (gc < ce && lu < kb) ? M[(long long)(k0 + lu) * N + gc] : double2{0.0, 0.0};
+    Us[lu * UT + cc] = (live && gc < ce && lu < kb) ? M[(long long)(k0 + lu) * N + gc] : double2{0.0, 0.0};
   }
   // this lane's outputs: tile (rt, ct), register e -> row (l / 16) + 4 e, column l % 16
   const int jj = l & 15, qrow = l >> 4;
@@ -502,9 +538,10 @@ __global__ void __launch_bounds__(256, 2) update_mfma_kernel(double2* __restrict
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int gi = r0 + 32 * wr + 16 * rt + qrow + 4 * e, gc = c0 + 32 * wc + 16 * ct + jj;
-        cv[rt][ct][e] = (gi < N && gc < ce) ? M[(long long)gi * N + gc] : double2{0.0, 0.0};
+        cv[rt][ct][e] = (live && gi < N && gc < ce) ? M[(long long)gi * N + gc] : double2{0.0, 0.0};
       }
   __syncthreads();
+  if (!live) return;
   d4v dre[2][2], dim[2][2];
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
@@ -547,6 +584,38 @@ __global__ void __launch_bounds__(256, 2) update_mfma_kernel(double2* __restrict
         if (gi < N && gc < ce)
           M[(long long)gi * N + gc] = double2{cv[rt][ct][e].x - dre[rt][ct][e], cv[rt][ct][e].y - dim[rt][ct][e]};
       }
+}
+
+__global__ void __launch_bounds__(256, 2) update_mfma_kernel(double2* __restrict__ A, int N, int k0, int kb, int cb,
+                                                               int ce) {
+  __shared__ double2 Ls[UT * ULP];     // [row][l]
+  __shared__ double2 Us[PANEL * UT];   // [l][col]
+  update_tile(A + (long long)blockIdx.z * N * N, N, k0, kb, ce, k0 + kb + blockIdx.y * UT, cb + blockIdx.x * UT, true,
+              Ls, Us, threadIdx.x);
+}
+
+// The same update by a persistent grid for the far columns of the lookahead:
+// workgroups of 512 threads, two tiles at a time (one per half, each with
+// its own LDS), 133 KB of LDS so that a CU holds at most one of them.  With a
+// grid of (CUs - panel workgroups) the update never occupies every CU, and
+// the next panel, whose workgroups each need a CU to themselves, starts on
+// the ones it leaves instead of waiting for the update to drain.  Tiles run
+// matrix-major, row tile, then column tile.
+__global__ void __launch_bounds__(512) update_persist_kernel(double2* __restrict__ A, int N, int k0, int kb, int cb,
+                                                             int ce, int nrt, int nct, int T) {
+  __shared__ double2 Ls[2][UT * ULP];
+  __shared__ double2 Us[2][PANEL * UT];
+  const int half = threadIdx.x >> 8, t256 = threadIdx.x & 255;
+  const int ntiles = nct * nrt * T;
+  for (int it = blockIdx.x; 2 * it < ntiles; it += gridDim.x) {
+    const int t = 2 * it + half;
+    const bool live = t < ntiles;
+    const int tt = live ? t : 0;
+    const int ct = tt % nct, rt = (tt / nct) % nrt, b = tt / (nct * nrt);
+    update_tile(A + (long long)b * N * N, N, k0, kb, ce, k0 + kb + rt * UT, cb + ct * UT, live, Ls[half], Us[half],
+                t256);
+    __syncthreads();   // every read of this tile's LDS precedes the next tile's fill
+  }
 }
 
 // A1[t] = [[Z_int,int, Z_int,eq], [Z_eq,int, Z_eq,eq]] from Z[t] = [[Z_eq,eq, ...]]
@@ -629,13 +698,15 @@ hipStream_t lookahead_stream() {
 }
 
 struct EventPair {
-  hipEvent_t panel = nullptr, rest = nullptr;
+  hipEvent_t panel = nullptr, near = nullptr, rest = nullptr;
   EventPair() {
     EMS_HIP(hipEventCreateWithFlags(&panel, hipEventDisableTiming));
+    EMS_HIP(hipEventCreateWithFlags(&near, hipEventDisableTiming));
     EMS_HIP(hipEventCreateWithFlags(&rest, hipEventDisableTiming));
   }
   ~EventPair() {
     if (panel) (void)hipEventDestroy(panel);
+    if (near) (void)hipEventDestroy(near);
     if (rest) (void)hipEventDestroy(rest);
   }
   EventPair(const EventPair&) = delete;
@@ -654,44 +725,63 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
   hipStream_t aux = lookahead_stream();
   EventPair ev;
   bool rest_pending = false;
-  auto swap_update = [&](hipStream_t st, int k0, int kb, int cb, int ce) {
-    hipLaunchKernelGGL(swap_trsm_kernel, dim3((unsigned)((ce - cb + 63) / 64), (unsigned)T), dim3(64), 0, st, A, N, K,
-                       k0, kb, cb, ce, piv);
-    const unsigned rt = (unsigned)((N - k0 - kb + UT - 1) / UT), ct = (unsigned)((ce - cb + UT - 1) / UT);
-    hipLaunchKernelGGL(update_mfma_kernel, dim3(ct, rt, (unsigned)T), dim3(256), 0, st, A, N, k0, kb, cb, ce);
+  int cus = 0, dev = 0;
+  EMS_HIP(hipGetDevice(&dev));
+  EMS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  // far columns: a persistent grid that leaves the panel's T CUs free
+  const int persist_grid = (T <= 64 && cus - T >= 64) ? cus - T : 0;
+  auto swap_trsm = [&](hipStream_t st, int k0, int kb, int cb, int ce) {
+    hipLaunchKernelGGL(swap_trsm_kernel, dim3((unsigned)((ce - cb + STC - 1) / STC), (unsigned)T), dim3(4 * STC), 0, st,
+                       A, N, K, k0, kb, cb, ce, piv);
+  };
+  auto update = [&](hipStream_t st, int k0, int kb, int cb, int ce, bool far) {
+    const int rt = (N - k0 - kb + UT - 1) / UT, ct = (ce - cb + UT - 1) / UT;
+    const long long pairs = ((long long)rt * ct * T + 1) / 2;
+    if (far && persist_grid > 0)
+      hipLaunchKernelGGL(update_persist_kernel, dim3((unsigned)(pairs < persist_grid ? pairs : persist_grid)),
+                         dim3(512), 0, st, A, N, k0, kb, cb, ce, rt, ct, T);
+    else
+      hipLaunchKernelGGL(update_mfma_kernel, dim3((unsigned)ct, (unsigned)rt, (unsigned)T), dim3(256), 0, st, A, N, k0,
+                         kb, cb, ce);
   };
   for (int k0 = 0; k0 < K; k0 += PANEL) {
     const int kb = K - k0 < PANEL ? K - k0 : PANEL;
-    const int rpt = (N - k0 + PNT_REG - 1) / PNT_REG;
     const size_t shm = (size_t)(N - k0) * PSB * sizeof(double2);
-    if (rpt == 1)
-      hipLaunchKernelGGL(panel_reg_kernel<1>, dim3((unsigned)T), dim3(PNT_REG), shm, s, A, N, K, k0, kb, piv, info);
-    else if (rpt == 2)
-      hipLaunchKernelGGL(panel_reg_kernel<2>, dim3((unsigned)T), dim3(PNT_REG), shm, s, A, N, K, k0, kb, piv, info);
-    else if (rpt == 3)
-      hipLaunchKernelGGL(panel_reg_kernel<3>, dim3((unsigned)T), dim3(PNT_REG), shm, s, A, N, K, k0, kb, piv, info);
-    else if (rpt == 4)
-      hipLaunchKernelGGL(panel_reg_kernel<4>, dim3((unsigned)T), dim3(PNT_REG), shm, s, A, N, K, k0, kb, piv, info);
+    const int rows = N - k0;
+    if (rows <= 1024)   // (the sub-block staging holds rows * PSB values in LDS)
+      hipLaunchKernelGGL((panel_reg_kernel<512, 2>), dim3((unsigned)T), dim3(512), shm, s, A, N, K, k0, kb, piv, info);
     else
       hipLaunchKernelGGL(panel_kernel, dim3((unsigned)T), dim3(512), 0, s, A, N, K, k0, kb, piv, info);
     EMS_LAUNCH_CHECK();
-    // the previous step's far columns, [k0 + kb, N), are final on the second stream
-    if (rest_pending) EMS_HIP(hipStreamWaitEvent(s, ev.rest, 0));
-    rest_pending = false;
     const int c1 = k0 + kb;
-    if (c1 >= N) continue;
+    if (c1 >= N) break;   // (no trailing columns: K == N)
     const int nk = K - c1 < PANEL ? K - c1 : PANEL;   // width of the next panel (0 after the last)
     const int c2 = nk > 0 ? c1 + nk : N;
-    if (c2 < N) {
-      EMS_HIP(hipEventRecord(ev.panel, s));
+    // the far columns [c2, N) on the second stream, after this panel (and,
+    // in its own order, after the previous step's far columns)
+    const bool far = c2 < N;
+    if (far) EMS_HIP(hipEventRecord(ev.panel, s));
+    // the previous step's far columns, [c1, N), are final on the second stream
+    if (rest_pending) EMS_HIP(hipStreamWaitEvent(s, ev.rest, 0));
+    rest_pending = false;
+    if (far) {
       EMS_HIP(hipStreamWaitEvent(aux, ev.panel, 0));
-      swap_update(aux, k0, kb, c2, N);
+      swap_trsm(aux, k0, kb, c2, N);
+    }
+    swap_trsm(s, k0, kb, c1, c2);
+    update(s, k0, kb, c1, c2, false);
+    EMS_LAUNCH_CHECK();
+    if (far) {
+      // the far update after the near one: the near update (on the path to
+      // the next panel) has the whole device, the far one then runs beside
+      // the next panel
+      EMS_HIP(hipEventRecord(ev.near, s));
+      EMS_HIP(hipStreamWaitEvent(aux, ev.near, 0));
+      update(aux, k0, kb, c2, N, true);
       EMS_LAUNCH_CHECK();
       EMS_HIP(hipEventRecord(ev.rest, aux));
       rest_pending = true;
     }
-    swap_update(s, k0, kb, c1, c2);
-    EMS_LAUNCH_CHECK();
   }
   if (rest_pending) EMS_HIP(hipStreamWaitEvent(s, ev.rest, 0));
 }
@@ -715,34 +805,38 @@ extern "C" emsurf_status emsurf_macromodels(int32_t n_types, int32_t n_eq, int32
     EMS_CHECK_ARG(Z_dev != nullptr && S_dev != nullptr, "Z_dev and S_dev must be non-NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int n = n_eq, m = n_int, N1 = n + m, N2 = 2 * n, T = n_types;
-    DevBuf A1((size_t)T * N1 * N1 * 16), A2((size_t)T * N2 * N2 * 16);
+    // one allocation for the call: A1, A2, the pivots, and the two steps'
+    // singular flags (kept apart, read once at the end)
     const int Kmax = m > n ? m : n;
-    DevBuf piv((size_t)T * (Kmax > 0 ? Kmax : 1) * 4), info((size_t)T * 4);
-    EMS_HIP(hipMemsetAsync(info.p, 0, info.bytes, s));
+    const size_t b_a1 = (size_t)T * N1 * N1 * 16, b_a2 = (size_t)T * N2 * N2 * 16;
+    const size_t b_piv = ((size_t)T * (Kmax > 0 ? Kmax : 1) * 4 + 255) / 256 * 256;
+    DevBuf ws(b_a1 + b_a2 + b_piv + (size_t)2 * T * 4);
+    double2* A1 = static_cast<double2*>(ws.p);
+    double2* A2 = reinterpret_cast<double2*>(static_cast<char*>(ws.p) + b_a1);
+    int* piv = reinterpret_cast<int*>(static_cast<char*>(ws.p) + b_a1 + b_a2);
+    int* info = piv + b_piv / 4;   // [2][T]
+    EMS_HIP(hipMemsetAsync(info, 0, (size_t)2 * T * 4, s));
     hipLaunchKernelGGL(interior_first_kernel, dim3(grid1((long long)T * N1 * N1)), dim3(256), 0, s,
-                       static_cast<const double2*>(Z_dev), n, m, T, A1.as<double2>());
+                       static_cast<const double2*>(Z_dev), n, m, T, A1);
     EMS_LAUNCH_CHECK();
-    if (m > 0) eliminate(A1.as<double2>(), N1, m, T, piv.as<int>(), info.as<int>(), s);
+    if (m > 0) eliminate(A1, N1, m, T, piv, info, s);
     if (Zt_dev) {
-      hipLaunchKernelGGL(trailing_copy_kernel, dim3(grid1((long long)T * n * n)), dim3(256), 0, s,
-                         A1.as<const double2>(), N1, m, n, T, static_cast<double2*>(Zt_dev));
+      hipLaunchKernelGGL(trailing_copy_kernel, dim3(grid1((long long)T * n * n)), dim3(256), 0, s, A1, N1, m, n, T,
+                         static_cast<double2*>(Zt_dev));
       EMS_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(inverse_setup_kernel, dim3(grid1((long long)T * N2 * N2)), dim3(256), 0, s,
-                       A1.as<const double2>(), N1, m, static_cast<const double2*>(Zself_dev), n, T,
-                       A2.as<double2>());
+    hipLaunchKernelGGL(inverse_setup_kernel, dim3(grid1((long long)T * N2 * N2)), dim3(256), 0, s, A1, N1, m,
+                       static_cast<const double2*>(Zself_dev), n, T, A2);
     EMS_LAUNCH_CHECK();
-    // the interior step's singular flags are kept apart from the inverse step's
-    std::vector<int> info1(T), info2(T);
-    EMS_HIP(hipMemcpyAsync(info1.data(), info.p, (size_t)T * 4, hipMemcpyDeviceToHost, s));
-    EMS_HIP(hipStreamSynchronize(s));
-    EMS_HIP(hipMemsetAsync(info.p, 0, info.bytes, s));
-    eliminate(A2.as<double2>(), N2, n, T, piv.as<int>(), info.as<int>(), s);
-    hipLaunchKernelGGL(trailing_copy_kernel, dim3(grid1((long long)T * n * n)), dim3(256), 0, s,
-                       A2.as<const double2>(), N2, n, n, T, static_cast<double2*>(S_dev));
+    eliminate(A2, N2, n, T, piv, info + T, s);
+    hipLaunchKernelGGL(trailing_copy_kernel, dim3(grid1((long long)T * n * n)), dim3(256), 0, s, A2, N2, n, n, T,
+                       static_cast<double2*>(S_dev));
     EMS_LAUNCH_CHECK();
-    EMS_HIP(hipMemcpyAsync(info2.data(), info.p, (size_t)T * 4, hipMemcpyDeviceToHost, s));
+    std::vector<int> flags(2 * (size_t)T);
+    EMS_HIP(hipMemcpyAsync(flags.data(), info, (size_t)2 * T * 4, hipMemcpyDeviceToHost, s));
     EMS_HIP(hipStreamSynchronize(s));
+    const int* info1 = flags.data();
+    const int* info2 = flags.data() + T;
     for (int t = 0; t < T; ++t) {
       if (info1[t]) {
         set_error("cell type " + std::to_string(t) + ": interior block Z_int,int is singular");
