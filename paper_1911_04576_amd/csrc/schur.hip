@@ -164,7 +164,7 @@ __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
 // flags.
 constexpr int PSB = 8;
 template <int NT, int RPT>
-__global__ void __launch_bounds__(NT) panel_reg_kernel(double2* __restrict__ A, int N, int K, int k0, int kb,
+__global__ void __launch_bounds__(NT) panel_reg_kernel(double2* __restrict__ A, int N, int K, int k0, int kb, int lw,
                                                             int* __restrict__ piv, int* __restrict__ info) {
   const int b = blockIdx.x;
   double2* M = A + (long long)b * N * N;
@@ -298,20 +298,22 @@ __global__ void __launch_bounds__(NT) panel_reg_kernel(double2* __restrict__ A, 
       const int e = tid + NT * j, c = e & (PSB - 1);
       if (e < nsub && c < sbw) M[(long long)(c0 + (e / PSB)) * N + k0 + sb0 + c] = sub[e];
     }
-    // the sub-block's swaps on the other panel columns at once: (slot x,
-    // panel column c) writes row X (c0 + x / 2, or the pivot row of column
-    // x / 2) with the value the swap sequence brings to it, the value that
-    // row sigma(X) held before, sigma the swaps applied in reverse order
+    // the sub-block's swaps on the other panel columns, and on the lw
+    // columns left of the panel, at once: (slot x, column k0 - lw + c)
+    // writes row X (c0 + x / 2, or the pivot row of column x / 2) with the
+    // value the swap sequence brings to it, the value that row sigma(X) held
+    // before, sigma the swaps applied in reverse order
     {
-      int Xs[2], srcs[2];
-      double2 mv[2];
+      constexpr int H = (2 * PSB * 2 * PANEL + NT - 1) / NT;
+      int Xs[H], srcs[H];
+      double2 mv[H];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int e = tid + NT * h, x = e >> 5, c = e & 31;
+      for (int h = 0; h < H; ++h) {
+        const int e = tid + NT * h, x = e / (2 * PANEL), c = e % (2 * PANEL);
         Xs[h] = -1;
         srcs[h] = -1;
         mv[h] = double2{0.0, 0.0};
-        if (x < 2 * sbw && c < kb && (c < sb0 || c >= sb0 + sbw)) {
+        if (x < 2 * sbw && c < lw + kb && (c < lw + sb0 || c >= lw + sb0 + sbw)) {
           const int X = (x & 1) ? spv[x >> 1] : c0 + (x >> 1);
           int src = X;
           for (int i = sbw - 1; i >= 0; --i) {
@@ -324,15 +326,15 @@ __global__ void __launch_bounds__(NT) panel_reg_kernel(double2* __restrict__ A, 
           if (src != X) {
             Xs[h] = X;
             srcs[h] = src;
-            mv[h] = M[(long long)src * N + k0 + c];
+            mv[h] = M[(long long)src * N + k0 - lw + c];
           }
         }
       }
       __syncthreads();   // every value is read before any is written
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int c = (tid + NT * h) & 31;
-        if (Xs[h] >= 0) M[(long long)Xs[h] * N + k0 + c] = mv[h];
+      for (int h = 0; h < H; ++h) {
+        const int c = (tid + NT * h) % (2 * PANEL);
+        if (Xs[h] >= 0) M[(long long)Xs[h] * N + k0 - lw + c] = mv[h];
       }
       if (tid < sbw) piv[(long long)b * K + c0 + tid] = spv[tid];
     }
@@ -397,57 +399,84 @@ __global__ void __launch_bounds__(NT) panel_reg_kernel(double2* __restrict__ A, 
   if (tid == 0 && first_singular >= 0 && info[b] == 0) info[b] = first_singular + 1;
 }
 
-// Columns [cb, ce) right of the panel (cb >= k0 + kb): the panel's row swaps,
-// then U12 = L11^-1 A12 (unit lower triangular L11 of the panel).  Four
-// threads per column (one quad of lanes), thread g holding rows g, g + 4, ...
-// of the column.  The swaps are composed before any memory is touched: only
-// the panel rows and the pivot rows move, and after the swap sequence row X
-// holds what row sigma(X) held before, sigma the swaps applied in reverse
-// order; a column is read once for those rows and written once.  The
-// substitution goes by columns of L11: the owner of x[l] passes it to its
-// quad by DPP and each thread updates its own rows below l.
+// Columns [cb, ce) right of the block (cb >= k0 + kb): the block's row
+// swaps, then U12 = L11^-1 A12 (unit lower triangular L11 of the block).
+// STP lanes per column (a row of 16 lanes, or a quad), lane g holding rows
+// g, g + STP, ... of it.  The
+// swaps are composed before any memory is touched: only the block rows and
+// the pivot rows move, and after the swap sequence row X holds what row
+// sigma(X) held before, sigma the swaps applied in reverse order; a column
+// is read once for those rows and written once.  The substitution goes by
+// columns of L11: the owner of x[l] broadcasts it to the column's lanes by
+// DPP (row_newbcast, or a quad permute) and each lane updates its own rows
+// below l.
 template <int CTRL> __device__ __forceinline__ double2 dpp_d2(double2 v) {
   return double2{dpp_d<CTRL>(v.x), dpp_d<CTRL>(v.y)};
 }
+__device__ __forceinline__ double2 row_bcast(double2 v, int src) {
+  switch (src) {   // (src is a constant where this is called)
+    case 0: return dpp_d2<0x150>(v);
+    case 1: return dpp_d2<0x151>(v);
+    case 2: return dpp_d2<0x152>(v);
+    case 3: return dpp_d2<0x153>(v);
+    case 4: return dpp_d2<0x154>(v);
+    case 5: return dpp_d2<0x155>(v);
+    case 6: return dpp_d2<0x156>(v);
+    case 7: return dpp_d2<0x157>(v);
+    case 8: return dpp_d2<0x158>(v);
+    case 9: return dpp_d2<0x159>(v);
+    case 10: return dpp_d2<0x15A>(v);
+    case 11: return dpp_d2<0x15B>(v);
+    case 12: return dpp_d2<0x15C>(v);
+    case 13: return dpp_d2<0x15D>(v);
+    case 14: return dpp_d2<0x15E>(v);
+    default: return dpp_d2<0x15F>(v);
+  }
+}
 __device__ __forceinline__ double2 quad_bcast(double2 v, int src) {
-  switch (src) {
+  switch (src) {   // (src is a constant where this is called)
     case 0: return dpp_d2<0x00>(v);   // quad_perm [0,0,0,0]
     case 1: return dpp_d2<0x55>(v);   // quad_perm [1,1,1,1]
     case 2: return dpp_d2<0xAA>(v);   // quad_perm [2,2,2,2]
     default: return dpp_d2<0xFF>(v);  // quad_perm [3,3,3,3]
   }
 }
-constexpr int STC = 64;                 // columns per workgroup
-constexpr int STR = PANEL / 4;          // rows per thread
-__global__ void __launch_bounds__(4 * STC) swap_trsm_kernel(double2* __restrict__ A, int N, int K, int k0, int kb,
-                                                            int cb, int ce, const int* __restrict__ piv) {
+constexpr int SWT = 256;   // threads per workgroup
+// W: the largest block width kb it takes (32 or 64: one panel, or two
+// panels taken as one block); STP: threads per column (16 where few columns
+// are to be done and the work should spread over many workgroups, 4 where
+// there are many and the per-workgroup set-up should be shared by more)
+template <int W, int STP>
+__global__ void __launch_bounds__(SWT) swap_trsm_kernel(double2* __restrict__ A, int N, int K, int k0, int kb, int cb,
+                                                        int ce, const int* __restrict__ piv) {
+  constexpr int NTH = SWT, STC = SWT / STP, STR = W / STP;   // threads, columns, rows per thread
   const int b = blockIdx.y;
   double2* M = A + (long long)b * N * N;
-  __shared__ double2 L[PANEL][PANEL + 1];
-  __shared__ int pv[PANEL], Xs[2 * PANEL], Ss[2 * PANEL];
-  const int tid = threadIdx.x, g = tid & 3;
+  __shared__ double2 L[W][W + 1];
+  __shared__ int pv[W], Xs[2 * W], Ss[2 * W];
+  const int tid = threadIdx.x, g = tid & (STP - 1);
   {
-    // every load of L11 is issued before the first is used (kb^2 <= 4 * 256)
-    double2 lv[PANEL * PANEL / (4 * STC)];
+    // every load of L11 is issued before the first is used (kb^2 <= W^2)
+    double2 lv[W * W / NTH];
 #pragma unroll
-    for (int q = 0; q < PANEL * PANEL / (4 * STC); ++q) {
-      const int t = tid + 4 * STC * q, i = t / kb, l = t - i * kb;
+    for (int q = 0; q < W * W / NTH; ++q) {
+      const int t = tid + NTH * q, i = t / kb, l = t - i * kb;
       lv[q] = t < kb * kb ? M[(long long)(k0 + i) * N + k0 + l] : double2{0.0, 0.0};
     }
 #pragma unroll
-    for (int q = 0; q < PANEL * PANEL / (4 * STC); ++q) {
-      const int t = tid + 4 * STC * q, i = t / kb, l = t - i * kb;
+    for (int q = 0; q < W * W / NTH; ++q) {
+      const int t = tid + NTH * q, i = t / kb, l = t - i * kb;
       if (t < kb * kb) L[i][l] = lv[q];
     }
   }
   if (tid < kb) pv[tid] = piv[(long long)b * K + k0 + tid];
   __syncthreads();
-  // slot t < kb: panel row k0 + t; slot kb + i: the pivot row of column k0 + i
+  // slot t < kb: block row k0 + t; slot kb + i: the pivot row of column k0 + i
   if (tid < 2 * kb) {
     const int X = tid < kb ? k0 + tid : pv[tid - kb];
     int src = X;
 #pragma unroll
-    for (int i = PANEL - 1; i >= 0; --i) {
+    for (int i = W - 1; i >= 0; --i) {
       if (i < kb) {
         const int pi = pv[i];
         src = src == k0 + i ? pi : (src == pi ? k0 + i : src);
@@ -457,13 +486,13 @@ __global__ void __launch_bounds__(4 * STC) swap_trsm_kernel(double2* __restrict_
     Ss[tid] = src;
   }
   __syncthreads();
-  const int j = cb + blockIdx.x * STC + (tid >> 2);
+  const int j = cb + blockIdx.x * STC + tid / STP;
   const bool live = j < ce;
   const int jc = live ? j : cb;   // (a column in range for the idle threads' addresses)
   double2 x[STR], y[STR];
 #pragma unroll
   for (int m = 0; m < STR; ++m) {
-    const int i = g + 4 * m;
+    const int i = g + STP * m;
     x[m] = double2{0.0, 0.0};
     y[m] = double2{0.0, 0.0};
     if (live && i < kb) {
@@ -471,37 +500,38 @@ __global__ void __launch_bounds__(4 * STC) swap_trsm_kernel(double2* __restrict_
       if (Xs[kb + i] >= k0 + kb) y[m] = M[(long long)Ss[kb + i] * N + jc];
     }
   }
-  // every read of the column (by its four threads) completes before its
+  // every read of the column (by its 16 threads) completes before its
   // writes; a pivot row named by several columns gets the same value from
   // each slot
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < STR; ++m) {
-    const int i = g + 4 * m;
+    const int i = g + STP * m;
     if (live && i < kb && Xs[kb + i] >= k0 + kb && Ss[kb + i] != Xs[kb + i])
       M[(long long)Xs[kb + i] * N + jc] = y[m];
   }
-#pragma unroll
-  for (int l = 0; l < PANEL - 1; ++l) {
+#pragma clang loop unroll(full)
+  for (int l = 0; l < W - 1; ++l) {
     if (l < kb) {
-      const double2 xl = quad_bcast(x[l >> 2], l & 3);
-#pragma unroll
-      for (int m = 0; m < STR; ++m) {
-        const int i = g + 4 * m;
+      const double2 xl = STP == 16 ? row_bcast(x[l / STP], l % STP) : quad_bcast(x[l / STP], l % STP);
+      // (rows g + 16 m below l: m >= l / 16)
+#pragma clang loop unroll(full)
+      for (int m = l / STP; m < STR; ++m) {
+        const int i = g + STP * m;
         if (i > l && i < kb) x[m] = csub_mul(x[m], L[i][l], xl);
       }
     }
   }
 #pragma unroll
   for (int m = 0; m < STR; ++m) {
-    const int i = g + 4 * m;
+    const int i = g + STP * m;
     if (live && i < kb) M[(long long)(k0 + i) * N + jc] = x[m];
   }
 }
 
-// Trailing update A22 -= L21 U12 over rows [k0 + kb, N) and columns [cb, ce) on the
-// matrix cores (v_mfma_f64_16x16x4f64): 64 x 64
+// Trailing update A22 -= L21 U12 over rows [k0 + kb, N) and columns [cb, ce)
+// (kb <= 64 columns of the block, in chunks of 32) on the matrix cores (v_mfma_f64_16x16x4f64): 64 x 64
 // output tiles, 4 wavefronts of 2 x 2 tiles of 16 x 16.  The complex
 // product in two real ones that share the B operand: k-slot kk = (source
 // pair offset h = kk / 2, part p = kk % 2) of l = 2 s + h for MFMA s,
@@ -514,20 +544,11 @@ constexpr int UT = 64;
 constexpr int ULP = PANEL + 1;   // L rows padded: the 16 rows of a read start on distinct banks
 // One 64 x 64 tile of the update by 256 threads (Ls, Us: this tile's LDS);
 // every thread of the workgroup calls it, live or not (it holds barriers).
+template <int ROUNDS>
 __device__ __forceinline__ void update_tile(double2* __restrict__ M, int N, int k0, int kb, int ce, int r0, int c0,
                                             bool live, double2* __restrict__ Ls, double2* __restrict__ Us, int tid) {
   typedef double d4v __attribute__((ext_vector_type(4)));
   const int l = tid & 63, wv = tid >> 6, wr = wv & 1, wc = wv >> 1;
-#pragma unroll
-  for (int j = 0; j < UT * PANEL / 256; ++j) {
-    const int e = tid + 256 * j;
-    const int i = e / PANEL, ll = e - i * PANEL;   // L: row i, column ll
-    const int gi = r0 + i;
-    Ls[i * ULP + ll] = (live && gi < N && ll < kb) ? M[(long long)gi * N + k0 + ll] : double2{0.0, 0.0};
-    const int lu = e / UT, cc = e - lu * UT;       // U: row lu, column cc
-    const int gc = c0 + cc;
-    Us[lu * UT + cc] = (live && gc < ce && lu < kb) ? M[(long long)(k0 + lu) * N + gc] : double2{0.0, 0.0};
-  }
   // this lane's outputs: tile (rt, ct), register e -> row (l / 16) + 4 e, column l % 16
   const int jj = l & 15, qrow = l >> 4;
   double2 cv[2][2][4];
@@ -540,8 +561,6 @@ __device__ __forceinline__ void update_tile(double2* __restrict__ M, int N, int 
         const int gi = r0 + 32 * wr + 16 * rt + qrow + 4 * e, gc = c0 + 32 * wc + 16 * ct + jj;
         cv[rt][ct][e] = (live && gi < N && gc < ce) ? M[(long long)gi * N + gc] : double2{0.0, 0.0};
       }
-  __syncthreads();
-  if (!live) return;
   d4v dre[2][2], dim[2][2];
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
@@ -551,29 +570,68 @@ __device__ __forceinline__ void update_tile(double2* __restrict__ M, int N, int 
       dim[rt][ct] = d4v{0, 0, 0, 0};
     }
   const int kk = l >> 4, h = kk >> 1, p = kk & 1, i16 = l & 15;
-  const int ns = (kb + 1) / 2;
-  for (int s = 0; s < ns; ++s) {
-    const int ll = 2 * s + h;
-    double are[2], aim[2], bb[2];
+  // the block's columns in chunks of PANEL through LDS
+  for (int kc = 0; kc < kb; kc += PANEL) {
+    const int kw = kb - kc < PANEL ? kb - kc : PANEL;
+    if (kc > 0) __syncthreads();   // the previous chunk's reads precede this fill
+    // (the loads of a round are all issued before its first LDS store, so
+    // that they are in flight together; ROUNDS > 1 holds fewer registers)
+    constexpr int PER = UT * PANEL / 256 / ROUNDS;
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-      const double2 Lv = Ls[(32 * wr + 16 * rt + i16) * ULP + ll];
-      are[rt] = p == 0 ? Lv.x : -Lv.y;
-      aim[rt] = p == 0 ? Lv.y : Lv.x;
-    }
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+      double2 lv[PER], uv[PER];
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-      const double2 Uv = Us[ll * UT + 32 * wc + 16 * ct + jj];
-      bb[ct] = p == 0 ? Uv.x : Uv.y;
-    }
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
-        dre[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[rt], bb[ct], dre[rt][ct], 0, 0, 0);
-        dim[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[rt], bb[ct], dim[rt][ct], 0, 0, 0);
+      for (int j = 0; j < PER; ++j) {
+        const int e = tid + 256 * (rd * PER + j);
+        const int i = e / PANEL, ll = e - i * PANEL;   // L: row i, column ll
+        const int gi = r0 + i;
+        lv[j] = (live && gi < N && ll < kw) ? M[(long long)gi * N + k0 + kc + ll] : double2{0.0, 0.0};
+        const int lu = e / UT, cc = e - lu * UT;       // U: row lu, column cc
+        const int gc = c0 + cc;
+        uv[j] = (live && gc < ce && lu < kw) ? M[(long long)(k0 + kc + lu) * N + gc] : double2{0.0, 0.0};
       }
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int e = tid + 256 * (rd * PER + j);
+        const int i = e / PANEL, ll = e - i * PANEL;
+        Ls[i * ULP + ll] = lv[j];
+        const int lu = e / UT, cc = e - lu * UT;
+        Us[lu * UT + cc] = uv[j];
+      }
+    }
+    __syncthreads();
+    if (live) {
+      const int ns = (kw + 1) / 2;
+      for (int s = 0; s < ns; ++s) {
+        const int ll = 2 * s + h;
+        double are[2], aim[2], bb[2];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+          const double2 Lv = Ls[(32 * wr + 16 * rt + i16) * ULP + ll];
+          are[rt] = p == 0 ? Lv.x : -Lv.y;
+          aim[rt] = p == 0 ? Lv.y : Lv.x;
+        }
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          const double2 Uv = Us[ll * UT + 32 * wc + 16 * ct + jj];
+          bb[ct] = p == 0 ? Uv.x : Uv.y;
+        }
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            dre[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[rt], bb[ct], dre[rt][ct], 0, 0, 0);
+            dim[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[rt], bb[ct], dim[rt][ct], 0, 0, 0);
+          }
+      }
+    }
   }
+  if (!live) return;
+  // (the tile's loads all complete here, once: the stores below sit in
+  // conditional blocks, and a load still counted as pending at each block's
+  // join would otherwise cost a wait for every store before it)
+  __builtin_amdgcn_s_waitcnt(0);
+  const bool full = r0 + UT <= N && c0 + UT <= ce;
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
@@ -581,8 +639,12 @@ __device__ __forceinline__ void update_tile(double2* __restrict__ M, int N, int 
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int gi = r0 + 32 * wr + 16 * rt + qrow + 4 * e, gc = c0 + 32 * wc + 16 * ct + jj;
-        if (gi < N && gc < ce)
-          M[(long long)gi * N + gc] = double2{cv[rt][ct][e].x - dre[rt][ct][e], cv[rt][ct][e].y - dim[rt][ct][e]};
+        const double2 o{cv[rt][ct][e].x - dre[rt][ct][e], cv[rt][ct][e].y - dim[rt][ct][e]};
+        if (full) {
+          M[(long long)gi * N + gc] = o;
+        } else if (gi < N && gc < ce) {
+          M[(long long)gi * N + gc] = o;
+        }
       }
 }
 
@@ -590,8 +652,8 @@ __global__ void __launch_bounds__(256, 2) update_mfma_kernel(double2* __restrict
                                                                int ce) {
   __shared__ double2 Ls[UT * ULP];     // [row][l]
   __shared__ double2 Us[PANEL * UT];   // [l][col]
-  update_tile(A + (long long)blockIdx.z * N * N, N, k0, kb, ce, k0 + kb + blockIdx.y * UT, cb + blockIdx.x * UT, true,
-              Ls, Us, threadIdx.x);
+  update_tile<1>(A + (long long)blockIdx.z * N * N, N, k0, kb, ce, k0 + kb + blockIdx.y * UT, cb + blockIdx.x * UT,
+                 true, Ls, Us, threadIdx.x);
 }
 
 // The same update by a persistent grid for the far columns of the lookahead:
@@ -612,8 +674,8 @@ __global__ void __launch_bounds__(512) update_persist_kernel(double2* __restrict
     const bool live = t < ntiles;
     const int tt = live ? t : 0;
     const int ct = tt % nct, rt = (tt / nct) % nrt, b = tt / (nct * nrt);
-    update_tile(A + (long long)b * N * N, N, k0, kb, ce, k0 + kb + rt * UT, cb + ct * UT, live, Ls[half], Us[half],
-                t256);
+    update_tile<2>(A + (long long)b * N * N, N, k0, kb, ce, k0 + kb + rt * UT, cb + ct * UT, live, Ls[half],
+                   Us[half], t256);
     __syncthreads();   // every read of this tile's LDS precedes the next tile's fill
   }
 }
@@ -714,13 +776,17 @@ struct EventPair {
 };
 
 // Leading K x K elimination of T matrices N x N at A (see the file header),
-// with a lookahead of one panel: after panel k the columns of panel k + 1
-// take its swaps, U12 and update on the caller's stream, and panel k + 1
-// starts at once, while the columns beyond take theirs on the second stream
-// (their update, the largest kernel of the step, runs beside the next panel,
-// which holds one workgroup per matrix).  Before it touches those columns the
-// caller's stream waits for the second one.  On return all work is on the
-// caller's stream.
+// in blocks of two panels (one where the panel kernel cannot hold the rows):
+// the block's first panel, then the second panel's columns take its swaps,
+// U12 and update, then the second panel (whose swaps also reach the first
+// panel's columns), and the columns right of the block take the block's
+// swaps, U12 = L11^-1 A12 with its 64 x 64 unit lower L11 and one rank-64
+// update.  Lookahead of one block: the next block's columns are updated on
+// the caller's stream and the next block starts at once, while the columns
+// beyond are updated on a second stream (their update, the largest kernel of
+// the step, runs beside the next block's panels, which hold one workgroup
+// per matrix).  Before it touches those columns the caller's stream waits
+// for the second one.  On return all work is on the caller's stream.
 void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t s) {
   hipStream_t aux = lookahead_stream();
   EventPair ev;
@@ -730,9 +796,28 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
   EMS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   // far columns: a persistent grid that leaves the panel's T CUs free
   const int persist_grid = (T <= 64 && cus - T >= 64) ? cus - T : 0;
+  auto panel = [&](int k0, int kb, int lw) {
+    const int rows = N - k0;
+    const size_t shm = (size_t)rows * PSB * sizeof(double2);
+    if (rows <= 1024)   // (the sub-block staging holds rows * PSB values in LDS)
+      hipLaunchKernelGGL((panel_reg_kernel<512, 2>), dim3((unsigned)T), dim3(512), shm, s, A, N, K, k0, kb, lw, piv,
+                         info);
+    else   // (lw == 0 here: blocks of one panel)
+      hipLaunchKernelGGL(panel_kernel, dim3((unsigned)T), dim3(512), 0, s, A, N, K, k0, kb, piv, info);
+  };
   auto swap_trsm = [&](hipStream_t st, int k0, int kb, int cb, int ce) {
-    hipLaunchKernelGGL(swap_trsm_kernel, dim3((unsigned)((ce - cb + STC - 1) / STC), (unsigned)T), dim3(4 * STC), 0, st,
-                       A, N, K, k0, kb, cb, ce, piv);
+    // (16 lanes per column up to 128 columns, 4 beyond)
+    const bool few = ce - cb <= 128;
+    const int stc = few ? SWT / 16 : SWT / 4;
+    const dim3 grid((unsigned)((ce - cb + stc - 1) / stc), (unsigned)T);
+    if (kb <= PANEL && few)
+      hipLaunchKernelGGL((swap_trsm_kernel<PANEL, 16>), grid, dim3(SWT), 0, st, A, N, K, k0, kb, cb, ce, piv);
+    else if (kb <= PANEL)
+      hipLaunchKernelGGL((swap_trsm_kernel<PANEL, 4>), grid, dim3(SWT), 0, st, A, N, K, k0, kb, cb, ce, piv);
+    else if (few)
+      hipLaunchKernelGGL((swap_trsm_kernel<2 * PANEL, 16>), grid, dim3(SWT), 0, st, A, N, K, k0, kb, cb, ce, piv);
+    else
+      hipLaunchKernelGGL((swap_trsm_kernel<2 * PANEL, 4>), grid, dim3(SWT), 0, st, A, N, K, k0, kb, cb, ce, piv);
   };
   auto update = [&](hipStream_t st, int k0, int kb, int cb, int ce, bool far) {
     const int rt = (N - k0 - kb + UT - 1) / UT, ct = (ce - cb + UT - 1) / UT;
@@ -744,20 +829,24 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
       hipLaunchKernelGGL(update_mfma_kernel, dim3((unsigned)ct, (unsigned)rt, (unsigned)T), dim3(256), 0, st, A, N, k0,
                          kb, cb, ce);
   };
-  for (int k0 = 0; k0 < K; k0 += PANEL) {
-    const int kb = K - k0 < PANEL ? K - k0 : PANEL;
-    const size_t shm = (size_t)(N - k0) * PSB * sizeof(double2);
-    const int rows = N - k0;
-    if (rows <= 1024)   // (the sub-block staging holds rows * PSB values in LDS)
-      hipLaunchKernelGGL((panel_reg_kernel<512, 2>), dim3((unsigned)T), dim3(512), shm, s, A, N, K, k0, kb, piv, info);
-    else
-      hipLaunchKernelGGL(panel_kernel, dim3((unsigned)T), dim3(512), 0, s, A, N, K, k0, kb, piv, info);
+  auto block_width = [&](int k0) {
+    const int w = N - k0 <= 1024 ? 2 * PANEL : PANEL;
+    return K - k0 < w ? K - k0 : w;
+  };
+  for (int k0 = 0; k0 < K;) {
+    const int ob = block_width(k0), ka = ob < PANEL ? ob : PANEL;
+    panel(k0, ka, 0);
+    if (ob > ka) {
+      swap_trsm(s, k0, ka, k0 + ka, k0 + ob);
+      update(s, k0, ka, k0 + ka, k0 + ob, false);
+      panel(k0 + ka, ob - ka, ka);
+    }
     EMS_LAUNCH_CHECK();
-    const int c1 = k0 + kb;
+    const int c1 = k0 + ob;
     if (c1 >= N) break;   // (no trailing columns: K == N)
-    const int nk = K - c1 < PANEL ? K - c1 : PANEL;   // width of the next panel (0 after the last)
-    const int c2 = nk > 0 ? c1 + nk : N;
-    // the far columns [c2, N) on the second stream, after this panel (and,
+    const int nb = c1 < K ? block_width(c1) : 0;   // width of the next block (0 after the last)
+    const int c2 = nb > 0 ? c1 + nb : N;
+    // the far columns [c2, N) on the second stream, after this block (and,
     // in its own order, after the previous step's far columns)
     const bool far = c2 < N;
     if (far) EMS_HIP(hipEventRecord(ev.panel, s));
@@ -766,22 +855,23 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
     rest_pending = false;
     if (far) {
       EMS_HIP(hipStreamWaitEvent(aux, ev.panel, 0));
-      swap_trsm(aux, k0, kb, c2, N);
+      swap_trsm(aux, k0, ob, c2, N);
     }
-    swap_trsm(s, k0, kb, c1, c2);
-    update(s, k0, kb, c1, c2, false);
+    swap_trsm(s, k0, ob, c1, c2);
+    update(s, k0, ob, c1, c2, false);
     EMS_LAUNCH_CHECK();
     if (far) {
       // the far update after the near one: the near update (on the path to
-      // the next panel) has the whole device, the far one then runs beside
-      // the next panel
+      // the next block) has the whole device, the far one then runs beside
+      // the next block's panels
       EMS_HIP(hipEventRecord(ev.near, s));
       EMS_HIP(hipStreamWaitEvent(aux, ev.near, 0));
-      update(aux, k0, kb, c2, N, true);
+      update(aux, k0, ob, c2, N, true);
       EMS_LAUNCH_CHECK();
       EMS_HIP(hipEventRecord(ev.rest, aux));
       rest_pending = true;
     }
+    k0 = c1;
   }
   if (rest_pending) EMS_HIP(hipStreamWaitEvent(s, ev.rest, 0));
 }
