@@ -232,15 +232,31 @@ __global__ void __launch_bounds__(SA_THREADS, 2) apply_S_mfma_kernel(
   const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6, wc = wv & 1, wu = wv >> 1;
   // A staging: columns ac + 64 g of the block, source indices 4 aq .. 4 aq + 3 of the k-tile
   const int ac = tid >> 2, aq = tid & 3;
+  // Element indices of the block's columns: the input columns of this
+  // thread's A staging (NAC) and the output chunks' columns (NXC), loaded
+  // at a clamped index without conditions and all before the first is used
+  // (the compiler barrier keeps them from sinking into the conditional
+  // blocks that use them, where each would cost a wait of its own)
+  constexpr int XC = 16 / (2 * (int)sizeof(R)), CPC = 64 / XC, NXC = NCOL * CPC / SA_THREADS;
+  int el_a[NAC], el_x[NXC];
+#pragma unroll
+  for (int g = 0; g < NAC; ++g) {
+    const int acol = col0 + ac + 64 * g;
+    const bool ok = ac + 64 * g < NCOL && acol < ncols;
+    el_a[g] = elem_sorted[start + (ok ? acol % count : 0)];
+  }
+#pragma unroll
+  for (int k = 0; k < NXC; ++k) {
+    const int col = col0 + (tid + SA_THREADS * k) / CPC;
+    el_x[k] = elem_sorted[start + (col < ncols ? col % count : 0)];
+  }
+  asm volatile("" ::: "memory");
   const V2* tcol[NAC];
 #pragma unroll
   for (int g = 0; g < NAC; ++g) {
     const int acol = col0 + ac + 64 * g;
-    tcol[g] = nullptr;
-    if (ac + 64 * g < NCOL && acol < ncols) {
-      const int r = acol / count, e = acol - r * count;
-      tcol[g] = t + ((long long)r * M + elem_sorted[start + e]) * n;
-    }
+    const bool ok = ac + 64 * g < NCOL && acol < ncols;
+    tcol[g] = ok ? t + ((long long)(acol / count) * M + el_a[g]) * n : nullptr;
   }
   V2 an[NAC][4];
   auto load_a = [&](int vt) {
@@ -314,7 +330,6 @@ __global__ void __launch_bounds__(SA_THREADS, 2) apply_S_mfma_kernel(
   // this thread is column c = k-th chunk / (64 / XC), rows 8 ut0 + XC (chunk
   // % (64 / XC)) + 0 .. XC - 1.  Whole chunks where n allows 16-byte access
   // (n even for FP32 vectors); value by value otherwise.
-  constexpr int XC = 16 / (2 * (int)sizeof(R)), CPC = 64 / XC, NXC = NCOL * CPC / SA_THREADS;
   using XV = typename std::conditional<sizeof(R) == 4, f4, d2>::type;
   const bool whole = XC == 1 || (n & 1) == 0;
   // twice the vector offset (in reals) of the column of each chunk, -1 past the block's columns
@@ -322,11 +337,7 @@ __global__ void __launch_bounds__(SA_THREADS, 2) apply_S_mfma_kernel(
 #pragma unroll
   for (int k = 0; k < NXC; ++k) {
     const int col = col0 + (tid + SA_THREADS * k) / CPC;
-    colbase[k] = -1;
-    if (col < ncols) {
-      const int r = col / count, el = col - r * count;
-      colbase[k] = 2 * (((long long)r * M + elem_sorted[start + el]) * n);
-    }
+    colbase[k] = col < ncols ? 2 * (((long long)(col / count) * M + el_x[k]) * n) : -1;
   }
   // the vectors of the fused y = x - S t, requested before the last products
   XV xv[NXC];
@@ -373,6 +384,10 @@ __global__ void __launch_bounds__(SA_THREADS, 2) apply_S_mfma_kernel(
       }
   }
   __syncthreads();
+  // (the loads of x all complete here, once: the stores below sit in
+  // conditional blocks, and a load still counted as pending at each block's
+  // join would cost a wait for every store before it)
+  __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
   for (int k = 0; k < NXC; ++k) {
     const int ch = tid + SA_THREADS * k, c = ch / CPC, ul = XC * (ch - c * CPC), u = 8 * ut0 + ul;
