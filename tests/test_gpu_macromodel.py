@@ -46,8 +46,11 @@ def rel_types(a, b):
     return max(float(np.linalg.norm(a[t] - b[t]) / np.linalg.norm(b[t])) for t in range(b.shape[0]))
 
 
+# (the last two: more than 1024 rows below the first panels, which then take
+# the global-memory panel in one-panel blocks before the register panels and
+# two-panel blocks take over)
 @pytest.mark.parametrize("T,n,m", [(1, 1, 0), (1, 1, 1), (1, 3, 5), (2, 7, 33), (3, 33, 70), (2, 40, 0),
-                                   (4, 96, 192), (5, 50, 129), (2, 64, 31)])
+                                   (4, 96, 192), (5, 50, 129), (2, 64, 31), (1, 64, 1000), (2, 100, 1100)])
 def test_macromodels_match_oracle(T, n, m):
     e = E()
     say(f"macromodels: {T} types, n_eq {n}, n_int {m}")
