@@ -380,14 +380,15 @@ __global__ void __launch_bounds__(NT) panel_reg_kernel(double2* __restrict__ A, 
             const int rl = rb + z * rstep;
             vv[z] = rl < nrow ? M[(long long)(c0 + sbw + rl) * N + k0 + c] : double2{0.0, 0.0};
           }
+          // (u[i] is zero for i >= sbw: an element's eight multipliers are
+          // read without conditions, together)
 #pragma unroll
           for (int z = 0; z < UB; ++z) {
             const int rl = rb + z * rstep;
             if (rl < nrow) {
               double2 w = vv[z];
 #pragma unroll
-              for (int i = 0; i < PSB; ++i)
-                if (i < sbw) w = csub_mul(w, sub[(sbw + rl) * PSB + i], u[i]);
+              for (int i = 0; i < PSB; ++i) w = csub_mul(w, sub[(sbw + rl) * PSB + i], u[i]);
               M[(long long)(c0 + sbw + rl) * N + k0 + c] = w;
             }
           }
