@@ -795,8 +795,9 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
   int cus = 0, dev = 0;
   EMS_HIP(hipGetDevice(&dev));
   EMS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  // far columns: a persistent grid that leaves the panel's T CUs free
-  const int persist_grid = (T <= 64 && cus - T >= 64) ? cus - T : 0;
+  // far columns: a persistent grid that leaves 2 T CUs free, the panels'
+  // and as many again for the near columns' kernels that run beside it
+  const int persist_grid = (T <= 64 && cus - 2 * T >= 64) ? cus - 2 * T : 0;
   auto panel = [&](int k0, int kb, int lw) {
     const int rows = N - k0;
     const size_t shm = (size_t)rows * PSB * sizeof(double2);
