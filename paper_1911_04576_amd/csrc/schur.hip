@@ -165,7 +165,7 @@ __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
 constexpr int PSB = 8;
 template <int NT, int RPT>
 __global__ void __launch_bounds__(NT) panel_reg_kernel(double2* __restrict__ A, int N, int K, int k0, int kb, int lw,
-                                                            int* __restrict__ piv, int* __restrict__ info) {
+                                                            int rw, int* __restrict__ piv, int* __restrict__ info) {
   const int b = blockIdx.x;
   double2* M = A + (long long)b * N * N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(NT) panel_reg_kernel(double2* __restrict__ A, 
   __shared__ int ri[2][NT / 64];
   __shared__ double2 cand[2][NT / 64][PSB];   // each wavefront's best candidate row
   __shared__ double2 krow[2][PSB];                 // row col, which the pivot row displaces
-  __shared__ double2 U[PSB][PANEL];        // the sub-block's U rows over the columns to its right
+  __shared__ double2 U[PSB][2 * PANEL];    // the sub-block's U rows over the columns to its right
   __shared__ int spv[PSB];                 // the sub-block's pivot rows
   extern __shared__ double2 sub[];         // [N - c0][PSB]: the sub-block, rows c0 ..
   auto rowof = [&](int q) { return k0 + tid + NT * q; };
@@ -313,7 +313,7 @@ __global__ void __launch_bounds__(NT) panel_reg_kernel(double2* __restrict__ A, 
         Xs[h] = -1;
         srcs[h] = -1;
         mv[h] = double2{0.0, 0.0};
-        if (x < 2 * sbw && c < lw + kb && (c < lw + sb0 || c >= lw + sb0 + sbw)) {
+        if (x < 2 * sbw && c < lw + kb + rw && (c < lw + sb0 || c >= lw + sb0 + sbw)) {
           const int X = (x & 1) ? spv[x >> 1] : c0 + (x >> 1);
           int src = X;
           for (int i = sbw - 1; i >= 0; --i) {
@@ -338,12 +338,12 @@ __global__ void __launch_bounds__(NT) panel_reg_kernel(double2* __restrict__ A, 
       }
       if (tid < sbw) piv[(long long)b * K + c0 + tid] = spv[tid];
     }
-    if (rc0 < kb) {
+    if (rc0 < kb + rw) {
       // (the sub-block's unit lower factor: rows 0 .. sbw - 1 of sub)
       __syncthreads();
       // U rows c0 .. c0 + sbw - 1 over the columns to the right: forward
       // substitution with the unit lower L11, one lane per column
-      if (wave == 0 && rc0 + lane < kb) {
+      if (wave == 0 && rc0 + lane < kb + rw) {
         const int c = rc0 + lane;
         double2 x[PSB];
 #pragma unroll
@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(NT) panel_reg_kernel(double2* __restrict__ A, 
       // consecutive columns of a row, the row's multipliers from LDS), with
       // UB rows' requests in flight at once
       constexpr int UB = NT >= 1024 ? 8 : 16;
-      const int nrc = kb - rc0, rstep = NT / nrc, nrow = N - c0 - sbw;
+      const int nrc = kb + rw - rc0, rstep = NT / nrc, nrow = N - c0 - sbw;
       const int rofs = tid / nrc, c = rc0 + tid % nrc;
       if (rofs < rstep) {
         double2 u[PSB];
@@ -798,13 +798,13 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
   // far columns: a persistent grid that leaves 2 T CUs free, the panels'
   // and as many again for the near columns' kernels that run beside it
   const int persist_grid = (T <= 64 && cus - 2 * T >= 64) ? cus - 2 * T : 0;
-  auto panel = [&](int k0, int kb, int lw) {
+  auto panel = [&](int k0, int kb, int lw, int rw) {
     const int rows = N - k0;
     const size_t shm = (size_t)rows * PSB * sizeof(double2);
     if (rows <= 1024)   // (the sub-block staging holds rows * PSB values in LDS)
-      hipLaunchKernelGGL((panel_reg_kernel<512, 2>), dim3((unsigned)T), dim3(512), shm, s, A, N, K, k0, kb, lw, piv,
-                         info);
-    else   // (lw == 0 here: blocks of one panel)
+      hipLaunchKernelGGL((panel_reg_kernel<512, 2>), dim3((unsigned)T), dim3(512), shm, s, A, N, K, k0, kb, lw, rw,
+                         piv, info);
+    else   // (lw == rw == 0 here: blocks of one panel)
       hipLaunchKernelGGL(panel_kernel, dim3((unsigned)T), dim3(512), 0, s, A, N, K, k0, kb, piv, info);
   };
   auto swap_trsm = [&](hipStream_t st, int k0, int kb, int cb, int ce) {
@@ -837,12 +837,11 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
   };
   for (int k0 = 0; k0 < K;) {
     const int ob = block_width(k0), ka = ob < PANEL ? ob : PANEL;
-    panel(k0, ka, 0);
-    if (ob > ka) {
-      swap_trsm(s, k0, ka, k0 + ka, k0 + ob);
-      update(s, k0, ka, k0 + ka, k0 + ob, false);
-      panel(k0 + ka, ob - ka, ka);
-    }
+    // the first panel also takes the second panel's columns through its
+    // swaps, U rows and in-panel updates; the second panel's swaps also
+    // reach the first panel's columns
+    panel(k0, ka, 0, ob - ka);
+    if (ob > ka) panel(k0 + ka, ob - ka, ka, 0);
     EMS_LAUNCH_CHECK();
     const int c1 = k0 + ob;
     if (c1 >= N) break;   // (no trailing columns: K == N)
