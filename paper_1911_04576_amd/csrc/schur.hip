@@ -10,12 +10,13 @@
 // A22 - A21 A11^-1 A12:
 //   step 1: [[Z_int,int, Z_int,eq], [Z_eq,int, Z_eq,eq]], K = n_int  ->  Z~
 //   step 2: [[Z~ + Z_self, I], [I, 0]],                  K = n_eq   ->  -(Z~ + Z_self)^-1 = S
-// The elimination is right-looking and blocked (panels of 32 columns) with
-// partial pivoting among the leading rows (trailing rows never move, so the
-// trailing block is exactly the Schur complement); every matrix of the batch
-// (one per cell type) runs in the same launches, and the trailing update of a
-// panel spreads over many workgroups per matrix.  FP64 complex throughout;
-// row-major storage, matrix b at A + b N^2.
+// The elimination is right-looking and blocked (blocks of two 32-column
+// panels, a lookahead of one block on a second stream) with partial pivoting
+// among the leading rows (trailing rows never move, so the trailing block is
+// exactly the Schur complement); every matrix of the batch (one per cell
+// type) runs in the same launches, and the trailing updates spread over many
+// workgroups per matrix.  FP64 complex throughout; row-major storage, matrix
+// b at A + b N^2.
 #include <vector>
 
 #include "internal.h"
@@ -153,15 +154,15 @@ __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
 // wavefronts keep the per-column barriers and reductions short).  The
 // panel's columns go in sub-blocks of PSB: a sub-block is staged through
 // LDS with coalesced loads and stores (rows [c0, N)), held in registers, its
-// columns are
-// factorised there (pivot by a reduction over the thread's rows, a
-// wavefront reduction and one over the NT / 64 wavefronts in LDS, row exchange
-// through LDS), and the panel columns outside it then take the sub-block's
-// row swaps at once, and the columns to its right its U rows (L11^-1 A12 by
-// one wavefront) and one rank-PSB update, so that the panel makes one pass
-// through memory per sub-block instead of one per column.  Same pivots
-// (largest |a|^2 among rows [kk, K), first index on ties), same singular
-// flags.
+// columns are factorised there (pivot by a reduction over the thread's rows,
+// a wavefront reduction and one over the NT / 64 wavefronts in LDS, row
+// exchange through LDS), and the columns outside it then take the
+// sub-block's row swaps at once (the panel's others, the lw columns left of
+// the panel and the rw columns right of it), and the columns to its right
+// (the panel's and the rw beyond) its U rows (L11^-1 A12 by one wavefront)
+// and one rank-PSB update, so that the panel makes one pass through memory
+// per sub-block instead of one per column.  Same pivots (largest |a|^2
+// among rows [kk, K), first index on ties), same singular flags.
 constexpr int PSB = 8;
 template <int NT, int RPT>
 __global__ void __launch_bounds__(NT) panel_reg_kernel(double2* __restrict__ A, int N, int K, int k0, int kb, int lw,
