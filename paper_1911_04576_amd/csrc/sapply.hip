@@ -199,7 +199,7 @@ __global__ void pack_S_kernel(const double2* __restrict__ S, T* __restrict__ out
 // (wc, wu) = (w % 2, w / 2) takes column tiles CTW wc .. CTW wc + CTW - 1 and
 // row tiles 4 wu .. 4 wu + 3 of the item.
 template <typename T, typename VX, int CTW>
-__global__ void __launch_bounds__(SA_THREADS, 2) apply_S_mfma_kernel(
+__global__ void __launch_bounds__(SA_THREADS, sizeof(T) == 8 ? 3 : 2) apply_S_mfma_kernel(
     const T* __restrict__ Sp, const int* __restrict__ elem_sorted, const int* __restrict__ tiles, int n, int M,
     int nrhs, int ncb, int nub, int items, int per, const typename SM<T>::V2* __restrict__ t,
     const VX* __restrict__ x_axpy, VX* __restrict__ y) {
@@ -214,12 +214,15 @@ __global__ void __launch_bounds__(SA_THREADS, 2) apply_S_mfma_kernel(
   // two buffers: the next k-tile is staged while the current one is used.
   // At the end the same memory holds the output tile, rows of YROW values
   // (64 rows u x (re, im) and padding: the rows start 16 banks apart)
+  // (FP64 keeps one macromodel buffer: 48 KB of LDS, three workgroups per CU,
+  // for a second barrier per k-tile)
+  constexpr int NB = sizeof(T) == 8 ? 1 : 2;
   constexpr int AS = 2 * CTW * 512, BS = SA_UT * 512;
   constexpr int YROW = sizeof(T) == 4 ? 132 : 144;
-  constexpr int LDS_T = 2 * (AS + BS) > NCOL * YROW ? 2 * (AS + BS) : NCOL * YROW;
+  constexpr int LDS_T = 2 * AS + NB * BS > NCOL * YROW ? 2 * AS + NB * BS : NCOL * YROW;
   __shared__ __align__(16) T lds[LDS_T];
   auto As = [&](int bf) { return lds + bf * AS; };
-  auto Bs = [&](int bf) { return lds + 2 * AS + bf * BS; };
+  auto Bs = [&](int bf) { return lds + 2 * AS + (NB == 2 ? bf : 0) * BS; };
   const int w = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (w >= items) return;   // the whole workgroup: no barrier reached
   const int cb = w % ncb, tub = w / ncb, tile = tub / nub, ub = tub - tile * nub;
@@ -365,6 +368,7 @@ __global__ void __launch_bounds__(SA_THREADS, 2) apply_S_mfma_kernel(
     load_a(vt + 1);   // the next k-tile is on its way during the products
     load_b(vt + 1);
     products(vt & 1);
+    if constexpr (NB == 1) __syncthreads();   // (one buffer: every read of it precedes the next fill)
     stage((vt + 1) & 1);
     __syncthreads();
   }
