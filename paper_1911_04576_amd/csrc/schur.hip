@@ -659,26 +659,133 @@ __global__ void __launch_bounds__(256, 2) update_mfma_kernel(double2* __restrict
 }
 
 // The same update by a persistent grid for the far columns of the lookahead:
-// workgroups of 512 threads, two tiles at a time (one per half, each with
-// its own LDS), 133 KB of LDS so that a CU holds at most one of them.  With a
-// grid of (CUs - panel workgroups) the update never occupies every CU, and
-// the next panel, whose workgroups each need a CU to themselves, starts on
-// the ones it leaves instead of waiting for the update to drain.  Tiles run
-// matrix-major, row tile, then column tile.
+// workgroups of 512 threads, two halves of 256 with a tile each and LDS of
+// their own (133 KB in all, so that a CU holds at most one workgroup).  With a
+// grid of (CUs - 2 panel workgroups' worth) the update never occupies every
+// CU, and the next block's panels and near-column kernels, whose workgroups
+// each need a CU to themselves, start on the ones it leaves instead of
+// waiting for it to drain.  A tile's work is a sequence of phases, for each
+// chunk of 32 block columns a load phase (the chunk of L21 and U12 into LDS,
+// with the tile of A22 into registers before the first) and a product phase
+// (the matrix-core products; the tile's stores after the last).  The second
+// half runs its sequence one phase behind the first, with a barrier after
+// every phase, so that while one half waits for its loads the other keeps the
+// matrix cores busy.  Each half walks tiles 2 (blockIdx.x + i gridDim.x) +
+// half, matrix-major, row tile, then column tile.
 __global__ void __launch_bounds__(512) update_persist_kernel(double2* __restrict__ A, int N, int k0, int kb, int cb,
                                                              int ce, int nrt, int nct, int T) {
-  __shared__ double2 Ls[2][UT * ULP];
-  __shared__ double2 Us[2][PANEL * UT];
-  const int half = threadIdx.x >> 8, t256 = threadIdx.x & 255;
-  const int ntiles = nct * nrt * T;
-  for (int it = blockIdx.x; 2 * it < ntiles; it += gridDim.x) {
-    const int t = 2 * it + half;
-    const bool live = t < ntiles;
-    const int tt = live ? t : 0;
-    const int ct = tt % nct, rt = (tt / nct) % nrt, b = tt / (nct * nrt);
-    update_tile<2>(A + (long long)b * N * N, N, k0, kb, ce, k0 + kb + rt * UT, cb + ct * UT, live, Ls[half],
-                   Us[half], t256);
-    __syncthreads();   // every read of this tile's LDS precedes the next tile's fill
+  typedef double d4v __attribute__((ext_vector_type(4)));
+  __shared__ double2 Lsh[2][UT * ULP];
+  __shared__ double2 Ush[2][PANEL * UT];
+  const int half = threadIdx.x >> 8, tid = threadIdx.x & 255;
+  double2* Ls = Lsh[half];
+  double2* Us = Ush[half];
+  const int l = tid & 63, wv = tid >> 6, wr = wv & 1, wc = wv >> 1;
+  const int jj = l & 15, qrow = l >> 4;
+  const int kk = l >> 4, h = kk >> 1, p = kk & 1, i16 = l & 15;
+  const int ntiles = nct * nrt * T, npairs = (ntiles + 1) / 2;
+  const int nch = (kb + PANEL - 1) / PANEL;
+  const int ntile_half = blockIdx.x < npairs ? (npairs - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x : 0;
+  const int nphase = 2 * nch * ntile_half;
+  double2 cv[2][2][4];
+  d4v dre[2][2], dim[2][2];
+  // (the same count of steps, and so of barriers, in both halves)
+  for (int step = 0; step <= nphase; ++step) {
+    const int ph = step - half;   // this half's phase
+    if (ph >= 0 && ph < nphase) {
+      const int i = ph / (2 * nch), w = ph - i * (2 * nch), c = w >> 1;
+      const int t = 2 * ((int)blockIdx.x + i * (int)gridDim.x) + half;
+      const bool live = t < ntiles;
+      const int tt = live ? t : 0;
+      const int ct = tt % nct, rtl = (tt / nct) % nrt, b = tt / (nct * nrt);
+      double2* M = A + (long long)b * N * N;
+      const int r0 = k0 + kb + rtl * UT, c0 = cb + ct * UT;
+      const int kc = c * PANEL, kw = kb - kc < PANEL ? kb - kc : PANEL;
+      if ((w & 1) == 0) {
+        // load phase
+        if (c == 0) {
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct2 = 0; ct2 < 2; ++ct2) {
+              dre[rt][ct2] = d4v{0, 0, 0, 0};
+              dim[rt][ct2] = d4v{0, 0, 0, 0};
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const int gi = r0 + 32 * wr + 16 * rt + qrow + 4 * e, gc = c0 + 32 * wc + 16 * ct2 + jj;
+                cv[rt][ct2][e] = (live && gi < N && gc < ce) ? M[(long long)gi * N + gc] : double2{0.0, 0.0};
+              }
+            }
+        }
+        constexpr int ROUNDS = 2, PER = UT * PANEL / 256 / ROUNDS;
+#pragma unroll
+        for (int rd = 0; rd < ROUNDS; ++rd) {
+          double2 lv[PER], uv[PER];
+#pragma unroll
+          for (int j = 0; j < PER; ++j) {
+            const int e = tid + 256 * (rd * PER + j);
+            const int ii = e / PANEL, ll = e - ii * PANEL;
+            const int gi = r0 + ii;
+            lv[j] = (live && gi < N && ll < kw) ? M[(long long)gi * N + k0 + kc + ll] : double2{0.0, 0.0};
+            const int lu = e / UT, cc = e - lu * UT;
+            const int gc = c0 + cc;
+            uv[j] = (live && gc < ce && lu < kw) ? M[(long long)(k0 + kc + lu) * N + gc] : double2{0.0, 0.0};
+          }
+#pragma unroll
+          for (int j = 0; j < PER; ++j) {
+            const int e = tid + 256 * (rd * PER + j);
+            const int ii = e / PANEL, ll = e - ii * PANEL;
+            Ls[ii * ULP + ll] = lv[j];
+            const int lu = e / UT, cc = e - lu * UT;
+            Us[lu * UT + cc] = uv[j];
+          }
+        }
+      } else if (live) {
+        // product phase
+        const int ns = (kw + 1) / 2;
+        for (int s2 = 0; s2 < ns; ++s2) {
+          const int ll = 2 * s2 + h;
+          double are[2], aim[2], bb[2];
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt) {
+            const double2 Lv = Ls[(32 * wr + 16 * rt + i16) * ULP + ll];
+            are[rt] = p == 0 ? Lv.x : -Lv.y;
+            aim[rt] = p == 0 ? Lv.y : Lv.x;
+          }
+#pragma unroll
+          for (int ct2 = 0; ct2 < 2; ++ct2) {
+            const double2 Uv = Us[ll * UT + 32 * wc + 16 * ct2 + jj];
+            bb[ct2] = p == 0 ? Uv.x : Uv.y;
+          }
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct2 = 0; ct2 < 2; ++ct2) {
+              dre[rt][ct2] = __builtin_amdgcn_mfma_f64_16x16x4f64(are[rt], bb[ct2], dre[rt][ct2], 0, 0, 0);
+              dim[rt][ct2] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim[rt], bb[ct2], dim[rt][ct2], 0, 0, 0);
+            }
+        }
+        if (c == nch - 1) {
+          __builtin_amdgcn_s_waitcnt(0);   // (once, not at every conditional store below)
+          const bool full = r0 + UT <= N && c0 + UT <= ce;
+#pragma unroll
+          for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct2 = 0; ct2 < 2; ++ct2)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const int gi = r0 + 32 * wr + 16 * rt + qrow + 4 * e, gc = c0 + 32 * wc + 16 * ct2 + jj;
+                const double2 o{cv[rt][ct2][e].x - dre[rt][ct2][e], cv[rt][ct2][e].y - dim[rt][ct2][e]};
+                if (full) {
+                  M[(long long)gi * N + gc] = o;
+                } else if (gi < N && gc < ce) {
+                  M[(long long)gi * N + gc] = o;
+                }
+              }
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
