@@ -11,7 +11,7 @@ Paper passages followed (Patel, Triverio, Hum):
   example in Sec. IV-B fixes the sign of d.
 
 Synthetic block content (the paper's blocks are Galerkin RWG reaction
-integrals, which need its meshes; this build uses a point-sampled stand-in):
+integrals, which need its meshes; this implementation uses a point-sampled stand-in):
 
     T(d)[(tau,p,a),(tau',q,b)] = delta(tau,tau') (t_pa . t_qb) A_q g(R),
     R = | rho_p - rho_q + pitch (dx, dy, 0) |,  g(R) = exp(-j k R) / (4 pi R),

@@ -10,7 +10,7 @@ Far field of J and M in free space (eta = 1, e^{jwt}), common factor
 -jk e^{-jkr} / (4 pi r) dropped:
     E_theta = N . theta^ + L . phi^,      E_phi = N . phi^ - L . theta^,
     N = sum over sources of A_q J_q e^{jk rhat . r'},  L likewise with M,
-with the point-sampled currents of this build: on patch q of element m,
+with the point-sampled currents used here: on patch q of element m,
 J = sum_a xJ[m, q, a] t_qa at r' = rho_q + pitch (ix, iy, 0) (M likewise).
 Directions are given by direction cosines (u, v) with w = cos(theta) =
 sqrt(1 - u^2 - v^2) >= 0 (upper half space; lower=True takes w <= 0); theta^

@@ -7,7 +7,7 @@ Paper passages followed (Patel, Triverio, Hum):
       Z~ = Z_eq,eq - Z_eq,int Z_int,int^-1 Z_int,eq,
   which needs an LU factorisation of Z_int,int; only unique cells need one
   (Sec. II-D), and cells are independent (parallel).
-* Sec. III-A/III-C with the block-Jacobi reading of this build: the element
+* Sec. III-A/III-C with the block-Jacobi reading taken here: the element
   operator of (I - S T) x = b is S = -(Z~ + Z_o^self)^-1, Z_o^self being the
   self block of the outer operator (identical for every box).
 

@@ -6,7 +6,7 @@ box coincides with a face of its neighbour and the currents of that face are
 expanded twice.  The paper keeps one set of unknowns through the sparse
 incidence U_o, Y = U_o Y~, and solves U_o^T [Z_eq + Z_o] U_o Y~ = U_o^T V.
 
-Readings for the point-sampled patches of this build:
+Readings for the point-sampled patches used here:
 * duplicates: patch p' of element m' = m + d (d = (0, 1) or (1, 0), the
   neighbour in +x or +y) whose centre coincides with patch p of element m;
   the tangential fields are continuous across the shared face and the two
@@ -101,5 +101,5 @@ def dense_D(S: np.ndarray, tm: np.ndarray) -> np.ndarray:
 
 
 def reduced_operator(U: np.ndarray, D: np.ndarray, T: np.ndarray) -> np.ndarray:
-    """A~ = U_o^T (D + T) U_o (eq. (final), this build's D and T)."""
+    """A~ = U_o^T (D + T) U_o (eq. (final), the D and T defined here)."""
     return U.T @ (D + T) @ U
