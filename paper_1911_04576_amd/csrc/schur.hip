@@ -909,7 +909,12 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
   auto panel = [&](int k0, int kb, int lw, int rw) {
     const int rows = N - k0;
     const size_t shm = (size_t)rows * PSB * sizeof(double2);
-    if (rows <= 1024)   // (the sub-block staging holds rows * PSB values in LDS)
+    // (the sub-block staging holds rows * PSB values in LDS; one row per
+    // thread where they fit, which shortens every column step)
+    if (rows <= 512)
+      hipLaunchKernelGGL((panel_reg_kernel<512, 1>), dim3((unsigned)T), dim3(512), shm, s, A, N, K, k0, kb, lw, rw,
+                         piv, info);
+    else if (rows <= 1024)
       hipLaunchKernelGGL((panel_reg_kernel<512, 2>), dim3((unsigned)T), dim3(512), shm, s, A, N, K, k0, kb, lw, rw,
                          piv, info);
     else   // (lw == rw == 0 here: blocks of one panel)
