@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(NT) panel_reg_kernel(double2* __restrict__ A, 
       // walks rows rofs, rofs + rstep, ... (consecutive threads on
       // consecutive columns of a row, the row's multipliers from LDS), with
       // UB rows' requests in flight at once
-      constexpr int UB = NT >= 1024 ? 8 : 16;
+      constexpr int UB = NT > 512 ? 8 : 16;   // (fewer registers for the larger workgroups)
       const int nrc = kb + rw - rc0, rstep = NT / nrc, nrow = N - c0 - sbw;
       const int rofs = tid / nrc, c = rc0 + tid % nrc;
       if (rofs < rstep) {
@@ -910,9 +910,13 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
     const int rows = N - k0;
     const size_t shm = (size_t)rows * PSB * sizeof(double2);
     // (the sub-block staging holds rows * PSB values in LDS; one row per
-    // thread where they fit, which shortens every column step)
+    // thread up to 768 rows, which shortens every column step; 1024 threads
+    // with one row each were slower than 512 with two)
     if (rows <= 512)
       hipLaunchKernelGGL((panel_reg_kernel<512, 1>), dim3((unsigned)T), dim3(512), shm, s, A, N, K, k0, kb, lw, rw,
+                         piv, info);
+    else if (rows <= 768)
+      hipLaunchKernelGGL((panel_reg_kernel<768, 1>), dim3((unsigned)T), dim3(768), shm, s, A, N, K, k0, kb, lw, rw,
                          piv, info);
     else if (rows <= 1024)
       hipLaunchKernelGGL((panel_reg_kernel<512, 2>), dim3((unsigned)T), dim3(512), shm, s, A, N, K, k0, kb, lw, rw,
