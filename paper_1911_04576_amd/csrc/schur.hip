@@ -19,8 +19,6 @@
 // b at A + b N^2.
 #include <vector>
 
-#include <hip/hip_ext.h>
-
 #include "internal.h"
 
 namespace emsurf {
@@ -908,27 +906,23 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
   // far columns: a persistent grid that leaves 2 T CUs free, the panels'
   // and as many again for the near columns' kernels that run beside it
   const int persist_grid = (T <= 64 && cus - 2 * T >= 64) ? cus - 2 * T : 0;
-  // (launches that record an event do so as the kernel completes, through
-  // the extended launch, instead of with a marker of their own on the
-  // stream, which costs the stream a few microseconds each time)
-  auto panel = [&](int k0, int kb, int lw, int rw, hipEvent_t stop) {
+  auto panel = [&](int k0, int kb, int lw, int rw) {
     const int rows = N - k0;
-    const uint32_t shm = (uint32_t)((size_t)rows * PSB * sizeof(double2));
+    const size_t shm = (size_t)rows * PSB * sizeof(double2);
     // (the sub-block staging holds rows * PSB values in LDS; one row per
     // thread up to 768 rows, which shortens every column step; 1024 threads
     // with one row each were slower than 512 with two)
     if (rows <= 512)
-      hipExtLaunchKernelGGL((panel_reg_kernel<512, 1>), dim3((unsigned)T), dim3(512), shm, s, nullptr, stop, 0u, A, N, K,
-                            k0, kb, lw, rw, piv, info);
+      hipLaunchKernelGGL((panel_reg_kernel<512, 1>), dim3((unsigned)T), dim3(512), shm, s, A, N, K, k0, kb, lw, rw,
+                         piv, info);
     else if (rows <= 768)
-      hipExtLaunchKernelGGL((panel_reg_kernel<768, 1>), dim3((unsigned)T), dim3(768), shm, s, nullptr, stop, 0u, A, N, K,
-                            k0, kb, lw, rw, piv, info);
+      hipLaunchKernelGGL((panel_reg_kernel<768, 1>), dim3((unsigned)T), dim3(768), shm, s, A, N, K, k0, kb, lw, rw,
+                         piv, info);
     else if (rows <= 1024)
-      hipExtLaunchKernelGGL((panel_reg_kernel<512, 2>), dim3((unsigned)T), dim3(512), shm, s, nullptr, stop, 0u, A, N, K,
-                            k0, kb, lw, rw, piv, info);
+      hipLaunchKernelGGL((panel_reg_kernel<512, 2>), dim3((unsigned)T), dim3(512), shm, s, A, N, K, k0, kb, lw, rw,
+                         piv, info);
     else   // (lw == rw == 0 here: blocks of one panel)
-      hipExtLaunchKernelGGL(panel_kernel, dim3((unsigned)T), dim3(512), 0u, s, nullptr, stop, 0u, A, N, K, k0, kb, piv,
-                            info);
+      hipLaunchKernelGGL(panel_kernel, dim3((unsigned)T), dim3(512), 0, s, A, N, K, k0, kb, piv, info);
   };
   auto swap_trsm = [&](hipStream_t st, int k0, int kb, int cb, int ce) {
     // (16 lanes per column up to 128 columns, 4 beyond)
@@ -944,15 +938,15 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
     else
       hipLaunchKernelGGL((swap_trsm_kernel<2 * PANEL, 4>), grid, dim3(SWT), 0, st, A, N, K, k0, kb, cb, ce, piv);
   };
-  auto update = [&](hipStream_t st, int k0, int kb, int cb, int ce, bool far, hipEvent_t stop) {
+  auto update = [&](hipStream_t st, int k0, int kb, int cb, int ce, bool far) {
     const int rt = (N - k0 - kb + UT - 1) / UT, ct = (ce - cb + UT - 1) / UT;
     const long long pairs = ((long long)rt * ct * T + 1) / 2;
     if (far && persist_grid > 0)
-      hipExtLaunchKernelGGL(update_persist_kernel, dim3((unsigned)(pairs < persist_grid ? pairs : persist_grid)),
-                            dim3(512), 0u, st, nullptr, stop, 0u, A, N, k0, kb, cb, ce, rt, ct, T);
+      hipLaunchKernelGGL(update_persist_kernel, dim3((unsigned)(pairs < persist_grid ? pairs : persist_grid)),
+                         dim3(512), 0, st, A, N, k0, kb, cb, ce, rt, ct, T);
     else
-      hipExtLaunchKernelGGL(update_mfma_kernel, dim3((unsigned)ct, (unsigned)rt, (unsigned)T), dim3(256), 0u, st, nullptr,
-                            stop, 0u, A, N, k0, kb, cb, ce);
+      hipLaunchKernelGGL(update_mfma_kernel, dim3((unsigned)ct, (unsigned)rt, (unsigned)T), dim3(256), 0, st, A, N, k0,
+                         kb, cb, ce);
   };
   auto block_width = [&](int k0) {
     const int w = N - k0 <= 1024 ? 2 * PANEL : PANEL;
@@ -960,19 +954,24 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
   };
   for (int k0 = 0; k0 < K;) {
     const int ob = block_width(k0), ka = ob < PANEL ? ob : PANEL;
-    const int c1 = k0 + ob;
-    const int nb = c1 < K ? block_width(c1) : 0;   // width of the next block (0 after the last)
-    const int c2 = nb > 0 ? c1 + nb : N;
-    // the far columns [c2, N) go to the second stream, after this block's
-    // panels (and, in its own order, after the previous step's far columns)
-    const bool far = c1 < N && c2 < N;
     // the first panel also takes the second panel's columns through its
     // swaps, U rows and in-panel updates; the second panel's swaps also
     // reach the first panel's columns
-    panel(k0, ka, 0, ob - ka, far && ob == ka ? ev.panel : nullptr);
-    if (ob > ka) panel(k0 + ka, ob - ka, ka, 0, far ? ev.panel : nullptr);
+    panel(k0, ka, 0, ob - ka);
+    if (ob > ka) panel(k0 + ka, ob - ka, ka, 0);
     EMS_LAUNCH_CHECK();
+    const int c1 = k0 + ob;
     if (c1 >= N) break;   // (no trailing columns: K == N)
+    const int nb = c1 < K ? block_width(c1) : 0;   // width of the next block (0 after the last)
+    const int c2 = nb > 0 ? c1 + nb : N;
+    // the far columns [c2, N) on the second stream, after this block (and,
+    // in its own order, after the previous step's far columns)
+    const bool far = c2 < N;
+    // (plain event records: attaching the events to the kernels through the
+    // extended launch saved a few microseconds per block here, but made the
+    // solves running on other streams of the same process wait several
+    // times longer)
+    if (far) EMS_HIP(hipEventRecord(ev.panel, s));
     // the previous step's far columns, [c1, N), are final on the second stream
     if (rest_pending) EMS_HIP(hipStreamWaitEvent(s, ev.rest, 0));
     rest_pending = false;
@@ -981,15 +980,17 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
       swap_trsm(aux, k0, ob, c2, N);
     }
     swap_trsm(s, k0, ob, c1, c2);
-    // the far update after the near one: the near update (on the path to the
-    // next block) has the whole device, the far one then runs beside the
-    // next block's panels
-    update(s, k0, ob, c1, c2, false, far ? ev.near : nullptr);
+    update(s, k0, ob, c1, c2, false);
     EMS_LAUNCH_CHECK();
     if (far) {
+      // the far update after the near one: the near update (on the path to
+      // the next block) has the whole device, the far one then runs beside
+      // the next block's panels
+      EMS_HIP(hipEventRecord(ev.near, s));
       EMS_HIP(hipStreamWaitEvent(aux, ev.near, 0));
-      update(aux, k0, ob, c2, N, true, ev.rest);
+      update(aux, k0, ob, c2, N, true);
       EMS_LAUNCH_CHECK();
+      EMS_HIP(hipEventRecord(ev.rest, aux));
       rest_pending = true;
     }
     k0 = c1;
