@@ -131,22 +131,29 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
-// (largest v, first index on ties) over the 64 lanes, in every lane: quad
-// exchanges 1 and 2 and row rotations 4 and 8 by DPP leave each row of 16
-// lanes with its own result, and the four rows' results are then combined
-// as wavefront-uniform values read from lanes 0, 16, 32 and 48 (the order
+// The same as a DPP move that only the rows in RM take (the other rows keep
+// their value): the row broadcasts of 64-lane reductions
+template <int CTRL, int RM> __device__ __forceinline__ double bcast_dpp_d(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, RM, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, RM, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+// (largest v, first index on ties) over the 64 lanes, as wavefront-uniform
+// values: quad exchanges 1 and 2 and row rotations 4 and 8 by DPP leave each
+// row of 16 lanes with its own result; row_bcast:15 then brings lane 15 of
+// rows 0 and 2 into rows 1 and 3, row_bcast:31 lane 31 into rows 2 and 3, so
+// that row 3 holds the result of all four, read from lane 63 (the order
 // does not matter: the rule is a maximum over (v, -index))
 __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
   argmax_take(v, idx, dpp_d<0xB1>(v), dpp_i<0xB1>(idx));   // quad_perm [1,0,3,2]
   argmax_take(v, idx, dpp_d<0x4E>(v), dpp_i<0x4E>(idx));   // quad_perm [2,3,0,1]
   argmax_take(v, idx, dpp_d<0x124>(v), dpp_i<0x124>(idx)); // row_ror 4
   argmax_take(v, idx, dpp_d<0x128>(v), dpp_i<0x128>(idx)); // row_ror 8
-  double w = readlane_d(v, 0);
-  int wi = __builtin_amdgcn_readlane(idx, 0);
-#pragma unroll
-  for (int r = 1; r < 4; ++r) argmax_take(w, wi, readlane_d(v, 16 * r), __builtin_amdgcn_readlane(idx, 16 * r));
-  v = w;
-  idx = wi;
+  argmax_take(v, idx, bcast_dpp_d<0x142, 0xA>(v), __builtin_amdgcn_update_dpp(idx, idx, 0x142, 0xA, 0xF, false));
+  argmax_take(v, idx, bcast_dpp_d<0x143, 0xC>(v), __builtin_amdgcn_update_dpp(idx, idx, 0x143, 0xC, 0xF, false));
+  v = readlane_d(v, 63);
+  idx = __builtin_amdgcn_readlane(idx, 63);
 }
 
 // The same panel with the rows in registers, for N - k0 <= NT * RPT: NT
