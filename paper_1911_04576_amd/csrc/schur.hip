@@ -19,6 +19,8 @@
 // b at A + b N^2.
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 
 namespace emsurf {
@@ -876,15 +878,13 @@ hipStream_t lookahead_stream() {
 }
 
 struct EventPair {
-  hipEvent_t panel = nullptr, near = nullptr, rest = nullptr;
+  hipEvent_t panel = nullptr, rest = nullptr;
   EventPair() {
     EMS_HIP(hipEventCreateWithFlags(&panel, hipEventDisableTiming));
-    EMS_HIP(hipEventCreateWithFlags(&near, hipEventDisableTiming));
     EMS_HIP(hipEventCreateWithFlags(&rest, hipEventDisableTiming));
   }
   ~EventPair() {
     if (panel) (void)hipEventDestroy(panel);
-    if (near) (void)hipEventDestroy(near);
     if (rest) (void)hipEventDestroy(rest);
   }
   EventPair(const EventPair&) = delete;
@@ -913,23 +913,23 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
   // far columns: a persistent grid that leaves 2 T CUs free, the panels'
   // and as many again for the near columns' kernels that run beside it
   const int persist_grid = (T <= 64 && cus - 2 * T >= 64) ? cus - 2 * T : 0;
-  auto panel = [&](int k0, int kb, int lw, int rw) {
+  auto panel = [&](int k0, int kb, int lw, int rw, hipEvent_t stop) {
     const int rows = N - k0;
-    const size_t shm = (size_t)rows * PSB * sizeof(double2);
+    const uint32_t shm = (uint32_t)((size_t)rows * PSB * sizeof(double2));
     // (the sub-block staging holds rows * PSB values in LDS; one row per
     // thread up to 768 rows, which shortens every column step; 1024 threads
     // with one row each were slower than 512 with two)
     if (rows <= 512)
-      hipLaunchKernelGGL((panel_reg_kernel<512, 1>), dim3((unsigned)T), dim3(512), shm, s, A, N, K, k0, kb, lw, rw,
-                         piv, info);
+      hipExtLaunchKernelGGL((panel_reg_kernel<512, 1>), dim3((unsigned)T), dim3(512), shm, s, nullptr, stop, 0u, A, N,
+                            K, k0, kb, lw, rw, piv, info);
     else if (rows <= 768)
-      hipLaunchKernelGGL((panel_reg_kernel<768, 1>), dim3((unsigned)T), dim3(768), shm, s, A, N, K, k0, kb, lw, rw,
-                         piv, info);
+      hipExtLaunchKernelGGL((panel_reg_kernel<768, 1>), dim3((unsigned)T), dim3(768), shm, s, nullptr, stop, 0u, A, N,
+                            K, k0, kb, lw, rw, piv, info);
     else if (rows <= 1024)
-      hipLaunchKernelGGL((panel_reg_kernel<512, 2>), dim3((unsigned)T), dim3(512), shm, s, A, N, K, k0, kb, lw, rw,
-                         piv, info);
+      hipExtLaunchKernelGGL((panel_reg_kernel<512, 2>), dim3((unsigned)T), dim3(512), shm, s, nullptr, stop, 0u, A, N,
+                            K, k0, kb, lw, rw, piv, info);
     else   // (lw == rw == 0 here: blocks of one panel)
-      hipLaunchKernelGGL(panel_kernel, dim3((unsigned)T), dim3(512), 0, s, A, N, K, k0, kb, piv, info);
+      hipExtLaunchKernelGGL(panel_kernel, dim3((unsigned)T), dim3(512), 0u, s, nullptr, stop, 0u, A, N, K, k0, kb, piv, info);
   };
   auto swap_trsm = [&](hipStream_t st, int k0, int kb, int cb, int ce) {
     // (16 lanes per column up to 128 columns, 4 beyond)
@@ -945,15 +945,15 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
     else
       hipLaunchKernelGGL((swap_trsm_kernel<2 * PANEL, 4>), grid, dim3(SWT), 0, st, A, N, K, k0, kb, cb, ce, piv);
   };
-  auto update = [&](hipStream_t st, int k0, int kb, int cb, int ce, bool far) {
+  auto update = [&](hipStream_t st, int k0, int kb, int cb, int ce, bool far, hipEvent_t stop) {
     const int rt = (N - k0 - kb + UT - 1) / UT, ct = (ce - cb + UT - 1) / UT;
     const long long pairs = ((long long)rt * ct * T + 1) / 2;
     if (far && persist_grid > 0)
-      hipLaunchKernelGGL(update_persist_kernel, dim3((unsigned)(pairs < persist_grid ? pairs : persist_grid)),
-                         dim3(512), 0, st, A, N, k0, kb, cb, ce, rt, ct, T);
+      hipExtLaunchKernelGGL(update_persist_kernel, dim3((unsigned)(pairs < persist_grid ? pairs : persist_grid)),
+                            dim3(512), 0u, st, nullptr, stop, 0u, A, N, k0, kb, cb, ce, rt, ct, T);
     else
-      hipLaunchKernelGGL(update_mfma_kernel, dim3((unsigned)ct, (unsigned)rt, (unsigned)T), dim3(256), 0, st, A, N, k0,
-                         kb, cb, ce);
+      hipExtLaunchKernelGGL(update_mfma_kernel, dim3((unsigned)ct, (unsigned)rt, (unsigned)T), dim3(256), 0u, st, nullptr,
+                            stop, 0u, A, N, k0, kb, cb, ce);
   };
   auto block_width = [&](int k0) {
     const int w = N - k0 <= 1024 ? 2 * PANEL : PANEL;
@@ -961,24 +961,21 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
   };
   for (int k0 = 0; k0 < K;) {
     const int ob = block_width(k0), ka = ob < PANEL ? ob : PANEL;
-    // the first panel also takes the second panel's columns through its
-    // swaps, U rows and in-panel updates; the second panel's swaps also
-    // reach the first panel's columns
-    panel(k0, ka, 0, ob - ka);
-    if (ob > ka) panel(k0 + ka, ob - ka, ka, 0);
-    EMS_LAUNCH_CHECK();
     const int c1 = k0 + ob;
-    if (c1 >= N) break;   // (no trailing columns: K == N)
     const int nb = c1 < K ? block_width(c1) : 0;   // width of the next block (0 after the last)
     const int c2 = nb > 0 ? c1 + nb : N;
-    // the far columns [c2, N) on the second stream, after this block (and,
-    // in its own order, after the previous step's far columns)
-    const bool far = c2 < N;
-    // (plain event records: attaching the events to the kernels through the
-    // extended launch saved a few microseconds per block here, but made the
-    // solves running on other streams of the same process wait several
-    // times longer)
-    if (far) EMS_HIP(hipEventRecord(ev.panel, s));
+    // the far columns [c2, N) go to the second stream, after this block's
+    // panels (and, in its own order, after the previous step's far columns)
+    const bool far = c1 < N && c2 < N;
+    // the first panel also takes the second panel's columns through its
+    // swaps, U rows and in-panel updates; the second panel's swaps also
+    // reach the first panel's columns.  The events between the streams
+    // complete with the kernels before them (extended launches with a stop
+    // event), so that the caller's stream carries no marker of its own
+    panel(k0, ka, 0, ob - ka, far && ob == ka ? ev.panel : nullptr);
+    if (ob > ka) panel(k0 + ka, ob - ka, ka, 0, far ? ev.panel : nullptr);
+    EMS_LAUNCH_CHECK();
+    if (c1 >= N) break;   // (no trailing columns: K == N)
     // the previous step's far columns, [c1, N), are final on the second stream
     if (rest_pending) EMS_HIP(hipStreamWaitEvent(s, ev.rest, 0));
     rest_pending = false;
@@ -987,17 +984,16 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
       swap_trsm(aux, k0, ob, c2, N);
     }
     swap_trsm(s, k0, ob, c1, c2);
-    update(s, k0, ob, c1, c2, false);
+    update(s, k0, ob, c1, c2, false, nullptr);
     EMS_LAUNCH_CHECK();
     if (far) {
-      // the far update after the near one: the near update (on the path to
-      // the next block) has the whole device, the far one then runs beside
-      // the next block's panels
-      EMS_HIP(hipEventRecord(ev.near, s));
-      EMS_HIP(hipStreamWaitEvent(aux, ev.near, 0));
-      update(aux, k0, ob, c2, N, true);
+      // the far update follows the far swap at once and runs beside the near
+      // columns' update and the next block's panels (its persistent grid
+      // leaves them CUs); waiting for the near update as well took an event
+      // on the caller's stream per block, which cost more than the near
+      // update gains from having the device to itself
+      update(aux, k0, ob, c2, N, true, ev.rest);
       EMS_LAUNCH_CHECK();
-      EMS_HIP(hipEventRecord(ev.rest, aux));
       rest_pending = true;
     }
     k0 = c1;
