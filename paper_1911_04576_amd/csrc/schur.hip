@@ -250,17 +250,23 @@ __global__ void __launch_bounds__(NT) panel_reg_kernel(double2* __restrict__ A, 
           for (int c = 0; c < PSB; ++c) krow[par][c] = r[q][c];
       }
       __syncthreads();
-      double bv = rv[par][0];
-      int p = ri[par][0], pw = 0;
-#pragma unroll
-      for (int w = 1; w < NT / 64; ++w) {
-        const double ov = rv[par][w];
-        const int oi = ri[par][w];
-        const bool take = (ov > bv) | ((ov == bv) & (oi < p));
-        bv = take ? ov : bv;
-        p = take ? oi : p;
-        pw = take ? w : pw;
+      // the wavefronts' candidates: lane w (w < NT / 64) of every row of 16
+      // lanes takes wavefront w's, the others an empty one that never wins;
+      // four DPP steps leave every lane with the best, read as uniform values
+      double bv;
+      int p;
+      {
+        const int w = lane & 15;
+        double cv = w < NT / 64 ? rv[par][w < NT / 64 ? w : 0] : -2.0;
+        int ci = w < NT / 64 ? ri[par][w < NT / 64 ? w : 0] : 0x7fffffff;
+        argmax_take(cv, ci, dpp_d<0xB1>(cv), dpp_i<0xB1>(ci));
+        argmax_take(cv, ci, dpp_d<0x4E>(cv), dpp_i<0x4E>(ci));
+        argmax_take(cv, ci, dpp_d<0x124>(cv), dpp_i<0x124>(ci));
+        argmax_take(cv, ci, dpp_d<0x128>(cv), dpp_i<0x128>(ci));
+        bv = readlane_d(cv, 0);
+        p = __builtin_amdgcn_readlane(ci, 0);
       }
+      const int pw = ((p - k0) % NT) / 64;   // the wavefront that holds row p
       const double2* prow = cand[par][pw];   // the pivot row over the sub-block
       const bool singular = !(bv > 0.0);
       if (singular && first_singular < 0) first_singular = col;
