@@ -382,7 +382,7 @@ __global__ void __launch_bounds__(NT) panel_reg_kernel(double2* __restrict__ A, 
       // walks rows rofs, rofs + rstep, ... (consecutive threads on
       // consecutive columns of a row, the row's multipliers from LDS), with
       // UB rows' requests in flight at once
-      constexpr int UB = NT > 512 ? 8 : 16;   // (fewer registers for the larger workgroups)
+      constexpr int UB = NT >= 1024 ? 4 : 16;   // (fewer registers for the larger workgroup)
       const int nrc = kb + rw - rc0, rstep = NT / nrc, nrow = N - c0 - sbw;
       const int rofs = tid / nrc, c = rc0 + tid % nrc;
       if (rofs < rstep) {
@@ -923,16 +923,13 @@ void eliminate(double2* A, int N, int K, int T, int* piv, int* info, hipStream_t
     const int rows = N - k0;
     const uint32_t shm = (uint32_t)((size_t)rows * PSB * sizeof(double2));
     // (the sub-block staging holds rows * PSB values in LDS; one row per
-    // thread up to 768 rows, which shortens every column step; 1024 threads
-    // with one row each were slower than 512 with two)
+    // thread: 512 threads up to 512 rows, 1024 beyond, where the larger
+    // workgroup beat 768 threads and 512 with two rows each)
     if (rows <= 512)
       hipExtLaunchKernelGGL((panel_reg_kernel<512, 1>), dim3((unsigned)T), dim3(512), shm, s, nullptr, stop, 0u, A, N,
                             K, k0, kb, lw, rw, piv, info);
-    else if (rows <= 768)
-      hipExtLaunchKernelGGL((panel_reg_kernel<768, 1>), dim3((unsigned)T), dim3(768), shm, s, nullptr, stop, 0u, A, N,
-                            K, k0, kb, lw, rw, piv, info);
     else if (rows <= 1024)
-      hipExtLaunchKernelGGL((panel_reg_kernel<512, 2>), dim3((unsigned)T), dim3(512), shm, s, nullptr, stop, 0u, A, N,
+      hipExtLaunchKernelGGL((panel_reg_kernel<1024, 1>), dim3((unsigned)T), dim3(1024), shm, s, nullptr, stop, 0u, A, N,
                             K, k0, kb, lw, rw, piv, info);
     else   // (lw == rw == 0 here: blocks of one panel)
       hipExtLaunchKernelGGL(panel_kernel, dim3((unsigned)T), dim3(512), 0u, s, nullptr, stop, 0u, A, N, K, k0, kb, piv, info);
